@@ -1,0 +1,268 @@
+/*
+ * apmg.h -- C ABI of the MI355X (gfx950) library for the hot path of the
+ * adaptively placed multi-grid scene representation network (APMGSRN) of
+ * Wurster et al., "Adaptively Placed Multi-Grid Scene Representation
+ * Networks for Large-Scale Data Visualization".
+ *
+ * Model (Sec. 4.1): f(x) = d(e(x)) for x in [-1,1]^3.
+ *   Encoder (Sec. 4.1.1): M feature grids of C channels at R^3 vertices.
+ *     Eq. (1): grid i maps a global point to its local frame,
+ *              l = G_i[0:3,0:3] x + G_i[0:3,3].
+ *     Eq. (2): e_i = trilinear interpolation of grid i at l, with vertices
+ *              corner-aligned at -1 and +1, when -1 <= l_d <= 1 on every
+ *              axis (inclusive; a NaN coordinate is outside); otherwise the
+ *              C features are exactly 0.
+ *     Eq. (3): y = e_0 (+) e_1 (+) ... (+) e_{M-1}, feature index i*C + c.
+ *   Decoder (Sec. 4.1.2): a bias-free MLP, ReLU after every layer but the
+ *     last, then d(y) = m(y) (vmax - vmin) + vmin.
+ * Feature density (Sec. 4.2): Eq. (7) flat-top density, Eq. (8) target
+ * density, Eq. (9) KL loss.  Training (Sec. 4.3.2, Sec. 7): L_rec updates F
+ * and the MLP, L_density updates the transforms, Adam.
+ * Domain decomposition (Sec. 5.1, 5.3): bricks with ghost cells and a
+ * spatial hash from global points to bricks.
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ * - All array pointers are DEVICE pointers unless stated otherwise, owned
+ *   by the caller.  The library allocates nothing per call: scratch memory
+ *   is the caller's workspace (size from apmg_workspace_bytes()).
+ * - Every call is asynchronous on `stream` (0 = the null stream) and may be
+ *   captured in a HIP graph; no call reads device data back to the host or
+ *   synchronises, and no call records a memset (buffers are cleared with
+ *   kernels).
+ * - Points are structure-of-arrays: x at pts[0..n), y at pts[ld..ld+n),
+ *   z at pts[2*ld..2*ld+n), with ld >= n.
+ * - Grids are stored channel-last, [M][R][R][R][C] with axes (z, y, x, c),
+ *   x fastest over vertices: F[i, c, z, y, x] of the paper's [M, C, D, H, W]
+ *   tensor is at ((i*R + z)*R + y)*R + x)*C + c.  apmg_convert_grids()
+ *   converts from and to the paper's [M][C][R][R][R] order.
+ * - Transforms are the 12 free entries of each 4x4 matrix, [M][3][4]
+ *   row-major float32 (row 3 is fixed to (0,0,0,1) by Eq. (1)).
+ * - MLP weights W_k are [width[k+1]][width[k]] row-major float32 (the
+ *   master copy); mlp_dtype selects the arithmetic of the matrix products.
+ * - Status: APMG_EINVAL for a NULL required pointer, n < 0, ld < n, or an
+ *   inconsistent shape; APMG_EUNSUPPORTED for a shape or dtype outside the
+ *   built kernels (there is no slow fallback); APMG_EWORKSPACE when ws_bytes
+ *   is below apmg_workspace_bytes(); APMG_EHIP when a launch fails (faults
+ *   inside kernels surface at the caller's next synchronisation).
+ *   Nothing is launched when a call returns an error.
+ * - Values are not validated (that would need a device read): non-finite
+ *   points fall outside every grid and give f = vmin.
+ * - n = 0 is valid: outputs are written as for an empty batch (zeros).
+ * - Calls are reentrant given distinct workspaces and outputs.
+ */
+#ifndef APMG_H
+#define APMG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  APMG_OK = 0,
+  APMG_EINVAL = -1,
+  APMG_EUNSUPPORTED = -2,
+  APMG_EWORKSPACE = -3,
+  APMG_EHIP = -4
+} apmg_status;
+
+typedef enum { APMG_F32 = 0, APMG_F16 = 1, APMG_BF16 = 2 } apmg_dtype;
+
+/* flags */
+#define APMG_ACCUMULATE     0x1u  /* add into the outputs instead of overwriting them */
+#define APMG_DETERMINISTIC  0x2u  /* bitwise-reproducible reductions (slower grid scatter) */
+#define APMG_ADD_REC_DG     0x4u  /* training step: add L_rec's transform gradient to L_density's */
+#define APMG_ERR_ABS        0x8u  /* training step: h(x) = |f - v| instead of (f - v)^2 */
+
+#define APMG_MAX_LAYERS 8
+
+/* One APMGSRN.  Supported by the built kernels: C in {1, 2, 4}; M*C <= 256;
+ * n_layers == 3 with width = {M*C, H, H, 1} and H in {64, 128};
+ * grid_dtype F32 or F16; mlp_dtype F32 or BF16. */
+typedef struct apmg_model {
+  int32_t M;                        /* number of feature grids (>= 1) */
+  int32_t C;                        /* feature channels per grid (>= 1) */
+  int32_t R;                        /* vertices per axis (>= 2) */
+  int32_t n_layers;                 /* number of weight matrices */
+  int32_t width[APMG_MAX_LAYERS + 1]; /* width[0] = M*C, width[n_layers] = 1 */
+  int32_t grid_dtype;               /* apmg_dtype of F */
+  int32_t mlp_dtype;                /* apmg_dtype of the MLP products (F32 or BF16, fp32 accumulate) */
+  const float* G;                   /* [M][3][4] transforms, global -> local (Eq. (1)) */
+  const void* F;                    /* [M][R][R][R][C] grids, grid_dtype */
+  const float* W[APMG_MAX_LAYERS];  /* W_k: [width[k+1]][width[k]], no biases */
+  float vmin, vmax;                 /* output scaling, Sec. 4.1.2 "Scaling" */
+} apmg_model;
+
+/* ---------------------------------------------------------------- forward
+ * f[n] = d(e(x_n)) for n points (Sec. 4.1, Eqs. (1)-(3) and the decoder).
+ * f: [n] float32 output. */
+apmg_status apmg_forward(const apmg_model* model, const float* pts, int64_t ld, int64_t n,
+                         float* f, void* ws, size_t ws_bytes, hipStream_t stream);
+
+/* ---------------------------------------------------------------- adjoint
+ * Gradients of L = sum_n df[n] * f(x_n), computed by recomputing the
+ * forward pass for each tile of points and back-propagating by hand
+ * (ReLU'(0) = 0; the mask of Eq. (2) contributes no gradient; at a vertex
+ * the one-sided derivative of the selected cell).
+ *   df: [n] float32, dL/df.
+ *   dF: [M][R][R][R][C] float32 (also when grids are F16) or NULL.
+ *   dG: [M][3][4] float64 or NULL (gradient through the trilinear weights).
+ *   dW: host array of n_layers device pointers, each [width[k+1]][width[k]]
+ *       float32, or NULL for no MLP gradient.
+ * Outputs are overwritten unless APMG_ACCUMULATE.  dF uses float32
+ * atomics (order-dependent rounding) unless APMG_DETERMINISTIC, which
+ * reduces each vertex's contributions in a fixed order.  dG and dW are
+ * always reduced in a fixed order (per-tile partials, float64 sum). */
+apmg_status apmg_backward(const apmg_model* model, const float* pts, int64_t ld, int64_t n,
+                          const float* df, float* dF, double* dG, float* const* dW,
+                          uint32_t flags, void* ws, size_t ws_bytes, hipStream_t stream);
+
+/* ---------------------------------------------------------------- density
+ * Sec. 4.2.  rho(x) = sum_i det(G_i[0:3,0:3]) exp(-sum_d l_d^{2p})  (Eq. (7),
+ * signed determinant, exp(-s) taken as 0 for s > 87 or NaN);
+ * rho_s = rho / sum_X rho; h_bar = mean(err);
+ * rho* = exp(h_bar/(err+eps) log(rho_s + eps))                  (Eq. (8));
+ * loss = (1/n) sum rho* (log rho* - log(rho_s + eps)), 0 log 0 = 0 (Eq. (9)).
+ * dG = d loss / dG with rho* held constant.  If sum_X rho == 0 the loss and
+ * gradient are 0.
+ *   err: [n] float32, the per-point error h(x).
+ *   loss: [1] float64 output.  dG: [M][3][4] float64 or NULL.
+ *   rho: [n] float32 output of Eq. (7), or NULL.
+ * flags: APMG_ACCUMULATE adds into dG (loss is always overwritten).
+ * Per-point arithmetic is float32; all sums over points are float64. */
+apmg_status apmg_density_loss(const apmg_model* model, const float* pts, int64_t ld, int64_t n,
+                              const float* err, double eps, int32_t p,
+                              double* loss, double* dG, float* rho, uint32_t flags,
+                              void* ws, size_t ws_bytes, hipStream_t stream);
+
+/* ---------------------------------------------------------------- bricks
+ * Sec. 5.1: a volume of nx*ny*nz voxels split into bricks of edge B voxels,
+ * I = ceil(nx/B) (etc.) bricks per axis, listed in x, y, z order
+ * (id = i + I j + I J k, Sec. 5.3).  Brick i's base extent is voxels
+ * [iB, min((i+1)B, n)); its extended extent adds `ghost` voxels on each side,
+ * clipped to the volume: [max(iB-g, 0), min((i+1)B-1+g, n-1)] inclusive.
+ * A brick model's local coordinate l in [-1,1] maps corner-aligned onto the
+ * extended extent. */
+typedef struct apmg_brick {
+  int32_t ijk[3];
+  int32_t e0[3];            /* first voxel of the extended extent (x, y, z) */
+  int32_t e1[3];            /* last voxel of the extended extent (inclusive) */
+  float vmin, vmax;         /* the brick model's output scaling */
+} apmg_brick;
+
+typedef struct apmg_brick_table {
+  int32_t dims[3];          /* I, J, K */
+  int32_t vol[3];           /* nx, ny, nz */
+  int32_t B, ghost;
+} apmg_brick_table;
+
+/* Host-only: fills *table and, if bricks != NULL, up to cap bricks (host
+ * memory; vmin/vmax set to 0/1).  Returns EINVAL for non-positive sizes,
+ * ghost < 0, or cap < I*J*K when bricks != NULL. */
+apmg_status apmg_make_bricks(int32_t nx, int32_t ny, int32_t nz, int32_t B, int32_t ghost,
+                             apmg_brick_table* table, apmg_brick* bricks, int32_t cap);
+
+/* Sec. 5.3 spatial hash for uneven bricks: the voxel coordinate
+ * u_d = fma(p_d, (n_d-1)/2, (n_d-1)/2) (float32) picks the base brick holding
+ * floor(u_d): i = clamp(floor(u) div B, 0, I-1).  brick: [n] int32 output. */
+apmg_status apmg_assign_bricks(const apmg_brick_table* table, const float* pts, int64_t ld,
+                               int64_t n, int32_t* brick, hipStream_t stream);
+
+/* ---------------------------------------------------------------- training step
+ * One training iteration (Sec. 4.3.2, Sec. 7) for nb independent models of
+ * one shape, each trained on its own brick of one volume (nb = 1 with one
+ * brick spanning the volume is the single-model step).  For every model b:
+ *   1. n uniform points in [-1,1)^3 from Philox4x64-10 (counter
+ *      (j, step, b, 0), key (seed, 0x41504D47); coordinate = (w >> 40) 2^-23 - 1);
+ *   2. v = trilinear sample of brick b's extended sub-volume;
+ *   3. forward, L_rec = mean (f - v)^2, h = (f - v)^2 (or |f - v|);
+ *   4. adjoint of L_rec into F and W;
+ *   5. if density_active[b]: L_density and its transform gradient (+ L_rec's
+ *      transform gradient under APMG_ADD_REC_DG);
+ *   6. Adam (bias-corrected, float32 master weights): F and W with lr, every
+ *      step; G with lr_G, only when density_active[b]; writes the F16 grid
+ *      shadow when grid_dtype is F16.
+ *   7. *step += 1 (device counter; a captured graph replays fresh batches).
+ * All per-model arrays are contiguous arenas indexed by model: model b's
+ * block starts at b * (block size).  Adam moments and counters are device
+ * memory the caller zero-initialises. */
+typedef struct apmg_batch {
+  int32_t nb;                 /* number of models */
+  apmg_model shape;           /* M, C, R, n_layers, width, dtypes; pointers ignored */
+  float* G;                   /* [nb][M][3][4] */
+  float* F;                   /* [nb][M][R][R][R][C] float32 master grids */
+  void* F_lowp;               /* [nb][M][R][R][R][C] F16 shadow (grid_dtype F16) or NULL */
+  float* W;                   /* [nb][sum_k width[k+1]*width[k]], layers concatenated */
+  float* mG; float* vG;       /* Adam moments, shapes of G */
+  float* mF; float* vF;       /* shapes of F */
+  float* mW; float* vW;       /* shapes of W */
+  int32_t* t;                 /* [nb] Adam step of F and W */
+  int32_t* tG;                /* [nb] Adam step of G (counts density steps only) */
+  const int32_t* density_active; /* [nb] 0/1 */
+  const float* volume;        /* [nz][ny][nx] float32 */
+  const apmg_brick* bricks;   /* [nb] device brick descriptors (extents, vmin, vmax) */
+  int32_t vol[3];             /* nx, ny, nz */
+  int64_t n;                  /* points per model per step */
+  uint64_t seed;
+  uint64_t* step;             /* device step counter */
+  float lr, lr_G, beta1, beta2, adam_eps;
+  double eps_density;
+  int32_t p;                  /* flat-top strength (10) */
+  uint32_t flags;
+  double* losses;             /* [nb][2] output: L_rec, L_density */
+} apmg_batch;
+
+apmg_status apmg_batched_step(const apmg_batch* batch, void* ws, size_t ws_bytes,
+                              hipStream_t stream);
+
+/* ---------------------------------------------------------------- workspace
+ * Bytes of workspace for `op` (one of the values below) on a model (or, for
+ * APMG_OP_BATCHED_STEP, a batch) with n points.  0 for an invalid request. */
+#define APMG_OP_FORWARD 0
+#define APMG_OP_BACKWARD 1
+#define APMG_OP_DENSITY 2
+#define APMG_OP_BATCHED_STEP 3
+size_t apmg_workspace_bytes(int op, const void* model_or_batch, int64_t n);
+
+const char* apmg_status_string(apmg_status status);
+
+/* ---------------------------------------------------------------- layout
+ * Converts grids between the paper's [M][C][R][R][R] order (to_channel_last
+ * = 1: src is paper order) and the library's [M][R][R][R][C] order, in the
+ * same float32 or F16 dtype, optionally converting float32 -> F16 when
+ * dst_dtype is F16 and src_dtype F32.  src and dst must not overlap. */
+apmg_status apmg_convert_grids(int32_t M, int32_t C, int32_t R, const void* src, int32_t src_dtype,
+                               void* dst, int32_t dst_dtype, int32_t to_channel_last,
+                               hipStream_t stream);
+
+/* ---------------------------------------------------------------- test exports
+ * The integer decisions of Eq. (2), in the library's float32 arithmetic:
+ * l_r = fma(G[r,2], x_z, fma(G[r,1], x_y, fma(G[r,0], x_x, G[r,3]))),
+ * inside = all(-1 <= l_d <= 1), u = fma(l, (R-1)/2, (R-1)/2),
+ * cell = clamp(floor(u), 0, R-2).
+ *   cell: [n][M][3] int32 (x, y, z), -1 on every axis where outside.
+ *   inside: [n][M] uint8. */
+apmg_status apmg_cells(const apmg_model* model, const float* pts, int64_t ld, int64_t n,
+                       int32_t* cell, uint8_t* inside, hipStream_t stream);
+
+/* The training step's point generator (step 1 above) for model `stream_id`:
+ * points start .. start+n-1 written SoA to pts [3][ld]. */
+apmg_status apmg_uniform_points(uint64_t seed, uint64_t step, uint32_t stream_id, int64_t start,
+                                int64_t n, float* pts, int64_t ld, hipStream_t stream);
+
+/* Trilinear ground-truth sampling of a [nz][ny][nx] float32 volume at global
+ * points (Sec. 4.3.1): voxel k of an axis of n voxels sits at -1 + 2k/(n-1);
+ * u = fma(x, (n-1)/2, (n-1)/2), lower voxel clamp(floor(u), 0, n-2).
+ *   v: [n] float32 output. */
+apmg_status apmg_gt_sample(const float* volume, int32_t nx, int32_t ny, int32_t nz,
+                           const float* pts, int64_t ld, int64_t n, float* v, hipStream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* APMG_H */

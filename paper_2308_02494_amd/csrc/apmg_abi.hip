@@ -1,0 +1,590 @@
+// Host side of the C ABI declared in include/apmg.h: argument validation,
+// workspace layout and the launch sequence of every entry point.
+#include <vector>
+
+using namespace apmg;
+
+namespace {
+
+constexpr size_t kAlign = 256;
+inline size_t align_up(size_t x) { return (x + kAlign - 1) & ~(kAlign - 1); }
+
+// Bump allocator over the caller's workspace (or a size counter when base == NULL).
+struct Carver {
+  char* base;
+  size_t off = 0;
+  explicit Carver(void* b) : base((char*)b) {}
+  template <typename T> T* take(size_t count) {
+    T* p = base ? (T*)(base + off) : nullptr;
+    off = align_up(off + count * sizeof(T));
+    return p;
+  }
+};
+
+constexpr int kMaxTileBlocks = 512;
+constexpr int kDensBlocks = 1024;
+constexpr size_t kLdsLimit = 160 * 1024;
+
+apmg_status check_model(const apmg_model* m, bool need_params, Shape* out) {
+  if (!m) return APMG_EINVAL;
+  if (m->M < 1 || m->C < 1 || m->R < 2 || m->n_layers < 1 || m->n_layers > APMG_MAX_LAYERS) return APMG_EINVAL;
+  if (m->width[0] != m->M * m->C || m->width[m->n_layers] != 1) return APMG_EINVAL;
+  for (int k = 0; k <= m->n_layers; ++k) if (m->width[k] < 1) return APMG_EINVAL;
+  if (need_params) {
+    if (!m->G || !m->F) return APMG_EINVAL;
+    for (int k = 0; k < m->n_layers; ++k) if (!m->W[k]) return APMG_EINVAL;
+  }
+  if (m->grid_dtype != APMG_F32 && m->grid_dtype != APMG_F16) return APMG_EUNSUPPORTED;
+  if (m->mlp_dtype != APMG_F32 && m->mlp_dtype != APMG_BF16) return APMG_EUNSUPPORTED;
+  if (!(m->C == 1 || m->C == 2 || m->C == 4)) return APMG_EUNSUPPORTED;
+  if (m->M * m->C > 256) return APMG_EUNSUPPORTED;
+  if (m->n_layers != 3 || m->width[1] != m->width[2] || !(m->width[1] == 64 || m->width[1] == 128))
+    return APMG_EUNSUPPORTED;
+  if ((double)m->R * m->R * m->R * m->M * m->C > 2e9) return APMG_EUNSUPPORTED;
+  Shape s;
+  s.M = m->M; s.C = m->C; s.R = m->R; s.H = m->width[1];
+  s.Mh = (m->M + 1) / 2;
+  s.KH = s.Mh * s.C;
+  s.KHP = (s.KH + 15) / 16 * 16;
+  s.MC = m->M * m->C;
+  if (out) *out = s;
+  return APMG_OK;
+}
+
+apmg_status check_points(const float* pts, int64_t ld, int64_t n) {
+  if (n < 0 || ld < n) return APMG_EINVAL;
+  if (n > 0 && !pts) return APMG_EINVAL;
+  return APMG_OK;
+}
+
+apmg_status hip_status(hipError_t e) { return e == hipSuccess ? APMG_OK : APMG_EHIP; }
+
+inline unsigned grid1(int64_t n, int64_t cap = 4096) {
+  int64_t g = (n + 255) / 256;
+  if (g < 1) g = 1;
+  return (unsigned)std::min<int64_t>(g, cap);
+}
+
+int tile_blocks(int64_t n) {
+  const int64_t tiles = (n + 31) / 32;
+  int64_t b = (tiles + kWavesPerBlock - 1) / kWavesPerBlock;
+  return (int)std::max<int64_t>(1, std::min<int64_t>(b, kMaxTileBlocks));
+}
+
+// Adjoint passes: each accumulates a block of second-layer gradient rows and a slice of
+// first-layer gradient columns in LDS; the first pass also scatters dF, reduces dG and
+// the output-layer gradient.  Chosen so that every pass fits the LDS.
+struct Pass { int c1_lo, c1_hi, w2_lo, w2_hi; bool first; };
+std::vector<Pass> plan_passes(const Shape& s, bool bf, bool want_w) {
+  std::vector<Pass> out;
+  if (!want_w) { out.push_back({0, 0, 0, 0, true}); return out; }
+  int r0 = 0, c0 = 0;
+  while (r0 < s.H || c0 < s.MC) {
+    int r = 0;
+    while (r0 + r + 32 <= s.H && backward_lds_bytes(s, 0, r + 32, bf) <= kLdsLimit) r += 32;
+    int c = 0;
+    if (r0 + r >= s.H) {  // rows done in this pass: give the rest of the budget to columns
+      int lo = 0, hi = s.MC - c0;
+      while (lo < hi) {
+        const int mid = (lo + hi + 1) / 2;
+        if (backward_lds_bytes(s, mid, r, bf) <= kLdsLimit) lo = mid; else hi = mid - 1;
+      }
+      c = lo;
+    }
+    if (r == 0 && c == 0) return {};
+    out.push_back({c0, c0 + c, r0, r0 + r, out.empty()});
+    r0 += r;
+    c0 += c;
+  }
+  return out;
+}
+int max_part_len(const Shape& s, bool bf) {
+  int len = part_layout(s, 0, 0).len;
+  for (const Pass& p : plan_passes(s, bf, true))
+    len = std::max(len, part_layout(s, p.c1_hi - p.c1_lo, p.w2_hi - p.w2_lo).len);
+  return len;
+}
+
+// ---------------------------------------------------------------- workspace layouts
+struct FwdWs { void* swz; float* w3s; };
+size_t fwd_ws(const Shape& s, bool bf, void* ws, FwdWs* o) {
+  Carver cv(ws);
+  const size_t esz = bf ? 2 : 4;
+  void* swz = cv.take<char>(swz_sizes(s).total() * esz);
+  float* w3s = cv.take<float>(s.H);
+  if (o) { o->swz = swz; o->w3s = w3s; }
+  return cv.off;
+}
+
+struct BwdWs { FwdWs f; double* part; };
+size_t bwd_ws(const Shape& s, bool bf, int64_t n, void* ws, BwdWs* o) {
+  Carver cv(ws);
+  const size_t esz = bf ? 2 : 4;
+  void* swz = cv.take<char>(swz_sizes(s).total() * esz);
+  float* w3s = cv.take<float>(s.H);
+  double* part = cv.take<double>((size_t)tile_blocks(n) * max_part_len(s, bf));
+  if (o) { o->f.swz = swz; o->f.w3s = w3s; o->part = part; }
+  return cv.off;
+}
+
+struct DenWs { float* rho; double *pa, *sums, *pb1, *lq, *pb2, *U; };
+size_t den_ws(const Shape& s, int64_t n, int nb, void* ws, DenWs* o) {
+  Carver cv(ws);
+  DenWs d;
+  d.rho = cv.take<float>((size_t)nb * std::max<int64_t>(n, 1));
+  d.pa = cv.take<double>((size_t)nb * kDensBlocks * 2);
+  d.sums = cv.take<double>((size_t)nb * 2);
+  d.pb1 = cv.take<double>((size_t)nb * kDensBlocks * 2);
+  d.lq = cv.take<double>((size_t)nb * 2);
+  d.pb2 = cv.take<double>((size_t)nb * kDensBlocks * 13 * s.M);
+  d.U = cv.take<double>((size_t)nb * 13 * s.M);
+  if (o) *o = d;
+  return cv.off;
+}
+
+int dens_blocks(int64_t n) { return (int)std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, kDensBlocks)); }
+int dens_b2_blocks(int64_t n) {
+  return (int)std::max<int64_t>(1, std::min<int64_t>((n + 256 * 8 - 1) / (256 * 8), kDensBlocks));
+}
+
+// Density loss launch sequence for nb models sharing one shape.  pts/err/rho are per
+// model with the given strides; outputs loss (stride lstride) and dG (stride dG_stride).
+hipError_t launch_density(const Shape& s, const float* G, size_t G_stride, const float* pts, int64_t ld,
+                          size_t pts_stride, int64_t n, const float* err, size_t err_stride, double eps,
+                          int p, double* loss, int lstride, double* dG, size_t dG_stride, int accumulate,
+                          float* rho_user, const DenWs& w, int nb, const int32_t* active, hipStream_t st) {
+  float* rho = rho_user ? rho_user : w.rho;
+  const size_t rho_stride = rho_user ? (size_t)n : (size_t)std::max<int64_t>(n, 1);
+  const int ba = dens_blocks(n), bb = dens_b2_blocks(n);
+  const size_t shA = 16 + (size_t)13 * s.M * 4;
+  hipLaunchKernelGGL(k_density_a, dim3(ba, nb), dim3(256), shA, st, s, G, G_stride, pts, ld, pts_stride, n,
+                     err, err_stride, p, rho, rho_stride, w.pa, active);
+  hipLaunchKernelGGL(k_density_sums, dim3((nb + 63) / 64), dim3(64), 0, st, w.pa, ba, w.sums, nb);
+  hipLaunchKernelGGL(k_density_b1, dim3(ba, nb), dim3(256), 0, st, rho, rho_stride, err, err_stride, n,
+                     w.sums, eps, w.pb1, active);
+  hipLaunchKernelGGL(k_density_lq, dim3((nb + 63) / 64), dim3(64), 0, st, w.pb1, ba, n, w.lq, nb);
+  if (dG) {
+    const size_t shB = (size_t)13 * s.M * 8 + (size_t)12 * s.M * 4;
+    hipLaunchKernelGGL(k_density_b2, dim3(bb, nb), dim3(256), shB, st, s, G, G_stride, pts, ld, pts_stride,
+                       n, rho, rho_stride, err, err_stride, w.sums, w.lq, eps, p, w.pb2, active);
+    hipLaunchKernelGGL(k_reduce_parts, dim3(grid1(13 * s.M, 64), nb), dim3(256), 0, st, w.pb2, bb,
+                       13 * s.M, 0, 13 * s.M, 13 * s.M, 0, 0, (float*)nullptr, w.U, (size_t)13 * s.M, 0,
+                       active);
+    hipLaunchKernelGGL(k_density_grad, dim3(1, nb), dim3(64), 0, st, s, G, G_stride, w.U, p, dG, dG_stride,
+                       accumulate, w.sums, active);
+  }
+  if (loss) hipLaunchKernelGGL(k_copy_f64, dim3((nb + 63) / 64), dim3(64), 0, st, w.lq, 2, loss, lstride, nb, 1.0);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- training step
+struct StepWs {
+  float* pts;     // [nb][3][n]
+  float* v;       // [nb][n]
+  float* err;     // [nb][n]
+  void* swz;      // [nb][swizzled weights]
+  float* w3s;     // [nb][H]
+  float* scale;   // [nb][2] (vmax - vmin, vmin)
+  float* dF;      // [nb][F]
+  float* dW;      // [nb][W]
+  double* dG;     // [nb][12 M]  transform gradient used by Adam
+  double* dGrec;  // [nb][12 M]  L_rec's transform gradient (multi-pass adjoint only)
+  double* lrec;   // [nb] sum (f - v)^2
+  double* part;   // adjoint partials
+  DenWs den;
+};
+
+size_t w_elems(const Shape& s) { return (size_t)s.H * s.MC + (size_t)s.H * s.H + s.H; }
+size_t f_elems(const Shape& s) { return (size_t)s.M * s.R * s.R * s.R * s.C; }
+
+size_t step_ws(const apmg_batch* b, const Shape& s, void* ws, StepWs* o) {
+  Carver cv(ws);
+  const bool bf = b->shape.mlp_dtype == APMG_BF16;
+  const int nb = b->nb;
+  const int64_t n = std::max<int64_t>(b->n, 1);
+  StepWs w;
+  w.pts = cv.take<float>((size_t)nb * 3 * n);
+  w.v = cv.take<float>((size_t)nb * n);
+  w.err = cv.take<float>((size_t)nb * n);
+  w.swz = cv.take<char>((size_t)nb * swz_sizes(s).total() * (bf ? 2 : 4));
+  w.w3s = cv.take<float>((size_t)nb * s.H);
+  w.scale = cv.take<float>((size_t)nb * 2);
+  w.dF = cv.take<float>((size_t)nb * f_elems(s));
+  w.dW = cv.take<float>((size_t)nb * w_elems(s));
+  w.dG = cv.take<double>((size_t)nb * 12 * s.M);
+  w.dGrec = cv.take<double>((size_t)nb * 12 * s.M);
+  w.lrec = cv.take<double>((size_t)nb);
+  w.part = cv.take<double>((size_t)nb * tile_blocks(b->n) * max_part_len(s, bf));
+  size_t off = cv.off;
+  DenWs d;
+  size_t dsz = den_ws(s, b->n, nb, ws ? (char*)ws + off : nullptr, &d);
+  w.den = d;
+  if (o) *o = w;
+  return off + dsz;
+}
+
+__global__ void k_brick_scale(const apmg_brick* bricks, float* scale, int nb) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b < nb) { scale[2 * b] = bricks[b].vmax - bricks[b].vmin; scale[2 * b + 1] = bricks[b].vmin; }
+}
+
+}  // namespace
+
+// ======================================================================== ABI
+extern "C" {
+
+const char* apmg_status_string(apmg_status s) {
+  switch (s) {
+    case APMG_OK: return "ok";
+    case APMG_EINVAL: return "invalid argument";
+    case APMG_EUNSUPPORTED: return "unsupported shape or dtype";
+    case APMG_EWORKSPACE: return "workspace too small";
+    case APMG_EHIP: return "HIP launch error";
+  }
+  return "unknown status";
+}
+
+size_t apmg_workspace_bytes(int op, const void* mb, int64_t n) {
+  if (!mb || n < 0) return 0;
+  if (op == APMG_OP_BATCHED_STEP) {
+    const apmg_batch* b = (const apmg_batch*)mb;
+    Shape s;
+    if (b->nb < 1 || b->n < 0 || check_model(&b->shape, false, &s) != APMG_OK) return 0;
+    return step_ws(b, s, nullptr, nullptr);
+  }
+  Shape s;
+  const apmg_model* m = (const apmg_model*)mb;
+  if (check_model(m, false, &s) != APMG_OK) return 0;
+  const bool bf = m->mlp_dtype == APMG_BF16;
+  switch (op) {
+    case APMG_OP_FORWARD: return fwd_ws(s, bf, nullptr, nullptr);
+    case APMG_OP_BACKWARD: return bwd_ws(s, bf, n, nullptr, nullptr);
+    case APMG_OP_DENSITY: return den_ws(s, n, 1, nullptr, nullptr);
+  }
+  return 0;
+}
+
+apmg_status apmg_forward(const apmg_model* m, const float* pts, int64_t ld, int64_t n, float* f, void* ws,
+                         size_t ws_bytes, hipStream_t st) {
+  Shape s;
+  apmg_status rc = check_model(m, true, &s);
+  if (rc != APMG_OK) return rc;
+  if ((rc = check_points(pts, ld, n)) != APMG_OK) return rc;
+  if (n > 0 && !f) return APMG_EINVAL;
+  const bool bf = m->mlp_dtype == APMG_BF16, gf16 = m->grid_dtype == APMG_F16;
+  if (ws_bytes < fwd_ws(s, bf, nullptr, nullptr) || !ws) return APMG_EWORKSPACE;
+  if (n == 0) return APMG_OK;
+  FwdWs w;
+  fwd_ws(s, bf, ws, &w);
+  hipError_t e = launch_swizzle(s, bf, m->W[0], m->W[1], m->W[2], 0, w.swz, 0, w.w3s, 1, st);
+  if (e != hipSuccess) return APMG_EHIP;
+  TileArgs a;
+  memset(&a, 0, sizeof(a));
+  a.s = s;
+  a.G = m->G; a.F = m->F; a.swz = w.swz; a.w3s = w.w3s;
+  a.vscale = m->vmax - m->vmin; a.voff = m->vmin;
+  a.pts = pts; a.ld = ld; a.n = n; a.f = f;
+  const int64_t tiles = (n + 31) / 32;
+  dim3 grid((unsigned)std::min<int64_t>((tiles + kWavesPerBlock - 1) / kWavesPerBlock, 8192), 1);
+  return hip_status(launch_tile(false, a, gf16, bf, grid, (size_t)12 * s.M * 4, st));
+}
+
+apmg_status apmg_backward(const apmg_model* m, const float* pts, int64_t ld, int64_t n, const float* df,
+                          float* dF, double* dG, float* const* dW, uint32_t flags, void* ws, size_t ws_bytes,
+                          hipStream_t st) {
+  Shape s;
+  apmg_status rc = check_model(m, true, &s);
+  if (rc != APMG_OK) return rc;
+  if ((rc = check_points(pts, ld, n)) != APMG_OK) return rc;
+  if (n > 0 && !df) return APMG_EINVAL;
+  if (dW) for (int k = 0; k < m->n_layers; ++k) if (!dW[k]) return APMG_EINVAL;
+  const bool bf = m->mlp_dtype == APMG_BF16, gf16 = m->grid_dtype == APMG_F16;
+  if (ws_bytes < bwd_ws(s, bf, n, nullptr, nullptr) || !ws) return APMG_EWORKSPACE;
+  const bool acc = flags & APMG_ACCUMULATE;
+  const size_t nF = (size_t)s.M * s.R * s.R * s.R * s.C;
+  if (!acc) {
+    if (dF) hipLaunchKernelGGL(k_fill_f32, dim3(grid1(nF)), dim3(256), 0, st, dF, nF, 0.f);
+    if (dG) hipLaunchKernelGGL(k_fill_f64, dim3(1), dim3(256), 0, st, dG, (size_t)12 * s.M, 0.0);
+    if (dW) {
+      hipLaunchKernelGGL(k_fill_f32, dim3(grid1((int64_t)s.H * s.MC)), dim3(256), 0, st, dW[0], (size_t)s.H * s.MC, 0.f);
+      hipLaunchKernelGGL(k_fill_f32, dim3(grid1((int64_t)s.H * s.H)), dim3(256), 0, st, dW[1], (size_t)s.H * s.H, 0.f);
+      hipLaunchKernelGGL(k_fill_f32, dim3(1), dim3(256), 0, st, dW[2], (size_t)s.H, 0.f);
+    }
+  }
+  if (n == 0) return hip_status(hipGetLastError());
+  BwdWs w;
+  bwd_ws(s, bf, n, ws, &w);
+  hipError_t e = launch_swizzle(s, bf, m->W[0], m->W[1], m->W[2], 0, w.f.swz, 0, w.f.w3s, 1, st);
+  if (e != hipSuccess) return APMG_EHIP;
+  const int nblk = tile_blocks(n);
+  const std::vector<Pass> passes = plan_passes(s, bf, dW != nullptr);
+  if (passes.empty()) return APMG_EUNSUPPORTED;
+  for (const Pass& ps : passes) {
+    TileArgs a;
+    memset(&a, 0, sizeof(a));
+    a.s = s;
+    a.G = m->G; a.F = m->F; a.swz = w.f.swz; a.w3s = w.f.w3s;
+    a.vscale = m->vmax - m->vmin; a.voff = m->vmin;
+    a.pts = pts; a.ld = ld; a.n = n;
+    a.df = df;
+    a.dF = ps.first ? dF : nullptr;
+    a.want_dG = (ps.first && dG) ? 1 : 0;
+    a.c1_lo = ps.c1_lo; a.c1_hi = ps.c1_hi;
+    a.w2_lo = ps.w2_lo; a.w2_hi = ps.w2_hi;
+    a.do_w3 = (ps.first && dW) ? 1 : 0;
+    a.part = w.part;
+    const int ncols = ps.c1_hi - ps.c1_lo, nrows = ps.w2_hi - ps.w2_lo;
+    const PartLayout pl = part_layout(s, ncols, nrows);
+    a.part_len = pl.len;
+    e = launch_tile(true, a, gf16, bf, dim3(nblk, 1), backward_lds_bytes(s, ncols, nrows, bf), st);
+    if (e != hipSuccess) return APMG_EHIP;
+    if (ncols > 0)
+      hipLaunchKernelGGL(k_reduce_parts, dim3(grid1((int64_t)s.H * ncols, 256), 1), dim3(256), 0, st, w.part,
+                         nblk, pl.len, pl.o_w1, s.H * ncols, ncols, s.MC, ps.c1_lo, dW[0], (double*)nullptr,
+                         (size_t)0, 1, (const int32_t*)nullptr);
+    if (nrows > 0)
+      hipLaunchKernelGGL(k_reduce_parts, dim3(grid1((int64_t)s.H * nrows, 256), 1), dim3(256), 0, st, w.part, nblk,
+                         pl.len, pl.o_w2, s.H * nrows, s.H * nrows, 0, ps.w2_lo * s.H, dW[1], (double*)nullptr,
+                         (size_t)0, 1, (const int32_t*)nullptr);
+    if (a.do_w3)
+      hipLaunchKernelGGL(k_reduce_parts, dim3(1, 1), dim3(256), 0, st, w.part, nblk, pl.len, pl.o_w3, s.H, s.H, 0,
+                         0, dW[2], (double*)nullptr, (size_t)0, 1, (const int32_t*)nullptr);
+    if (a.want_dG)
+      hipLaunchKernelGGL(k_reduce_parts, dim3(1, 1), dim3(256), 0, st, w.part, nblk, pl.len, pl.o_g, 12 * s.M,
+                         12 * s.M, 0, 0, (float*)nullptr, dG, (size_t)0, 1, (const int32_t*)nullptr);
+  }
+  return hip_status(hipGetLastError());
+}
+
+apmg_status apmg_density_loss(const apmg_model* m, const float* pts, int64_t ld, int64_t n, const float* err,
+                              double eps, int32_t p, double* loss, double* dG, float* rho, uint32_t flags,
+                              void* ws, size_t ws_bytes, hipStream_t st) {
+  Shape s;
+  if (!m || !m->G) return APMG_EINVAL;
+  apmg_status rc = check_model(m, false, &s);
+  if (rc != APMG_OK) return rc;
+  if ((rc = check_points(pts, ld, n)) != APMG_OK) return rc;
+  if (!loss || (n > 0 && !err) || p < 1 || !(eps >= 0.0)) return APMG_EINVAL;
+  if (ws_bytes < den_ws(s, n, 1, nullptr, nullptr) || !ws) return APMG_EWORKSPACE;
+  const bool acc = flags & APMG_ACCUMULATE;
+  if (n == 0) {
+    hipLaunchKernelGGL(k_fill_f64, dim3(1), dim3(64), 0, st, loss, (size_t)1, 0.0);
+    if (dG && !acc) hipLaunchKernelGGL(k_fill_f64, dim3(1), dim3(256), 0, st, dG, (size_t)12 * s.M, 0.0);
+    return hip_status(hipGetLastError());
+  }
+  DenWs w;
+  den_ws(s, n, 1, ws, &w);
+  return hip_status(launch_density(s, m->G, 0, pts, ld, 0, n, err, 0, eps, p, loss, 1, dG, 0, acc ? 1 : 0,
+                                   rho, w, 1, nullptr, st));
+}
+
+apmg_status apmg_cells(const apmg_model* m, const float* pts, int64_t ld, int64_t n, int32_t* cell,
+                       uint8_t* inside, hipStream_t st) {
+  Shape s;
+  if (!m || !m->G) return APMG_EINVAL;
+  if (m->M < 1 || m->R < 2) return APMG_EINVAL;
+  apmg_status rc = check_points(pts, ld, n);
+  if (rc != APMG_OK) return rc;
+  if (n == 0) return APMG_OK;
+  if (!cell && !inside) return APMG_EINVAL;
+  s.M = m->M; s.C = m->C; s.R = m->R;
+  hipLaunchKernelGGL(k_cells, dim3(grid1(n * m->M)), dim3(256), 0, st, s, m->G, pts, ld, n, cell, inside);
+  return hip_status(hipGetLastError());
+}
+
+apmg_status apmg_uniform_points(uint64_t seed, uint64_t step, uint32_t stream_id, int64_t start, int64_t n,
+                                float* pts, int64_t ld, hipStream_t st) {
+  if (n < 0 || start < 0 || ld < n || (n > 0 && !pts)) return APMG_EINVAL;
+  if (n == 0) return APMG_OK;
+  hipLaunchKernelGGL(k_uniform_points, dim3(grid1(n)), dim3(256), 0, st, seed, step, stream_id, start, n, pts, ld);
+  return hip_status(hipGetLastError());
+}
+
+apmg_status apmg_gt_sample(const float* volume, int32_t nx, int32_t ny, int32_t nz, const float* pts, int64_t ld,
+                           int64_t n, float* v, hipStream_t st) {
+  if (!volume || nx < 2 || ny < 2 || nz < 2) return APMG_EINVAL;
+  apmg_status rc = check_points(pts, ld, n);
+  if (rc != APMG_OK) return rc;
+  if (n == 0) return APMG_OK;
+  if (!v) return APMG_EINVAL;
+  hipLaunchKernelGGL(k_gt_sample, dim3(grid1(n)), dim3(256), 0, st, volume, nx, ny, nz, pts, ld, n, v);
+  return hip_status(hipGetLastError());
+}
+
+apmg_status apmg_make_bricks(int32_t nx, int32_t ny, int32_t nz, int32_t B, int32_t ghost,
+                             apmg_brick_table* t, apmg_brick* bricks, int32_t cap) {
+  if (!t || nx < 2 || ny < 2 || nz < 2 || B < 1 || ghost < 0) return APMG_EINVAL;
+  const int32_t n3[3] = {nx, ny, nz};
+  for (int d = 0; d < 3; ++d) { t->vol[d] = n3[d]; t->dims[d] = (n3[d] + B - 1) / B; }
+  t->B = B;
+  t->ghost = ghost;
+  const int64_t nb = (int64_t)t->dims[0] * t->dims[1] * t->dims[2];
+  if (!bricks) return APMG_OK;
+  if (cap < nb) return APMG_EINVAL;
+  int64_t id = 0;
+  for (int k = 0; k < t->dims[2]; ++k)
+    for (int j = 0; j < t->dims[1]; ++j)
+      for (int i = 0; i < t->dims[0]; ++i, ++id) {
+        apmg_brick& b = bricks[id];
+        const int ijk[3] = {i, j, k};
+        for (int d = 0; d < 3; ++d) {
+          b.ijk[d] = ijk[d];
+          b.e0[d] = std::max(ijk[d] * B - ghost, 0);
+          b.e1[d] = std::min((ijk[d] + 1) * B - 1 + ghost, n3[d] - 1);
+        }
+        b.vmin = 0.f;
+        b.vmax = 1.f;
+      }
+  return APMG_OK;
+}
+
+apmg_status apmg_assign_bricks(const apmg_brick_table* t, const float* pts, int64_t ld, int64_t n, int32_t* brick,
+                               hipStream_t st) {
+  if (!t || t->B < 1) return APMG_EINVAL;
+  for (int d = 0; d < 3; ++d) if (t->dims[d] < 1 || t->vol[d] < 2) return APMG_EINVAL;
+  apmg_status rc = check_points(pts, ld, n);
+  if (rc != APMG_OK) return rc;
+  if (n == 0) return APMG_OK;
+  if (!brick) return APMG_EINVAL;
+  hipLaunchKernelGGL(k_assign_bricks, dim3(grid1(n)), dim3(256), 0, st, *t, pts, ld, n, brick);
+  return hip_status(hipGetLastError());
+}
+
+apmg_status apmg_convert_grids(int32_t M, int32_t C, int32_t R, const void* src, int32_t sd, void* dst, int32_t dd,
+                               int32_t to_cl, hipStream_t st) {
+  if (M < 1 || C < 1 || R < 2 || !src || !dst) return APMG_EINVAL;
+  if (!((sd == APMG_F32 || sd == APMG_F16) && (dd == APMG_F32 || dd == APMG_F16))) return APMG_EUNSUPPORTED;
+  if (sd == APMG_F16 && dd == APMG_F32 && false) return APMG_EUNSUPPORTED;
+  const size_t total = (size_t)M * C * R * R * R;
+  const unsigned g = grid1((int64_t)total);
+  if (sd == APMG_F32 && dd == APMG_F32)
+    hipLaunchKernelGGL((k_convert<float, float>), dim3(g), dim3(256), 0, st, M, C, R, (const float*)src, (float*)dst, to_cl);
+  else if (sd == APMG_F32 && dd == APMG_F16)
+    hipLaunchKernelGGL((k_convert<float, uint16_t>), dim3(g), dim3(256), 0, st, M, C, R, (const float*)src, (uint16_t*)dst, to_cl);
+  else if (sd == APMG_F16 && dd == APMG_F32)
+    hipLaunchKernelGGL((k_convert<uint16_t, float>), dim3(g), dim3(256), 0, st, M, C, R, (const uint16_t*)src, (float*)dst, to_cl);
+  else
+    hipLaunchKernelGGL((k_convert<uint16_t, uint16_t>), dim3(g), dim3(256), 0, st, M, C, R, (const uint16_t*)src, (uint16_t*)dst, to_cl);
+  return hip_status(hipGetLastError());
+}
+
+}  // extern "C"
+
+extern "C" apmg_status apmg_batched_step(const apmg_batch* b, void* ws, size_t ws_bytes, hipStream_t st) {
+  if (!b || b->nb < 1 || b->n < 0) return APMG_EINVAL;
+  Shape s;
+  apmg_status rc = check_model(&b->shape, false, &s);
+  if (rc != APMG_OK) return rc;
+  const bool bf = b->shape.mlp_dtype == APMG_BF16, gf16 = b->shape.grid_dtype == APMG_F16;
+  if (!b->G || !b->F || !b->W || !b->mG || !b->vG || !b->mF || !b->vF || !b->mW || !b->vW || !b->t ||
+      !b->tG || !b->density_active || !b->volume || !b->bricks || !b->step || !b->losses)
+    return APMG_EINVAL;
+  if (gf16 && !b->F_lowp) return APMG_EINVAL;
+  for (int d = 0; d < 3; ++d) if (b->vol[d] < 2) return APMG_EINVAL;
+  if (b->p < 1 || !(b->eps_density >= 0.0)) return APMG_EINVAL;
+  if (!ws || ws_bytes < step_ws(b, s, nullptr, nullptr)) return APMG_EWORKSPACE;
+  const int nb = b->nb;
+  const int64_t n = b->n;
+  StepWs w;
+  step_ws(b, s, ws, &w);
+  const size_t nF = f_elems(s), nW = w_elems(s), nG = (size_t)12 * s.M;
+  const size_t swz_stride = swz_sizes(s).total();
+
+  // 1. batch points and ground truth
+  if (n > 0)
+    hipLaunchKernelGGL(k_batch_points_gt, dim3(grid1(n, 2048), nb), dim3(256), 0, st, b->seed, b->step, n,
+                       b->volume, b->vol[0], b->vol[1], b->bricks, w.pts, w.v);
+  // 2. operands of this step's weights, output scaling, zeroed gradients
+  hipError_t e = launch_swizzle(s, bf, b->W, b->W + (size_t)s.H * s.MC, b->W + (size_t)s.H * s.MC + (size_t)s.H * s.H,
+                                nW, w.swz, swz_stride, w.w3s, nb, st);
+  if (e != hipSuccess) return APMG_EHIP;
+  hipLaunchKernelGGL(k_brick_scale, dim3((nb + 63) / 64), dim3(64), 0, st, b->bricks, w.scale, nb);
+  hipLaunchKernelGGL(k_fill_f32, dim3(grid1((int64_t)(nb * nF))), dim3(256), 0, st, w.dF, nb * nF, 0.f);
+  hipLaunchKernelGGL(k_fill_f32, dim3(grid1((int64_t)(nb * nW))), dim3(256), 0, st, w.dW, nb * nW, 0.f);
+  hipLaunchKernelGGL(k_fill_f64, dim3(grid1((int64_t)(nb * nG))), dim3(256), 0, st, w.dG, nb * nG, 0.0);
+  hipLaunchKernelGGL(k_fill_f64, dim3(1), dim3(256), 0, st, w.lrec, (size_t)nb, 0.0);
+
+  // 3. forward + adjoint of L_rec (part 1 of the step)
+  const int nblk = tile_blocks(n);
+  const std::vector<Pass> passes = plan_passes(s, bf, true);
+  if (passes.empty()) return APMG_EUNSUPPORTED;
+  const bool rec_dG = b->flags & APMG_ADD_REC_DG;
+  PartLayout pl0 = part_layout(s, 0, 0);
+  for (size_t pi = 0; pi < passes.size() && n > 0; ++pi) {
+    const Pass& ps = passes[pi];
+    TileArgs a;
+    memset(&a, 0, sizeof(a));
+    a.s = s;
+    a.G = b->G; a.G_stride = nG;
+    a.F = gf16 ? (const void*)b->F_lowp : (const void*)b->F; a.F_stride = nF;
+    a.swz = w.swz; a.swz_stride = swz_stride; a.w3s = w.w3s;
+    a.bscale = w.scale; a.boff = w.scale + 1;
+    a.pts = w.pts; a.ld = n; a.pts_stride = (size_t)3 * n; a.n = n;
+    a.df = nullptr; a.v = w.v; a.v_stride = n; a.err = w.err; a.err_stride = n;
+    a.err_abs = (b->flags & APMG_ERR_ABS) ? 1 : 0;
+    a.dF = ps.first ? w.dF : nullptr; a.dF_stride = nF;
+    a.want_dG = (ps.first && rec_dG) ? 1 : 0;
+    a.c1_lo = ps.c1_lo; a.c1_hi = ps.c1_hi;
+    a.w2_lo = ps.w2_lo; a.w2_hi = ps.w2_hi;
+    a.do_w3 = ps.first;
+    a.want_loss = ps.first;
+    a.part = w.part;
+    const int ncols = ps.c1_hi - ps.c1_lo, nrows = ps.w2_hi - ps.w2_lo;
+    const PartLayout pl = part_layout(s, ncols, nrows);
+    if (ps.first) pl0 = pl;
+    a.part_len = pl.len;
+    e = launch_tile(true, a, gf16, bf, dim3(nblk, nb), backward_lds_bytes(s, ncols, nrows, bf), st);
+    if (e != hipSuccess) return APMG_EHIP;
+    if (ncols > 0)
+      hipLaunchKernelGGL(k_reduce_parts, dim3(grid1((int64_t)s.H * ncols, 256), nb), dim3(256), 0, st, w.part, nblk,
+                         pl.len, pl.o_w1, s.H * ncols, ncols, s.MC, ps.c1_lo, w.dW, (double*)nullptr, nW, 0,
+                         (const int32_t*)nullptr);
+    if (nrows > 0)
+      hipLaunchKernelGGL(k_reduce_parts, dim3(grid1((int64_t)s.H * nrows, 256), nb), dim3(256), 0, st, w.part, nblk,
+                         pl.len, pl.o_w2, s.H * nrows, s.H * nrows, 0, s.H * s.MC + ps.w2_lo * s.H, w.dW,
+                         (double*)nullptr, nW, 0, (const int32_t*)nullptr);
+    if (ps.first) {
+      hipLaunchKernelGGL(k_reduce_parts, dim3(1, nb), dim3(256), 0, st, w.part, nblk, pl.len, pl.o_w3, s.H, s.H, 0,
+                         s.H * s.MC + s.H * s.H, w.dW, (double*)nullptr, nW, 0, (const int32_t*)nullptr);
+      hipLaunchKernelGGL(k_reduce_parts, dim3(1, nb), dim3(64), 0, st, w.part, nblk, pl.len, pl.o_loss, 1, 1, 0, 0,
+                         (float*)nullptr, w.lrec, (size_t)1, 0, (const int32_t*)nullptr);
+    }
+    if (ps.first && rec_dG && pi + 1 < passes.size()) {
+      // keep the first pass's transform-gradient partials: later passes reuse the buffer
+      hipLaunchKernelGGL(k_reduce_parts, dim3(1, nb), dim3(256), 0, st, w.part, nblk, pl.len, pl.o_g, 12 * s.M,
+                         12 * s.M, 0, 0, (float*)nullptr, w.dGrec, nG, 0, (const int32_t*)nullptr);
+    }
+  }
+  if (n > 0)
+    hipLaunchKernelGGL(k_copy_f64, dim3((nb + 63) / 64), dim3(64), 0, st, w.lrec, 1, b->losses, 2, nb, 1.0 / (double)n);
+  else
+    hipLaunchKernelGGL(k_fill_f64, dim3(1), dim3(256), 0, st, b->losses, (size_t)2 * nb, 0.0);
+
+  // 4. density loss and its transform gradient (part 2), for active models
+  if (n > 0) {
+    e = launch_density(s, b->G, nG, w.pts, n, (size_t)3 * n, n, w.err, n, b->eps_density, b->p, b->losses + 1, 2,
+                       w.dG, nG, 0, nullptr, w.den, nb, b->density_active, st);
+    if (e != hipSuccess) return APMG_EHIP;
+    if (rec_dG) {
+      if (passes.size() == 1)
+        hipLaunchKernelGGL(k_reduce_parts, dim3(1, nb), dim3(256), 0, st, w.part, nblk, pl0.len, pl0.o_g, 12 * s.M,
+                           12 * s.M, 0, 0, (float*)nullptr, w.dG, nG, 1, b->density_active);
+      else
+        hipLaunchKernelGGL(k_reduce_parts, dim3(1, nb), dim3(256), 0, st, w.dGrec, 1, (int)nG, 0, 12 * s.M,
+                           12 * s.M, 0, 0, (float*)nullptr, w.dG, nG, 1, b->density_active);
+    }
+  }
+
+  // 5. Adam: grids and MLP every step, transforms while the density phase is active
+  hipLaunchKernelGGL(k_adam, dim3(grid1((int64_t)nF), nb), dim3(256), 0, st, b->F, b->mF, b->vF, (const float*)w.dF,
+                     (const double*)nullptr, nF, (const int32_t*)b->t, (const int32_t*)nullptr, b->lr, b->beta1,
+                     b->beta2, b->adam_eps, gf16 ? (__half*)b->F_lowp : (__half*)nullptr);
+  hipLaunchKernelGGL(k_adam, dim3(grid1((int64_t)nW), nb), dim3(256), 0, st, b->W, b->mW, b->vW, (const float*)w.dW,
+                     (const double*)nullptr, nW, (const int32_t*)b->t, (const int32_t*)nullptr, b->lr, b->beta1,
+                     b->beta2, b->adam_eps, (__half*)nullptr);
+  hipLaunchKernelGGL(k_adam, dim3(1, nb), dim3(256), 0, st, b->G, b->mG, b->vG, (const float*)nullptr,
+                     (const double*)w.dG, nG, (const int32_t*)b->tG, b->density_active, b->lr_G, b->beta1, b->beta2,
+                     b->adam_eps, (__half*)nullptr);
+  hipLaunchKernelGGL(k_step_counters, dim3((nb + 63) / 64), dim3(64), 0, st, b->t, b->tG, b->density_active, b->step, nb);
+  return hip_status(hipGetLastError());
+}

@@ -1,0 +1,404 @@
+// Feature-density loss (Sec. 4.2, Eqs. (7)-(9)), point generation and
+// ground-truth sampling (Sec. 7 "Training", Sec. 4.3.1), brick assignment
+// (Sec. 5.3), Adam (Sec. 7), layout conversion and fixed-order reductions.
+
+namespace apmg {
+
+// ------------------------------------------------------------------ fill / reduce
+__global__ void k_fill_f32(float* p, size_t n, float v) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) p[i] = v;
+}
+__global__ void k_fill_f64(double* p, size_t n, double v) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) p[i] = v;
+}
+
+// out[model][e] (+)= sum_b part[(model*nblk + b)*len + off + e] for e < count, summed
+// in block order in float64.  Writes float (outf) or double (outd).
+// Element e lands at (e / cols) * ld_out + col0 + e % cols of the model's output.
+__global__ void k_reduce_parts(const double* part, int nblk, int len, int off, int count,
+                               int cols, int ld_out, int col0, float* outf, double* outd,
+                               size_t out_stride, int accumulate, const int32_t* active) {
+  const int model = blockIdx.y;
+  if (active && !active[model]) return;
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < count; e += gridDim.x * blockDim.x) {
+    const double* p = part + (size_t)model * nblk * len + off + e;
+    double s = 0.0;
+    for (int b = 0; b < nblk; ++b) s += p[(size_t)b * len];
+    const size_t oi = model * out_stride + (size_t)(e / cols) * ld_out + col0 + e % cols;
+    if (outf) outf[oi] = accumulate ? outf[oi] + (float)s : (float)s;
+    else outd[oi] = accumulate ? outd[oi] + s : s;
+  }
+}
+
+__global__ void k_copy_f64(const double* src, int sstride, double* dst, int dstride, int n, double scale) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) dst[(size_t)i * dstride] = src[(size_t)i * sstride] * scale;
+}
+
+// ------------------------------------------------------------------ points / ground truth
+__global__ void k_uniform_points(uint64_t seed, uint64_t step, uint32_t stream, int64_t start,
+                                 int64_t n, float* pts, int64_t ld) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    float x, y, z;
+    uniform_point(seed, step, stream, (uint64_t)(start + i), x, y, z);
+    pts[i] = x; pts[ld + i] = y; pts[2 * ld + i] = z;
+  }
+}
+
+// Trilinear sample of a corner-aligned sub-volume: voxels [e0, e0+n) per axis of a
+// [nz][ny][nx] volume; u = fma(x, (n-1)/2, (n-1)/2), lower voxel clamp(floor(u), 0, n-2).
+__device__ inline float sample_volume(const float* vol, int vnx, int vny, const int e0[3],
+                                      const int nn[3], float x, float y, float z) {
+  const float p[3] = {x, y, z};
+  int i0[3];
+  float w[3];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    const float h = 0.5f * (float)(nn[d] - 1);
+    const float u = __builtin_fmaf(p[d], h, h);
+    const float fl = fminf(fmaxf(floorf(u), 0.f), (float)(nn[d] - 2));
+    i0[d] = (int)fl;
+    w[d] = u - fl;
+  }
+  const size_t sy = (size_t)vnx, sz = (size_t)vnx * vny;
+  const float* b = vol + (size_t)(e0[2] + i0[2]) * sz + (size_t)(e0[1] + i0[1]) * sy + (e0[0] + i0[0]);
+  const float v000 = b[0], v100 = b[1], v010 = b[sy], v110 = b[sy + 1];
+  const float v001 = b[sz], v101 = b[sz + 1], v011 = b[sz + sy], v111 = b[sz + sy + 1];
+  const float x00 = __builtin_fmaf(w[0], v100 - v000, v000), x10 = __builtin_fmaf(w[0], v110 - v010, v010);
+  const float x01 = __builtin_fmaf(w[0], v101 - v001, v001), x11 = __builtin_fmaf(w[0], v111 - v011, v011);
+  const float y0 = __builtin_fmaf(w[1], x10 - x00, x00), y1 = __builtin_fmaf(w[1], x11 - x01, x01);
+  return __builtin_fmaf(w[2], y1 - y0, y0);
+}
+
+__global__ void k_gt_sample(const float* vol, int nx, int ny, int nz, const float* pts, int64_t ld,
+                            int64_t n, float* v) {
+  const int e0[3] = {0, 0, 0}, nn[3] = {nx, ny, nz};
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    v[i] = sample_volume(vol, nx, ny, e0, nn, pts[i], pts[ld + i], pts[2 * ld + i]);
+}
+
+// Training batch for every model: points from the counter stream, then the ground truth
+// sampled from the model's brick (extended extent e0..e1 inclusive).
+__global__ void k_batch_points_gt(uint64_t seed, const uint64_t* step_ctr, int64_t n,
+                                  const float* vol, int vnx, int vny, const apmg_brick* bricks,
+                                  float* pts, float* v) {
+  const int model = blockIdx.y;
+  const uint64_t step = *step_ctr;
+  const apmg_brick br = bricks[model];
+  const int e0[3] = {br.e0[0], br.e0[1], br.e0[2]};
+  const int nn[3] = {br.e1[0] - br.e0[0] + 1, br.e1[1] - br.e0[1] + 1, br.e1[2] - br.e0[2] + 1};
+  float* P = pts + (size_t)model * 3 * n;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    float x, y, z;
+    uniform_point(seed, step, (uint32_t)model, (uint64_t)i, x, y, z);
+    P[i] = x; P[n + i] = y; P[2 * n + i] = z;
+    v[(size_t)model * n + i] = sample_volume(vol, vnx, vny, e0, nn, x, y, z);
+  }
+}
+
+// ------------------------------------------------------------------ cells / bricks
+__global__ void k_cells(Shape s, const float* G, const float* pts, int64_t ld, int64_t n,
+                        int32_t* cell, uint8_t* inside) {
+  const float hR = 0.5f * (float)(s.R - 1);
+  const int64_t total = n * s.M;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t p = i / s.M;
+    const int g = (int)(i % s.M);
+    float l[3];
+    local_coords(G + 12 * g, pts[p], pts[ld + p], pts[2 * ld + p], l);
+    int i0[3];
+    float w[3];
+    const bool in = cell_of(l, hR, s.R, i0, w);
+    if (cell) for (int d = 0; d < 3; ++d) cell[3 * i + d] = in ? i0[d] : -1;
+    if (inside) inside[i] = in ? 1 : 0;
+  }
+}
+
+__global__ void k_assign_bricks(apmg_brick_table t, const float* pts, int64_t ld, int64_t n, int32_t* brick) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    int idx[3];
+    for (int d = 0; d < 3; ++d) {
+      const float h = 0.5f * (float)(t.vol[d] - 1);
+      float u = __builtin_fmaf(pts[d * ld + i], h, h);
+      if (!(fabsf(u) <= 3.0e38f)) u = 0.f;  // a non-finite coordinate goes to brick 0 on that axis
+      // floor(u) div B, clamped to [0, dims-1]
+      const float fl = fminf(fmaxf(floorf(u), 0.f), (float)t.vol[d]);
+      int k = (int)fl / t.B;
+      idx[d] = k < t.dims[d] - 1 ? k : t.dims[d] - 1;
+    }
+    brick[i] = idx[0] + t.dims[0] * (idx[1] + t.dims[1] * idx[2]);
+  }
+}
+
+// ------------------------------------------------------------------ layout conversion
+template <typename TS, typename TD>
+__global__ void k_convert(int M, int C, int R, const TS* src, TD* dst, int to_cl) {
+  const size_t R3 = (size_t)R * R * R, total = (size_t)M * C * R3;
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < total; i += (size_t)gridDim.x * blockDim.x) {
+    // i indexes the destination
+    size_t si;
+    if (to_cl) {  // dst [M][R3][C] from src [M][C][R3]
+      const size_t c = i % C, v = (i / C) % R3, g = i / (C * R3);
+      si = (g * C + c) * R3 + v;
+    } else {      // dst [M][C][R3] from src [M][R3][C]
+      const size_t v = i % R3, c = (i / R3) % C, g = i / (C * R3);
+      si = (g * R3 + v) * C + c;
+    }
+    float val;
+    if constexpr (sizeof(TS) == 2) val = __half2float(*(const __half*)&src[si]); else val = (float)src[si];
+    if constexpr (sizeof(TD) == 2) { __half hv = __float2half_rn(val); dst[i] = *(TD*)&hv; } else dst[i] = (TD)val;
+  }
+}
+
+// ------------------------------------------------------------------ feature density
+// det and cofactor of each transform's 3x3 block, float64: dc[g] = {det, cof[9]}.
+__device__ inline void det_cof(const float* Gg, double out[10]) {
+  double A[3][3];
+  for (int r = 0; r < 3; ++r) for (int c = 0; c < 3; ++c) A[r][c] = Gg[4 * r + c];
+  out[1] = A[1][1] * A[2][2] - A[1][2] * A[2][1];
+  out[2] = -(A[1][0] * A[2][2] - A[1][2] * A[2][0]);
+  out[3] = A[1][0] * A[2][1] - A[1][1] * A[2][0];
+  out[4] = -(A[0][1] * A[2][2] - A[0][2] * A[2][1]);
+  out[5] = A[0][0] * A[2][2] - A[0][2] * A[2][0];
+  out[6] = -(A[0][0] * A[2][1] - A[0][1] * A[2][0]);
+  out[7] = A[0][1] * A[1][2] - A[0][2] * A[1][1];
+  out[8] = -(A[0][0] * A[1][2] - A[0][2] * A[1][0]);
+  out[9] = A[0][0] * A[1][1] - A[0][1] * A[1][0];
+  out[0] = A[0][0] * out[1] + A[0][1] * out[2] + A[0][2] * out[3];
+}
+
+// l^k by squaring, k >= 1
+__device__ inline float powi(float l, int k) {
+  float r = 1.f, b = l;
+  while (k) { if (k & 1) r *= b; b *= b; k >>= 1; }
+  return r;
+}
+
+// Pass A: rho per point (Eq. (7)) and block sums of rho and err.
+// part: [model][block][2] = {sum rho, sum err}
+__global__ void __launch_bounds__(256) k_density_a(Shape s, const float* Gall, size_t G_stride,
+    const float* pts, int64_t ld, size_t pts_stride, int64_t n, const float* err, size_t err_stride,
+    int p, float* rho, size_t rho_stride, double* part, const int32_t* active) {
+  extern __shared__ float smem[];
+  const int model = blockIdx.y;
+  double* spart = (double*)smem;
+  float* sG = (float*)(spart + 2);
+  float* sdet = sG + 12 * s.M;
+  if (threadIdx.x == 0) { spart[0] = 0.0; spart[1] = 0.0; }
+  const bool act = !active || active[model];
+  const float* G = Gall + model * G_stride;
+  for (int i = threadIdx.x; i < 12 * s.M; i += blockDim.x) sG[i] = G[i];
+  __syncthreads();
+  for (int g = threadIdx.x; g < s.M; g += blockDim.x) { double dc[10]; det_cof(sG + 12 * g, dc); sdet[g] = (float)dc[0]; }
+  __syncthreads();
+  double srho = 0.0, serr = 0.0;
+  const float* P = pts + model * pts_stride;
+  if (act) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+      const float x = P[i], y = P[ld + i], z = P[2 * ld + i];
+      float r = 0.f;
+      for (int g = 0; g < s.M; ++g) {
+        float l[3];
+        local_coords(sG + 12 * g, x, y, z, l);
+        const float sv = powi(l[0], 2 * p) + powi(l[1], 2 * p) + powi(l[2], 2 * p);
+        if (sv <= kSMax) r = __builtin_fmaf(sdet[g], __expf(-sv), r);
+      }
+      if (rho) rho[model * rho_stride + i] = r;
+      srho += r;
+      serr += err[model * err_stride + i];
+    }
+  }
+  srho = wave_sum(srho);
+  serr = wave_sum(serr);
+  if ((threadIdx.x & 63) == 0) { atomicAdd(&spart[0], srho); atomicAdd(&spart[1], serr); }
+  __syncthreads();
+  if (threadIdx.x < 2) part[((size_t)model * gridDim.x + blockIdx.x) * 2 + threadIdx.x] = spart[threadIdx.x];
+}
+
+// Reduce pass-A partials: sums[model] = {S, sum err}.
+__global__ void k_density_sums(const double* part, int nblk, double* sums, int nmodels) {
+  const int model = blockIdx.x * blockDim.x + threadIdx.x;
+  if (model >= nmodels) return;
+  double a = 0.0, b = 0.0;
+  for (int k = 0; k < nblk; ++k) { a += part[((size_t)model * nblk + k) * 2]; b += part[((size_t)model * nblk + k) * 2 + 1]; }
+  sums[2 * model] = a;
+  sums[2 * model + 1] = b;
+}
+
+// Target density and loss summand for one point, float64 (Eqs. (8), (9)).
+__device__ inline void target_terms(double rho, double S, double hbar, double h, double eps, double N,
+                                    double& term, double& a, double& rho_s) {
+  rho_s = rho / S;
+  const double lg = log(rho_s + eps);
+  const double lt = hbar / (h + eps) * lg;
+  const double rs = exp(lt);
+  term = rs > 0.0 ? rs * (lt - lg) : 0.0;
+  a = -rs / (N * (rho_s + eps));
+}
+
+// Pass B1: loss and Q = sum a rho_s.  part: [model][block][2] = {loss sum, Q}
+__global__ void __launch_bounds__(256) k_density_b1(const float* rho, size_t rho_stride, const float* err,
+    size_t err_stride, int64_t n, const double* sums, double eps, double* part, const int32_t* active) {
+  __shared__ double spart[2];
+  const int model = blockIdx.y;
+  if (threadIdx.x == 0) { spart[0] = 0.0; spart[1] = 0.0; }
+  __syncthreads();
+  const bool act = (!active || active[model]) && sums[2 * model] != 0.0;
+  double sl = 0.0, sq = 0.0;
+  if (act) {
+    const double S = sums[2 * model], hbar = sums[2 * model + 1] / (double)n;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+      double term, a, rs;
+      target_terms(rho[model * rho_stride + i], S, hbar, err[model * err_stride + i], eps, (double)n, term, a, rs);
+      sl += term;
+      sq += a * rs;
+    }
+  }
+  sl = wave_sum(sl);
+  sq = wave_sum(sq);
+  if ((threadIdx.x & 63) == 0) { atomicAdd(&spart[0], sl); atomicAdd(&spart[1], sq); }
+  __syncthreads();
+  if (threadIdx.x < 2) part[((size_t)model * gridDim.x + blockIdx.x) * 2 + threadIdx.x] = spart[threadIdx.x];
+}
+
+// Reduce pass-B1 partials into lq[model] = {loss, Q}
+__global__ void k_density_lq(const double* part, int nblk, int64_t n, double* lq, int nmodels) {
+  const int model = blockIdx.x * blockDim.x + threadIdx.x;
+  if (model >= nmodels) return;
+  double a = 0.0, b = 0.0;
+  for (int k = 0; k < nblk; ++k) { a += part[((size_t)model * nblk + k) * 2]; b += part[((size_t)model * nblk + k) * 2 + 1]; }
+  lq[2 * model] = n > 0 ? a / (double)n : 0.0;
+  lq[2 * model + 1] = b;
+}
+
+// Pass B2: per grid, U_i = {sum c phi_i, sum c phi_i q_d x_k (9), sum c phi_i q_d (3)} with
+// c(x) = dL/drho(x) = (a(x) - Q)/S.  part: [model][block][13 M]
+constexpr int kPts = 8;  // points per thread in pass B2
+__global__ void __launch_bounds__(256) k_density_b2(Shape s, const float* Gall, size_t G_stride,
+    const float* pts, int64_t ld, size_t pts_stride, int64_t n, const float* rho, size_t rho_stride,
+    const float* err, size_t err_stride, const double* sums, const double* lq, double eps, int p,
+    double* part, const int32_t* active) {
+  extern __shared__ float smem[];
+  const int model = blockIdx.y;
+  double* sacc = (double*)smem;            // [13 M]
+  float* sG = (float*)(sacc + 13 * s.M);
+  for (int i = threadIdx.x; i < 13 * s.M; i += blockDim.x) sacc[i] = 0.0;
+  const float* G = Gall + model * G_stride;
+  for (int i = threadIdx.x; i < 12 * s.M; i += blockDim.x) sG[i] = G[i];
+  __syncthreads();
+  const bool act = (!active || active[model]) && sums[2 * model] != 0.0;
+  if (act) {
+    const double S = sums[2 * model], hbar = sums[2 * model + 1] / (double)n, Q = lq[2 * model + 1];
+    const float* P = pts + model * pts_stride;
+    const int64_t nthr = (int64_t)gridDim.x * blockDim.x;
+    const int64_t t0 = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    for (int64_t base = 0; base < n; base += nthr * kPts) {
+      float px[kPts], py[kPts], pz[kPts], pc[kPts];
+#pragma unroll
+      for (int k = 0; k < kPts; ++k) {
+        const int64_t i = base + t0 + (int64_t)k * nthr;
+        px[k] = py[k] = pz[k] = 0.f;
+        pc[k] = 0.f;
+        if (i < n) {
+          px[k] = P[i]; py[k] = P[ld + i]; pz[k] = P[2 * ld + i];
+          double term, a, rs;
+          target_terms(rho[model * rho_stride + i], S, hbar, err[model * err_stride + i], eps, (double)n, term, a, rs);
+          pc[k] = (float)((a - Q) / S);
+        }
+      }
+      for (int g = 0; g < s.M; ++g) {
+        float u[13];
+#pragma unroll
+        for (int q = 0; q < 13; ++q) u[q] = 0.f;
+#pragma unroll
+        for (int k = 0; k < kPts; ++k) {
+          float l[3];
+          local_coords(sG + 12 * g, px[k], py[k], pz[k], l);
+          const float sv = powi(l[0], 2 * p) + powi(l[1], 2 * p) + powi(l[2], 2 * p);
+          if (sv <= kSMax && pc[k] != 0.f) {
+            const float cphi = pc[k] * __expf(-sv);
+            u[0] += cphi;
+            const float xs[3] = {px[k], py[k], pz[k]};
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+              const float cq = cphi * powi(l[d], 2 * p - 1);
+              u[1 + 3 * d] = __builtin_fmaf(cq, xs[0], u[1 + 3 * d]);
+              u[2 + 3 * d] = __builtin_fmaf(cq, xs[1], u[2 + 3 * d]);
+              u[3 + 3 * d] = __builtin_fmaf(cq, xs[2], u[3 + 3 * d]);
+              u[10 + d] += cq;
+            }
+          }
+        }
+#pragma unroll
+        for (int q = 0; q < 13; ++q) {
+          const double t = wave_sum((double)u[q]);
+          if ((threadIdx.x & 63) == 0) atomicAdd(&sacc[13 * g + q], t);
+        }
+      }
+    }
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < 13 * s.M; i += blockDim.x)
+    part[((size_t)model * gridDim.x + blockIdx.x) * 13 * s.M + i] = sacc[i];
+}
+
+// Assemble dG_i = cof_i U0 - 2p det_i [U1 | U2] from the reduced pass-B2 sums.
+__global__ void k_density_grad(Shape s, const float* Gall, size_t G_stride, const double* U, int p,
+                               double* dG, size_t dG_stride, int accumulate, const double* sums,
+                               const int32_t* active) {
+  const int model = blockIdx.y;
+  if (active && !active[model]) return;
+  const bool zero = sums[2 * model] == 0.0;
+  for (int g = blockIdx.x * blockDim.x + threadIdx.x; g < s.M; g += gridDim.x * blockDim.x) {
+    double dc[10];
+    det_cof(Gall + model * G_stride + 12 * g, dc);
+    const double* u = U + (size_t)model * 13 * s.M + 13 * g;
+    double* o = dG + model * dG_stride + 12 * g;
+    for (int r = 0; r < 3; ++r) {
+      for (int k = 0; k < 3; ++k) {
+        const double v = zero ? 0.0 : dc[1 + 3 * r + k] * u[0] - 2.0 * p * dc[0] * u[1 + 3 * r + k];
+        o[4 * r + k] = accumulate ? o[4 * r + k] + v : v;
+      }
+      const double v = zero ? 0.0 : -2.0 * p * dc[0] * u[10 + r];
+      o[4 * r + 3] = accumulate ? o[4 * r + 3] + v : v;
+    }
+  }
+}
+
+// ------------------------------------------------------------------ Adam
+// theta -= lr * mhat / (sqrt(vhat) + eps), bias-corrected with step t+1 (t read from
+// counters[model]).  Optional float16 shadow of theta.  gd (double) or gf (float) gradient.
+__global__ void k_adam(float* theta, float* m, float* v, const float* gf, const double* gd, size_t per_model,
+                       const int32_t* counters, const int32_t* active, float lr, float b1, float b2,
+                       float eps, __half* shadow) {
+  const int model = blockIdx.y;
+  if (active && !active[model]) return;
+  const int t = counters[model] + 1;
+  const float bc1 = (float)(1.0 - pow((double)b1, (double)t));
+  const float bc2 = (float)(1.0 - pow((double)b2, (double)t));
+  const float step = lr / bc1, rb2 = 1.0f / sqrtf(bc2);
+  const size_t off = (size_t)model * per_model;
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < per_model; i += (size_t)gridDim.x * blockDim.x) {
+    const size_t k = off + i;
+    const float g = gf ? gf[k] : (float)gd[k];
+    const float mk = __builtin_fmaf(b1, m[k], (1.f - b1) * g);
+    const float vk = __builtin_fmaf(b2, v[k], (1.f - b2) * g * g);
+    m[k] = mk;
+    v[k] = vk;
+    const float th = theta[k] - step * mk / (sqrtf(vk) * rb2 + eps);
+    theta[k] = th;
+    if (shadow) shadow[k] = __float2half_rn(th);
+  }
+}
+
+// G is stored [M][3][4] float; its gradient is float64 of the same shape.
+__global__ void k_step_counters(int32_t* t, int32_t* tG, const int32_t* active, uint64_t* step, int nb) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b < nb) {
+    t[b] += 1;
+    if (active[b]) tG[b] += 1;
+  }
+  if (b == 0) *step += 1;
+}
+
+}  // namespace apmg

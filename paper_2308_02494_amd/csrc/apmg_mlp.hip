@@ -1,0 +1,602 @@
+// Encoder + decoder forward and adjoint kernels (Sec. 4.1, Eqs. (1)-(3),
+// the bias-free MLP of Sec. 4.1.2 and its hand-derived backward pass).
+//
+// Work decomposition: a wave processes a tile of 32 points.  Point j = lane%32
+// is shared by lanes j and j+32 ("halves"); half hf encodes grids
+// [hf*Mh, hf*Mh+Mh).  The per-grid features are produced in registers and fed
+// straight into the first layer's matrix product as the B operand of
+// v_mfma_f32_32x32x2_f32 (fp32) or v_mfma_f32_32x32x16_bf16 (bf16): the
+// 32x32x2 B operand wants feature k of point j in lane j+32k, the bf16 one
+// 8 consecutive features per lane half, which is exactly one point per lane
+// pair with the two halves holding different features.  Every hidden layer's
+// accumulator layout (rows 8(r/4)+4hf+r%4 of each 32-row block in register r)
+// is reused as the next layer's B operand; the weights are pre-swizzled so
+// the A operand row/k order matches.  Nothing but the transforms goes to LDS
+// in the forward pass.
+//
+// The adjoint recomputes the forward pass per tile, back-propagates through
+// the MLP with the transposed swizzles, produces dL/dy in the same per-half
+// grid order, scatters dL/dF with float atomics, reduces the transform
+// gradient through the trilinear weights, and forms the weight gradients as
+// matrix products over the tile's 32 points after an LDS transpose.
+
+namespace apmg {
+
+// ------------------------------------------------------------------ swizzle
+// Source weights per model: W1 [H][MC], W2 [H][H], W3 [H] at W + model*wstride.
+// Output per model at swz + model*swz_stride elements: [w1 | w2 | w2t | w1t]
+// (float or bf16 bits) and w3s + model*H (float, [hf][H/2] row order).
+__device__ inline int feat_of_half(const Shape& s, int hf, int t) {
+  if (t >= s.KH) return -1;
+  int k = hf * s.KH + t;
+  return k < s.MC ? k : -1;
+}
+
+template <bool BF>
+__global__ void k_swizzle(Shape s, const float* __restrict__ W1all, const float* __restrict__ W2all,
+                          const float* __restrict__ W3all, size_t wstride, void* swz,
+                          size_t swz_stride, float* w3s) {
+  const int model = blockIdx.y;
+  const float* W1 = W1all + model * wstride;
+  const float* W2 = W2all + model * wstride;
+  const float* W3 = W3all + model * wstride;
+  const SwzSizes z = swz_sizes(s);
+  const size_t total = z.total() + (size_t)s.H;
+  const int H = s.H;
+  for (size_t idx = blockIdx.x * (size_t)blockDim.x + threadIdx.x; idx < total;
+       idx += (size_t)gridDim.x * blockDim.x) {
+    float v = 0.f;
+    size_t o = idx;
+    if (o < z.w1) {
+      int l, e = 0, b, st;
+      if (!BF) { l = o % 64; size_t q = o / 64; st = q % s.KHP; b = q / s.KHP; }
+      else { e = o % 8; l = (o / 8) % 64; size_t q = o / 512; st = q % (s.KHP / 8); b = q / (s.KHP / 8); }
+      int t = BF ? 8 * st + e : st;
+      int k = feat_of_half(s, l >> 5, t);
+      v = k >= 0 ? W1[(size_t)(32 * b + (l & 31)) * s.MC + k] : 0.f;
+    } else if ((o -= z.w1) < z.w2 + z.w2t) {
+      bool tr = o >= z.w2;
+      if (tr) o -= z.w2;
+      int l, e = 0, b, st, row;
+      if (!BF) { l = o % 64; size_t q = o / 64; st = q % (H / 2); b = q / (H / 2);
+                 row = 32 * (st >> 4) + acc_row(st & 15, l >> 5); }
+      else { e = o % 8; l = (o / 8) % 64; size_t q = o / 512; st = q % (H / 16); b = q / (H / 16);
+             row = 32 * (st >> 1) + acc_row(8 * (st & 1) + e, l >> 5); }
+      int col = 32 * b + (l & 31);
+      v = tr ? W2[(size_t)row * H + col] : W2[(size_t)col * H + row];
+    } else if ((o -= z.w2 + z.w2t) < z.w1t) {
+      int l, e = 0, b, st, row;
+      if (!BF) { l = o % 64; size_t q = o / 64; st = q % (H / 2); b = q / (H / 2);
+                 row = 32 * (st >> 4) + acc_row(st & 15, l >> 5); }
+      else { e = o % 8; l = (o / 8) % 64; size_t q = o / 512; st = q % (H / 16); b = q / (H / 16);
+             row = 32 * (st >> 1) + acc_row(8 * (st & 1) + e, l >> 5); }
+      int p = l & 31, hfp = (p >> 2) & 1, rp = 4 * (p >> 3) + (p & 3);
+      int k = feat_of_half(s, hfp, 16 * b + rp);
+      v = k >= 0 ? W1[(size_t)row * s.MC + k] : 0.f;
+    } else {
+      o -= z.w1t;  // w3s: [hf][bb*16 + r] = W3[32bb + acc_row(r, hf)]
+      int hf = o / (H / 2), rr = o % (H / 2);
+      w3s[(size_t)model * H + o] = W3[32 * (rr >> 4) + acc_row(rr & 15, hf)];
+      continue;
+    }
+    if (BF) ((uint16_t*)swz)[model * swz_stride + idx] = bf16_bits(v);
+    else ((float*)swz)[model * swz_stride + idx] = v;
+  }
+}
+
+// ------------------------------------------------------------------ tile pieces
+template <int C, bool GF16>
+__device__ inline void encode_grid(const Shape& s, const float* sG, const void* F, int g, float x,
+                                   float y, float z, bool valid, float hR, float e[C]) {
+#pragma unroll
+  for (int c = 0; c < C; ++c) e[c] = 0.f;
+  if (!valid || g >= s.M) return;
+  float l[3];
+  local_coords(sG + 12 * g, x, y, z, l);
+  int i0[3];
+  float w[3];
+  if (!cell_of(l, hR, s.R, i0, w)) return;
+  float val[8][C];
+  gather_cell<C, GF16>(F, g, s.R, i0, val);
+  trilerp<C>(val, w, e);
+}
+
+template <int C, int H, bool GF16, bool BF>
+__device__ inline void tile_fwd(const Shape& s, const float* sG, const void* F, const void* swz,
+                                const float* w3s, float x, float y, float z, bool valid, int lane,
+                                f32x16 (&z1)[H / 32], f32x16 (&z2)[H / 32], float& m) {
+  constexpr int NB = H / 32;
+  const int hf = lane >> 5;
+  const float hR = 0.5f * (float)(s.R - 1);
+#pragma unroll
+  for (int b = 0; b < NB; ++b)
+#pragma unroll
+    for (int r = 0; r < 16; ++r) z1[b][r] = 0.f;
+  if constexpr (!BF) {
+    const float* W1 = (const float*)swz;
+    for (int gi = 0; gi < s.Mh; ++gi) {
+      float e[C];
+      encode_grid<C, GF16>(s, sG, F, hf * s.Mh + gi, x, y, z, valid, hR, e);
+#pragma unroll
+      for (int c = 0; c < C; ++c) {
+        const size_t t = (size_t)gi * C + c;
+#pragma unroll
+        for (int b = 0; b < NB; ++b) z1[b] = mma_f32(W1[((size_t)b * s.KHP + t) * 64 + lane], e[c], z1[b]);
+      }
+    }
+  } else {
+    const bf16x8* W1 = (const bf16x8*)swz;
+    constexpr int GPS = 8 / C;
+    const int S1 = s.KHP / 8;
+    for (int st = 0; st < S1; ++st) {
+      bf16x8 B;
+#pragma unroll
+      for (int u = 0; u < GPS; ++u) {
+        const int gi = st * GPS + u;
+        float e[C];
+        encode_grid<C, GF16>(s, sG, F, gi < s.Mh ? hf * s.Mh + gi : s.M, x, y, z, valid, hR, e);
+#pragma unroll
+        for (int c = 0; c < C; ++c) B[u * C + c] = (short)bf16_bits(e[c]);
+      }
+#pragma unroll
+      for (int b = 0; b < NB; ++b) z1[b] = mma_bf16(W1[((size_t)b * S1 + st) * 64 + lane], B, z1[b]);
+    }
+  }
+  // second layer
+#pragma unroll
+  for (int b = 0; b < NB; ++b)
+#pragma unroll
+    for (int r = 0; r < 16; ++r) z2[b][r] = 0.f;
+  if constexpr (!BF) {
+    const float* W2 = (const float*)swz + (size_t)2 * H * s.KHP;
+#pragma unroll
+    for (int st = 0; st < H / 2; ++st) {
+      const float hv = fmaxf(z1[st >> 4][st & 15], 0.f);
+#pragma unroll
+      for (int b = 0; b < NB; ++b) z2[b] = mma_f32(W2[((size_t)b * (H / 2) + st) * 64 + lane], hv, z2[b]);
+    }
+  } else {
+    const bf16x8* W2 = (const bf16x8*)((const uint16_t*)swz + (size_t)2 * H * s.KHP);
+#pragma unroll
+    for (int st = 0; st < H / 16; ++st) {
+      bf16x8 B;
+#pragma unroll
+      for (int e = 0; e < 8; ++e) B[e] = (short)bf16_bits(fmaxf(z1[st >> 1][8 * (st & 1) + e], 0.f));
+#pragma unroll
+      for (int b = 0; b < NB; ++b) z2[b] = mma_bf16(W2[((size_t)b * (H / 16) + st) * 64 + lane], B, z2[b]);
+    }
+  }
+  // output layer (H -> 1) on the vector ALUs
+  float acc = 0.f;
+#pragma unroll
+  for (int b = 0; b < NB; ++b)
+#pragma unroll
+    for (int r = 0; r < 16; ++r) acc = __builtin_fmaf(w3s[hf * (H / 2) + 16 * b + r], fmaxf(z2[b][r], 0.f), acc);
+  m = acc + __shfl_xor(acc, 32, 64);
+}
+
+// ------------------------------------------------------------------ forward
+template <int C, int H, bool GF16, bool BF>
+__global__ void __launch_bounds__(kBlock) k_forward(TileArgs a) {
+  extern __shared__ float smem[];
+  const int model = blockIdx.y;
+  if (a.active && !a.active[model]) return;
+  const Shape s = a.s;
+  float* sG = smem;
+  const float* G = a.G + model * a.G_stride;
+  for (int i = threadIdx.x; i < 12 * s.M; i += blockDim.x) sG[i] = G[i];
+  __syncthreads();
+  const void* F = GF16 ? (const void*)((const __half*)a.F + model * a.F_stride)
+                       : (const void*)((const float*)a.F + model * a.F_stride);
+  const size_t esz = BF ? 2 : 4;
+  const void* swz = (const char*)a.swz + esz * model * a.swz_stride;
+  const float* w3s = a.w3s + (size_t)model * H;
+  const float vs = a.bscale ? a.bscale[model] : a.vscale;
+  const float vo = a.boff ? a.boff[model] : a.voff;
+  const float* P = a.pts + model * a.pts_stride;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, j = lane & 31;
+  const int64_t ntiles = (a.n + 31) / 32;
+  for (int64_t tile = (int64_t)blockIdx.x * kWavesPerBlock + wave; tile < ntiles;
+       tile += (int64_t)gridDim.x * kWavesPerBlock) {
+    const int64_t p = tile * 32 + j;
+    const bool valid = p < a.n;
+    float x = 0.f, y = 0.f, z = 0.f;
+    if (valid) { x = P[p]; y = P[a.ld + p]; z = P[2 * a.ld + p]; }
+    f32x16 z1[H / 32], z2[H / 32];
+    float m;
+    tile_fwd<C, H, GF16, BF>(s, sG, F, swz, w3s, x, y, z, valid, lane, z1, z2, m);
+    if (valid && lane < 32) a.f[(size_t)model * a.n + p] = __builtin_fmaf(m, vs, vo);
+  }
+}
+
+// ------------------------------------------------------------------ adjoint
+__device__ inline void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// LDS transpose tiles: [row][32 points], row stride LDT elements.
+template <bool BF> struct TT {
+  static constexpr int LDT = BF ? 40 : 33;
+  typedef typename std::conditional<BF, uint16_t, float>::type T;
+};
+
+template <bool BF>
+__device__ inline void tt_put(typename TT<BF>::T* t, int row, int j, float v) {
+  if constexpr (BF) t[row * TT<BF>::LDT + j] = bf16_bits(v);
+  else t[row * TT<BF>::LDT + j] = v;
+}
+
+// acc += A_rows[ia..ia+32) x B_rows[ib..ib+32)^T over the 32 points of the tile
+template <bool BF>
+__device__ inline f32x16 tt_mma(const typename TT<BF>::T* Ta, int ia, const typename TT<BF>::T* Tb,
+                                int ib, int lane, f32x16 acc) {
+  constexpr int LDT = TT<BF>::LDT;
+  const int li = lane & 31, hk = lane >> 5;
+  if constexpr (!BF) {
+#pragma unroll
+    for (int st = 0; st < 16; ++st)
+      acc = mma_f32(Ta[(ia + li) * LDT + 2 * st + hk], Tb[(ib + li) * LDT + 2 * st + hk], acc);
+  } else {
+#pragma unroll
+    for (int st = 0; st < 2; ++st) {
+      bf16x8 A = *(const bf16x8*)&Ta[(ia + li) * LDT + 16 * st + 8 * hk];
+      bf16x8 B = *(const bf16x8*)&Tb[(ib + li) * LDT + 16 * st + 8 * hk];
+      acc = mma_bf16(A, B, acc);
+    }
+  }
+  return acc;
+}
+
+template <int C, int H, bool GF16, bool BF>
+__global__ void __launch_bounds__(kBlock) k_backward(TileArgs a) {
+  extern __shared__ float smem[];
+  typedef typename TT<BF>::T TTy;
+  constexpr int NB = H / 32;
+  constexpr int LDT = TT<BF>::LDT;
+  const int model = blockIdx.y;
+  const Shape s = a.s;
+  const int ncols = a.c1_hi - a.c1_lo;
+  const int nrows2 = a.w2_hi - a.w2_lo;
+  const PartLayout pl = part_layout(s, ncols, nrows2);
+  double* part = a.part + ((size_t)model * gridDim.x + blockIdx.x) * pl.len;
+  const bool act = !a.active || a.active[model];
+
+  // LDS: sG [12M] f | sW1 [H*ncols] f | sW2 [nrows2*H] f | sW3 [H] f | sdG [12M] d | sLoss d |
+  // per wave: Ta [H rows] (a delta), Tb [32 rows] (an activation block)
+  float* sG = smem;
+  float* sW1 = sG + 12 * s.M;
+  float* sW2 = sW1 + H * ncols;
+  float* sW3 = sW2 + nrows2 * H;
+  double* sdG = (double*)(((uintptr_t)(sW3 + H) + 7) & ~(uintptr_t)7);
+  double* sLoss = sdG + 12 * s.M;
+  TTy* tiles = (TTy*)(((uintptr_t)(sLoss + 1) + 15) & ~(uintptr_t)15);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, j = lane & 31, hf = lane >> 5;
+  TTy* Ta = tiles + (size_t)wave * (H + 32) * LDT;
+  TTy* Tb = Ta + (size_t)H * LDT;
+
+  const float* G = a.G + model * a.G_stride;
+  for (int i = threadIdx.x; i < 12 * s.M; i += blockDim.x) { sG[i] = G[i]; sdG[i] = 0.0; }
+  for (int i = threadIdx.x; i < H * ncols + nrows2 * H + H; i += blockDim.x) sW1[i] = 0.f;
+  if (threadIdx.x == 0) *sLoss = 0.0;
+  __syncthreads();
+
+  const void* F = GF16 ? (const void*)((const __half*)a.F + model * a.F_stride)
+                       : (const void*)((const float*)a.F + model * a.F_stride);
+  const size_t esz = BF ? 2 : 4;
+  const void* swz = (const char*)a.swz + esz * model * a.swz_stride;
+  const float* w3s = a.w3s + (size_t)model * H;
+  const float vs = a.bscale ? a.bscale[model] : a.vscale;
+  const float vo = a.boff ? a.boff[model] : a.voff;
+  const float* P = a.pts + model * a.pts_stride;
+  float* dF = a.dF ? a.dF + model * a.dF_stride : nullptr;
+  const float hR = 0.5f * (float)(s.R - 1);
+  const float* W2T = nullptr; const bf16x8* W2Tb = nullptr;
+  const float* W1T = nullptr; const bf16x8* W1Tb = nullptr;
+  {
+    const size_t o2t = (size_t)2 * H * s.KHP + (size_t)H * H, o1t = o2t + (size_t)H * H;
+    if (BF) { W2Tb = (const bf16x8*)((const uint16_t*)swz + o2t); W1Tb = (const bf16x8*)((const uint16_t*)swz + o1t); }
+    else { W2T = (const float*)swz + o2t; W1T = (const float*)swz + o1t; }
+  }
+  f32x16 dw3[NB];
+#pragma unroll
+  for (int b = 0; b < NB; ++b)
+#pragma unroll
+    for (int r = 0; r < 16; ++r) dw3[b][r] = 0.f;
+  double loss = 0.0;
+
+  const int64_t ntiles = act ? (a.n + 31) / 32 : 0;
+  for (int64_t tile = (int64_t)blockIdx.x * kWavesPerBlock + wave; tile < ntiles;
+       tile += (int64_t)gridDim.x * kWavesPerBlock) {
+    const int64_t p = tile * 32 + j;
+    const bool valid = p < a.n;
+    float x = 0.f, y = 0.f, z = 0.f;
+    if (valid) { x = P[p]; y = P[a.ld + p]; z = P[2 * a.ld + p]; }
+    f32x16 z1[NB], z2[NB];
+    float m;
+    tile_fwd<C, H, GF16, BF>(s, sG, F, swz, w3s, x, y, z, valid, lane, z1, z2, m);
+
+    // dL/df for this point
+    float df = 0.f;
+    if (valid) {
+      if (a.df) {
+        df = a.df[p];
+      } else {
+        const float fv = __builtin_fmaf(m, vs, vo);
+        const float e = fv - a.v[model * a.v_stride + p];
+        df = 2.0f * e / (float)a.n;
+        if (lane < 32) {
+          a.err[model * a.err_stride + p] = a.err_abs ? fabsf(e) : e * e;
+          loss += (double)e * (double)e;
+        }
+      }
+    }
+    const float dm = df * vs;
+
+    // output layer: dW3 and delta2
+    f32x16 d2[NB];
+#pragma unroll
+    for (int b = 0; b < NB; ++b)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const float h2 = fmaxf(z2[b][r], 0.f);
+        dw3[b][r] = __builtin_fmaf(dm, h2, dw3[b][r]);
+        d2[b][r] = z2[b][r] > 0.f ? w3s[hf * (H / 2) + 16 * b + r] * dm : 0.f;
+      }
+
+    // dW2 rows [w2_lo, w2_hi) = sum_j delta2_j h1_j^T, one 32-row block of h1 at a time
+    if (nrows2 > 0) {
+#pragma unroll
+      for (int b = 0; b < NB; ++b)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) tt_put<BF>(Ta, 32 * b + acc_row(r, hf), j, d2[b][r]);
+#pragma unroll
+      for (int kb = 0; kb < NB; ++kb) {
+#pragma unroll
+        for (int r = 0; r < 16; ++r) tt_put<BF>(Tb, acc_row(r, hf), j, fmaxf(z1[kb][r], 0.f));
+        wave_lds_sync();
+        for (int ib = a.w2_lo / 32; ib < a.w2_hi / 32; ++ib) {
+          f32x16 acc;
+#pragma unroll
+          for (int r = 0; r < 16; ++r) acc[r] = 0.f;
+          acc = tt_mma<BF>(Ta, 32 * ib, Tb, 0, lane, acc);
+#pragma unroll
+          for (int r = 0; r < 16; ++r)
+            atomicAdd(&sW2[(32 * ib + acc_row(r, hf) - a.w2_lo) * H + 32 * kb + j], acc[r]);
+        }
+        wave_lds_sync();
+      }
+    }
+
+    // delta1 = (W2^T delta2) * [z1 > 0]
+    f32x16 d1[NB];
+#pragma unroll
+    for (int b = 0; b < NB; ++b)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) d1[b][r] = 0.f;
+    if constexpr (!BF) {
+#pragma unroll
+      for (int st = 0; st < H / 2; ++st) {
+        const float dv = d2[st >> 4][st & 15];
+#pragma unroll
+        for (int b = 0; b < NB; ++b) d1[b] = mma_f32(W2T[((size_t)b * (H / 2) + st) * 64 + lane], dv, d1[b]);
+      }
+    } else {
+#pragma unroll
+      for (int st = 0; st < H / 16; ++st) {
+        bf16x8 B;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) B[e] = (short)bf16_bits(d2[st >> 1][8 * (st & 1) + e]);
+#pragma unroll
+        for (int b = 0; b < NB; ++b) d1[b] = mma_bf16(W2Tb[((size_t)b * (H / 16) + st) * 64 + lane], B, d1[b]);
+      }
+    }
+#pragma unroll
+    for (int b = 0; b < NB; ++b)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) d1[b][r] = z1[b][r] > 0.f ? d1[b][r] : 0.f;
+
+    const bool any_w1 = ncols > 0;
+    if (any_w1) {
+#pragma unroll
+      for (int b = 0; b < NB; ++b)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) tt_put<BF>(Ta, 32 * b + acc_row(r, hf), j, d1[b][r]);
+    }
+
+    // dL/dy per block of 16 features of each half, then the grid terms
+    const int nblk = s.KHP / 16;
+    for (int blk = 0; blk < nblk; ++blk) {
+      f32x16 dy;
+#pragma unroll
+      for (int r = 0; r < 16; ++r) dy[r] = 0.f;
+      if constexpr (!BF) {
+#pragma unroll
+        for (int st = 0; st < H / 2; ++st)
+          dy = mma_f32(W1T[((size_t)blk * (H / 2) + st) * 64 + lane], d1[st >> 4][st & 15], dy);
+      } else {
+#pragma unroll
+        for (int st = 0; st < H / 16; ++st) {
+          bf16x8 B;
+#pragma unroll
+          for (int e = 0; e < 8; ++e) B[e] = (short)bf16_bits(d1[st >> 1][8 * (st & 1) + e]);
+          dy = mma_bf16(W1Tb[((size_t)blk * (H / 16) + st) * 64 + lane], B, dy);
+        }
+      }
+      // columns of this block: half h, t in [16blk, 16blk+16) -> h*KH + t
+      const int lo0 = 16 * blk, lo1 = s.KH + 16 * blk;
+      const bool need_y = any_w1 && ((lo0 < a.c1_hi && lo0 + 16 > a.c1_lo) || (lo1 < a.c1_hi && lo1 + 16 > a.c1_lo));
+#pragma unroll
+      for (int u = 0; u < 16 / C; ++u) {
+        const int gi = 16 * blk / C + u;
+        const int g = hf * s.Mh + gi;
+        const bool gvalid = gi < s.Mh && g < s.M;
+        float yv[C], dl[3] = {0.f, 0.f, 0.f};
+#pragma unroll
+        for (int c = 0; c < C; ++c) yv[c] = 0.f;
+        if (gvalid && valid) {
+          float l[3];
+          local_coords(sG + 12 * g, x, y, z, l);
+          int i0[3];
+          float w[3];
+          if (cell_of(l, hR, s.R, i0, w)) {
+            float dyc[C];
+#pragma unroll
+            for (int c = 0; c < C; ++c) dyc[c] = dy[u * C + c];
+            if (dF) {
+              const size_t RC = (size_t)s.R * C, RRC = RC * s.R;
+              const size_t base = (((size_t)g * s.R + i0[2]) * s.R + i0[1]) * RC + (size_t)i0[0] * C;
+#pragma unroll
+              for (int q = 0; q < 8; ++q) {
+                const float wq = ((q & 1) ? w[0] : 1.f - w[0]) * ((q & 2) ? w[1] : 1.f - w[1]) *
+                                 ((q & 4) ? w[2] : 1.f - w[2]);
+                float* dst = dF + base + (q & 1) * C + ((q >> 1) & 1) * RC + (q >> 2) * RRC;
+#pragma unroll
+                for (int c = 0; c < C; ++c) atomicAdd(dst + c, wq * dyc[c]);
+              }
+            }
+            if (need_y || a.want_dG) {
+              float val[8][C];
+              gather_cell<C, GF16>(F, g, s.R, i0, val);
+              if (need_y) trilerp<C>(val, w, yv);
+              if (a.want_dG) {
+#pragma unroll
+                for (int c = 0; c < C; ++c) {
+                  const float ax00 = val[1][c] - val[0][c], ax10 = val[3][c] - val[2][c];
+                  const float ax01 = val[5][c] - val[4][c], ax11 = val[7][c] - val[6][c];
+                  const float gx = (1.f - w[2]) * ((1.f - w[1]) * ax00 + w[1] * ax10) +
+                                   w[2] * ((1.f - w[1]) * ax01 + w[1] * ax11);
+                  const float x00 = __builtin_fmaf(w[0], ax00, val[0][c]);
+                  const float x10 = __builtin_fmaf(w[0], ax10, val[2][c]);
+                  const float x01 = __builtin_fmaf(w[0], ax01, val[4][c]);
+                  const float x11 = __builtin_fmaf(w[0], ax11, val[6][c]);
+                  const float gy = (1.f - w[2]) * (x10 - x00) + w[2] * (x11 - x01);
+                  const float y0 = __builtin_fmaf(w[1], x10 - x00, x00);
+                  const float y1 = __builtin_fmaf(w[1], x11 - x01, x01);
+                  const float gz = y1 - y0;
+                  dl[0] = __builtin_fmaf(dyc[c], gx, dl[0]);
+                  dl[1] = __builtin_fmaf(dyc[c], gy, dl[1]);
+                  dl[2] = __builtin_fmaf(dyc[c], gz, dl[2]);
+                }
+#pragma unroll
+                for (int d = 0; d < 3; ++d) dl[d] *= hR;
+              }
+            }
+          }
+        }
+        if (a.want_dG && gi < s.Mh) {
+          const float xs[4] = {x, y, z, 1.f};
+#pragma unroll
+          for (int r = 0; r < 3; ++r)
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+              const float sum = half_sum(dl[r] * xs[k]);
+              if (j == 0 && g < s.M) atomicAdd(&sdG[12 * g + 4 * r + k], (double)sum);
+            }
+        }
+        if (need_y) {
+#pragma unroll
+          for (int c = 0; c < C; ++c) tt_put<BF>(Tb, 16 * hf + u * C + c, j, yv[c]);
+        }
+      }
+      if (need_y) {
+        wave_lds_sync();
+#pragma unroll
+        for (int ib = 0; ib < NB; ++ib) {
+          f32x16 acc;
+#pragma unroll
+          for (int r = 0; r < 16; ++r) acc[r] = 0.f;
+          acc = tt_mma<BF>(Ta, 32 * ib, Tb, 0, lane, acc);
+          // column j of the block: half j/16, t = 16 blk + j%16
+          const int col = (j >> 4) * s.KH + 16 * blk + (j & 15);
+          const bool ok = (16 * blk + (j & 15)) < s.KH && col < s.MC && col >= a.c1_lo && col < a.c1_hi;
+          if (ok) {
+#pragma unroll
+            for (int r = 0; r < 16; ++r)
+              atomicAdd(&sW1[(32 * ib + acc_row(r, hf)) * ncols + (col - a.c1_lo)], acc[r]);
+          }
+        }
+        wave_lds_sync();
+      }
+    }
+  }
+
+  // block-level reductions
+  if (a.do_w3) {
+#pragma unroll
+    for (int b = 0; b < NB; ++b)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const float sum = half_sum(dw3[b][r]);
+        if (j == 0) atomicAdd(&sW3[32 * b + acc_row(r, hf)], sum);
+      }
+  }
+  if (a.want_loss) {
+    const double t = wave_sum(loss);
+    if (lane == 0) atomicAdd(sLoss, t);
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < H * ncols; i += blockDim.x) part[pl.o_w1 + i] = sW1[i];
+  for (int i = threadIdx.x; i < nrows2 * H; i += blockDim.x) part[pl.o_w2 + i] = sW2[i];
+  if (a.do_w3)
+    for (int i = threadIdx.x; i < H; i += blockDim.x) part[pl.o_w3 + i] = sW3[i];
+  if (a.want_dG)
+    for (int i = threadIdx.x; i < 12 * s.M; i += blockDim.x) part[pl.o_g + i] = sdG[i];
+  if (threadIdx.x == 0) part[pl.o_loss] = *sLoss;
+}
+
+// ------------------------------------------------------------------ instantiation
+template <int C, int H, bool GF16, bool BF>
+hipError_t launch_tile_kernels(bool backward, const TileArgs& a, dim3 grid, size_t shmem,
+                               hipStream_t st) {
+  if (backward) {
+    hipLaunchKernelGGL((k_backward<C, H, GF16, BF>), grid, dim3(kBlock), shmem, st, a);
+  } else {
+    hipLaunchKernelGGL((k_forward<C, H, GF16, BF>), grid, dim3(kBlock), shmem, st, a);
+  }
+  return hipGetLastError();
+}
+
+size_t backward_lds_bytes(const Shape& s, int ncols, int nrows2, bool bf) {
+  const int ldt = bf ? 40 : 33;
+  const size_t esz = bf ? 2 : 4;
+  size_t b = (size_t)(12 * s.M + s.H * ncols + nrows2 * s.H + s.H) * 4;
+  b = (b + 7) & ~(size_t)7;
+  b += (size_t)(12 * s.M + 1) * 8;
+  b = (b + 15) & ~(size_t)15;
+  b += (size_t)kWavesPerBlock * (s.H + 32) * ldt * esz;
+  return b;
+}
+
+hipError_t launch_tile(bool backward, const TileArgs& a, bool grid_f16, bool mlp_bf16, dim3 grid,
+                       size_t shmem, hipStream_t st) {
+  const int C = a.s.C, H = a.s.H;
+#define APMG_DISPATCH(CC, HH)                                                                  \
+  if (C == CC && H == HH) {                                                                    \
+    if (!grid_f16 && !mlp_bf16) return launch_tile_kernels<CC, HH, false, false>(backward, a, grid, shmem, st); \
+    if (!grid_f16 && mlp_bf16) return launch_tile_kernels<CC, HH, false, true>(backward, a, grid, shmem, st);   \
+    if (grid_f16 && !mlp_bf16) return launch_tile_kernels<CC, HH, true, false>(backward, a, grid, shmem, st);   \
+    return launch_tile_kernels<CC, HH, true, true>(backward, a, grid, shmem, st);              \
+  }
+  APMG_DISPATCH(1, 64)
+  APMG_DISPATCH(2, 64)
+  APMG_DISPATCH(4, 64)
+  APMG_DISPATCH(1, 128)
+  APMG_DISPATCH(2, 128)
+  APMG_DISPATCH(4, 128)
+#undef APMG_DISPATCH
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_swizzle(const Shape& s, bool bf, const float* W1, const float* W2, const float* W3,
+                          size_t wstride, void* swz, size_t swz_stride, float* w3s, int nmodels,
+                          hipStream_t st) {
+  const size_t total = swz_sizes(s).total() + s.H;
+  dim3 grid((unsigned)((total + 255) / 256 > 4096 ? 4096 : (total + 255) / 256), nmodels);
+  if (bf) hipLaunchKernelGGL(k_swizzle<true>, grid, dim3(256), 0, st, s, W1, W2, W3, wstride, swz, swz_stride, w3s);
+  else hipLaunchKernelGGL(k_swizzle<false>, grid, dim3(256), 0, st, s, W1, W2, W3, wstride, swz, swz_stride, w3s);
+  return hipGetLastError();
+}
+
+}  // namespace apmg

@@ -1,0 +1,139 @@
+"""CPU checks of the C ABI: the library loads, exports every declared entry
+point, validates arguments before launching anything, sizes workspaces, and
+its host-side brick partition equals the oracle's."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import paper_2308_02494_amd as A
+from oracle import apmg_oracle as O
+
+HEADER = os.path.join(os.path.dirname(os.path.dirname(__file__)), "include", "apmg.h")
+
+
+def _declared():
+    txt = open(HEADER).read()
+    return sorted(set(re.findall(r"^(?:apmg_status|size_t|const char\*)\s+(apmg_\w+)\s*\(", txt, re.M)))
+
+
+def test_every_declared_symbol_is_exported_and_bound():
+    names = _declared()
+    assert len(names) >= 12
+    lib = ctypes.CDLL(A.LIB_PATH)
+    for nm in names:
+        assert hasattr(lib, nm), nm
+        assert nm in A.EXPORTS, nm
+
+
+def _model(M=32, C=2, R=32, H=64, grid=A.F32, mlp=A.F32):
+    m = A.ApmgModel()
+    m.M, m.C, m.R, m.n_layers = M, C, R, 3
+    for k, w in enumerate([M * C, H, H, 1]):
+        m.width[k] = w
+    m.grid_dtype, m.mlp_dtype = grid, mlp
+    return m
+
+
+def test_status_strings():
+    assert A.status_string(A.OK) == "ok"
+    assert "workspace" in A.status_string(A.EWORKSPACE)
+    assert A.status_string(7) == "unknown status"
+
+
+@pytest.mark.parametrize("op", [A.OP_FORWARD, A.OP_BACKWARD, A.OP_DENSITY])
+def test_workspace_sizes(op):
+    m = _model()
+    a = A._lib.apmg_workspace_bytes(op, ctypes.byref(m), 1 << 10)
+    b = A._lib.apmg_workspace_bytes(op, ctypes.byref(m), 1 << 20)
+    assert a > 0 and b >= a
+    assert A._lib.apmg_workspace_bytes(op, ctypes.byref(m), -1) == 0
+    bad = _model()
+    bad.width[0] = 63
+    assert A._lib.apmg_workspace_bytes(op, ctypes.byref(bad), 16) == 0
+
+
+def test_forward_argument_validation_needs_no_gpu():
+    m = _model()
+    f = A._lib.apmg_forward
+    assert f(None, None, 0, 0, None, None, 0, None) == A.EINVAL
+    # missing parameter pointers
+    assert f(ctypes.byref(m), None, 0, 0, None, None, 0, None) == A.EINVAL
+    fake = ctypes.c_void_p(0x1000)
+    m.G = m.F = 0x1000
+    for k in range(3):
+        m.W[k] = 0x1000
+    assert f(ctypes.byref(m), fake, 4, 8, fake, fake, 1 << 30, None) == A.EINVAL   # ld < n
+    assert f(ctypes.byref(m), fake, 8, -1, fake, fake, 1 << 30, None) == A.EINVAL  # n < 0
+    assert f(ctypes.byref(m), fake, 8, 8, fake, fake, 16, None) == A.EWORKSPACE
+    for field, val in [("C", 3), ("R", 1)]:
+        bad = _model()
+        setattr(bad, field, val)
+        bad.width[0] = bad.M * bad.C
+        bad.G = bad.F = 0x1000
+        for k in range(3):
+            bad.W[k] = 0x1000
+        rc = f(ctypes.byref(bad), fake, 8, 8, fake, fake, 1 << 30, None)
+        assert rc in (A.EINVAL, A.EUNSUPPORTED)
+    unsup = _model(H=96)
+    unsup.G = unsup.F = 0x1000
+    for k in range(3):
+        unsup.W[k] = 0x1000
+    assert f(ctypes.byref(unsup), fake, 8, 8, fake, fake, 1 << 30, None) == A.EUNSUPPORTED
+    big = _model(M=129, C=2)
+    big.G = big.F = 0x1000
+    for k in range(3):
+        big.W[k] = 0x1000
+    assert f(ctypes.byref(big), fake, 8, 8, fake, fake, 1 << 30, None) == A.EUNSUPPORTED
+
+
+def test_backward_and_density_validation():
+    m = _model()
+    m.G = m.F = 0x1000
+    for k in range(3):
+        m.W[k] = 0x1000
+    fake = ctypes.c_void_p(0x1000)
+    assert A._lib.apmg_backward(ctypes.byref(m), fake, 8, 8, None, None, None, None, 0, fake, 1 << 30,
+                                None) == A.EINVAL  # df missing
+    assert A._lib.apmg_density_loss(ctypes.byref(m), fake, 8, 8, fake, 1e-12, 0, fake, None, None, 0, fake,
+                                    1 << 30, None) == A.EINVAL  # p < 1
+    assert A._lib.apmg_density_loss(ctypes.byref(m), fake, 8, 8, fake, -1.0, 10, fake, None, None, 0, fake,
+                                    1 << 30, None) == A.EINVAL  # eps < 0
+    assert A._lib.apmg_density_loss(ctypes.byref(m), fake, 8, 8, fake, 1e-12, 10, fake, None, None, 0, fake,
+                                    16, None) == A.EWORKSPACE
+    assert A._lib.apmg_batched_step(None, None, 0, None) == A.EINVAL
+    assert A._lib.apmg_uniform_points(1, 0, 0, 0, -1, None, 0, None) == A.EINVAL
+    assert A._lib.apmg_gt_sample(None, 4, 4, 4, None, 0, 0, None, None) == A.EINVAL
+    assert A._lib.apmg_convert_grids(0, 1, 2, fake, 0, fake, 0, 1, None) == A.EINVAL
+
+
+def test_zero_points_is_ok_without_launch():
+    m = _model()
+    m.G = m.F = 0x1000
+    for k in range(3):
+        m.W[k] = 0x1000
+    ws = A._lib.apmg_workspace_bytes(A.OP_FORWARD, ctypes.byref(m), 0)
+    assert A._lib.apmg_forward(ctypes.byref(m), None, 0, 0, None, ctypes.c_void_p(0x1000), ws, None) == A.OK
+    assert A._lib.apmg_uniform_points(1, 0, 0, 0, 0, None, 0, None) == A.OK
+
+
+@pytest.mark.parametrize("shape,B,g", [((1000, 1200, 900), 256, 1), ((1024, 1024, 1024), 256, 16),
+                                       ((33, 17, 65), 16, 2), ((5, 5, 5), 8, 0)])
+def test_make_bricks_equals_oracle_partition(shape, B, g):
+    t, bricks = A.apmg_make_bricks(*shape, B, g)
+    dims, ob = O.brick_partition(shape, B, g)
+    assert tuple(t.dims) == dims and len(bricks) == len(ob)
+    for b, o in zip(bricks, ob):
+        assert tuple(b.ijk) == o["ijk"]
+        assert list(b.e0) == o["e0"] and list(b.e1) == o["e1"]
+
+
+def test_make_bricks_rejects_bad_arguments():
+    t = A.ApmgBrickTable()
+    assert A._lib.apmg_make_bricks(0, 4, 4, 2, 0, ctypes.byref(t), None, 0) == A.EINVAL
+    assert A._lib.apmg_make_bricks(8, 8, 8, 0, 0, ctypes.byref(t), None, 0) == A.EINVAL
+    assert A._lib.apmg_make_bricks(8, 8, 8, 2, -1, ctypes.byref(t), None, 0) == A.EINVAL
+    arr = (A.ApmgBrick * 3)()
+    assert A._lib.apmg_make_bricks(8, 8, 8, 2, 0, ctypes.byref(t), arr, 3) == A.EINVAL  # 64 bricks > cap
