@@ -1,0 +1,184 @@
+"""Training-step throughput of the APMGSRN hot path on one MI355X.
+
+Workload (one model, "plain FP32 training step at paper-like scale"): a
+256^3 float32 synthetic volume (64 Gaussian blobs of widths 0.01-0.1 plus a
+turbulent patch on 5% of the domain), G = 32 grids at 32^3 with F = 2
+features, MLP 64-64-64-1, 2^20 uniform points per step.  A step is the whole
+hot path: point generation, ground-truth sampling, forward, L_rec and its
+adjoint, the density loss (both passes) and its transform gradient, and Adam.
+
+Prints one JSON line: train points/s of the fp32 step (value), plus the
+roofline of the dominant kernel (the fused forward+adjoint tile kernel),
+the FP64 oracle timed on a sample on the host, and extra figures
+(inference points/s, the bf16-MLP step).
+"""
+import argparse
+import ctypes
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# MI355X published peaks
+PEAK_FP32_MFMA_TFLOPS = 157.3
+PEAK_BF16_MFMA_TFLOPS = 2500.0
+PEAK_HBM_GBS = 8000.0
+
+M, C, R, H = 32, 2, 32, 64
+VOL = (256, 256, 256)
+N = 1 << 20
+
+
+def mlp_flops_fwd_bwd(K, Hd):
+    """Algorithmic MLP flop per point of one forward + adjoint: forward
+    2(KH + H^2 + H); adjoint dW1, dW2, dW3 (2KH + 2H^2 + 2H) and dL/dh1,
+    dL/dy (2H^2 + 2KH)."""
+    fwd = 2 * (K * Hd + Hd * Hd + Hd)
+    bwd = 2 * (K * Hd + Hd * Hd + Hd) + 2 * (Hd * Hd + K * Hd)
+    return fwd + bwd
+
+
+def hip():
+    lib = ctypes.CDLL("libamdhip64.so")
+    lib.hipEventCreate.argtypes = [ctypes.POINTER(ctypes.c_void_p)]
+    lib.hipEventElapsedTime.argtypes = [ctypes.POINTER(ctypes.c_float), ctypes.c_void_p, ctypes.c_void_p]
+    lib.hipEventDestroy.argtypes = [ctypes.c_void_p]
+    return lib
+
+
+def make_trainer(A, torch, synth, mlp_dtype, n):
+    vol = synth.make_volume("blobs_turb", VOL, device="cuda")
+    nz, ny, nx = vol.shape
+    _, bricks = A.apmg_make_bricks(nx, ny, nz, max(nx, ny, nz), 0)
+    host = synth.init_model(M, C, R, [M * C, H, H, 1], seed=synth.SEED_MODEL)
+    tr = A.Trainer([host], vol, bricks, n, seed=synth.SEED_POINTS, mlp_dtype=mlp_dtype)
+    tr.density_active.fill_(1)
+    return tr, vol, host
+
+
+def time_steps(A, torch, tr, steps, warmup, hl):
+    for _ in range(warmup):
+        tr.step()
+    torch.cuda.synchronize()
+    evs = []
+    for _ in range(steps):
+        a, b = ctypes.c_void_p(), ctypes.c_void_p()
+        hl.hipEventCreate(ctypes.byref(a))
+        hl.hipEventCreate(ctypes.byref(b))
+        evs.append((a, b))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for a, b in evs:
+        A.apmg_profile_events(a, b)
+        tr.step()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    ks = []
+    for a, b in evs:
+        ms = ctypes.c_float()
+        hl.hipEventElapsedTime(ctypes.byref(ms), a, b)
+        ks.append(ms.value)
+        hl.hipEventDestroy(a)
+        hl.hipEventDestroy(b)
+    return dt, sum(ks) / len(ks)
+
+
+def time_forward(A, torch, host, n, reps=10):
+    model = A.Model.from_host(host, "cuda")
+    pts = A.apmg_uniform_points(11, 0, 0, 0, n)
+    ws = torch.empty(A._lib.apmg_workspace_bytes(A.OP_FORWARD, ctypes.byref(model.struct()), n),
+                     dtype=torch.uint8, device="cuda")
+    out = torch.empty(n, device="cuda")
+    for _ in range(3):
+        A.apmg_forward(model, pts, out=out, ws=ws)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        A.apmg_forward(model, pts, out=out, ws=ws)
+    torch.cuda.synchronize()
+    return n * reps / (time.perf_counter() - t0)
+
+
+def cpu_baseline(vol_np, host, n_sample):
+    """The FP64 oracle's training step on a bounded sample of the same workload."""
+    import numpy as np
+    from threadpoolctl import threadpool_limits
+
+    from oracle import apmg_oracle as O
+    model = {"G": host["G"].astype(np.float64), "F": host["F"].astype(np.float64),
+             "W": [w.astype(np.float64) for w in host["W"]], "vmin": 0.0, "vmax": 1.0}
+    brick = {"e0": [0, 0, 0], "e1": [VOL[2] - 1, VOL[1] - 1, VOL[0] - 1]}
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        x = O.uniform_points(7, 0, 0, n_sample)
+        v = O.brick_gt_sample(vol_np, brick, x)
+        O.train_step(model, O.zero_adam_state(model), x, v, density_active=True)
+        dt = time.perf_counter() - t0
+    return {"value": n_sample / dt, "unit": "train pts/s", "cores": 1, "kind": "oracle",
+            "sample": f"one FP64 oracle training step (points, ground truth, forward, adjoint, density, "
+                      f"Adam) on {n_sample} of the {N} points, same model and volume, 1 thread, "
+                      f"{dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample", type=int, default=1 << 15)
+    ap.add_argument("--skip-extra", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (the path is one GPU's "
+              f"share; see the sharding notes in the design document)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import paper_2308_02494_amd as A
+    import synth
+
+    hl = hip()
+    tr, vol, host = make_trainer(A, torch, synth, A.F32, N)
+    dt, kern_ms = time_steps(A, torch, tr, args.steps, args.warmup, hl)
+    ms_step = dt * 1e3 / args.steps
+    value = N * args.steps / dt
+    flops = mlp_flops_fwd_bwd(M * C, H) * N
+    achieved = flops / (kern_ms * 1e-3) / 1e12
+    out = {
+        "metric": "train pts/s (fwd+bwd), 32-grid APMGSRN, FP32",
+        "value": value, "unit": "pts/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic (seeded closed-form volume, paper initialisation)",
+        "config": {"workload": "single-model training step: 256^3 blobs+turbulence volume, 32 grids "
+                               "at 32^3 x 2 features, MLP 64-64-64-1, 2^20 points, density phase on",
+                   "global_batch": N, "parallelism": "none (1 GPU)"},
+        "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK_FP32_MFMA_TFLOPS,
+                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_MFMA_TFLOPS, "traffic": None,
+                     "kernel": "k_backward (fused forward + adjoint tile kernel)",
+                     "kernel_ms": kern_ms},
+    }
+    L = tr.losses.cpu().numpy()
+    out["losses_last_step"] = {"L_rec": float(L[0, 0]), "L_density": float(L[0, 1])}
+    if not args.skip_extra:
+        extra = {}
+        extra["infer_pts_per_s_fp32"] = time_forward(A, torch, host, N)
+        del tr
+        torch.cuda.empty_cache()
+        trb, _, _ = make_trainer(A, torch, synth, A.BF16, N)
+        dtb, kb = time_steps(A, torch, trb, args.steps, args.warmup, hl)
+        extra["train_pts_per_s_bf16_mlp"] = N * args.steps / dtb
+        extra["bf16_kernel_ms"] = kb
+        out["extra"] = extra
+        del trb
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(vol.cpu().numpy().astype("float64"), host, args.cpu_sample)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

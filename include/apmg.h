@@ -262,6 +262,14 @@ apmg_status apmg_uniform_points(uint64_t seed, uint64_t step, uint32_t stream_id
 apmg_status apmg_gt_sample(const float* volume, int32_t nx, int32_t ny, int32_t nz,
                            const float* pts, int64_t ld, int64_t n, float* v, hipStream_t stream);
 
+/* ---------------------------------------------------------------- tracing
+ * Timing hook for the dominant kernel: once set, the next apmg_backward or
+ * apmg_batched_step call records `start` on its stream just before the first
+ * launch of the adjoint tile kernel and `stop` just after its last launch,
+ * then clears the hook.  The events are the caller's (hipEventCreate);
+ * NULL, NULL clears the hook.  One hook per process; not thread-safe. */
+apmg_status apmg_profile_events(hipEvent_t start, hipEvent_t stop);
+
 #ifdef __cplusplus
 }
 #endif

@@ -72,6 +72,7 @@ _sigs = {
     "apmg_cells": [ctypes.POINTER(ApmgModel), c_p, c_i64, c_i64, c_p, c_p, c_p],
     "apmg_uniform_points": [c_u64, c_u64, c_u32, c_i64, c_i64, c_p, c_i64, c_p],
     "apmg_gt_sample": [c_p, c_i32, c_i32, c_i32, c_p, c_i64, c_i64, c_p, c_p],
+    "apmg_profile_events": [c_p, c_p],
 }
 for _name, _args in _sigs.items():
     _fn = getattr(_lib, _name)
@@ -411,3 +412,8 @@ class DensityLossFunction(torch.autograd.Function):
     def backward(ctx, g):
         (dG,) = ctx.saved_tensors
         return None, (g * dG).to(torch.float32), None, None, None
+
+
+def apmg_profile_events(start, stop):
+    """Arm the adjoint-kernel timing hook with two hipEvent_t handles (ints), or clear it."""
+    _check("apmg_profile_events", _lib.apmg_profile_events(start, stop))

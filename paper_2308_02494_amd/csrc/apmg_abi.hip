@@ -184,7 +184,7 @@ struct StepWs {
   float* err;     // [nb][n]
   void* swz;      // [nb][swizzled weights]
   float* w3s;     // [nb][H]
-  float* scale;   // [nb][2] (vmax - vmin, vmin)
+  float* scale;   // [2][nb]: vmax - vmin, then vmin
   float* dF;      // [nb][F]
   float* dW;      // [nb][W]
   double* dG;     // [nb][12 M]  transform gradient used by Adam
@@ -223,15 +223,30 @@ size_t step_ws(const apmg_batch* b, const Shape& s, void* ws, StepWs* o) {
   return off + dsz;
 }
 
+// scale[b] = vmax - vmin, scale[nb + b] = vmin of brick b
 __global__ void k_brick_scale(const apmg_brick* bricks, float* scale, int nb) {
   const int b = blockIdx.x * blockDim.x + threadIdx.x;
-  if (b < nb) { scale[2 * b] = bricks[b].vmax - bricks[b].vmin; scale[2 * b + 1] = bricks[b].vmin; }
+  if (b < nb) { scale[b] = bricks[b].vmax - bricks[b].vmin; scale[nb + b] = bricks[b].vmin; }
 }
 
 }  // namespace
 
+hipEvent_t g_prof_start = nullptr, g_prof_stop = nullptr;
+void prof_begin(hipStream_t st) { if (g_prof_start) hipEventRecord(g_prof_start, st); }
+void prof_end(hipStream_t st) {
+  if (g_prof_stop) hipEventRecord(g_prof_stop, st);
+  g_prof_start = g_prof_stop = nullptr;
+}
+
 // ======================================================================== ABI
 extern "C" {
+
+apmg_status apmg_profile_events(hipEvent_t start, hipEvent_t stop) {
+  if ((start == nullptr) != (stop == nullptr)) return APMG_EINVAL;
+  g_prof_start = start;
+  g_prof_stop = stop;
+  return APMG_OK;
+}
 
 const char* apmg_status_string(apmg_status s) {
   switch (s) {
@@ -320,6 +335,7 @@ apmg_status apmg_backward(const apmg_model* m, const float* pts, int64_t ld, int
   const std::vector<Pass> passes = plan_passes(s, bf, dW != nullptr);
   if (passes.empty()) return APMG_EUNSUPPORTED;
   for (const Pass& ps : passes) {
+    if (ps.first) prof_begin(st);
     TileArgs a;
     memset(&a, 0, sizeof(a));
     a.s = s;
@@ -338,6 +354,7 @@ apmg_status apmg_backward(const apmg_model* m, const float* pts, int64_t ld, int
     a.part_len = pl.len;
     e = launch_tile(true, a, gf16, bf, dim3(nblk, 1), backward_lds_bytes(s, ncols, nrows, bf), st);
     if (e != hipSuccess) return APMG_EHIP;
+    if (&ps == &passes.back()) prof_end(st);
     if (ncols > 0)
       hipLaunchKernelGGL(k_reduce_parts, dim3(grid1((int64_t)s.H * ncols, 256), 1), dim3(256), 0, st, w.part,
                          nblk, pl.len, pl.o_w1, s.H * ncols, ncols, s.MC, ps.c1_lo, dW[0], (double*)nullptr,
@@ -518,7 +535,7 @@ extern "C" apmg_status apmg_batched_step(const apmg_batch* b, void* ws, size_t w
     a.G = b->G; a.G_stride = nG;
     a.F = gf16 ? (const void*)b->F_lowp : (const void*)b->F; a.F_stride = nF;
     a.swz = w.swz; a.swz_stride = swz_stride; a.w3s = w.w3s;
-    a.bscale = w.scale; a.boff = w.scale + 1;
+    a.bscale = w.scale; a.boff = w.scale + nb;
     a.pts = w.pts; a.ld = n; a.pts_stride = (size_t)3 * n; a.n = n;
     a.df = nullptr; a.v = w.v; a.v_stride = n; a.err = w.err; a.err_stride = n;
     a.err_abs = (b->flags & APMG_ERR_ABS) ? 1 : 0;
@@ -533,8 +550,10 @@ extern "C" apmg_status apmg_batched_step(const apmg_batch* b, void* ws, size_t w
     const PartLayout pl = part_layout(s, ncols, nrows);
     if (ps.first) pl0 = pl;
     a.part_len = pl.len;
+    if (pi == 0) prof_begin(st);
     e = launch_tile(true, a, gf16, bf, dim3(nblk, nb), backward_lds_bytes(s, ncols, nrows, bf), st);
     if (e != hipSuccess) return APMG_EHIP;
+    if (pi + 1 == passes.size()) prof_end(st);
     if (ncols > 0)
       hipLaunchKernelGGL(k_reduce_parts, dim3(grid1((int64_t)s.H * ncols, 256), nb), dim3(256), 0, st, w.part, nblk,
                          pl.len, pl.o_w1, s.H * ncols, ncols, s.MC, ps.c1_lo, w.dW, (double*)nullptr, nW, 0,
