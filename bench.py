@@ -129,7 +129,7 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample", type=int, default=1 << 15)
+    ap.add_argument("--cpu-sample", type=int, default=1 << 16)
     ap.add_argument("--skip-extra", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:

@@ -114,10 +114,12 @@ apmg_status apmg_forward(const apmg_model* model, const float* pts, int64_t ld, 
  *   dG: [M][3][4] float64 or NULL (gradient through the trilinear weights).
  *   dW: host array of n_layers device pointers, each [width[k+1]][width[k]]
  *       float32, or NULL for no MLP gradient.
- * Outputs are overwritten unless APMG_ACCUMULATE.  dF uses float32
- * atomics (order-dependent rounding) unless APMG_DETERMINISTIC, which
- * reduces each vertex's contributions in a fixed order.  dG and dW are
- * always reduced in a fixed order (per-tile partials, float64 sum). */
+ * Outputs are overwritten unless APMG_ACCUMULATE.  The points are first
+ * sorted (stably) into spatial bins; dF is then gathered per grid cell from
+ * the points of the bins the cell overlaps, with no atomics, and every
+ * reduction (dF, dG in float64, dW in float64 over per-block partials) runs
+ * in a fixed order: results are bitwise reproducible, and
+ * APMG_DETERMINISTIC is accepted but changes nothing. */
 apmg_status apmg_backward(const apmg_model* model, const float* pts, int64_t ld, int64_t n,
                           const float* df, float* dF, double* dG, float* const* dW,
                           uint32_t flags, void* ws, size_t ws_bytes, hipStream_t stream);

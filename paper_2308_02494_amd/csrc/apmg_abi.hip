@@ -81,13 +81,13 @@ std::vector<Pass> plan_passes(const Shape& s, bool bf, bool want_w) {
   int r0 = 0, c0 = 0;
   while (r0 < s.H || c0 < s.MC) {
     int r = 0;
-    while (r0 + r + 32 <= s.H && backward_lds_bytes(s, 0, r + 32, bf) <= kLdsLimit) r += 32;
+    while (r0 + r + 32 <= s.H && backward_lds_bytes(s, 0, r + 32, bf, 0) <= kLdsLimit) r += 32;
     int c = 0;
     if (r0 + r >= s.H) {  // rows done in this pass: give the rest of the budget to columns
       int lo = 0, hi = s.MC - c0;
       while (lo < hi) {
         const int mid = (lo + hi + 1) / 2;
-        if (backward_lds_bytes(s, mid, r, bf) <= kLdsLimit) lo = mid; else hi = mid - 1;
+        if (backward_lds_bytes(s, mid, r, bf, 0) <= kLdsLimit) lo = mid; else hi = mid - 1;
       }
       c = lo;
     }
@@ -116,14 +116,90 @@ size_t fwd_ws(const Shape& s, bool bf, void* ws, FwdWs* o) {
   return cv.off;
 }
 
-struct BwdWs { FwdWs f; double* part; };
+// Spatial sort of nb models' points: keys/values ping-pong, digit histograms, bin starts,
+// sorted points and an optional permuted per-point array.
+struct SortWs { uint32_t *k0, *v0, *k1, *v1, *hist, *start; float *spts, *sf; };
+inline int sort_tiles(int64_t n) { return (int)std::max<int64_t>(1, (n + kSortTile - 1) / kSortTile); }
+void take_sort(Carver& cv, int64_t n, int nb, bool with_f, SortWs* o) {
+  const int64_t nn = std::max<int64_t>(n, 1);
+  o->k0 = cv.take<uint32_t>((size_t)nb * nn);
+  o->v0 = cv.take<uint32_t>((size_t)nb * nn);
+  o->k1 = cv.take<uint32_t>((size_t)nb * nn);
+  o->v1 = cv.take<uint32_t>((size_t)nb * nn);
+  o->hist = cv.take<uint32_t>((size_t)nb * kRadixDigits * sort_tiles(n));
+  o->start = cv.take<uint32_t>((size_t)nb * (kBinsPerAxis * kBinsPerAxis * kBinsPerAxis + 1));
+  o->spts = cv.take<float>((size_t)nb * 3 * nn);
+  o->sf = with_f ? cv.take<float>((size_t)nb * nn) : nullptr;
+}
+
+hipError_t launch_sort(const float* pts, int64_t ld, size_t pts_stride, int64_t n, int nb, const SortWs& w,
+                       const float* src_f, hipStream_t st) {
+  const int nt = sort_tiles(n);
+  hipLaunchKernelGGL(k_bin_keys, dim3(grid1(n), nb), dim3(256), 0, st, pts, ld, pts_stride, n, w.k0, w.v0);
+  uint32_t *ki = w.k0, *vi = w.v0, *ko = w.k1, *vo = w.v1;
+  for (int shift = 0; shift < kBinBits; shift += kRadixBits) {
+    hipLaunchKernelGGL(k_radix_hist, dim3(nt, nb), dim3(256), 0, st, ki, n, shift, w.hist, nt);
+    hipLaunchKernelGGL(k_radix_scan, dim3(nb), dim3(1024), 0, st, w.hist, kRadixDigits * nt);
+    hipLaunchKernelGGL(k_radix_scatter, dim3(nt, nb), dim3(256), 0, st, ki, vi, ko, vo, n, shift, w.hist, nt);
+    std::swap(ki, ko);
+    std::swap(vi, vo);
+  }
+  // after an even number of passes the sorted keys/values are back in k0/v0
+  hipLaunchKernelGGL(k_permute_points, dim3(grid1(n), nb), dim3(256), 0, st, pts, ld, pts_stride, n, w.v0, w.spts,
+                     src_f, w.sf);
+  hipLaunchKernelGGL(k_bin_starts, dim3(grid1(kBinsPerAxis * kBinsPerAxis * kBinsPerAxis + 1), nb), dim3(256), 0,
+                     st, w.k0, n, w.start);
+  return hipGetLastError();
+}
+
+// Per-cell pass buffers: dL/dy per grid, corner sums per cell, transform-gradient partials.
+struct CellWs { float *dY, *CC; double* dGpart; };
+inline int64_t n_cells(const Shape& s) { return (int64_t)(s.R - 1) * (s.R - 1) * (s.R - 1); }
+inline int cell_blocks(const Shape& s) { return (int)((n_cells(s) + 255) / 256); }
+void take_cell(Carver& cv, const Shape& s, int64_t n, int nb, CellWs* o) {
+  o->dY = cv.take<float>((size_t)nb * s.M * std::max<int64_t>(n, 1) * s.C);
+  o->CC = cv.take<float>((size_t)nb * s.M * n_cells(s) * 8 * s.C);
+  o->dGpart = cv.take<double>((size_t)nb * s.M * cell_blocks(s) * 12);
+}
+
+// Grid gradient (into dF when non-NULL) and, when want_dG, the per-block transform-gradient
+// partials (reduced into dG when non-NULL; otherwise left for a later k_reduce_cell_dG).
+hipError_t launch_cells(const Shape& s, bool gf16, const float* G, size_t G_stride, const void* F, size_t F_stride,
+                        const SortWs& sw, int64_t n, const CellWs& cw, float* dF, size_t dF_stride, int accumulate,
+                        bool want_dG, double* dG, size_t dG_stride, int dG_accumulate, int nb,
+                        const int32_t* active, hipStream_t st) {
+  CellArgs c;
+  memset(&c, 0, sizeof(c));
+  c.s = s; c.G = G; c.G_stride = G_stride; c.F = F; c.F_stride = F_stride;
+  c.pts = sw.spts; c.n = n; c.start = sw.start; c.dY = cw.dY; c.CC = cw.CC;
+  c.want_dG = want_dG ? 1 : 0; c.dGpart = cw.dGpart; c.active = active;
+  const dim3 grid(cell_blocks(s), s.M, nb);
+#define APMG_CELL(CC_, F16_)                                                                        \
+  if (s.C == CC_ && gf16 == F16_) {                                                                 \
+    hipLaunchKernelGGL((k_cell_pull<CC_, F16_>), grid, dim3(256), 0, st, c);                        \
+    if (dF) hipLaunchKernelGGL((k_cell_to_vertex<CC_>), dim3(grid1((int64_t)s.R * s.R * s.R, 1024), s.M, nb), \
+                               dim3(256), 0, st, s, cw.CC, dF, dF_stride, accumulate, active);       \
+  }
+  APMG_CELL(1, false) APMG_CELL(2, false) APMG_CELL(4, false)
+  APMG_CELL(1, true) APMG_CELL(2, true) APMG_CELL(4, true)
+#undef APMG_CELL
+  if (dG)
+    hipLaunchKernelGGL(k_reduce_cell_dG, dim3(1, nb), dim3(256), 0, st, cw.dGpart, s.M, cell_blocks(s), dG,
+                       dG_stride, dG_accumulate, active);
+  return hipGetLastError();
+}
+
+struct BwdWs { FwdWs f; double* part; SortWs srt; CellWs cell; };
 size_t bwd_ws(const Shape& s, bool bf, int64_t n, void* ws, BwdWs* o) {
   Carver cv(ws);
+  BwdWs w;
   const size_t esz = bf ? 2 : 4;
-  void* swz = cv.take<char>(swz_sizes(s).total() * esz);
-  float* w3s = cv.take<float>(s.H);
-  double* part = cv.take<double>((size_t)tile_blocks(n) * max_part_len(s, bf));
-  if (o) { o->f.swz = swz; o->f.w3s = w3s; o->part = part; }
+  w.f.swz = cv.take<char>(swz_sizes(s).total() * esz);
+  w.f.w3s = cv.take<float>(s.H);
+  w.part = cv.take<double>((size_t)tile_blocks(n) * max_part_len(s, bf));
+  take_sort(cv, n, 1, true, &w.srt);
+  take_cell(cv, s, n, 1, &w.cell);
+  if (o) *o = w;
   return cv.off;
 }
 
@@ -156,7 +232,7 @@ hipError_t launch_density(const Shape& s, const float* G, size_t G_stride, const
   float* rho = rho_user ? rho_user : w.rho;
   const size_t rho_stride = rho_user ? (size_t)n : (size_t)std::max<int64_t>(n, 1);
   const int ba = dens_blocks(n), bb = dens_b2_blocks(n);
-  const size_t shA = 16 + (size_t)13 * s.M * 4;
+  const size_t shA = 64 + (size_t)13 * s.M * 4;
   hipLaunchKernelGGL(k_density_a, dim3(ba, nb), dim3(256), shA, st, s, G, G_stride, pts, ld, pts_stride, n,
                      err, err_stride, p, rho, rho_stride, w.pa, active);
   hipLaunchKernelGGL(k_density_sums, dim3((nb + 63) / 64), dim3(64), 0, st, w.pa, ba, w.sums, nb);
@@ -164,7 +240,7 @@ hipError_t launch_density(const Shape& s, const float* G, size_t G_stride, const
                      w.sums, eps, w.pb1, active);
   hipLaunchKernelGGL(k_density_lq, dim3((nb + 63) / 64), dim3(64), 0, st, w.pb1, ba, n, w.lq, nb);
   if (dG) {
-    const size_t shB = (size_t)13 * s.M * 8 + (size_t)12 * s.M * 4;
+    const size_t shB = (size_t)4 * 13 * s.M * 8 + (size_t)12 * s.M * 4;
     hipLaunchKernelGGL(k_density_b2, dim3(bb, nb), dim3(256), shB, st, s, G, G_stride, pts, ld, pts_stride,
                        n, rho, rho_stride, err, err_stride, w.sums, w.lq, eps, p, w.pb2, active);
     hipLaunchKernelGGL(k_reduce_parts, dim3(grid1(13 * s.M, 64), nb), dim3(256), 0, st, w.pb2, bb,
@@ -179,8 +255,8 @@ hipError_t launch_density(const Shape& s, const float* G, size_t G_stride, const
 
 // ---------------------------------------------------------------- training step
 struct StepWs {
-  float* pts;     // [nb][3][n]
-  float* v;       // [nb][n]
+  float* pts;     // [nb][3][n] generated (unsorted)
+  float* v;       // [nb][n] ground truth at the sorted points
   float* err;     // [nb][n]
   void* swz;      // [nb][swizzled weights]
   float* w3s;     // [nb][H]
@@ -188,9 +264,10 @@ struct StepWs {
   float* dF;      // [nb][F]
   float* dW;      // [nb][W]
   double* dG;     // [nb][12 M]  transform gradient used by Adam
-  double* dGrec;  // [nb][12 M]  L_rec's transform gradient (multi-pass adjoint only)
   double* lrec;   // [nb] sum (f - v)^2
   double* part;   // adjoint partials
+  SortWs srt;
+  CellWs cell;
   DenWs den;
 };
 
@@ -212,9 +289,10 @@ size_t step_ws(const apmg_batch* b, const Shape& s, void* ws, StepWs* o) {
   w.dF = cv.take<float>((size_t)nb * f_elems(s));
   w.dW = cv.take<float>((size_t)nb * w_elems(s));
   w.dG = cv.take<double>((size_t)nb * 12 * s.M);
-  w.dGrec = cv.take<double>((size_t)nb * 12 * s.M);
   w.lrec = cv.take<double>((size_t)nb);
   w.part = cv.take<double>((size_t)nb * tile_blocks(b->n) * max_part_len(s, bf));
+  take_sort(cv, b->n, nb, false, &w.srt);
+  take_cell(cv, s, b->n, nb, &w.cell);
   size_t off = cv.off;
   DenWs d;
   size_t dsz = den_ws(s, b->n, nb, ws ? (char*)ws + off : nullptr, &d);
@@ -223,7 +301,6 @@ size_t step_ws(const apmg_batch* b, const Shape& s, void* ws, StepWs* o) {
   return off + dsz;
 }
 
-// scale[b] = vmax - vmin, scale[nb + b] = vmin of brick b
 __global__ void k_brick_scale(const apmg_brick* bricks, float* scale, int nb) {
   const int b = blockIdx.x * blockDim.x + threadIdx.x;
   if (b < nb) { scale[b] = bricks[b].vmax - bricks[b].vmin; scale[nb + b] = bricks[b].vmin; }
@@ -301,7 +378,7 @@ apmg_status apmg_forward(const apmg_model* m, const float* pts, int64_t ld, int6
   a.pts = pts; a.ld = ld; a.n = n; a.f = f;
   const int64_t tiles = (n + 31) / 32;
   dim3 grid((unsigned)std::min<int64_t>((tiles + kWavesPerBlock - 1) / kWavesPerBlock, 8192), 1);
-  return hip_status(launch_tile(false, a, gf16, bf, grid, (size_t)12 * s.M * 4, st));
+  return hip_status(launch_tile(false, 0, a, gf16, bf, grid, forward_lds_bytes(s, bf), st));
 }
 
 apmg_status apmg_backward(const apmg_model* m, const float* pts, int64_t ld, int64_t n, const float* df,
@@ -315,36 +392,41 @@ apmg_status apmg_backward(const apmg_model* m, const float* pts, int64_t ld, int
   if (dW) for (int k = 0; k < m->n_layers; ++k) if (!dW[k]) return APMG_EINVAL;
   const bool bf = m->mlp_dtype == APMG_BF16, gf16 = m->grid_dtype == APMG_F16;
   if (ws_bytes < bwd_ws(s, bf, n, nullptr, nullptr) || !ws) return APMG_EWORKSPACE;
+  const std::vector<Pass> passes = plan_passes(s, bf, dW != nullptr);
+  if (passes.empty()) return APMG_EUNSUPPORTED;
   const bool acc = flags & APMG_ACCUMULATE;
   const size_t nF = (size_t)s.M * s.R * s.R * s.R * s.C;
   if (!acc) {
-    if (dF) hipLaunchKernelGGL(k_fill_f32, dim3(grid1(nF)), dim3(256), 0, st, dF, nF, 0.f);
-    if (dG) hipLaunchKernelGGL(k_fill_f64, dim3(1), dim3(256), 0, st, dG, (size_t)12 * s.M, 0.0);
     if (dW) {
       hipLaunchKernelGGL(k_fill_f32, dim3(grid1((int64_t)s.H * s.MC)), dim3(256), 0, st, dW[0], (size_t)s.H * s.MC, 0.f);
       hipLaunchKernelGGL(k_fill_f32, dim3(grid1((int64_t)s.H * s.H)), dim3(256), 0, st, dW[1], (size_t)s.H * s.H, 0.f);
       hipLaunchKernelGGL(k_fill_f32, dim3(1), dim3(256), 0, st, dW[2], (size_t)s.H, 0.f);
     }
+    if (n == 0) {
+      if (dF) hipLaunchKernelGGL(k_fill_f32, dim3(grid1(nF)), dim3(256), 0, st, dF, nF, 0.f);
+      if (dG) hipLaunchKernelGGL(k_fill_f64, dim3(1), dim3(256), 0, st, dG, (size_t)12 * s.M, 0.0);
+    }
   }
   if (n == 0) return hip_status(hipGetLastError());
   BwdWs w;
   bwd_ws(s, bf, n, ws, &w);
-  hipError_t e = launch_swizzle(s, bf, m->W[0], m->W[1], m->W[2], 0, w.f.swz, 0, w.f.w3s, 1, st);
+  // points (and dL/df) in spatial-bin order
+  hipError_t e = launch_sort(pts, ld, 0, n, 1, w.srt, df, st);
+  if (e != hipSuccess) return APMG_EHIP;
+  e = launch_swizzle(s, bf, m->W[0], m->W[1], m->W[2], 0, w.f.swz, 0, w.f.w3s, 1, st);
   if (e != hipSuccess) return APMG_EHIP;
   const int nblk = tile_blocks(n);
-  const std::vector<Pass> passes = plan_passes(s, bf, dW != nullptr);
-  if (passes.empty()) return APMG_EUNSUPPORTED;
+  const bool want_cells = dF || dG;
+  const int kb = passes.size() == 1 ? register_kb(s) : 0;
   for (const Pass& ps : passes) {
-    if (ps.first) prof_begin(st);
     TileArgs a;
     memset(&a, 0, sizeof(a));
     a.s = s;
     a.G = m->G; a.F = m->F; a.swz = w.f.swz; a.w3s = w.f.w3s;
     a.vscale = m->vmax - m->vmin; a.voff = m->vmin;
-    a.pts = pts; a.ld = ld; a.n = n;
-    a.df = df;
-    a.dF = ps.first ? dF : nullptr;
-    a.want_dG = (ps.first && dG) ? 1 : 0;
+    a.pts = w.srt.spts; a.ld = n; a.n = n;
+    a.df = w.srt.sf;
+    a.dY = (ps.first && want_cells) ? w.cell.dY : nullptr;
     a.c1_lo = ps.c1_lo; a.c1_hi = ps.c1_hi;
     a.w2_lo = ps.w2_lo; a.w2_hi = ps.w2_hi;
     a.do_w3 = (ps.first && dW) ? 1 : 0;
@@ -352,7 +434,8 @@ apmg_status apmg_backward(const apmg_model* m, const float* pts, int64_t ld, int
     const int ncols = ps.c1_hi - ps.c1_lo, nrows = ps.w2_hi - ps.w2_lo;
     const PartLayout pl = part_layout(s, ncols, nrows);
     a.part_len = pl.len;
-    e = launch_tile(true, a, gf16, bf, dim3(nblk, 1), backward_lds_bytes(s, ncols, nrows, bf), st);
+    if (ps.first) prof_begin(st);
+    e = launch_tile(true, kb, a, gf16, bf, dim3(nblk, 1), backward_lds_bytes(s, ncols, nrows, bf, kb), st);
     if (e != hipSuccess) return APMG_EHIP;
     if (&ps == &passes.back()) prof_end(st);
     if (ncols > 0)
@@ -366,9 +449,11 @@ apmg_status apmg_backward(const apmg_model* m, const float* pts, int64_t ld, int
     if (a.do_w3)
       hipLaunchKernelGGL(k_reduce_parts, dim3(1, 1), dim3(256), 0, st, w.part, nblk, pl.len, pl.o_w3, s.H, s.H, 0,
                          0, dW[2], (double*)nullptr, (size_t)0, 1, (const int32_t*)nullptr);
-    if (a.want_dG)
-      hipLaunchKernelGGL(k_reduce_parts, dim3(1, 1), dim3(256), 0, st, w.part, nblk, pl.len, pl.o_g, 12 * s.M,
-                         12 * s.M, 0, 0, (float*)nullptr, dG, (size_t)0, 1, (const int32_t*)nullptr);
+  }
+  if (want_cells) {
+    e = launch_cells(s, gf16, m->G, 0, m->F, 0, w.srt, n, w.cell, dF, 0, acc ? 1 : 0, dG != nullptr, dG, 0,
+                     acc ? 1 : 0, 1, nullptr, st);
+    if (e != hipSuccess) return APMG_EHIP;
   }
   return hip_status(hipGetLastError());
 }
@@ -507,26 +592,29 @@ extern "C" apmg_status apmg_batched_step(const apmg_batch* b, void* ws, size_t w
   const size_t nF = f_elems(s), nW = w_elems(s), nG = (size_t)12 * s.M;
   const size_t swz_stride = swz_sizes(s).total();
 
-  // 1. batch points and ground truth
-  if (n > 0)
-    hipLaunchKernelGGL(k_batch_points_gt, dim3(grid1(n, 2048), nb), dim3(256), 0, st, b->seed, b->step, n,
-                       b->volume, b->vol[0], b->vol[1], b->bricks, w.pts, w.v);
+  // 1. batch points, sorted by spatial bin, and the ground truth at the sorted points
+  if (n > 0) {
+    hipLaunchKernelGGL(k_batch_points, dim3(grid1(n, 2048), nb), dim3(256), 0, st, b->seed, b->step, n, w.pts);
+    hipError_t e0 = launch_sort(w.pts, n, (size_t)3 * n, n, nb, w.srt, nullptr, st);
+    if (e0 != hipSuccess) return APMG_EHIP;
+    hipLaunchKernelGGL(k_batch_gt, dim3(grid1(n, 2048), nb), dim3(256), 0, st, w.srt.spts, n, b->volume, b->vol[0],
+                       b->vol[1], b->bricks, w.v);
+  }
   // 2. operands of this step's weights, output scaling, zeroed gradients
   hipError_t e = launch_swizzle(s, bf, b->W, b->W + (size_t)s.H * s.MC, b->W + (size_t)s.H * s.MC + (size_t)s.H * s.H,
                                 nW, w.swz, swz_stride, w.w3s, nb, st);
   if (e != hipSuccess) return APMG_EHIP;
   hipLaunchKernelGGL(k_brick_scale, dim3((nb + 63) / 64), dim3(64), 0, st, b->bricks, w.scale, nb);
-  hipLaunchKernelGGL(k_fill_f32, dim3(grid1((int64_t)(nb * nF))), dim3(256), 0, st, w.dF, nb * nF, 0.f);
   hipLaunchKernelGGL(k_fill_f32, dim3(grid1((int64_t)(nb * nW))), dim3(256), 0, st, w.dW, nb * nW, 0.f);
-  hipLaunchKernelGGL(k_fill_f64, dim3(grid1((int64_t)(nb * nG))), dim3(256), 0, st, w.dG, nb * nG, 0.0);
   hipLaunchKernelGGL(k_fill_f64, dim3(1), dim3(256), 0, st, w.lrec, (size_t)nb, 0.0);
+  if (n == 0) hipLaunchKernelGGL(k_fill_f32, dim3(grid1((int64_t)(nb * nF))), dim3(256), 0, st, w.dF, nb * nF, 0.f);
 
   // 3. forward + adjoint of L_rec (part 1 of the step)
   const int nblk = tile_blocks(n);
   const std::vector<Pass> passes = plan_passes(s, bf, true);
   if (passes.empty()) return APMG_EUNSUPPORTED;
+  const int kb = passes.size() == 1 ? register_kb(s) : 0;
   const bool rec_dG = b->flags & APMG_ADD_REC_DG;
-  PartLayout pl0 = part_layout(s, 0, 0);
   for (size_t pi = 0; pi < passes.size() && n > 0; ++pi) {
     const Pass& ps = passes[pi];
     TileArgs a;
@@ -536,11 +624,10 @@ extern "C" apmg_status apmg_batched_step(const apmg_batch* b, void* ws, size_t w
     a.F = gf16 ? (const void*)b->F_lowp : (const void*)b->F; a.F_stride = nF;
     a.swz = w.swz; a.swz_stride = swz_stride; a.w3s = w.w3s;
     a.bscale = w.scale; a.boff = w.scale + nb;
-    a.pts = w.pts; a.ld = n; a.pts_stride = (size_t)3 * n; a.n = n;
+    a.pts = w.srt.spts; a.ld = n; a.pts_stride = (size_t)3 * n; a.n = n;
     a.df = nullptr; a.v = w.v; a.v_stride = n; a.err = w.err; a.err_stride = n;
     a.err_abs = (b->flags & APMG_ERR_ABS) ? 1 : 0;
-    a.dF = ps.first ? w.dF : nullptr; a.dF_stride = nF;
-    a.want_dG = (ps.first && rec_dG) ? 1 : 0;
+    a.dY = ps.first ? w.cell.dY : nullptr;
     a.c1_lo = ps.c1_lo; a.c1_hi = ps.c1_hi;
     a.w2_lo = ps.w2_lo; a.w2_hi = ps.w2_hi;
     a.do_w3 = ps.first;
@@ -548,10 +635,9 @@ extern "C" apmg_status apmg_batched_step(const apmg_batch* b, void* ws, size_t w
     a.part = w.part;
     const int ncols = ps.c1_hi - ps.c1_lo, nrows = ps.w2_hi - ps.w2_lo;
     const PartLayout pl = part_layout(s, ncols, nrows);
-    if (ps.first) pl0 = pl;
     a.part_len = pl.len;
     if (pi == 0) prof_begin(st);
-    e = launch_tile(true, a, gf16, bf, dim3(nblk, nb), backward_lds_bytes(s, ncols, nrows, bf), st);
+    e = launch_tile(true, kb, a, gf16, bf, dim3(nblk, nb), backward_lds_bytes(s, ncols, nrows, bf, kb), st);
     if (e != hipSuccess) return APMG_EHIP;
     if (pi + 1 == passes.size()) prof_end(st);
     if (ncols > 0)
@@ -568,30 +654,26 @@ extern "C" apmg_status apmg_batched_step(const apmg_batch* b, void* ws, size_t w
       hipLaunchKernelGGL(k_reduce_parts, dim3(1, nb), dim3(64), 0, st, w.part, nblk, pl.len, pl.o_loss, 1, 1, 0, 0,
                          (float*)nullptr, w.lrec, (size_t)1, 0, (const int32_t*)nullptr);
     }
-    if (ps.first && rec_dG && pi + 1 < passes.size()) {
-      // keep the first pass's transform-gradient partials: later passes reuse the buffer
-      hipLaunchKernelGGL(k_reduce_parts, dim3(1, nb), dim3(256), 0, st, w.part, nblk, pl.len, pl.o_g, 12 * s.M,
-                         12 * s.M, 0, 0, (float*)nullptr, w.dGrec, nG, 0, (const int32_t*)nullptr);
-    }
   }
   if (n > 0)
     hipLaunchKernelGGL(k_copy_f64, dim3((nb + 63) / 64), dim3(64), 0, st, w.lrec, 1, b->losses, 2, nb, 1.0 / (double)n);
   else
     hipLaunchKernelGGL(k_fill_f64, dim3(1), dim3(256), 0, st, b->losses, (size_t)2 * nb, 0.0);
 
-  // 4. density loss and its transform gradient (part 2), for active models
+  // 4. grid gradient from the per-cell pass; L_rec's transform gradient only under APMG_ADD_REC_DG
   if (n > 0) {
-    e = launch_density(s, b->G, nG, w.pts, n, (size_t)3 * n, n, w.err, n, b->eps_density, b->p, b->losses + 1, 2,
-                       w.dG, nG, 0, nullptr, w.den, nb, b->density_active, st);
+    e = launch_cells(s, gf16, b->G, nG, gf16 ? (const void*)b->F_lowp : (const void*)b->F, nF, w.srt, n, w.cell,
+                     w.dF, nF, 0, rec_dG, nullptr, 0, 0, nb, nullptr, st);
     if (e != hipSuccess) return APMG_EHIP;
-    if (rec_dG) {
-      if (passes.size() == 1)
-        hipLaunchKernelGGL(k_reduce_parts, dim3(1, nb), dim3(256), 0, st, w.part, nblk, pl0.len, pl0.o_g, 12 * s.M,
-                           12 * s.M, 0, 0, (float*)nullptr, w.dG, nG, 1, b->density_active);
-      else
-        hipLaunchKernelGGL(k_reduce_parts, dim3(1, nb), dim3(256), 0, st, w.dGrec, 1, (int)nG, 0, 12 * s.M,
-                           12 * s.M, 0, 0, (float*)nullptr, w.dG, nG, 1, b->density_active);
-    }
+  }
+  // 5. density loss and its transform gradient (part 2), for active models
+  if (n > 0) {
+    e = launch_density(s, b->G, nG, w.srt.spts, n, (size_t)3 * n, n, w.err, n, b->eps_density, b->p, b->losses + 1,
+                       2, w.dG, nG, 0, nullptr, w.den, nb, b->density_active, st);
+    if (e != hipSuccess) return APMG_EHIP;
+    if (rec_dG)
+      hipLaunchKernelGGL(k_reduce_cell_dG, dim3(1, nb), dim3(256), 0, st, w.cell.dGpart, s.M, cell_blocks(s), w.dG,
+                         nG, 1, b->density_active);
   }
 
   // 5. Adam: grids and MLP every step, transforms while the density phase is active

@@ -39,6 +39,10 @@ __device__ inline f32x16 mma_bf16(bf16x8 a, bf16x8 b, f32x16 c) {
   return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
 }
 
+// Keeps the scheduler from hoisting loads across this point (bounds the number of
+// operand loads kept in flight, and with it register pressure).
+__device__ inline void sched_fence() { asm volatile("" ::: "memory"); }
+
 // Row of a 32x32 accumulator block held in register r by lane half hf.
 __host__ __device__ inline int acc_row(int r, int hf) { return 8 * (r >> 2) + 4 * hf + (r & 3); }
 

@@ -50,8 +50,7 @@ struct TileArgs {
   const float* v; size_t v_stride;        // ground truth (training)
   float* err; size_t err_stride;          // h(x) out (training)
   int err_abs;
-  float* dF; size_t dF_stride;            // fp32 grid gradient (elements) or NULL
-  int want_dG;                            // reduce the transform gradient
+  float* dY;                              // [model][M][n][C] dL/dy per grid (sorted points) or NULL
   int c1_lo, c1_hi;                       // first-layer gradient columns accumulated by this launch
   int w2_lo, w2_hi;                       // second-layer gradient rows (multiples of 32)
   int do_w3;                              // accumulate the output layer gradient

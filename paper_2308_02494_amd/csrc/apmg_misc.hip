@@ -77,23 +77,29 @@ __global__ void k_gt_sample(const float* vol, int nx, int ny, int nz, const floa
     v[i] = sample_volume(vol, nx, ny, e0, nn, pts[i], pts[ld + i], pts[2 * ld + i]);
 }
 
-// Training batch for every model: points from the counter stream, then the ground truth
-// sampled from the model's brick (extended extent e0..e1 inclusive).
-__global__ void k_batch_points_gt(uint64_t seed, const uint64_t* step_ctr, int64_t n,
-                                  const float* vol, int vnx, int vny, const apmg_brick* bricks,
-                                  float* pts, float* v) {
+// Training batch of every model: points from the counter stream, SoA [model][3][n].
+__global__ void k_batch_points(uint64_t seed, const uint64_t* step_ctr, int64_t n, float* pts) {
   const int model = blockIdx.y;
   const uint64_t step = *step_ctr;
-  const apmg_brick br = bricks[model];
-  const int e0[3] = {br.e0[0], br.e0[1], br.e0[2]};
-  const int nn[3] = {br.e1[0] - br.e0[0] + 1, br.e1[1] - br.e0[1] + 1, br.e1[2] - br.e0[2] + 1};
   float* P = pts + (size_t)model * 3 * n;
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
     float x, y, z;
     uniform_point(seed, step, (uint32_t)model, (uint64_t)i, x, y, z);
     P[i] = x; P[n + i] = y; P[2 * n + i] = z;
-    v[(size_t)model * n + i] = sample_volume(vol, vnx, vny, e0, nn, x, y, z);
   }
+}
+
+// Ground truth of every model's (sorted) points: trilinear sample of the model's brick
+// (extended extent e0..e1 inclusive).
+__global__ void k_batch_gt(const float* pts, int64_t n, const float* vol, int vnx, int vny, const apmg_brick* bricks,
+                           float* v) {
+  const int model = blockIdx.y;
+  const apmg_brick br = bricks[model];
+  const int e0[3] = {br.e0[0], br.e0[1], br.e0[2]};
+  const int nn[3] = {br.e1[0] - br.e0[0] + 1, br.e1[1] - br.e0[1] + 1, br.e1[2] - br.e0[2] + 1};
+  const float* P = pts + (size_t)model * 3 * n;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    v[(size_t)model * n + i] = sample_volume(vol, vnx, vny, e0, nn, P[i], P[n + i], P[2 * n + i]);
 }
 
 // ------------------------------------------------------------------ cells / bricks
@@ -181,10 +187,9 @@ __global__ void __launch_bounds__(256) k_density_a(Shape s, const float* Gall, s
     int p, float* rho, size_t rho_stride, double* part, const int32_t* active) {
   extern __shared__ float smem[];
   const int model = blockIdx.y;
-  double* spart = (double*)smem;
-  float* sG = (float*)(spart + 2);
+  double* spart = (double*)smem;   // [wave][2]
+  float* sG = (float*)(spart + 8);
   float* sdet = sG + 12 * s.M;
-  if (threadIdx.x == 0) { spart[0] = 0.0; spart[1] = 0.0; }
   const bool act = !active || active[model];
   const float* G = Gall + model * G_stride;
   for (int i = threadIdx.x; i < 12 * s.M; i += blockDim.x) sG[i] = G[i];
@@ -210,9 +215,11 @@ __global__ void __launch_bounds__(256) k_density_a(Shape s, const float* Gall, s
   }
   srho = wave_sum(srho);
   serr = wave_sum(serr);
-  if ((threadIdx.x & 63) == 0) { atomicAdd(&spart[0], srho); atomicAdd(&spart[1], serr); }
+  if ((threadIdx.x & 63) == 0) { spart[2 * (threadIdx.x >> 6)] = srho; spart[2 * (threadIdx.x >> 6) + 1] = serr; }
   __syncthreads();
-  if (threadIdx.x < 2) part[((size_t)model * gridDim.x + blockIdx.x) * 2 + threadIdx.x] = spart[threadIdx.x];
+  if (threadIdx.x < 2)
+    part[((size_t)model * gridDim.x + blockIdx.x) * 2 + threadIdx.x] =
+        ((spart[threadIdx.x] + spart[2 + threadIdx.x]) + spart[4 + threadIdx.x]) + spart[6 + threadIdx.x];
 }
 
 // Reduce pass-A partials: sums[model] = {S, sum err}.
@@ -239,10 +246,8 @@ __device__ inline void target_terms(double rho, double S, double hbar, double h,
 // Pass B1: loss and Q = sum a rho_s.  part: [model][block][2] = {loss sum, Q}
 __global__ void __launch_bounds__(256) k_density_b1(const float* rho, size_t rho_stride, const float* err,
     size_t err_stride, int64_t n, const double* sums, double eps, double* part, const int32_t* active) {
-  __shared__ double spart[2];
+  __shared__ double spart[8];   // [wave][2]
   const int model = blockIdx.y;
-  if (threadIdx.x == 0) { spart[0] = 0.0; spart[1] = 0.0; }
-  __syncthreads();
   const bool act = (!active || active[model]) && sums[2 * model] != 0.0;
   double sl = 0.0, sq = 0.0;
   if (act) {
@@ -256,9 +261,11 @@ __global__ void __launch_bounds__(256) k_density_b1(const float* rho, size_t rho
   }
   sl = wave_sum(sl);
   sq = wave_sum(sq);
-  if ((threadIdx.x & 63) == 0) { atomicAdd(&spart[0], sl); atomicAdd(&spart[1], sq); }
+  if ((threadIdx.x & 63) == 0) { spart[2 * (threadIdx.x >> 6)] = sl; spart[2 * (threadIdx.x >> 6) + 1] = sq; }
   __syncthreads();
-  if (threadIdx.x < 2) part[((size_t)model * gridDim.x + blockIdx.x) * 2 + threadIdx.x] = spart[threadIdx.x];
+  if (threadIdx.x < 2)
+    part[((size_t)model * gridDim.x + blockIdx.x) * 2 + threadIdx.x] =
+        ((spart[threadIdx.x] + spart[2 + threadIdx.x]) + spart[4 + threadIdx.x]) + spart[6 + threadIdx.x];
 }
 
 // Reduce pass-B1 partials into lq[model] = {loss, Q}
@@ -280,9 +287,9 @@ __global__ void __launch_bounds__(256) k_density_b2(Shape s, const float* Gall, 
     double* part, const int32_t* active) {
   extern __shared__ float smem[];
   const int model = blockIdx.y;
-  double* sacc = (double*)smem;            // [13 M]
-  float* sG = (float*)(sacc + 13 * s.M);
-  for (int i = threadIdx.x; i < 13 * s.M; i += blockDim.x) sacc[i] = 0.0;
+  double* sacc = (double*)smem;            // [wave][13 M]
+  float* sG = (float*)(sacc + 4 * 13 * s.M);
+  for (int i = threadIdx.x; i < 4 * 13 * s.M; i += blockDim.x) sacc[i] = 0.0;
   const float* G = Gall + model * G_stride;
   for (int i = threadIdx.x; i < 12 * s.M; i += blockDim.x) sG[i] = G[i];
   __syncthreads();
@@ -332,14 +339,15 @@ __global__ void __launch_bounds__(256) k_density_b2(Shape s, const float* Gall, 
 #pragma unroll
         for (int q = 0; q < 13; ++q) {
           const double t = wave_sum((double)u[q]);
-          if ((threadIdx.x & 63) == 0) atomicAdd(&sacc[13 * g + q], t);
+          if ((threadIdx.x & 63) == 0) sacc[(threadIdx.x >> 6) * 13 * s.M + 13 * g + q] += t;
         }
       }
     }
   }
   __syncthreads();
   for (int i = threadIdx.x; i < 13 * s.M; i += blockDim.x)
-    part[((size_t)model * gridDim.x + blockIdx.x) * 13 * s.M + i] = sacc[i];
+    part[((size_t)model * gridDim.x + blockIdx.x) * 13 * s.M + i] =
+        ((sacc[i] + sacc[13 * s.M + i]) + sacc[2 * 13 * s.M + i]) + sacc[3 * 13 * s.M + i];
 }
 
 // Assemble dG_i = cof_i U0 - 2p det_i [U1 | U2] from the reduced pass-B2 sums.

@@ -85,6 +85,18 @@ __global__ void k_swizzle(Shape s, const float* __restrict__ W1all, const float*
 }
 
 // ------------------------------------------------------------------ tile pieces
+// LDS transpose tiles: [row][32 points], row stride LDT elements.
+template <bool BF> struct TT {
+  static constexpr int LDT = BF ? 40 : 33;
+  typedef typename std::conditional<BF, uint16_t, float>::type T;
+};
+
+template <bool BF>
+__device__ inline void tt_put(typename TT<BF>::T* t, int row, int j, float v) {
+  if constexpr (BF) t[row * TT<BF>::LDT + j] = bf16_bits(v);
+  else t[row * TT<BF>::LDT + j] = v;
+}
+
 template <int C, bool GF16>
 __device__ inline void encode_grid(const Shape& s, const float* sG, const void* F, int g, float x,
                                    float y, float z, bool valid, float hR, float e[C]) {
@@ -101,10 +113,13 @@ __device__ inline void encode_grid(const Shape& s, const float* sG, const void* 
   trilerp<C>(val, w, e);
 }
 
-template <int C, int H, bool GF16, bool BF>
+// Forward pass of one 32-point tile.  With STY, the features are also written to the
+// LDS tile Ty in dy-block order: feature t of half hf goes to row 32 (t/16) + 16 hf + t%16.
+template <int C, int H, bool GF16, bool BF, bool STY = false>
 __device__ inline void tile_fwd(const Shape& s, const float* sG, const void* F, const void* swz,
                                 const float* w3s, float x, float y, float z, bool valid, int lane,
-                                f32x16 (&z1)[H / 32], f32x16 (&z2)[H / 32], float& m) {
+                                f32x16 (&z1)[H / 32], f32x16 (&z2)[H / 32], float& m,
+                                typename TT<BF>::T* Ty = nullptr) {
   constexpr int NB = H / 32;
   const int hf = lane >> 5;
   const float hR = 0.5f * (float)(s.R - 1);
@@ -120,6 +135,7 @@ __device__ inline void tile_fwd(const Shape& s, const float* sG, const void* F, 
 #pragma unroll
       for (int c = 0; c < C; ++c) {
         const size_t t = (size_t)gi * C + c;
+        if constexpr (STY) tt_put<BF>(Ty, 32 * ((int)t >> 4) + 16 * hf + ((int)t & 15), lane & 31, e[c]);
 #pragma unroll
         for (int b = 0; b < NB; ++b) z1[b] = mma_f32(W1[((size_t)b * s.KHP + t) * 64 + lane], e[c], z1[b]);
       }
@@ -136,7 +152,11 @@ __device__ inline void tile_fwd(const Shape& s, const float* sG, const void* F, 
         float e[C];
         encode_grid<C, GF16>(s, sG, F, gi < s.Mh ? hf * s.Mh + gi : s.M, x, y, z, valid, hR, e);
 #pragma unroll
-        for (int c = 0; c < C; ++c) B[u * C + c] = (short)bf16_bits(e[c]);
+        for (int c = 0; c < C; ++c) {
+          B[u * C + c] = (short)bf16_bits(e[c]);
+          const int t = 8 * st + u * C + c;
+          if constexpr (STY) tt_put<BF>(Ty, 32 * (t >> 4) + 16 * hf + (t & 15), lane & 31, e[c]);
+        }
       }
 #pragma unroll
       for (int b = 0; b < NB; ++b) z1[b] = mma_bf16(W1[((size_t)b * S1 + st) * 64 + lane], B, z1[b]);
@@ -154,6 +174,7 @@ __device__ inline void tile_fwd(const Shape& s, const float* sG, const void* F, 
       const float hv = fmaxf(z1[st >> 4][st & 15], 0.f);
 #pragma unroll
       for (int b = 0; b < NB; ++b) z2[b] = mma_f32(W2[((size_t)b * (H / 2) + st) * 64 + lane], hv, z2[b]);
+      if ((st & 7) == 7) sched_fence();
     }
   } else {
     const bf16x8* W2 = (const bf16x8*)((const uint16_t*)swz + (size_t)2 * H * s.KHP);
@@ -176,7 +197,22 @@ __device__ inline void tile_fwd(const Shape& s, const float* sG, const void* F, 
 }
 
 // ------------------------------------------------------------------ forward
-template <int C, int H, bool GF16, bool BF>
+// Copies `bytes` (a multiple of 16) from global memory to LDS with the whole block.
+__device__ inline void block_copy16(void* dst, const void* src, size_t bytes) {
+  const u32x4a8* s = (const u32x4a8*)src;
+  typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+  u32x4* d = (u32x4*)dst;
+  for (size_t i = threadIdx.x; i < bytes / 16; i += blockDim.x) d[i] = s[i];
+}
+
+// Bytes of the swizzled first and second layer (the forward pass's operands).
+__host__ __device__ inline size_t fwd_weight_bytes(const Shape& s, bool bf) {
+  const SwzSizes z = swz_sizes(s);
+  return (z.w1 + z.w2) * (bf ? 2 : 4);
+}
+
+// WL: the swizzled weights are staged in LDS (after the transforms).
+template <int C, int H, bool GF16, bool BF, bool WL>
 __global__ void __launch_bounds__(kBlock) k_forward(TileArgs a) {
   extern __shared__ float smem[];
   const int model = blockIdx.y;
@@ -185,11 +221,17 @@ __global__ void __launch_bounds__(kBlock) k_forward(TileArgs a) {
   float* sG = smem;
   const float* G = a.G + model * a.G_stride;
   for (int i = threadIdx.x; i < 12 * s.M; i += blockDim.x) sG[i] = G[i];
-  __syncthreads();
   const void* F = GF16 ? (const void*)((const __half*)a.F + model * a.F_stride)
                        : (const void*)((const float*)a.F + model * a.F_stride);
   const size_t esz = BF ? 2 : 4;
   const void* swz = (const char*)a.swz + esz * model * a.swz_stride;
+  if constexpr (WL) {
+    // byte offsets from the LDS base keep the pointer in the LDS address space
+    char* lw = (char*)smem + ((12 * s.M * 4 + 15) & ~15);
+    block_copy16(lw, swz, fwd_weight_bytes(s, BF));
+    swz = lw;
+  }
+  __syncthreads();
   const float* w3s = a.w3s + (size_t)model * H;
   const float vs = a.bscale ? a.bscale[model] : a.vscale;
   const float vo = a.boff ? a.boff[model] : a.voff;
@@ -216,18 +258,6 @@ __device__ inline void wave_lds_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// LDS transpose tiles: [row][32 points], row stride LDT elements.
-template <bool BF> struct TT {
-  static constexpr int LDT = BF ? 40 : 33;
-  typedef typename std::conditional<BF, uint16_t, float>::type T;
-};
-
-template <bool BF>
-__device__ inline void tt_put(typename TT<BF>::T* t, int row, int j, float v) {
-  if constexpr (BF) t[row * TT<BF>::LDT + j] = bf16_bits(v);
-  else t[row * TT<BF>::LDT + j] = v;
-}
-
 // acc += A_rows[ia..ia+32) x B_rows[ib..ib+32)^T over the 32 points of the tile
 template <bool BF>
 __device__ inline f32x16 tt_mma(const typename TT<BF>::T* Ta, int ia, const typename TT<BF>::T* Tb,
@@ -236,8 +266,10 @@ __device__ inline f32x16 tt_mma(const typename TT<BF>::T* Ta, int ia, const type
   const int li = lane & 31, hk = lane >> 5;
   if constexpr (!BF) {
 #pragma unroll
-    for (int st = 0; st < 16; ++st)
+    for (int st = 0; st < 16; ++st) {
       acc = mma_f32(Ta[(ia + li) * LDT + 2 * st + hk], Tb[(ib + li) * LDT + 2 * st + hk], acc);
+      if ((st & 7) == 7) sched_fence();
+    }
   } else {
 #pragma unroll
     for (int st = 0; st < 2; ++st) {
@@ -249,12 +281,16 @@ __device__ inline f32x16 tt_mma(const typename TT<BF>::T* Ta, int ia, const type
   return acc;
 }
 
-template <int C, int H, bool GF16, bool BF>
+// KB > 0: register-resident weight-gradient accumulators (H = 64, KB = KHP/16 dy blocks,
+// every column and row in one launch).  KB == 0: per-tile LDS accumulation, any shape,
+// gradient rows/columns split across launches.
+template <int C, int H, bool GF16, bool BF, int KB>
 __global__ void __launch_bounds__(kBlock) k_backward(TileArgs a) {
   extern __shared__ float smem[];
   typedef typename TT<BF>::T TTy;
   constexpr int NB = H / 32;
   constexpr int LDT = TT<BF>::LDT;
+  constexpr bool REG = KB > 0;
   const int model = blockIdx.y;
   const Shape s = a.s;
   const int ncols = a.c1_hi - a.c1_lo;
@@ -263,34 +299,49 @@ __global__ void __launch_bounds__(kBlock) k_backward(TileArgs a) {
   double* part = a.part + ((size_t)model * gridDim.x + blockIdx.x) * pl.len;
   const bool act = !a.active || a.active[model];
 
-  // LDS: sG [12M] f | sW1 [H*ncols] f | sW2 [nrows2*H] f | sW3 [H] f | sdG [12M] d | sLoss d |
-  // per wave: Ta [H rows] (a delta), Tb [32 rows] (an activation block)
+  // LDS: sG [12M] | sW3w [wave][H] | sLoss (double) | (REG) swizzled weights | per-wave
+  // transpose tiles Ta [H rows] (a delta), Tb [32 rows] (an activation block) and (REG)
+  // Ty [32 KB rows] (the features) | sW1 [H*ncols], sW2 [nrows2*H] (after the tiles, or,
+  // with REG, aliased onto them once the tile loop is done)
+  const size_t esz = BF ? 2 : 4;
+  const size_t wbytes = REG ? swz_sizes(s).total() * esz : 0;
+  // carve by byte offsets from the LDS base (keeps every pointer in the LDS address space)
+  char* lbase = (char*)smem;
+  size_t off = (size_t)(12 * s.M + kWavesPerBlock * H) * 4;
   float* sG = smem;
-  float* sW1 = sG + 12 * s.M;
-  float* sW2 = sW1 + H * ncols;
-  float* sW3 = sW2 + nrows2 * H;
-  double* sdG = (double*)(((uintptr_t)(sW3 + H) + 7) & ~(uintptr_t)7);
-  double* sLoss = sdG + 12 * s.M;
-  TTy* tiles = (TTy*)(((uintptr_t)(sLoss + 1) + 15) & ~(uintptr_t)15);
+  float* sW3w = sG + 12 * s.M;
+  off = (off + 7) & ~(size_t)7;
+  double* sLoss = (double*)(lbase + off);   // [wave]
+  off = (off + 8 * kWavesPerBlock + 15) & ~(size_t)15;
+  char* lw = lbase + off;
+  TTy* tiles = (TTy*)(lbase + off + wbytes);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, j = lane & 31, hf = lane >> 5;
-  TTy* Ta = tiles + (size_t)wave * (H + 32) * LDT;
+  const int wrows = H + 32 + (REG ? 32 * KB : 0);
+  TTy* Ta = tiles + (size_t)wave * wrows * LDT;
   TTy* Tb = Ta + (size_t)H * LDT;
+  TTy* Ty = Tb + (size_t)32 * LDT;
+  float* sW1 = REG ? (float*)tiles : (float*)(tiles + (size_t)kWavesPerBlock * wrows * LDT);
+  float* sW2 = sW1 + H * ncols;
 
   const float* G = a.G + model * a.G_stride;
-  for (int i = threadIdx.x; i < 12 * s.M; i += blockDim.x) { sG[i] = G[i]; sdG[i] = 0.0; }
-  for (int i = threadIdx.x; i < H * ncols + nrows2 * H + H; i += blockDim.x) sW1[i] = 0.f;
-  if (threadIdx.x == 0) *sLoss = 0.0;
-  __syncthreads();
+  for (int i = threadIdx.x; i < 12 * s.M; i += blockDim.x) sG[i] = G[i];
+  for (int i = threadIdx.x; i < kWavesPerBlock * H; i += blockDim.x) sW3w[i] = 0.f;
+  if (!REG)
+    for (int i = threadIdx.x; i < H * ncols + nrows2 * H; i += blockDim.x) sW1[i] = 0.f;
 
   const void* F = GF16 ? (const void*)((const __half*)a.F + model * a.F_stride)
                        : (const void*)((const float*)a.F + model * a.F_stride);
-  const size_t esz = BF ? 2 : 4;
   const void* swz = (const char*)a.swz + esz * model * a.swz_stride;
+  if constexpr (REG) {
+    block_copy16(lw, swz, wbytes);
+    swz = lw;
+  }
+  __syncthreads();
   const float* w3s = a.w3s + (size_t)model * H;
   const float vs = a.bscale ? a.bscale[model] : a.vscale;
   const float vo = a.boff ? a.boff[model] : a.voff;
   const float* P = a.pts + model * a.pts_stride;
-  float* dF = a.dF ? a.dF + model * a.dF_stride : nullptr;
+  float* dY = a.dY ? a.dY + (size_t)model * s.M * a.n * C : nullptr;
   const float hR = 0.5f * (float)(s.R - 1);
   const float* W2T = nullptr; const bf16x8* W2Tb = nullptr;
   const float* W1T = nullptr; const bf16x8* W1Tb = nullptr;
@@ -299,12 +350,23 @@ __global__ void __launch_bounds__(kBlock) k_backward(TileArgs a) {
     if (BF) { W2Tb = (const bf16x8*)((const uint16_t*)swz + o2t); W1Tb = (const bf16x8*)((const uint16_t*)swz + o1t); }
     else { W2T = (const float*)swz + o2t; W1T = (const float*)swz + o1t; }
   }
-  f32x16 dw3[NB];
+  f32x16 aw2[REG ? NB : 1][REG ? NB : 1];
+  f32x16 aw1[REG ? NB : 1][REG ? KB : 1];
+  if constexpr (REG) {
 #pragma unroll
-  for (int b = 0; b < NB; ++b)
+    for (int ib = 0; ib < NB; ++ib) {
 #pragma unroll
-    for (int r = 0; r < 16; ++r) dw3[b][r] = 0.f;
+      for (int kb = 0; kb < NB; ++kb)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) aw2[ib][kb][r] = 0.f;
+#pragma unroll
+      for (int kb = 0; kb < KB; ++kb)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) aw1[ib][kb][r] = 0.f;
+    }
+  }
   double loss = 0.0;
+  const int nblk = REG ? KB : s.KHP / 16;
 
   const int64_t ntiles = act ? (a.n + 31) / 32 : 0;
   for (int64_t tile = (int64_t)blockIdx.x * kWavesPerBlock + wave; tile < ntiles;
@@ -315,7 +377,7 @@ __global__ void __launch_bounds__(kBlock) k_backward(TileArgs a) {
     if (valid) { x = P[p]; y = P[a.ld + p]; z = P[2 * a.ld + p]; }
     f32x16 z1[NB], z2[NB];
     float m;
-    tile_fwd<C, H, GF16, BF>(s, sG, F, swz, w3s, x, y, z, valid, lane, z1, z2, m);
+    tile_fwd<C, H, GF16, BF, REG>(s, sG, F, swz, w3s, x, y, z, valid, lane, z1, z2, m, Ty);
 
     // dL/df for this point
     float df = 0.f;
@@ -334,16 +396,21 @@ __global__ void __launch_bounds__(kBlock) k_backward(TileArgs a) {
     }
     const float dm = df * vs;
 
-    // output layer: dW3 and delta2
+    // output layer: dW3 (reduced over the tile's points into this wave's row) and delta2
+    if (a.do_w3) {
+#pragma unroll
+      for (int b = 0; b < NB; ++b)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+          const float t = half_sum(dm * fmaxf(z2[b][r], 0.f));
+          if (j == 0) sW3w[wave * H + 32 * b + acc_row(r, hf)] += t;
+        }
+    }
     f32x16 d2[NB];
 #pragma unroll
     for (int b = 0; b < NB; ++b)
 #pragma unroll
-      for (int r = 0; r < 16; ++r) {
-        const float h2 = fmaxf(z2[b][r], 0.f);
-        dw3[b][r] = __builtin_fmaf(dm, h2, dw3[b][r]);
-        d2[b][r] = z2[b][r] > 0.f ? w3s[hf * (H / 2) + 16 * b + r] * dm : 0.f;
-      }
+      for (int r = 0; r < 16; ++r) d2[b][r] = z2[b][r] > 0.f ? w3s[hf * (H / 2) + 16 * b + r] * dm : 0.f;
 
     // dW2 rows [w2_lo, w2_hi) = sum_j delta2_j h1_j^T, one 32-row block of h1 at a time
     if (nrows2 > 0) {
@@ -356,14 +423,19 @@ __global__ void __launch_bounds__(kBlock) k_backward(TileArgs a) {
 #pragma unroll
         for (int r = 0; r < 16; ++r) tt_put<BF>(Tb, acc_row(r, hf), j, fmaxf(z1[kb][r], 0.f));
         wave_lds_sync();
-        for (int ib = a.w2_lo / 32; ib < a.w2_hi / 32; ++ib) {
-          f32x16 acc;
+        if constexpr (REG) {
 #pragma unroll
-          for (int r = 0; r < 16; ++r) acc[r] = 0.f;
-          acc = tt_mma<BF>(Ta, 32 * ib, Tb, 0, lane, acc);
+          for (int ib = 0; ib < NB; ++ib) aw2[ib][kb] = tt_mma<BF>(Ta, 32 * ib, Tb, 0, lane, aw2[ib][kb]);
+        } else {
+          for (int ib = a.w2_lo / 32; ib < a.w2_hi / 32; ++ib) {
+            f32x16 acc;
 #pragma unroll
-          for (int r = 0; r < 16; ++r)
-            atomicAdd(&sW2[(32 * ib + acc_row(r, hf) - a.w2_lo) * H + 32 * kb + j], acc[r]);
+            for (int r = 0; r < 16; ++r) acc[r] = 0.f;
+            acc = tt_mma<BF>(Ta, 32 * ib, Tb, 0, lane, acc);
+#pragma unroll
+            for (int r = 0; r < 16; ++r)
+              atomicAdd(&sW2[(32 * ib + acc_row(r, hf) - a.w2_lo) * H + 32 * kb + j], acc[r]);
+          }
         }
         wave_lds_sync();
       }
@@ -381,6 +453,7 @@ __global__ void __launch_bounds__(kBlock) k_backward(TileArgs a) {
         const float dv = d2[st >> 4][st & 15];
 #pragma unroll
         for (int b = 0; b < NB; ++b) d1[b] = mma_f32(W2T[((size_t)b * (H / 2) + st) * 64 + lane], dv, d1[b]);
+        if ((st & 7) == 7) sched_fence();
       }
     } else {
 #pragma unroll
@@ -405,16 +478,19 @@ __global__ void __launch_bounds__(kBlock) k_backward(TileArgs a) {
         for (int r = 0; r < 16; ++r) tt_put<BF>(Ta, 32 * b + acc_row(r, hf), j, d1[b][r]);
     }
 
-    // dL/dy per block of 16 features of each half, then the grid terms
-    const int nblk = s.KHP / 16;
+    // dL/dy per block of 16 features of each half: stored per grid for the cell pass,
+    // and (with the features regathered) the first-layer gradient
+#pragma unroll(REG ? KB : 1)
     for (int blk = 0; blk < nblk; ++blk) {
       f32x16 dy;
 #pragma unroll
       for (int r = 0; r < 16; ++r) dy[r] = 0.f;
       if constexpr (!BF) {
 #pragma unroll
-        for (int st = 0; st < H / 2; ++st)
+        for (int st = 0; st < H / 2; ++st) {
           dy = mma_f32(W1T[((size_t)blk * (H / 2) + st) * 64 + lane], d1[st >> 4][st & 15], dy);
+          if ((st & 7) == 7) sched_fence();
+        }
       } else {
 #pragma unroll
         for (int st = 0; st < H / 16; ++st) {
@@ -424,97 +500,46 @@ __global__ void __launch_bounds__(kBlock) k_backward(TileArgs a) {
           dy = mma_bf16(W1Tb[((size_t)blk * (H / 16) + st) * 64 + lane], B, dy);
         }
       }
-      // columns of this block: half h, t in [16blk, 16blk+16) -> h*KH + t
       const int lo0 = 16 * blk, lo1 = s.KH + 16 * blk;
-      const bool need_y = any_w1 && ((lo0 < a.c1_hi && lo0 + 16 > a.c1_lo) || (lo1 < a.c1_hi && lo1 + 16 > a.c1_lo));
+      const bool need_y = any_w1 && (REG || (lo0 < a.c1_hi && lo0 + 16 > a.c1_lo) ||
+                                     (lo1 < a.c1_hi && lo1 + 16 > a.c1_lo));
 #pragma unroll
       for (int u = 0; u < 16 / C; ++u) {
         const int gi = 16 * blk / C + u;
         const int g = hf * s.Mh + gi;
-        const bool gvalid = gi < s.Mh && g < s.M;
-        float yv[C], dl[3] = {0.f, 0.f, 0.f};
+        const bool gvalid = gi < s.Mh && g < s.M && valid;
+        if (dY && gvalid) {
+          float* dst = dY + ((size_t)g * a.n + p) * C;
 #pragma unroll
-        for (int c = 0; c < C; ++c) yv[c] = 0.f;
-        if (gvalid && valid) {
-          float l[3];
-          local_coords(sG + 12 * g, x, y, z, l);
-          int i0[3];
-          float w[3];
-          if (cell_of(l, hR, s.R, i0, w)) {
-            float dyc[C];
-#pragma unroll
-            for (int c = 0; c < C; ++c) dyc[c] = dy[u * C + c];
-            if (dF) {
-              const size_t RC = (size_t)s.R * C, RRC = RC * s.R;
-              const size_t base = (((size_t)g * s.R + i0[2]) * s.R + i0[1]) * RC + (size_t)i0[0] * C;
-#pragma unroll
-              for (int q = 0; q < 8; ++q) {
-                const float wq = ((q & 1) ? w[0] : 1.f - w[0]) * ((q & 2) ? w[1] : 1.f - w[1]) *
-                                 ((q & 4) ? w[2] : 1.f - w[2]);
-                float* dst = dF + base + (q & 1) * C + ((q >> 1) & 1) * RC + (q >> 2) * RRC;
-#pragma unroll
-                for (int c = 0; c < C; ++c) atomicAdd(dst + c, wq * dyc[c]);
-              }
-            }
-            if (need_y || a.want_dG) {
-              float val[8][C];
-              gather_cell<C, GF16>(F, g, s.R, i0, val);
-              if (need_y) trilerp<C>(val, w, yv);
-              if (a.want_dG) {
-#pragma unroll
-                for (int c = 0; c < C; ++c) {
-                  const float ax00 = val[1][c] - val[0][c], ax10 = val[3][c] - val[2][c];
-                  const float ax01 = val[5][c] - val[4][c], ax11 = val[7][c] - val[6][c];
-                  const float gx = (1.f - w[2]) * ((1.f - w[1]) * ax00 + w[1] * ax10) +
-                                   w[2] * ((1.f - w[1]) * ax01 + w[1] * ax11);
-                  const float x00 = __builtin_fmaf(w[0], ax00, val[0][c]);
-                  const float x10 = __builtin_fmaf(w[0], ax10, val[2][c]);
-                  const float x01 = __builtin_fmaf(w[0], ax01, val[4][c]);
-                  const float x11 = __builtin_fmaf(w[0], ax11, val[6][c]);
-                  const float gy = (1.f - w[2]) * (x10 - x00) + w[2] * (x11 - x01);
-                  const float y0 = __builtin_fmaf(w[1], x10 - x00, x00);
-                  const float y1 = __builtin_fmaf(w[1], x11 - x01, x01);
-                  const float gz = y1 - y0;
-                  dl[0] = __builtin_fmaf(dyc[c], gx, dl[0]);
-                  dl[1] = __builtin_fmaf(dyc[c], gy, dl[1]);
-                  dl[2] = __builtin_fmaf(dyc[c], gz, dl[2]);
-                }
-#pragma unroll
-                for (int d = 0; d < 3; ++d) dl[d] *= hR;
-              }
-            }
-          }
+          for (int c = 0; c < C; ++c) dst[c] = dy[u * C + c];
         }
-        if (a.want_dG && gi < s.Mh) {
-          const float xs[4] = {x, y, z, 1.f};
-#pragma unroll
-          for (int r = 0; r < 3; ++r)
-#pragma unroll
-            for (int k = 0; k < 4; ++k) {
-              const float sum = half_sum(dl[r] * xs[k]);
-              if (j == 0 && g < s.M) atomicAdd(&sdG[12 * g + 4 * r + k], (double)sum);
-            }
-        }
-        if (need_y) {
+        if (!REG && need_y) {
+          float yv[C];
+          encode_grid<C, GF16>(s, sG, F, gvalid ? g : s.M, x, y, z, valid, hR, yv);
 #pragma unroll
           for (int c = 0; c < C; ++c) tt_put<BF>(Tb, 16 * hf + u * C + c, j, yv[c]);
         }
       }
       if (need_y) {
         wave_lds_sync();
+        if constexpr (REG) {
 #pragma unroll
-        for (int ib = 0; ib < NB; ++ib) {
-          f32x16 acc;
+          for (int ib = 0; ib < NB; ++ib)
+            aw1[ib][blk] = tt_mma<BF>(Ta, 32 * ib, Ty + (size_t)32 * blk * LDT, 0, lane, aw1[ib][blk]);
+        } else {
 #pragma unroll
-          for (int r = 0; r < 16; ++r) acc[r] = 0.f;
-          acc = tt_mma<BF>(Ta, 32 * ib, Tb, 0, lane, acc);
-          // column j of the block: half j/16, t = 16 blk + j%16
-          const int col = (j >> 4) * s.KH + 16 * blk + (j & 15);
-          const bool ok = (16 * blk + (j & 15)) < s.KH && col < s.MC && col >= a.c1_lo && col < a.c1_hi;
-          if (ok) {
+          for (int ib = 0; ib < NB; ++ib) {
+            f32x16 acc;
 #pragma unroll
-            for (int r = 0; r < 16; ++r)
-              atomicAdd(&sW1[(32 * ib + acc_row(r, hf)) * ncols + (col - a.c1_lo)], acc[r]);
+            for (int r = 0; r < 16; ++r) acc[r] = 0.f;
+            acc = tt_mma<BF>(Ta, 32 * ib, Tb, 0, lane, acc);
+            const int col = (j >> 4) * s.KH + 16 * blk + (j & 15);
+            const bool ok = (16 * blk + (j & 15)) < s.KH && col < s.MC && col >= a.c1_lo && col < a.c1_hi;
+            if (ok) {
+#pragma unroll
+              for (int r = 0; r < 16; ++r)
+                atomicAdd(&sW1[(32 * ib + acc_row(r, hf)) * ncols + (col - a.c1_lo)], acc[r]);
+            }
           }
         }
         wave_lds_sync();
@@ -522,62 +547,98 @@ __global__ void __launch_bounds__(kBlock) k_backward(TileArgs a) {
     }
   }
 
-  // block-level reductions
-  if (a.do_w3) {
+  // block-level reductions, waves added in a fixed order (bitwise reproducible)
+  if constexpr (REG) {
+    __syncthreads();  // the tiles are dead: reuse them for the cross-wave sums
+    for (int i = threadIdx.x; i < H * ncols + nrows2 * H; i += blockDim.x) sW1[i] = 0.f;
+    for (int w = 0; w < kWavesPerBlock; ++w) {
+      __syncthreads();
+      if (wave != w) continue;
 #pragma unroll
-    for (int b = 0; b < NB; ++b)
+      for (int ib = 0; ib < NB; ++ib) {
 #pragma unroll
-      for (int r = 0; r < 16; ++r) {
-        const float sum = half_sum(dw3[b][r]);
-        if (j == 0) atomicAdd(&sW3[32 * b + acc_row(r, hf)], sum);
+        for (int kb = 0; kb < NB; ++kb)
+#pragma unroll
+          for (int r = 0; r < 16; ++r) sW2[(32 * ib + acc_row(r, hf)) * H + 32 * kb + j] += aw2[ib][kb][r];
+#pragma unroll
+        for (int blk = 0; blk < KB; ++blk) {
+          const int col = (j >> 4) * s.KH + 16 * blk + (j & 15);
+          if ((16 * blk + (j & 15)) < s.KH && col < s.MC) {
+#pragma unroll
+            for (int r = 0; r < 16; ++r) sW1[(32 * ib + acc_row(r, hf)) * ncols + col] += aw1[ib][blk][r];
+          }
+        }
       }
+    }
   }
+
   if (a.want_loss) {
     const double t = wave_sum(loss);
-    if (lane == 0) atomicAdd(sLoss, t);
+    if (lane == 0) sLoss[wave] = t;
   }
   __syncthreads();
   for (int i = threadIdx.x; i < H * ncols; i += blockDim.x) part[pl.o_w1 + i] = sW1[i];
   for (int i = threadIdx.x; i < nrows2 * H; i += blockDim.x) part[pl.o_w2 + i] = sW2[i];
   if (a.do_w3)
-    for (int i = threadIdx.x; i < H; i += blockDim.x) part[pl.o_w3 + i] = sW3[i];
-  if (a.want_dG)
-    for (int i = threadIdx.x; i < 12 * s.M; i += blockDim.x) part[pl.o_g + i] = sdG[i];
-  if (threadIdx.x == 0) part[pl.o_loss] = *sLoss;
+    for (int i = threadIdx.x; i < H; i += blockDim.x)
+      part[pl.o_w3 + i] = (double)sW3w[i] + (double)sW3w[H + i] + (double)sW3w[2 * H + i] + (double)sW3w[3 * H + i];
+  if (threadIdx.x == 0) part[pl.o_loss] = a.want_loss ? ((sLoss[0] + sLoss[1]) + sLoss[2]) + sLoss[3] : 0.0;
 }
 
 // ------------------------------------------------------------------ instantiation
+constexpr size_t kFwdWeightLdsMax = 120 * 1024;
+
 template <int C, int H, bool GF16, bool BF>
-hipError_t launch_tile_kernels(bool backward, const TileArgs& a, dim3 grid, size_t shmem,
+hipError_t launch_tile_kernels(bool backward, int kb, const TileArgs& a, dim3 grid, size_t shmem,
                                hipStream_t st) {
-  if (backward) {
-    hipLaunchKernelGGL((k_backward<C, H, GF16, BF>), grid, dim3(kBlock), shmem, st, a);
+  if (!backward) {
+    if (fwd_weight_bytes(a.s, BF) <= kFwdWeightLdsMax)
+      hipLaunchKernelGGL((k_forward<C, H, GF16, BF, true>), grid, dim3(kBlock), shmem, st, a);
+    else
+      hipLaunchKernelGGL((k_forward<C, H, GF16, BF, false>), grid, dim3(kBlock), shmem, st, a);
+  } else if constexpr (H == 64) {
+    if (kb == 1) hipLaunchKernelGGL((k_backward<C, H, GF16, BF, 1>), grid, dim3(kBlock), shmem, st, a);
+    else if (kb == 2) hipLaunchKernelGGL((k_backward<C, H, GF16, BF, 2>), grid, dim3(kBlock), shmem, st, a);
+    else hipLaunchKernelGGL((k_backward<C, H, GF16, BF, 0>), grid, dim3(kBlock), shmem, st, a);
   } else {
-    hipLaunchKernelGGL((k_forward<C, H, GF16, BF>), grid, dim3(kBlock), shmem, st, a);
+    hipLaunchKernelGGL((k_backward<C, H, GF16, BF, 0>), grid, dim3(kBlock), shmem, st, a);
   }
   return hipGetLastError();
 }
 
-size_t backward_lds_bytes(const Shape& s, int ncols, int nrows2, bool bf) {
+// Register-accumulated adjoint applies when H = 64 and at most 2 dy blocks per half.
+int register_kb(const Shape& s) { return (s.H == 64 && s.KHP <= 32) ? s.KHP / 16 : 0; }
+
+size_t backward_lds_bytes(const Shape& s, int ncols, int nrows2, bool bf, int kb) {
   const int ldt = bf ? 40 : 33;
   const size_t esz = bf ? 2 : 4;
-  size_t b = (size_t)(12 * s.M + s.H * ncols + nrows2 * s.H + s.H) * 4;
+  size_t b = (size_t)(12 * s.M + kWavesPerBlock * s.H) * 4;
   b = (b + 7) & ~(size_t)7;
-  b += (size_t)(12 * s.M + 1) * 8;
+  b += 8 * kWavesPerBlock;
   b = (b + 15) & ~(size_t)15;
-  b += (size_t)kWavesPerBlock * (s.H + 32) * ldt * esz;
+  if (kb) b += swz_sizes(s).total() * esz;
+  const size_t tiles = (size_t)kWavesPerBlock * (s.H + 32 + 32 * kb) * ldt * esz;
+  const size_t red = (size_t)(s.H * ncols + nrows2 * s.H) * 4;
+  b += kb ? std::max(tiles, red) : tiles + red;
   return b;
 }
 
-hipError_t launch_tile(bool backward, const TileArgs& a, bool grid_f16, bool mlp_bf16, dim3 grid,
+size_t forward_lds_bytes(const Shape& s, bool bf) {
+  size_t b = (size_t)12 * s.M * 4;
+  b = (b + 15) & ~(size_t)15;
+  if (fwd_weight_bytes(s, bf) <= kFwdWeightLdsMax) b += fwd_weight_bytes(s, bf);
+  return b;
+}
+
+hipError_t launch_tile(bool backward, int kb, const TileArgs& a, bool grid_f16, bool mlp_bf16, dim3 grid,
                        size_t shmem, hipStream_t st) {
   const int C = a.s.C, H = a.s.H;
 #define APMG_DISPATCH(CC, HH)                                                                  \
   if (C == CC && H == HH) {                                                                    \
-    if (!grid_f16 && !mlp_bf16) return launch_tile_kernels<CC, HH, false, false>(backward, a, grid, shmem, st); \
-    if (!grid_f16 && mlp_bf16) return launch_tile_kernels<CC, HH, false, true>(backward, a, grid, shmem, st);   \
-    if (grid_f16 && !mlp_bf16) return launch_tile_kernels<CC, HH, true, false>(backward, a, grid, shmem, st);   \
-    return launch_tile_kernels<CC, HH, true, true>(backward, a, grid, shmem, st);              \
+    if (!grid_f16 && !mlp_bf16) return launch_tile_kernels<CC, HH, false, false>(backward, kb, a, grid, shmem, st); \
+    if (!grid_f16 && mlp_bf16) return launch_tile_kernels<CC, HH, false, true>(backward, kb, a, grid, shmem, st);   \
+    if (grid_f16 && !mlp_bf16) return launch_tile_kernels<CC, HH, true, false>(backward, kb, a, grid, shmem, st);   \
+    return launch_tile_kernels<CC, HH, true, true>(backward, kb, a, grid, shmem, st);              \
   }
   APMG_DISPATCH(1, 64)
   APMG_DISPATCH(2, 64)

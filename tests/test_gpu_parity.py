@@ -307,3 +307,121 @@ def test_batched_step_matches_oracle(nb_shape):
         print(f"mG[{b}] rel err {a:.2e}")
         assert a < 1e-3
     assert int(tr.step_ctr.item()) == 1 and int(tr.t[0].item()) == 1 and int(tr.tG[0].item()) == 1
+
+
+# --------------------------------------------------------------------------- graphs, determinism
+def _trainer(A_, vol, nb=2, n=3000, mlp=None):
+    nz, ny, nx = vol.shape
+    _, bricks = A_.apmg_make_bricks(nx, ny, nz, 24, 1)
+    bricks = bricks[:nb]
+    hosts = [host_model(8, 2, 8, 64, seed=20 + b, grid_range=0.2, vmin=0.0, vmax=1.0) for b in range(nb)]
+    tr = A_.Trainer(hosts, vol, bricks, n, seed=3, mlp_dtype=A_.F32 if mlp is None else mlp)
+    tr.density_active.fill_(1)
+    return tr
+
+
+def _state(tr):
+    return [t.clone() for t in (tr.G, tr.F, tr.W, tr.mG, tr.vG, tr.mF, tr.vF, tr.mW, tr.vW, tr.losses)]
+
+
+def test_training_step_is_bitwise_deterministic():
+    vol = synth.make_volume("blobs_turb", (40, 48, 44)).to(DEV)
+    a, b = _trainer(A(), vol), _trainer(A(), vol)
+    for _ in range(3):
+        a.step()
+        b.step()
+    torch.cuda.synchronize()
+    for x, y in zip(_state(a), _state(b)):
+        assert torch.equal(x, y)
+
+
+def test_graph_replay_matches_eager_steps():
+    # the step records no memset, so it can be captured; replays advance the device step
+    # counter, and every replay must equal the corresponding eager step
+    vol = synth.make_volume("blobs_turb", (40, 48, 44)).to(DEV)
+    eager, graphed = _trainer(A(), vol), _trainer(A(), vol)
+    eager.step()
+    graphed.step()                    # warm-up outside the capture (same first step)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        with torch.cuda.graph(g, stream=s):
+            graphed.step()
+    torch.cuda.synchronize()
+    # capture does not execute: replay now performs step 2, then 3, 4
+    for k in range(3):
+        g.replay()
+        eager.step()
+        torch.cuda.synchronize()
+        _ = (eager.W * 2).sum().item()  # unrelated eager work between replays
+        for x, y in zip(_state(eager), _state(graphed)):
+            assert torch.equal(x, y), k
+    assert int(graphed.step_ctr.item()) == 4
+
+
+# --------------------------------------------------------------------------- large model (render workload shape)
+def test_forward_wide_fp32_weights_outside_lds():
+    # 256 input features, 128 hidden, fp32: the operands exceed the LDS budget and are read
+    # from global memory
+    host = host_model(64, 4, 9, 128, grid_range=0.3)
+    x = make_points(3000)
+    got = A().apmg_forward(A().Model.from_host(host, DEV), soa(x)).cpu().numpy()
+    want, _ = O.forward(f64(host), x.astype(np.float64))
+    assert_close("forward 64x4 fp32", got, want)
+
+
+def test_render_model_bf16_forward_sampled():
+    # 64 grids at 64^3 x 4 features, MLP 256-128-128-1 in bf16; render-style points
+    host = synth.init_model(64, 4, 64, [256, 128, 128, 1], seed=5, grid_range=1.0, extra_translation=0.3)
+    pts = synth.ray_points(160, 90, 8)
+    model = A().Model.from_host(host, DEV, mlp_dtype=A().BF16)
+    got = A().apmg_forward(model, soa(pts)).cpu().numpy()
+    idx = np.random.default_rng(0).choice(pts.shape[0], 2048, replace=False)
+    want, _ = O.forward(f64(host), pts[idx].astype(np.float64))
+    a, b = errs(got[idx], want)
+    print(f"render bf16 forward: normwise {a:.2e} max {b:.2e}")
+    assert a < 3e-2
+
+
+def _fd_check(model, pts, wts, dirs, h, tol, name):
+    dF, dG, dW = A().apmg_backward(model, pts, wts)
+    pred = float((dG.float() * dirs["G"]).sum() + (dF * dirs["F"]).sum()
+                 + sum((g * d).sum() for g, d in zip(dW, dirs["W"])))
+
+    def L(t):
+        m2 = A().Model(model.G + t * dirs["G"], model.F + t * dirs["F"],
+                       [w + t * d for w, d in zip(model.W, dirs["W"])], model.vmin, model.vmax)
+        return float((A().apmg_forward(m2, pts).double() * wts.double()).sum())
+
+    fd = (L(h) - L(-h)) / (2 * h)
+    rel = abs(fd - pred) / abs(pred)
+    print(f"{name}: adjoint {pred:.6e} central difference {fd:.6e} rel {rel:.2e}")
+    assert rel < tol
+
+
+def test_adjoint_finite_difference_random_direction_2e20():
+    # <grad L, d> from the adjoint vs central differences of the GPU forward along a random
+    # direction d, L = sum_n w_n f(x_n) over 2^20 points.  f is continuous and piecewise linear
+    # in F and W; in G it jumps where a point crosses a cube face (Eq. (2)), which the adjoint
+    # (an almost-everywhere derivative) does not see, so the transform direction is checked
+    # on grids that contain the whole domain.
+    n = 1 << 20
+    pts = A().apmg_uniform_points(17, 0, 0, 0, n, DEV)
+    wts = torch.randn(n, device=DEV, generator=torch.Generator(device=DEV).manual_seed(2)) / n
+    gen = torch.Generator(device="cpu").manual_seed(1)
+    host = synth.init_model(32, 2, 32, [64, 64, 64, 1], seed=9, grid_range=0.3)
+    model = A().Model.from_host(host, DEV)
+    dirs = {"G": torch.zeros(model.G.shape, device=DEV),
+            "F": torch.randn(model.F.shape, generator=gen).to(DEV),
+            "W": [torch.randn(w.shape, generator=gen).to(DEV) for w in model.W]}
+    _fd_check(model, pts, wts, dirs, 1e-3, 1e-3, "F and W")
+    # transforms: scale 0.75 keeps every point of [-1,1]^3 inside every grid
+    host["G"][:, :, :3] *= 0.75
+    host["G"][:, :, 3] *= 0.3
+    model = A().Model.from_host(host, DEV)
+    dirs = {"G": torch.randn(model.G.shape, generator=gen).to(DEV),
+            "F": torch.zeros(model.F.shape, device=DEV),
+            "W": [torch.zeros(w.shape, device=DEV) for w in model.W]}
+    _fd_check(model, pts, wts, dirs, 1e-4, 2e-3, "G")
