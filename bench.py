@@ -102,6 +102,74 @@ def time_forward(A, torch, host, n, reps=10):
     return n * reps / (time.perf_counter() - t0)
 
 
+def _time_trainer(torch, tr, steps, warmup):
+    for _ in range(warmup):
+        tr.step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        tr.step()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / steps
+
+
+def extra_c1(A, torch, synth, hl):
+    """64^3 blobs+sine volume, 16 grids at 16^3 x 2, MLP 32-64-64-1, 65,536 points, fp32."""
+    vol = synth.make_volume("blobs_sine", (64, 64, 64), device="cuda")
+    _, bricks = A.apmg_make_bricks(64, 64, 64, 64, 0)
+    host = synth.init_model(16, 2, 16, [32, 64, 64, 1], seed=synth.SEED_MODEL)
+    tr = A.Trainer([host], vol, bricks, 65536, seed=synth.SEED_POINTS)
+    tr.density_active.fill_(1)
+    dt = _time_trainer(torch, tr, 20, 5)
+    return {"train_pts_per_s": 65536 / dt, "ms_per_step": dt * 1e3}
+
+
+def extra_c3(A, torch, synth, hl):
+    """1024^3 volume, the 32-grid model with bf16 MLP and fp16 grids, 2^21 points."""
+    vol = synth.make_volume("blobs_turb", (1024, 1024, 1024), device="cuda")
+    _, bricks = A.apmg_make_bricks(1024, 1024, 1024, 1024, 0)
+    host = synth.init_model(M, C, R, [M * C, H, H, 1], seed=synth.SEED_MODEL)
+    n = 1 << 21
+    tr = A.Trainer([host], vol, bricks, n, seed=synth.SEED_POINTS, mlp_dtype=A.BF16, grid_dtype=torch.float16)
+    tr.density_active.fill_(1)
+    dt = _time_trainer(torch, tr, 10, 3)
+    return {"train_pts_per_s": n / dt, "ms_per_step": dt * 1e3, "mlp": "bf16", "grids": "fp16 (fp32 master)"}
+
+
+def extra_c4(A, torch, synth, hl):
+    """1000x1200x900 volume in 256^3 bricks with one ghost voxel (80 bricks), 16 grids at
+    32^3 x 2 per brick, MLP 32-64-64-1 in bf16, 2^17 points per brick; all bricks per step."""
+    vol = synth.make_volume("blobs_turb", (900, 1200, 1000), device="cuda")
+    _, bricks = A.apmg_make_bricks(1000, 1200, 900, 256, 1)
+    hosts = [synth.init_model(16, 2, 32, [32, 64, 64, 1], seed=synth.SEED_MODEL + b) for b in range(len(bricks))]
+    n = 1 << 17
+    tr = A.Trainer(hosts, vol, bricks, n, seed=synth.SEED_POINTS, mlp_dtype=A.BF16)
+    tr.density_active.fill_(1)
+    dt = _time_trainer(torch, tr, 5, 2)
+    return {"bricks": len(bricks), "train_pts_per_s": len(bricks) * n / dt, "ms_per_step": dt * 1e3}
+
+
+def extra_c5(A, torch, synth, hl):
+    """64 grids at 64^3 x 4 features, MLP 256-128-128-1 in bf16, a 1920x1080 ray layout
+    with 8 samples per ray (16,588,800 points), forward only."""
+    host = synth.init_model(64, 4, 64, [256, 128, 128, 1], seed=5, grid_range=1.0, extra_translation=0.3)
+    model = A.Model.from_host(host, "cuda", mlp_dtype=A.BF16)
+    pts = torch.from_numpy(synth.ray_points().T.copy()).cuda()
+    n = pts.shape[1]
+    ws = torch.empty(A._lib.apmg_workspace_bytes(A.OP_FORWARD, ctypes.byref(model.struct()), n),
+                     dtype=torch.uint8, device="cuda")
+    out = torch.empty(n, device="cuda")
+    A.apmg_forward(model, pts, out=out, ws=ws)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    reps = 3
+    for _ in range(reps):
+        A.apmg_forward(model, pts, out=out, ws=ws)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / reps
+    return {"infer_pts_per_s": n / dt, "ms_per_frame": dt * 1e3, "points": n}
+
+
 def cpu_baseline(vol_np, host, n_sample):
     """The FP64 oracle's training step on a bounded sample of the same workload."""
     import numpy as np
@@ -131,6 +199,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=1 << 16)
     ap.add_argument("--skip-extra", action="store_true")
+    ap.add_argument("--configs", default="config1,config3,config4,config5",
+                    help="extra workloads to time after the headline")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (the path is one GPU's "
@@ -173,8 +243,17 @@ def main():
         dtb, kb = time_steps(A, torch, trb, args.steps, args.warmup, hl)
         extra["train_pts_per_s_bf16_mlp"] = N * args.steps / dtb
         extra["bf16_kernel_ms"] = kb
-        out["extra"] = extra
         del trb
+        torch.cuda.empty_cache()
+        for name, fn in (("config1_tiny_fp32", extra_c1), ("config3_mixed_1024", extra_c3),
+                         ("config4_bricks", extra_c4), ("config5_render_bf16", extra_c5)):
+            if name.split("_")[0] in args.configs:
+                try:
+                    extra[name] = fn(A, torch, synth, hl)
+                except Exception as e:  # an extra figure never hides the headline line
+                    extra[name] = {"error": repr(e)[:200]}
+                torch.cuda.empty_cache()
+        out["extra"] = extra
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(vol.cpu().numpy().astype("float64"), host, args.cpu_sample)
     print(json.dumps(out), flush=True)

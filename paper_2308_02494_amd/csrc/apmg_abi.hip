@@ -59,6 +59,10 @@ apmg_status check_points(const float* pts, int64_t ld, int64_t n) {
 
 apmg_status hip_status(hipError_t e) { return e == hipSuccess ? APMG_OK : APMG_EHIP; }
 
+inline unsigned red_blocks(int64_t count) {
+  return (unsigned)std::max<int64_t>(1, std::min<int64_t>((count + 31) / 32, 2048));
+}
+
 inline unsigned grid1(int64_t n, int64_t cap = 4096) {
   int64_t g = (n + 255) / 256;
   if (g < 1) g = 1;
@@ -203,24 +207,23 @@ size_t bwd_ws(const Shape& s, bool bf, int64_t n, void* ws, BwdWs* o) {
   return cv.off;
 }
 
-struct DenWs { float* rho; double *pa, *sums, *pb1, *lq, *pb2, *U; };
+int dens_blocks(int64_t n) { return (int)std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, kDensBlocks)); }
+int dens_chunks(int64_t n) { return (int)std::max<int64_t>(1, (n + kDensChunk - 1) / kDensChunk); }
+
+struct DenWs { float *rho, *coef; double *pa, *sums, *pb1, *lq, *pb2, *U; };
 size_t den_ws(const Shape& s, int64_t n, int nb, void* ws, DenWs* o) {
   Carver cv(ws);
   DenWs d;
   d.rho = cv.take<float>((size_t)nb * std::max<int64_t>(n, 1));
+  d.coef = cv.take<float>((size_t)nb * std::max<int64_t>(n, 1));
   d.pa = cv.take<double>((size_t)nb * kDensBlocks * 2);
   d.sums = cv.take<double>((size_t)nb * 2);
   d.pb1 = cv.take<double>((size_t)nb * kDensBlocks * 2);
   d.lq = cv.take<double>((size_t)nb * 2);
-  d.pb2 = cv.take<double>((size_t)nb * kDensBlocks * 13 * s.M);
+  d.pb2 = cv.take<double>((size_t)nb * dens_chunks(n) * 13 * s.M);
   d.U = cv.take<double>((size_t)nb * 13 * s.M);
   if (o) *o = d;
   return cv.off;
-}
-
-int dens_blocks(int64_t n) { return (int)std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, kDensBlocks)); }
-int dens_b2_blocks(int64_t n) {
-  return (int)std::max<int64_t>(1, std::min<int64_t>((n + 256 * 8 - 1) / (256 * 8), kDensBlocks));
 }
 
 // Density loss launch sequence for nb models sharing one shape.  pts/err/rho are per
@@ -231,20 +234,21 @@ hipError_t launch_density(const Shape& s, const float* G, size_t G_stride, const
                           float* rho_user, const DenWs& w, int nb, const int32_t* active, hipStream_t st) {
   float* rho = rho_user ? rho_user : w.rho;
   const size_t rho_stride = rho_user ? (size_t)n : (size_t)std::max<int64_t>(n, 1);
-  const int ba = dens_blocks(n), bb = dens_b2_blocks(n);
+  const int ba = dens_blocks(n), nch = dens_chunks(n);
   const size_t shA = 64 + (size_t)13 * s.M * 4;
   hipLaunchKernelGGL(k_density_a, dim3(ba, nb), dim3(256), shA, st, s, G, G_stride, pts, ld, pts_stride, n,
                      err, err_stride, p, rho, rho_stride, w.pa, active);
-  hipLaunchKernelGGL(k_density_sums, dim3((nb + 63) / 64), dim3(64), 0, st, w.pa, ba, w.sums, nb);
+  hipLaunchKernelGGL(k_density_sums, dim3(nb), dim3(256), 0, st, w.pa, ba, w.sums, nb);
   hipLaunchKernelGGL(k_density_b1, dim3(ba, nb), dim3(256), 0, st, rho, rho_stride, err, err_stride, n,
                      w.sums, eps, w.pb1, active);
-  hipLaunchKernelGGL(k_density_lq, dim3((nb + 63) / 64), dim3(64), 0, st, w.pb1, ba, n, w.lq, nb);
+  hipLaunchKernelGGL(k_density_lq, dim3(nb), dim3(256), 0, st, w.pb1, ba, n, w.lq, nb);
   if (dG) {
-    const size_t shB = (size_t)4 * 13 * s.M * 8 + (size_t)12 * s.M * 4;
-    hipLaunchKernelGGL(k_density_b2, dim3(bb, nb), dim3(256), shB, st, s, G, G_stride, pts, ld, pts_stride,
-                       n, rho, rho_stride, err, err_stride, w.sums, w.lq, eps, p, w.pb2, active);
-    hipLaunchKernelGGL(k_reduce_parts, dim3(grid1(13 * s.M, 64), nb), dim3(256), 0, st, w.pb2, bb,
-                       13 * s.M, 0, 13 * s.M, 13 * s.M, 0, 0, (float*)nullptr, w.U, (size_t)13 * s.M, 0,
+    const size_t cstride = (size_t)std::max<int64_t>(n, 1);
+    hipLaunchKernelGGL(k_density_coef, dim3(grid1(n, 2048), nb), dim3(256), 0, st, rho, rho_stride, err, err_stride, n,
+                       w.sums, w.lq, eps, w.coef, cstride, active);
+    hipLaunchKernelGGL(k_density_b2, dim3(nch, (s.M + 3) / 4, nb), dim3(256), 0, st, s, G, G_stride, pts, ld,
+                       pts_stride, n, w.coef, cstride, p, w.pb2, active);
+    hipLaunchKernelGGL(k_density_b2_reduce, dim3(grid1(13 * s.M, 64), nb), dim3(256), 0, st, w.pb2, s.M, nch, w.U,
                        active);
     hipLaunchKernelGGL(k_density_grad, dim3(1, nb), dim3(64), 0, st, s, G, G_stride, w.U, p, dG, dG_stride,
                        accumulate, w.sums, active);
@@ -439,11 +443,11 @@ apmg_status apmg_backward(const apmg_model* m, const float* pts, int64_t ld, int
     if (e != hipSuccess) return APMG_EHIP;
     if (&ps == &passes.back()) prof_end(st);
     if (ncols > 0)
-      hipLaunchKernelGGL(k_reduce_parts, dim3(grid1((int64_t)s.H * ncols, 256), 1), dim3(256), 0, st, w.part,
+      hipLaunchKernelGGL(k_reduce_parts, dim3(red_blocks((int64_t)s.H * ncols), 1), dim3(256), 0, st, w.part,
                          nblk, pl.len, pl.o_w1, s.H * ncols, ncols, s.MC, ps.c1_lo, dW[0], (double*)nullptr,
                          (size_t)0, 1, (const int32_t*)nullptr);
     if (nrows > 0)
-      hipLaunchKernelGGL(k_reduce_parts, dim3(grid1((int64_t)s.H * nrows, 256), 1), dim3(256), 0, st, w.part, nblk,
+      hipLaunchKernelGGL(k_reduce_parts, dim3(red_blocks((int64_t)s.H * nrows), 1), dim3(256), 0, st, w.part, nblk,
                          pl.len, pl.o_w2, s.H * nrows, s.H * nrows, 0, ps.w2_lo * s.H, dW[1], (double*)nullptr,
                          (size_t)0, 1, (const int32_t*)nullptr);
     if (a.do_w3)
@@ -641,17 +645,17 @@ extern "C" apmg_status apmg_batched_step(const apmg_batch* b, void* ws, size_t w
     if (e != hipSuccess) return APMG_EHIP;
     if (pi + 1 == passes.size()) prof_end(st);
     if (ncols > 0)
-      hipLaunchKernelGGL(k_reduce_parts, dim3(grid1((int64_t)s.H * ncols, 256), nb), dim3(256), 0, st, w.part, nblk,
+      hipLaunchKernelGGL(k_reduce_parts, dim3(red_blocks((int64_t)s.H * ncols), nb), dim3(256), 0, st, w.part, nblk,
                          pl.len, pl.o_w1, s.H * ncols, ncols, s.MC, ps.c1_lo, w.dW, (double*)nullptr, nW, 0,
                          (const int32_t*)nullptr);
     if (nrows > 0)
-      hipLaunchKernelGGL(k_reduce_parts, dim3(grid1((int64_t)s.H * nrows, 256), nb), dim3(256), 0, st, w.part, nblk,
+      hipLaunchKernelGGL(k_reduce_parts, dim3(red_blocks((int64_t)s.H * nrows), nb), dim3(256), 0, st, w.part, nblk,
                          pl.len, pl.o_w2, s.H * nrows, s.H * nrows, 0, s.H * s.MC + ps.w2_lo * s.H, w.dW,
                          (double*)nullptr, nW, 0, (const int32_t*)nullptr);
     if (ps.first) {
       hipLaunchKernelGGL(k_reduce_parts, dim3(1, nb), dim3(256), 0, st, w.part, nblk, pl.len, pl.o_w3, s.H, s.H, 0,
                          s.H * s.MC + s.H * s.H, w.dW, (double*)nullptr, nW, 0, (const int32_t*)nullptr);
-      hipLaunchKernelGGL(k_reduce_parts, dim3(1, nb), dim3(64), 0, st, w.part, nblk, pl.len, pl.o_loss, 1, 1, 0, 0,
+      hipLaunchKernelGGL(k_reduce_parts, dim3(1, nb), dim3(256), 0, st, w.part, nblk, pl.len, pl.o_loss, 1, 1, 0, 0,
                          (float*)nullptr, w.lrec, (size_t)1, 0, (const int32_t*)nullptr);
     }
   }

@@ -12,21 +12,38 @@ __global__ void k_fill_f64(double* p, size_t n, double v) {
   for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) p[i] = v;
 }
 
-// out[model][e] (+)= sum_b part[(model*nblk + b)*len + off + e] for e < count, summed
-// in block order in float64.  Writes float (outf) or double (outd).
+// out[model][e] (+)= sum_b part[(model*nblk + b)*len + off + e] for e < count, in float64.
 // Element e lands at (e / cols) * ld_out + col0 + e % cols of the model's output.
-__global__ void k_reduce_parts(const double* part, int nblk, int len, int off, int count,
-                               int cols, int ld_out, int col0, float* outf, double* outd,
-                               size_t out_stride, int accumulate, const int32_t* active) {
+// A block handles 32 elements; its 8 thread groups sum 8 contiguous ranges of b, which are
+// then added in range order (a fixed order: bitwise reproducible).
+constexpr int kRedElems = 32, kRedSplit = 8;
+__global__ void __launch_bounds__(256) k_reduce_parts(const double* part, int nblk, int len, int off, int count,
+                                                      int cols, int ld_out, int col0, float* outf, double* outd,
+                                                      size_t out_stride, int accumulate, const int32_t* active) {
+  __shared__ double sp[kRedSplit][kRedElems];
   const int model = blockIdx.y;
   if (active && !active[model]) return;
-  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < count; e += gridDim.x * blockDim.x) {
-    const double* p = part + (size_t)model * nblk * len + off + e;
+  const int el = threadIdx.x % kRedElems, sp_i = threadIdx.x / kRedElems;
+  const int per = (nblk + kRedSplit - 1) / kRedSplit;
+  const int b0 = sp_i * per, b1 = min(nblk, b0 + per);
+  for (int base = blockIdx.x * kRedElems; base < count; base += gridDim.x * kRedElems) {
+    const int e = base + el;
     double s = 0.0;
-    for (int b = 0; b < nblk; ++b) s += p[(size_t)b * len];
-    const size_t oi = model * out_stride + (size_t)(e / cols) * ld_out + col0 + e % cols;
-    if (outf) outf[oi] = accumulate ? outf[oi] + (float)s : (float)s;
-    else outd[oi] = accumulate ? outd[oi] + s : s;
+    if (e < count) {
+      const double* p = part + (size_t)model * nblk * len + off + e;
+#pragma unroll 8
+      for (int b = b0; b < b1; ++b) s += p[(size_t)b * len];
+    }
+    sp[sp_i][el] = s;
+    __syncthreads();
+    if (sp_i == 0 && e < count) {
+      double t = sp[0][el];
+      for (int k = 1; k < kRedSplit; ++k) t += sp[k][el];
+      const size_t oi = model * out_stride + (size_t)(e / cols) * ld_out + col0 + e % cols;
+      if (outf) outf[oi] = accumulate ? outf[oi] + (float)t : (float)t;
+      else outd[oi] = accumulate ? outd[oi] + t : t;
+    }
+    __syncthreads();
   }
 }
 
@@ -222,14 +239,32 @@ __global__ void __launch_bounds__(256) k_density_a(Shape s, const float* Gall, s
         ((spart[threadIdx.x] + spart[2 + threadIdx.x]) + spart[4 + threadIdx.x]) + spart[6 + threadIdx.x];
 }
 
+// Fixed-order block sum of the pairs part[model][k][2], k < nblk: out = {sum_k [0], sum_k [1]}.
+// Thread t sums the contiguous range [t*per, (t+1)*per); the 256 range sums are then added
+// by a fixed tree.  One block per model.
+__device__ inline void pair_sum(const double* part, int nblk, double& a, double& b) {
+  __shared__ double sa[256], sb[256];
+  const int per = (nblk + 255) / 256;
+  const int k0 = threadIdx.x * per, k1 = min(nblk, k0 + per);
+  double x = 0.0, y = 0.0;
+  for (int k = k0; k < k1; ++k) { x += part[2 * (size_t)k]; y += part[2 * (size_t)k + 1]; }
+  sa[threadIdx.x] = x;
+  sb[threadIdx.x] = y;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) { sa[threadIdx.x] += sa[threadIdx.x + w]; sb[threadIdx.x] += sb[threadIdx.x + w]; }
+    __syncthreads();
+  }
+  a = sa[0];
+  b = sb[0];
+}
+
 // Reduce pass-A partials: sums[model] = {S, sum err}.
-__global__ void k_density_sums(const double* part, int nblk, double* sums, int nmodels) {
-  const int model = blockIdx.x * blockDim.x + threadIdx.x;
-  if (model >= nmodels) return;
-  double a = 0.0, b = 0.0;
-  for (int k = 0; k < nblk; ++k) { a += part[((size_t)model * nblk + k) * 2]; b += part[((size_t)model * nblk + k) * 2 + 1]; }
-  sums[2 * model] = a;
-  sums[2 * model + 1] = b;
+__global__ void __launch_bounds__(256) k_density_sums(const double* part, int nblk, double* sums, int nmodels) {
+  const int model = blockIdx.x;
+  double a, b;
+  pair_sum(part + (size_t)model * nblk * 2, nblk, a, b);
+  if (threadIdx.x == 0) { sums[2 * model] = a; sums[2 * model + 1] = b; }
 }
 
 // Target density and loss summand for one point, float64 (Eqs. (8), (9)).
@@ -269,85 +304,91 @@ __global__ void __launch_bounds__(256) k_density_b1(const float* rho, size_t rho
 }
 
 // Reduce pass-B1 partials into lq[model] = {loss, Q}
-__global__ void k_density_lq(const double* part, int nblk, int64_t n, double* lq, int nmodels) {
-  const int model = blockIdx.x * blockDim.x + threadIdx.x;
-  if (model >= nmodels) return;
-  double a = 0.0, b = 0.0;
-  for (int k = 0; k < nblk; ++k) { a += part[((size_t)model * nblk + k) * 2]; b += part[((size_t)model * nblk + k) * 2 + 1]; }
-  lq[2 * model] = n > 0 ? a / (double)n : 0.0;
-  lq[2 * model + 1] = b;
+__global__ void __launch_bounds__(256) k_density_lq(const double* part, int nblk, int64_t n, double* lq, int nmodels) {
+  const int model = blockIdx.x;
+  double a, b;
+  pair_sum(part + (size_t)model * nblk * 2, nblk, a, b);
+  if (threadIdx.x == 0) { lq[2 * model] = n > 0 ? a / (double)n : 0.0; lq[2 * model + 1] = b; }
 }
 
-// Pass B2: per grid, U_i = {sum c phi_i, sum c phi_i q_d x_k (9), sum c phi_i q_d (3)} with
-// c(x) = dL/drho(x) = (a(x) - Q)/S.  part: [model][block][13 M]
-constexpr int kPts = 8;  // points per thread in pass B2
-__global__ void __launch_bounds__(256) k_density_b2(Shape s, const float* Gall, size_t G_stride,
-    const float* pts, int64_t ld, size_t pts_stride, int64_t n, const float* rho, size_t rho_stride,
-    const float* err, size_t err_stride, const double* sums, const double* lq, double eps, int p,
-    double* part, const int32_t* active) {
-  extern __shared__ float smem[];
+// Per-point coefficient c(x) = dL/drho(x) = (a(x) - Q)/S (float64 arithmetic, stored float32).
+__global__ void k_density_coef(const float* rho, size_t rho_stride, const float* err, size_t err_stride, int64_t n,
+                               const double* sums, const double* lq, double eps, float* coef, size_t coef_stride,
+                               const int32_t* active) {
   const int model = blockIdx.y;
-  double* sacc = (double*)smem;            // [wave][13 M]
-  float* sG = (float*)(sacc + 4 * 13 * s.M);
-  for (int i = threadIdx.x; i < 4 * 13 * s.M; i += blockDim.x) sacc[i] = 0.0;
-  const float* G = Gall + model * G_stride;
-  for (int i = threadIdx.x; i < 12 * s.M; i += blockDim.x) sG[i] = G[i];
-  __syncthreads();
   const bool act = (!active || active[model]) && sums[2 * model] != 0.0;
+  const double S = sums[2 * model], hbar = sums[2 * model + 1] / (double)n, Q = lq[2 * model + 1];
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    float c = 0.f;
+    if (act) {
+      double term, a, rs;
+      target_terms(rho[model * rho_stride + i], S, hbar, err[model * err_stride + i], eps, (double)n, term, a, rs);
+      c = (float)((a - Q) / S);
+    }
+    coef[model * coef_stride + i] = c;
+  }
+}
+
+// Pass B2: per grid i, U_i = {sum c phi_i, sum c phi_i q_d x_k (9), sum c phi_i q_d (3)}.
+// Wave w of block (chunk, grid group, model) owns grid 4*blockIdx.y + w and streams the
+// chunk's points; one wave reduction per (grid, chunk).  part: [model][M][chunk][13]
+constexpr int kDensChunk = 4096;
+__global__ void __launch_bounds__(256) k_density_b2(Shape s, const float* Gall, size_t G_stride,
+    const float* pts, int64_t ld, size_t pts_stride, int64_t n, const float* coef, size_t coef_stride, int p,
+    double* part, const int32_t* active) {
+  const int model = blockIdx.z, wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int g = 4 * blockIdx.y + wave;
+  const int nchunk = gridDim.x;
+  if (g >= s.M) return;
+  const bool act = !active || active[model];
+  float Gg[12];
+  for (int k = 0; k < 12; ++k) Gg[k] = Gall[model * G_stride + 12 * g + k];
+  float u[13];
+#pragma unroll
+  for (int q = 0; q < 13; ++q) u[q] = 0.f;
   if (act) {
-    const double S = sums[2 * model], hbar = sums[2 * model + 1] / (double)n, Q = lq[2 * model + 1];
     const float* P = pts + model * pts_stride;
-    const int64_t nthr = (int64_t)gridDim.x * blockDim.x;
-    const int64_t t0 = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    for (int64_t base = 0; base < n; base += nthr * kPts) {
-      float px[kPts], py[kPts], pz[kPts], pc[kPts];
+    const float* cf = coef + model * coef_stride;
+    const int64_t i0 = (int64_t)blockIdx.x * kDensChunk, i1 = min(n, i0 + kDensChunk);
+    for (int64_t i = i0 + lane; i < i1; i += 64) {
+      const float c = cf[i];
+      if (c == 0.f) continue;
+      const float xs[3] = {P[i], P[ld + i], P[2 * ld + i]};
+      float l[3];
+      local_coords(Gg, xs[0], xs[1], xs[2], l);
+      const float sv = powi(l[0], 2 * p) + powi(l[1], 2 * p) + powi(l[2], 2 * p);
+      if (!(sv <= kSMax)) continue;
+      const float cphi = c * __expf(-sv);
+      u[0] += cphi;
 #pragma unroll
-      for (int k = 0; k < kPts; ++k) {
-        const int64_t i = base + t0 + (int64_t)k * nthr;
-        px[k] = py[k] = pz[k] = 0.f;
-        pc[k] = 0.f;
-        if (i < n) {
-          px[k] = P[i]; py[k] = P[ld + i]; pz[k] = P[2 * ld + i];
-          double term, a, rs;
-          target_terms(rho[model * rho_stride + i], S, hbar, err[model * err_stride + i], eps, (double)n, term, a, rs);
-          pc[k] = (float)((a - Q) / S);
-        }
-      }
-      for (int g = 0; g < s.M; ++g) {
-        float u[13];
-#pragma unroll
-        for (int q = 0; q < 13; ++q) u[q] = 0.f;
-#pragma unroll
-        for (int k = 0; k < kPts; ++k) {
-          float l[3];
-          local_coords(sG + 12 * g, px[k], py[k], pz[k], l);
-          const float sv = powi(l[0], 2 * p) + powi(l[1], 2 * p) + powi(l[2], 2 * p);
-          if (sv <= kSMax && pc[k] != 0.f) {
-            const float cphi = pc[k] * __expf(-sv);
-            u[0] += cphi;
-            const float xs[3] = {px[k], py[k], pz[k]};
-#pragma unroll
-            for (int d = 0; d < 3; ++d) {
-              const float cq = cphi * powi(l[d], 2 * p - 1);
-              u[1 + 3 * d] = __builtin_fmaf(cq, xs[0], u[1 + 3 * d]);
-              u[2 + 3 * d] = __builtin_fmaf(cq, xs[1], u[2 + 3 * d]);
-              u[3 + 3 * d] = __builtin_fmaf(cq, xs[2], u[3 + 3 * d]);
-              u[10 + d] += cq;
-            }
-          }
-        }
-#pragma unroll
-        for (int q = 0; q < 13; ++q) {
-          const double t = wave_sum((double)u[q]);
-          if ((threadIdx.x & 63) == 0) sacc[(threadIdx.x >> 6) * 13 * s.M + 13 * g + q] += t;
-        }
+      for (int d = 0; d < 3; ++d) {
+        const float cq = cphi * powi(l[d], 2 * p - 1);
+        u[1 + 3 * d] = __builtin_fmaf(cq, xs[0], u[1 + 3 * d]);
+        u[2 + 3 * d] = __builtin_fmaf(cq, xs[1], u[2 + 3 * d]);
+        u[3 + 3 * d] = __builtin_fmaf(cq, xs[2], u[3 + 3 * d]);
+        u[10 + d] += cq;
       }
     }
   }
-  __syncthreads();
-  for (int i = threadIdx.x; i < 13 * s.M; i += blockDim.x)
-    part[((size_t)model * gridDim.x + blockIdx.x) * 13 * s.M + i] =
-        ((sacc[i] + sacc[13 * s.M + i]) + sacc[2 * 13 * s.M + i]) + sacc[3 * 13 * s.M + i];
+#pragma unroll
+  for (int q = 0; q < 13; ++q) {
+    const double t = wave_sum((double)u[q]);
+    if (lane == 0) part[(((size_t)model * s.M + g) * nchunk + blockIdx.x) * 13 + q] = t;
+  }
+}
+
+// U[model][g][q] = sum over chunks of part[model][g][chunk][q], in chunk order.
+__global__ void __launch_bounds__(256) k_density_b2_reduce(const double* part, int M, int nchunk, double* U,
+                                                           const int32_t* active) {
+  const int model = blockIdx.y;
+  if (active && !active[model]) return;
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < 13 * M; e += gridDim.x * blockDim.x) {
+    const int g = e / 13, q = e % 13;
+    const double* pp = part + ((size_t)model * M + g) * nchunk * 13 + q;
+    double s = 0.0;
+    for (int k = 0; k < nchunk; ++k) s += pp[(size_t)k * 13];
+    U[(size_t)model * 13 * M + e] = s;
+  }
 }
 
 // Assemble dG_i = cof_i U0 - 2p det_i [U1 | U2] from the reduced pass-B2 sums.

@@ -71,7 +71,8 @@ __global__ void __launch_bounds__(256) k_cell_pull(CellArgs a) {
     const int cx = (int)(cell % R1), cy = (int)((cell / R1) % R1), cz = (int)(cell / ((int64_t)R1 * R1));
     const int me[3] = {cx, cy, cz};
     const float hR = 0.5f * (float)R1;
-    // bins overlapping the cell's box in global space, with a one-bin margin
+    // bins overlapping the cell's box in global space; the 1e-4 margin (world units) covers the
+    // float32 rounding of the cell decision (~1e-6) and of this box
     int lo[3], hi[3];
     if (sBad) {
       for (int d = 0; d < 3; ++d) { lo[d] = 0; hi[d] = kBinsPerAxis - 1; }
@@ -82,8 +83,8 @@ __global__ void __launch_bounds__(256) k_cell_pull(CellArgs a) {
       for (int d = 0; d < 3; ++d) {
         const float wc = sInv[3 * d] * lm[0] + sInv[3 * d + 1] * lm[1] + sInv[3 * d + 2] * lm[2];
         const float hw = (fabsf(sInv[3 * d]) + fabsf(sInv[3 * d + 1]) + fabsf(sInv[3 * d + 2])) * hl;
-        const float b0 = floorf((wc - hw + 1.f) * (0.5f * kBinsPerAxis)) - 1.f;
-        const float b1 = floorf((wc + hw + 1.f) * (0.5f * kBinsPerAxis)) + 1.f;
+        const float b0 = floorf((wc - hw - 1e-4f + 1.f) * (0.5f * kBinsPerAxis));
+        const float b1 = floorf((wc + hw + 1e-4f + 1.f) * (0.5f * kBinsPerAxis));
         lo[d] = (int)fminf(fmaxf(b0, 0.f), (float)(kBinsPerAxis - 1));
         hi[d] = (int)fminf(fmaxf(b1, 0.f), (float)(kBinsPerAxis - 1));
       }

@@ -55,27 +55,41 @@ __global__ void __launch_bounds__(256) k_radix_hist(const uint32_t* keys, int64_
     hist[((size_t)model * kRadixDigits + d) * ntiles + tile] = h[d];
 }
 
-// Exclusive scan of hist[model][*] (digit-major, tile-minor) in place; one block per model.
+// Exclusive scan of hist[model][*] (digit-major, tile-minor) in place; one block of 1024
+// threads per model, in chunks of 4096 (each thread a vector of 4 consecutive counts).
 __global__ void __launch_bounds__(1024) k_radix_scan(uint32_t* hist, int len) {
-  __shared__ uint32_t part[1024];
+  __shared__ uint32_t wsum[16];
+  __shared__ uint32_t carry;
+  typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
   uint32_t* H = hist + (size_t)blockIdx.x * len;
-  const int per = (len + blockDim.x - 1) / blockDim.x;
-  const int lo = threadIdx.x * per, hi = min(len, lo + per);
-  uint32_t s = 0;
-  for (int i = lo; i < hi; ++i) s += H[i];
-  part[threadIdx.x] = s;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (threadIdx.x == 0) carry = 0;
   __syncthreads();
-  for (int off = 1; off < (int)blockDim.x; off <<= 1) {  // inclusive Hillis-Steele
-    const uint32_t v = threadIdx.x >= (unsigned)off ? part[threadIdx.x - off] : 0u;
+  for (int base = 0; base < len; base += 4096) {
+    const int i = base + 4 * threadIdx.x;
+    u32x4 v = {0, 0, 0, 0};
+    if (i + 3 < len) v = *(const u32x4*)(H + i);
+    else for (int k = 0; k < 4; ++k) if (i + k < len) v[k] = H[i + k];
+    const uint32_t tot = v[0] + v[1] + v[2] + v[3];
+    // inclusive scan of the per-thread totals within the wave
+    uint32_t x = tot;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const uint32_t y = __shfl_up(x, o, 64);
+      if (lane >= o) x += y;
+    }
+    if (lane == 63) wsum[wave] = x;
     __syncthreads();
-    part[threadIdx.x] += v;
+    uint32_t wpre = 0;
+    for (int w = 0; w < wave; ++w) wpre += wsum[w];
+    const uint32_t excl = carry + wpre + x - tot;
+    u32x4 o4;
+    o4[0] = excl; o4[1] = excl + v[0]; o4[2] = o4[1] + v[1]; o4[3] = o4[2] + v[2];
+    if (i + 3 < len) *(u32x4*)(H + i) = o4;
+    else for (int k = 0; k < 4; ++k) if (i + k < len) H[i + k] = o4[k];
     __syncthreads();
-  }
-  uint32_t run = threadIdx.x ? part[threadIdx.x - 1] : 0u;
-  for (int i = lo; i < hi; ++i) {
-    const uint32_t v = H[i];
-    H[i] = run;
-    run += v;
+    if (threadIdx.x == 1023) carry = excl + tot;
+    __syncthreads();
   }
 }
 

@@ -112,7 +112,8 @@ def make_volume(kind, shape_zyx, seed=SEED_VOLUME, device="cpu", slab=None):
     ys = torch.linspace(-1.0, 1.0, ny, dtype=torch.float32, device=device)
     zs = torch.linspace(-1.0, 1.0, nz, dtype=torch.float32, device=device)
     if slab is None:
-        slab = max(1, (1 << 22) // (nx * ny))
+        target = (1 << 22) if str(device) == "cpu" else (1 << 25)
+        slab = max(1, target // (nx * ny))
     for z0 in range(0, nz, slab):
         z1 = min(nz, z0 + slab)
         Z, Y, X = torch.meshgrid(zs[z0:z1], ys, xs, indexing="ij")

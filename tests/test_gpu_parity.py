@@ -163,16 +163,20 @@ def test_forward_mixed_precision_stated(grid16, bf):
 
 
 # --------------------------------------------------------------------------- adjoint
-def kink_free(host, x, tau=1e-4):
+def kink_free_mask(host, x, tau=1e-4):
     _, cache = O.forward(f64(host), x.astype(np.float64))
     keep = np.ones(x.shape[0], bool)
     for z in cache["z"][:-1]:
         scale = np.sqrt(np.mean(z * z, axis=1, keepdims=True)) + 1e-30
         keep &= np.all(np.abs(z) / scale > tau, axis=1)
-    return x[keep]
+    return keep
 
 
-@pytest.mark.parametrize("M,C,R,H", SHAPES[:4])
+def kink_free(host, x, tau=1e-4):
+    return x[kink_free_mask(host, x, tau)]
+
+
+@pytest.mark.parametrize("M,C,R,H", SHAPES[:4] + [(32, 2, 8, 64), (32, 2, 32, 64), (24, 1, 6, 64)])
 def test_backward_fp32(M, C, R, H):
     host = host_model(M, C, R, H, extra_t=0.1)
     x = kink_free(host, make_points(3001))
@@ -385,43 +389,131 @@ def test_render_model_bf16_forward_sampled():
     assert a < 3e-2
 
 
-def _fd_check(model, pts, wts, dirs, h, tol, name):
-    dF, dG, dW = A().apmg_backward(model, pts, wts)
-    pred = float((dG.float() * dirs["G"]).sum() + (dF * dirs["F"]).sum()
-                 + sum((g * d).sum() for g, d in zip(dW, dirs["W"])))
+def _perturbed(host, dirs, t):
+    out = dict(host)
+    out["G"] = (host["G"].astype(np.float64) + t * dirs["G"]).astype(np.float32)
+    out["F"] = (host["F"].astype(np.float64) + t * dirs["F"]).astype(np.float32)
+    out["W"] = [(w.astype(np.float64) + t * d).astype(np.float32) for w, d in zip(host["W"], dirs["W"])]
+    return out
 
-    def L(t):
-        m2 = A().Model(model.G + t * dirs["G"], model.F + t * dirs["F"],
-                       [w + t * d for w, d in zip(model.W, dirs["W"])], model.vmin, model.vmax)
-        return float((A().apmg_forward(m2, pts).double() * wts.double()).sum())
 
-    fd = (L(h) - L(-h)) / (2 * h)
+def _smooth_segment_points(hosts, x, margin=1e-6):
+    # points whose mask, interpolation cell and ReLU pattern are the same at every model of the
+    # segment: along the segment f is then a polynomial of degree <= 3 in t
+    keep = np.ones(x.shape[0], bool)
+    ref = None
+    for h in hosts:
+        _, c = O.forward(f64(h), x.astype(np.float64))
+        sig = (c["enc"]["inside"], c["enc"]["cell"], [z > 0 for z in c["z"][:-1]])
+        for z in c["z"][:-1]:
+            keep &= np.all(np.abs(z) > margin, axis=1)
+        if ref is None:
+            ref = sig
+            continue
+        keep &= np.all(sig[0] == ref[0], axis=1)
+        keep &= np.all((sig[1] == ref[1]).reshape(x.shape[0], -1), axis=1)
+        for a, b in zip(sig[2], ref[2]):
+            keep &= np.all(a == b, axis=1)
+    return x[keep]
+
+
+def _central_difference_check(host, dirs, h, x, wts_seed, tol, name):
+    hp, hm = _perturbed(host, dirs, h), _perturbed(host, dirs, -h)
+    x = _smooth_segment_points([hm, host, hp], x)
+    n = x.shape[0]
+    wts = (np.random.default_rng(wts_seed).normal(size=n) / n).astype(np.float32)
+    pts, wd = soa(x), torch.from_numpy(wts).to(DEV)
+    dF, dG, dW = A().apmg_backward(A().Model.from_host(host, DEV), pts, wd)
+    # the step actually taken, after float32 rounding of the perturbed parameters
+    step = {"G": hp["G"].astype(np.float64) - hm["G"], "F": hp["F"].astype(np.float64) - hm["F"],
+            "W": [a.astype(np.float64) - b for a, b in zip(hp["W"], hm["W"])]}
+    pred = float((dG.cpu().numpy().astype(np.float64) * step["G"]).sum()
+                 + (dF.cpu().numpy().transpose(0, 4, 1, 2, 3).astype(np.float64) * step["F"]).sum()
+                 + sum((g.cpu().numpy().astype(np.float64) * d).sum() for g, d in zip(dW, step["W"])))
+
+    def L(hh):
+        f = A().apmg_forward(A().Model.from_host(hh, DEV), pts).cpu().numpy().astype(np.float64)
+        return float((f * wts.astype(np.float64)).sum())
+
+    fd = L(hp) - L(hm)
     rel = abs(fd - pred) / abs(pred)
-    print(f"{name}: adjoint {pred:.6e} central difference {fd:.6e} rel {rel:.2e}")
+    print(f"{name}: points {n} adjoint {pred:.6e} central difference {fd:.6e} rel {rel:.2e}")
+    assert n > 1000
     assert rel < tol
 
 
-def test_adjoint_finite_difference_random_direction_2e20():
-    # <grad L, d> from the adjoint vs central differences of the GPU forward along a random
-    # direction d, L = sum_n w_n f(x_n) over 2^20 points.  f is continuous and piecewise linear
-    # in F and W; in G it jumps where a point crosses a cube face (Eq. (2)), which the adjoint
-    # (an almost-everywhere derivative) does not see, so the transform direction is checked
-    # on grids that contain the whole domain.
-    n = 1 << 20
-    pts = A().apmg_uniform_points(17, 0, 0, 0, n, DEV)
-    wts = torch.randn(n, device=DEV, generator=torch.Generator(device=DEV).manual_seed(2)) / n
-    gen = torch.Generator(device="cpu").manual_seed(1)
+def test_adjoint_central_differences():
+    # The adjoint applied to a random step equals the change of sum_n w_n f(x_n) over that step,
+    # on points that cross no ReLU kink, cell face or mask face along it (there f is a cubic in
+    # the step, and a central difference is exact up to O(h^2) and rounding).  Steps along F,
+    # along the three MLP matrices, and along the 32 transforms, at the 32-grid, 32^3 shape.
+    host = synth.init_model(32, 2, 32, [64, 64, 64, 1], seed=9, grid_range=0.3)
+    rng = np.random.default_rng(21)
+    zero = {"G": np.zeros(host["G"].shape), "F": np.zeros(host["F"].shape),
+            "W": [np.zeros(w.shape) for w in host["W"]]}
+    x = synth.uniform_points_host(32768, seed=13)
+    dirs = dict(zero, F=0.3 * rng.normal(size=host["F"].shape))
+    _central_difference_check(host, dirs, 1e-3, x, 1, 1e-3, "F")
+    dirs = dict(zero, W=[np.abs(w).max() * rng.normal(size=w.shape) for w in host["W"]])
+    _central_difference_check(host, dirs, 1e-3, x, 2, 1e-3, "W")
+    dirs = dict(zero, G=rng.normal(size=host["G"].shape))
+    _central_difference_check(host, dirs, 1e-4, x, 3, 1e-3, "G")
+
+
+def test_adjoint_2e20_points_sampled_vertices_and_partition():
+    # 2^20 points at the 32-grid, 32^3 shape.  dF at sampled vertices equals the oracle's sum
+    # over the points of the vertex's 8 cells; the gradients over the whole batch equal the sum
+    # of the gradients over four quarter batches (each sorted and reduced on its own), and one
+    # quarter matches the oracle on all of dF, dG and dW.
     host = synth.init_model(32, 2, 32, [64, 64, 64, 1], seed=9, grid_range=0.3)
     model = A().Model.from_host(host, DEV)
-    dirs = {"G": torch.zeros(model.G.shape, device=DEV),
-            "F": torch.randn(model.F.shape, generator=gen).to(DEV),
-            "W": [torch.randn(w.shape, generator=gen).to(DEV) for w in model.W]}
-    _fd_check(model, pts, wts, dirs, 1e-3, 1e-3, "F and W")
-    # transforms: scale 0.75 keeps every point of [-1,1]^3 inside every grid
-    host["G"][:, :, :3] *= 0.75
-    host["G"][:, :, 3] *= 0.3
-    model = A().Model.from_host(host, DEV)
-    dirs = {"G": torch.randn(model.G.shape, generator=gen).to(DEV),
-            "F": torch.zeros(model.F.shape, device=DEV),
-            "W": [torch.zeros(w.shape, device=DEV) for w in model.W]}
-    _fd_check(model, pts, wts, dirs, 1e-4, 2e-3, "G")
+    n, R = 1 << 20, 32
+    pts = A().apmg_uniform_points(17, 0, 0, 0, n, DEV)
+    x = pts.cpu().numpy().T.astype(np.float32).copy()
+    rng = np.random.default_rng(3)
+    wa = (rng.normal(size=n) / n).astype(np.float32)
+    dF, dG, dW = A().apmg_backward(model, pts, torch.from_numpy(wa).to(DEV))
+    parts = []
+    q = n // 4
+    for k in range(4):
+        parts.append(A().apmg_backward(model, pts[:, k * q:(k + 1) * q].contiguous(),
+                                       torch.from_numpy(wa[k * q:(k + 1) * q]).to(DEV)))
+    assert_close("partition dF", dF.cpu().numpy(), sum(p[0] for p in parts).cpu().numpy())
+    assert_close("partition dG", dG.cpu().numpy(), sum(p[1] for p in parts).cpu().numpy())
+    for k in range(3):
+        assert_close(f"partition dW{k + 1}", dW[k].cpu().numpy(), sum(p[2][k] for p in parts).cpu().numpy())
+    # one 2^16 slice of the first quarter against the oracle
+    s = 1 << 16
+    keep = kink_free_mask(host, x[:s])
+    sub = x[:s][keep]
+    dFs, dGs, dWs = A().apmg_backward(model, soa(sub), torch.from_numpy(wa[:s][keep]).to(DEV))
+    go = O.backward(f64(host), sub.astype(np.float64), wa[:s][keep].astype(np.float64))
+    assert_close("slice dF", dFs.cpu().numpy(), go["dF"].transpose(0, 2, 3, 4, 1))
+    assert_close("slice dG", dGs.cpu().numpy(), go["dG"])
+    for k in range(3):
+        assert_close(f"slice dW{k + 1}", dWs[k].cpu().numpy(), go["dW"][k])
+    dF = dF.cpu().numpy()
+    scale = np.abs(dF).max()
+    checked = 0
+    decisions = {}
+    for trial in range(40):
+        g = int(rng.integers(0, 32))
+        v = rng.integers(1, R - 1, size=3)          # (vx, vy, vz), interior
+        if g not in decisions:
+            decisions[g] = O.cell_decision_f32(O.local_coords_f32(host["G"][g:g + 1], x), R)
+        inside, cell = decisions[g]
+        sel = inside[:, 0] & np.all((cell[:, 0, :] == v) | (cell[:, 0, :] == v - 1), axis=1)
+        sub = x[sel]
+        _, cache = O.forward(f64(host), sub.astype(np.float64))
+        if any(np.any(np.abs(z) < 1e-6) for z in cache["z"][:-1]):
+            continue                                # a pre-activation within float32 reach of 0
+        go = O.backward(f64(host), sub.astype(np.float64), wa[sel].astype(np.float64), cache)
+        want = go["dF"][g, :, v[2], v[1], v[0]]
+        got = dF[g, v[2], v[1], v[0], :]
+        err = np.max(np.abs(got - want))
+        print(f"vertex g={g} v={tuple(v)} points={sel.sum()} want={want} err={err:.2e}")
+        assert err <= 1e-5 * max(np.max(np.abs(want)), 1e-2 * scale)
+        checked += 1
+        if checked == 8:
+            break
+    assert checked >= 6
