@@ -27,6 +27,8 @@ PEAK_FP32_MFMA_TFLOPS = 157.3
 PEAK_BF16_MFMA_TFLOPS = 2500.0
 PEAK_HBM_GBS = 8000.0
 
+COPY_PROBE_BYTES = 1 << 30
+
 M, C, R, H = 32, 2, 32, 64
 VOL = (256, 256, 256)
 N = 1 << 20
@@ -39,6 +41,43 @@ def mlp_flops_fwd_bwd(K, Hd):
     fwd = 2 * (K * Hd + Hd * Hd + Hd)
     bwd = 2 * (K * Hd + Hd * Hd + Hd) + 2 * (Hd * Hd + K * Hd)
     return fwd + bwd
+
+
+COUNTERS_FILE = os.path.join(ROOT, "profiles", "k_backward_train_c2_fp32_counters.txt")
+
+
+def source_hash():
+    """sha256 over the kernel sources and the ABI header (path and content, sorted)."""
+    import hashlib
+    h = hashlib.sha256()
+    files = [os.path.join("include", "apmg.h")]
+    cdir = os.path.join("paper_2308_02494_amd", "csrc")
+    files += sorted(os.path.join(cdir, f) for f in os.listdir(os.path.join(ROOT, cdir)))
+    for rel in files:
+        h.update(rel.encode() + b"\0")
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def measured_traffic():
+    """HBM bytes per launch of the dominant kernel from the committed FETCH_SIZE / WRITE_SIZE
+    counter summary, each scaled by what the counter reads for a plain copy of known size;
+    None when the summary is missing or was taken on other kernel sources."""
+    if not os.path.exists(COUNTERS_FILE):
+        return None
+    kv = {}
+    with open(COUNTERS_FILE) as f:
+        for line in f:
+            if "=" in line and not line.lstrip().startswith("#"):
+                k, v = line.split("=", 1)
+                kv[k.strip()] = v.strip()
+    if kv.get("source_sha256") != source_hash():
+        return None
+    cb = float(kv["copy_bytes"])
+    fetch = float(kv["fetch_kib_per_dispatch"]) * 1024 * cb / (float(kv["copy_fetch_kib"]) * 1024)
+    write = float(kv["write_kib_per_dispatch"]) * 1024 * cb / (float(kv["copy_write_kib"]) * 1024)
+    return fetch + write
 
 
 def hip():
@@ -201,7 +240,14 @@ def main():
     ap.add_argument("--skip-extra", action="store_true")
     ap.add_argument("--configs", default="config1,config3,config4,config5",
                     help="extra workloads to time after the headline")
+    ap.add_argument("--source-hash", action="store_true", help="print the kernel source hash and exit")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="end with a plain 1 GiB device-to-device copy (the reference kernel that "
+                         "calibrates the FETCH_SIZE / WRITE_SIZE counters)")
     args = ap.parse_args()
+    if args.source_hash:
+        print(source_hash())
+        return
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (the path is one GPU's "
               f"share; see the sharding notes in the design document)", file=sys.stderr)
@@ -228,7 +274,7 @@ def main():
                                "at 32^3 x 2 features, MLP 64-64-64-1, 2^20 points, density phase on",
                    "global_batch": N, "parallelism": "none (1 GPU)"},
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK_FP32_MFMA_TFLOPS,
-                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_MFMA_TFLOPS, "traffic": None,
+                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_MFMA_TFLOPS, "traffic": measured_traffic(),
                      "kernel": "k_backward (fused forward + adjoint tile kernel)",
                      "kernel_ms": kern_ms},
     }
@@ -254,6 +300,13 @@ def main():
                     extra[name] = {"error": repr(e)[:200]}
                 torch.cuda.empty_cache()
         out["extra"] = extra
+    if args.copy_probe:
+        src = torch.ones(COPY_PROBE_BYTES // 4, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(vol.cpu().numpy().astype("float64"), host, args.cpu_sample)
     print(json.dumps(out), flush=True)

@@ -122,7 +122,7 @@ size_t fwd_ws(const Shape& s, bool bf, void* ws, FwdWs* o) {
 
 // Spatial sort of nb models' points: keys/values ping-pong, digit histograms, bin starts,
 // sorted points and an optional permuted per-point array.
-struct SortWs { uint32_t *k0, *v0, *k1, *v1, *hist, *start; float *spts, *sf; };
+struct SortWs { uint32_t *k0, *v0, *k1, *v1, *hist, *rowtot, *dbase, *start; float *spts, *sf; float4* spts4; };
 inline int sort_tiles(int64_t n) { return (int)std::max<int64_t>(1, (n + kSortTile - 1) / kSortTile); }
 void take_sort(Carver& cv, int64_t n, int nb, bool with_f, SortWs* o) {
   const int64_t nn = std::max<int64_t>(n, 1);
@@ -131,25 +131,32 @@ void take_sort(Carver& cv, int64_t n, int nb, bool with_f, SortWs* o) {
   o->k1 = cv.take<uint32_t>((size_t)nb * nn);
   o->v1 = cv.take<uint32_t>((size_t)nb * nn);
   o->hist = cv.take<uint32_t>((size_t)nb * kRadixDigits * sort_tiles(n));
+  o->rowtot = cv.take<uint32_t>((size_t)nb * kRadixDigits);
+  o->dbase = cv.take<uint32_t>((size_t)nb * kRadixDigits);
   o->start = cv.take<uint32_t>((size_t)nb * (kBinsPerAxis * kBinsPerAxis * kBinsPerAxis + 1));
   o->spts = cv.take<float>((size_t)nb * 3 * nn);
   o->sf = with_f ? cv.take<float>((size_t)nb * nn) : nullptr;
+  o->spts4 = cv.take<float4>((size_t)nb * nn);
 }
 
-hipError_t launch_sort(const float* pts, int64_t ld, size_t pts_stride, int64_t n, int nb, const SortWs& w,
-                       const float* src_f, hipStream_t st) {
+hipError_t launch_sort(const float* pts, int64_t ld, size_t pts_stride, const float4* pts4, int64_t n, int nb,
+                       const SortWs& w, const float* src_f, hipStream_t st) {
   const int nt = sort_tiles(n);
-  hipLaunchKernelGGL(k_bin_keys, dim3(grid1(n), nb), dim3(256), 0, st, pts, ld, pts_stride, n, w.k0, w.v0);
+  SortIn in;
+  in.pts = pts; in.ld = ld; in.pts_stride = pts_stride; in.pts4 = pts4;
+  hipLaunchKernelGGL(k_bin_keys, dim3(grid1(n), nb), dim3(256), 0, st, in, n, w.k0, w.v0);
   uint32_t *ki = w.k0, *vi = w.v0, *ko = w.k1, *vo = w.v1;
   for (int shift = 0; shift < kBinBits; shift += kRadixBits) {
     hipLaunchKernelGGL(k_radix_hist, dim3(nt, nb), dim3(256), 0, st, ki, n, shift, w.hist, nt);
-    hipLaunchKernelGGL(k_radix_scan, dim3(nb), dim3(1024), 0, st, w.hist, kRadixDigits * nt);
-    hipLaunchKernelGGL(k_radix_scatter, dim3(nt, nb), dim3(256), 0, st, ki, vi, ko, vo, n, shift, w.hist, nt);
+    hipLaunchKernelGGL(k_radix_rowscan, dim3(kRadixDigits, nb), dim3(256), 0, st, w.hist, nt, w.rowtot);
+    hipLaunchKernelGGL(k_radix_digitscan, dim3(nb), dim3(256), 0, st, w.rowtot, w.dbase);
+    hipLaunchKernelGGL(k_radix_scatter, dim3(nt, nb), dim3(256), 0, st, ki, vi, ko, vo, n, shift, w.hist, w.dbase,
+                       nt);
     std::swap(ki, ko);
     std::swap(vi, vo);
   }
   // after an even number of passes the sorted keys/values are back in k0/v0
-  hipLaunchKernelGGL(k_permute_points, dim3(grid1(n), nb), dim3(256), 0, st, pts, ld, pts_stride, n, w.v0, w.spts,
+  hipLaunchKernelGGL(k_permute_points, dim3(grid1(n), nb), dim3(256), 0, st, in, n, w.v0, w.spts, w.spts4,
                      src_f, w.sf);
   hipLaunchKernelGGL(k_bin_starts, dim3(grid1(kBinsPerAxis * kBinsPerAxis * kBinsPerAxis + 1), nb), dim3(256), 0,
                      st, w.k0, n, w.start);
@@ -175,12 +182,15 @@ hipError_t launch_cells(const Shape& s, bool gf16, const float* G, size_t G_stri
   CellArgs c;
   memset(&c, 0, sizeof(c));
   c.s = s; c.G = G; c.G_stride = G_stride; c.F = F; c.F_stride = F_stride;
-  c.pts = sw.spts; c.n = n; c.start = sw.start; c.dY = cw.dY; c.CC = cw.CC;
-  c.want_dG = want_dG ? 1 : 0; c.dGpart = cw.dGpart; c.active = active;
-  const dim3 grid(cell_blocks(s), s.M, nb);
+  c.pts4 = sw.spts4; c.n = n; c.start = sw.start; c.dY = cw.dY; c.CC = cw.CC;
+  c.dGpart = cw.dGpart; c.active = active; c.nblk = cell_blocks(s);
+  const int64_t nblocks = (int64_t)cell_blocks(s) * s.M * nb;
+  if (nblocks > 0x7fffffff) return hipErrorInvalidValue;
+  const dim3 grid((unsigned)nblocks);
 #define APMG_CELL(CC_, F16_)                                                                        \
   if (s.C == CC_ && gf16 == F16_) {                                                                 \
-    hipLaunchKernelGGL((k_cell_pull<CC_, F16_>), grid, dim3(256), 0, st, c);                        \
+    if (want_dG) hipLaunchKernelGGL((k_cell_pull<CC_, F16_, true>), grid, dim3(256), 0, st, c);       \
+    else hipLaunchKernelGGL((k_cell_pull<CC_, F16_, false>), grid, dim3(256), 0, st, c);              \
     if (dF) hipLaunchKernelGGL((k_cell_to_vertex<CC_>), dim3(grid1((int64_t)s.R * s.R * s.R, 1024), s.M, nb), \
                                dim3(256), 0, st, s, cw.CC, dF, dF_stride, accumulate, active);       \
   }
@@ -236,8 +246,12 @@ hipError_t launch_density(const Shape& s, const float* G, size_t G_stride, const
   const size_t rho_stride = rho_user ? (size_t)n : (size_t)std::max<int64_t>(n, 1);
   const int ba = dens_blocks(n), nch = dens_chunks(n);
   const size_t shA = 64 + (size_t)13 * s.M * 4;
-  hipLaunchKernelGGL(k_density_a, dim3(ba, nb), dim3(256), shA, st, s, G, G_stride, pts, ld, pts_stride, n,
-                     err, err_stride, p, rho, rho_stride, w.pa, active);
+  if (p == 10)
+    hipLaunchKernelGGL(k_density_a<10>, dim3(ba, nb), dim3(256), shA, st, s, G, G_stride, pts, ld, pts_stride, n,
+                       err, err_stride, p, rho, rho_stride, w.pa, active);
+  else
+    hipLaunchKernelGGL(k_density_a<0>, dim3(ba, nb), dim3(256), shA, st, s, G, G_stride, pts, ld, pts_stride, n,
+                       err, err_stride, p, rho, rho_stride, w.pa, active);
   hipLaunchKernelGGL(k_density_sums, dim3(nb), dim3(256), 0, st, w.pa, ba, w.sums, nb);
   hipLaunchKernelGGL(k_density_b1, dim3(ba, nb), dim3(256), 0, st, rho, rho_stride, err, err_stride, n,
                      w.sums, eps, w.pb1, active);
@@ -246,9 +260,13 @@ hipError_t launch_density(const Shape& s, const float* G, size_t G_stride, const
     const size_t cstride = (size_t)std::max<int64_t>(n, 1);
     hipLaunchKernelGGL(k_density_coef, dim3(grid1(n, 2048), nb), dim3(256), 0, st, rho, rho_stride, err, err_stride, n,
                        w.sums, w.lq, eps, w.coef, cstride, active);
-    hipLaunchKernelGGL(k_density_b2, dim3(nch, (s.M + 3) / 4, nb), dim3(256), 0, st, s, G, G_stride, pts, ld,
-                       pts_stride, n, w.coef, cstride, p, w.pb2, active);
-    hipLaunchKernelGGL(k_density_b2_reduce, dim3(grid1(13 * s.M, 64), nb), dim3(256), 0, st, w.pb2, s.M, nch, w.U,
+    if (p == 10)
+      hipLaunchKernelGGL(k_density_b2<10>, dim3(nch, (s.M + 3) / 4, nb), dim3(256), 0, st, s, G, G_stride, pts,
+                         ld, pts_stride, n, w.coef, cstride, p, w.pb2, active);
+    else
+      hipLaunchKernelGGL(k_density_b2<0>, dim3(nch, (s.M + 3) / 4, nb), dim3(256), 0, st, s, G, G_stride, pts,
+                         ld, pts_stride, n, w.coef, cstride, p, w.pb2, active);
+    hipLaunchKernelGGL(k_density_b2_reduce, dim3(s.M, nb), dim3(256), 0, st, w.pb2, s.M, nch, w.U,
                        active);
     hipLaunchKernelGGL(k_density_grad, dim3(1, nb), dim3(64), 0, st, s, G, G_stride, w.U, p, dG, dG_stride,
                        accumulate, w.sums, active);
@@ -259,7 +277,7 @@ hipError_t launch_density(const Shape& s, const float* G, size_t G_stride, const
 
 // ---------------------------------------------------------------- training step
 struct StepWs {
-  float* pts;     // [nb][3][n] generated (unsorted)
+  float4* pts4;   // [nb][n] generated (unsorted) as (x, y, z, 0)
   float* v;       // [nb][n] ground truth at the sorted points
   float* err;     // [nb][n]
   void* swz;      // [nb][swizzled weights]
@@ -284,7 +302,7 @@ size_t step_ws(const apmg_batch* b, const Shape& s, void* ws, StepWs* o) {
   const int nb = b->nb;
   const int64_t n = std::max<int64_t>(b->n, 1);
   StepWs w;
-  w.pts = cv.take<float>((size_t)nb * 3 * n);
+  w.pts4 = cv.take<float4>((size_t)nb * n);
   w.v = cv.take<float>((size_t)nb * n);
   w.err = cv.take<float>((size_t)nb * n);
   w.swz = cv.take<char>((size_t)nb * swz_sizes(s).total() * (bf ? 2 : 4));
@@ -415,7 +433,7 @@ apmg_status apmg_backward(const apmg_model* m, const float* pts, int64_t ld, int
   BwdWs w;
   bwd_ws(s, bf, n, ws, &w);
   // points (and dL/df) in spatial-bin order
-  hipError_t e = launch_sort(pts, ld, 0, n, 1, w.srt, df, st);
+  hipError_t e = launch_sort(pts, ld, 0, nullptr, n, 1, w.srt, df, st);
   if (e != hipSuccess) return APMG_EHIP;
   e = launch_swizzle(s, bf, m->W[0], m->W[1], m->W[2], 0, w.f.swz, 0, w.f.w3s, 1, st);
   if (e != hipSuccess) return APMG_EHIP;
@@ -598,8 +616,8 @@ extern "C" apmg_status apmg_batched_step(const apmg_batch* b, void* ws, size_t w
 
   // 1. batch points, sorted by spatial bin, and the ground truth at the sorted points
   if (n > 0) {
-    hipLaunchKernelGGL(k_batch_points, dim3(grid1(n, 2048), nb), dim3(256), 0, st, b->seed, b->step, n, w.pts);
-    hipError_t e0 = launch_sort(w.pts, n, (size_t)3 * n, n, nb, w.srt, nullptr, st);
+    hipLaunchKernelGGL(k_batch_points, dim3(grid1(n, 2048), nb), dim3(256), 0, st, b->seed, b->step, n, w.pts4);
+    hipError_t e0 = launch_sort(nullptr, 0, 0, w.pts4, n, nb, w.srt, nullptr, st);
     if (e0 != hipSuccess) return APMG_EHIP;
     hipLaunchKernelGGL(k_batch_gt, dim3(grid1(n, 2048), nb), dim3(256), 0, st, w.srt.spts, n, b->volume, b->vol[0],
                        b->vol[1], b->bricks, w.v);

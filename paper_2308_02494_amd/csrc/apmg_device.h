@@ -42,6 +42,8 @@ __device__ inline f32x16 mma_bf16(bf16x8 a, bf16x8 b, f32x16 c) {
 // Keeps the scheduler from hoisting loads across this point (bounds the number of
 // operand loads kept in flight, and with it register pressure).
 __device__ inline void sched_fence() { asm volatile("" ::: "memory"); }
+// Machine-scheduler barrier: no instruction moves across it.
+__device__ inline void sched_barrier() { __builtin_amdgcn_sched_barrier(0); }
 
 // Row of a 32x32 accumulator block held in register r by lane half hf.
 __host__ __device__ inline int acc_row(int r, int hf) { return 8 * (r >> 2) + 4 * hf + (r & 3); }
@@ -124,7 +126,7 @@ __device__ inline bool cell_of(const float l[3], float h, int R, int i0[3], floa
 // Load the 2*C values of an x-adjacent vertex pair (channel-last layout):
 // out[0..C) = vertex x0, out[C..2C) = vertex x0+1.
 template <int C, bool F16>
-__device__ inline void load_pair(const void* base, size_t idx, float out[2 * C]) {
+__device__ inline void load_pair(const void* base, uint32_t idx, float out[2 * C]) {
   if constexpr (!F16) {
     const float* p = (const float*)base + idx;
     if constexpr (C == 1) {
@@ -161,10 +163,11 @@ __device__ inline void load_pair(const void* base, size_t idx, float out[2 * C])
 }
 
 // The 8 corner values (channel-last) of grid g's cell i0: val[q][c], q = a + 2b + 4c'.
+// Element offsets fit 32 bits: a model's grids hold fewer than 2^31 values (checked on entry).
 template <int C, bool F16>
 __device__ inline void gather_cell(const void* F, int g, int R, const int i0[3], float val[8][C]) {
-  const size_t RC = (size_t)R * C, RRC = (size_t)R * R * C;
-  size_t base = (((size_t)g * R + i0[2]) * R + i0[1]) * RC + (size_t)i0[0] * C;
+  const uint32_t RC = (uint32_t)R * C, RRC = (uint32_t)R * R * C;
+  const uint32_t base = (((uint32_t)g * R + i0[2]) * R + i0[1]) * RC + (uint32_t)i0[0] * C;
 #pragma unroll
   for (int q2 = 0; q2 < 4; ++q2) {  // q2 = b + 2c'
     float pr[2 * C];

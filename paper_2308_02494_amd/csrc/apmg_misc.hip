@@ -94,15 +94,16 @@ __global__ void k_gt_sample(const float* vol, int nx, int ny, int nz, const floa
     v[i] = sample_volume(vol, nx, ny, e0, nn, pts[i], pts[ld + i], pts[2 * ld + i]);
 }
 
-// Training batch of every model: points from the counter stream, SoA [model][3][n].
-__global__ void k_batch_points(uint64_t seed, const uint64_t* step_ctr, int64_t n, float* pts) {
+// Training batch of every model: points from the counter stream as (x, y, z, 0) records
+// [model][n] (one 16-byte load per point for the spatial sort's gathers).
+__global__ void k_batch_points(uint64_t seed, const uint64_t* step_ctr, int64_t n, float4* pts4) {
   const int model = blockIdx.y;
   const uint64_t step = *step_ctr;
-  float* P = pts + (size_t)model * 3 * n;
+  float4* P = pts4 + (size_t)model * n;
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
     float x, y, z;
     uniform_point(seed, step, (uint32_t)model, (uint64_t)i, x, y, z);
-    P[i] = x; P[n + i] = y; P[2 * n + i] = z;
+    P[i] = make_float4(x, y, z, 0.f);
   }
 }
 
@@ -197,8 +198,33 @@ __device__ inline float powi(float l, int k) {
   return r;
 }
 
+// The flat-top exponent terms of Eq. (7): l^(2p), and l^(2p-1) for its derivative.  P > 0
+// fixes p at compile time (P = 10, the paper's value, takes a short multiplication chain);
+// P = 0 uses the runtime p.
+template <int P>
+__device__ inline float flat_pow(float l, int p) {
+  if constexpr (P == 10) {
+    const float l2 = l * l, l4 = l2 * l2, l8 = l4 * l4, l16 = l8 * l8;
+    return l16 * l4;
+  } else {
+    return powi(l, 2 * p);
+  }
+}
+template <int P>
+__device__ inline void flat_pow2(float l, int p, float& e2p, float& e2pm1) {
+  if constexpr (P == 10) {
+    const float l2 = l * l, l4 = l2 * l2, l8 = l4 * l4, l16 = l8 * l8, l18 = l16 * l2;
+    e2pm1 = l18 * l;
+    e2p = l18 * l2;
+  } else {
+    e2p = powi(l, 2 * p);
+    e2pm1 = powi(l, 2 * p - 1);
+  }
+}
+
 // Pass A: rho per point (Eq. (7)) and block sums of rho and err.
 // part: [model][block][2] = {sum rho, sum err}
+template <int PF>
 __global__ void __launch_bounds__(256) k_density_a(Shape s, const float* Gall, size_t G_stride,
     const float* pts, int64_t ld, size_t pts_stride, int64_t n, const float* err, size_t err_stride,
     int p, float* rho, size_t rho_stride, double* part, const int32_t* active) {
@@ -222,7 +248,7 @@ __global__ void __launch_bounds__(256) k_density_a(Shape s, const float* Gall, s
       for (int g = 0; g < s.M; ++g) {
         float l[3];
         local_coords(sG + 12 * g, x, y, z, l);
-        const float sv = powi(l[0], 2 * p) + powi(l[1], 2 * p) + powi(l[2], 2 * p);
+        const float sv = flat_pow<PF>(l[0], p) + flat_pow<PF>(l[1], p) + flat_pow<PF>(l[2], p);
         if (sv <= kSMax) r = __builtin_fmaf(sdet[g], __expf(-sv), r);
       }
       if (rho) rho[model * rho_stride + i] = r;
@@ -333,6 +359,7 @@ __global__ void k_density_coef(const float* rho, size_t rho_stride, const float*
 // Wave w of block (chunk, grid group, model) owns grid 4*blockIdx.y + w and streams the
 // chunk's points; one wave reduction per (grid, chunk).  part: [model][M][chunk][13]
 constexpr int kDensChunk = 4096;
+template <int PF>
 __global__ void __launch_bounds__(256) k_density_b2(Shape s, const float* Gall, size_t G_stride,
     const float* pts, int64_t ld, size_t pts_stride, int64_t n, const float* coef, size_t coef_stride, int p,
     double* part, const int32_t* active) {
@@ -356,13 +383,16 @@ __global__ void __launch_bounds__(256) k_density_b2(Shape s, const float* Gall, 
       const float xs[3] = {P[i], P[ld + i], P[2 * ld + i]};
       float l[3];
       local_coords(Gg, xs[0], xs[1], xs[2], l);
-      const float sv = powi(l[0], 2 * p) + powi(l[1], 2 * p) + powi(l[2], 2 * p);
+      float e2p[3], e2pm1[3];
+#pragma unroll
+      for (int d = 0; d < 3; ++d) flat_pow2<PF>(l[d], p, e2p[d], e2pm1[d]);
+      const float sv = e2p[0] + e2p[1] + e2p[2];
       if (!(sv <= kSMax)) continue;
       const float cphi = c * __expf(-sv);
       u[0] += cphi;
 #pragma unroll
       for (int d = 0; d < 3; ++d) {
-        const float cq = cphi * powi(l[d], 2 * p - 1);
+        const float cq = cphi * e2pm1[d];
         u[1 + 3 * d] = __builtin_fmaf(cq, xs[0], u[1 + 3 * d]);
         u[2 + 3 * d] = __builtin_fmaf(cq, xs[1], u[2 + 3 * d]);
         u[3 + 3 * d] = __builtin_fmaf(cq, xs[2], u[3 + 3 * d]);
@@ -377,17 +407,27 @@ __global__ void __launch_bounds__(256) k_density_b2(Shape s, const float* Gall, 
   }
 }
 
-// U[model][g][q] = sum over chunks of part[model][g][chunk][q], in chunk order.
+// U[model][g][q] = sum over chunks of part[model][g][chunk][q]: thread t sums a contiguous
+// range of chunks, then a fixed tree adds the 256 range sums.  Grid (M, models).
 __global__ void __launch_bounds__(256) k_density_b2_reduce(const double* part, int M, int nchunk, double* U,
                                                            const int32_t* active) {
-  const int model = blockIdx.y;
+  __shared__ double sh[256];
+  const int model = blockIdx.y, g = blockIdx.x;
   if (active && !active[model]) return;
-  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < 13 * M; e += gridDim.x * blockDim.x) {
-    const int g = e / 13, q = e % 13;
-    const double* pp = part + ((size_t)model * M + g) * nchunk * 13 + q;
-    double s = 0.0;
-    for (int k = 0; k < nchunk; ++k) s += pp[(size_t)k * 13];
-    U[(size_t)model * 13 * M + e] = s;
+  const double* pp = part + ((size_t)model * M + g) * nchunk * 13;
+  const int per = (nchunk + 255) / 256;
+  const int k0 = threadIdx.x * per, k1 = min(nchunk, k0 + per);
+  for (int q = 0; q < 13; ++q) {
+    double x = 0.0;
+    for (int k = k0; k < k1; ++k) x += pp[(size_t)k * 13 + q];
+    sh[threadIdx.x] = x;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+      if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) U[((size_t)model * M + g) * 13 + q] = sh[0];
+    __syncthreads();
   }
 }
 

@@ -113,6 +113,37 @@ __device__ inline void encode_grid(const Shape& s, const float* sG, const void* 
   trilerp<C>(val, w, e);
 }
 
+// One grid's contribution split in two so the gathers of the next grid can be in flight
+// while this one is consumed: grid_tap issues the 8 corner loads (always from a valid
+// address: cell 0 of grid 0 when the point is outside, invalid or past the last grid),
+// grid_tap_value interpolates and applies the Eq. (2) mask.
+template <int C> struct GridTap {
+  float w[3];
+  float val[8][C];
+  bool in;
+};
+
+template <int C, bool GF16>
+__device__ inline void grid_tap(const Shape& s, const float* sG, const void* F, int g, float x, float y, float z,
+                                bool valid, float hR, GridTap<C>& t) {
+  const bool gok = valid && g < s.M;
+  const int gg = gok ? g : 0;
+  float l[3];
+  local_coords(sG + 12 * gg, x, y, z, l);
+  int i0[3];
+  t.in = cell_of(l, hR, s.R, i0, t.w) && gok;
+#pragma unroll
+  for (int d = 0; d < 3; ++d) i0[d] = t.in ? i0[d] : 0;
+  gather_cell<C, GF16>(F, gg, s.R, i0, t.val);
+}
+
+template <int C>
+__device__ inline void grid_tap_value(const GridTap<C>& t, float e[C]) {
+  trilerp<C>(t.val, t.w, e);
+#pragma unroll
+  for (int c = 0; c < C; ++c) e[c] = t.in ? e[c] : 0.f;
+}
+
 // Forward pass of one 32-point tile.  With STY, the features are also written to the
 // LDS tile Ty in dy-block order: feature t of half hf goes to row 32 (t/16) + 16 hf + t%16.
 template <int C, int H, bool GF16, bool BF, bool STY = false>
@@ -127,30 +158,49 @@ __device__ inline void tile_fwd(const Shape& s, const float* sG, const void* F, 
   for (int b = 0; b < NB; ++b)
 #pragma unroll
     for (int r = 0; r < 16; ++r) z1[b][r] = 0.f;
+  // grid gi of this half is g = hf * Mh + gi.  Its gathers are issued one grid ahead into
+  // two alternating taps (no register copies); every tap load is unconditional (a zero tap
+  // past the last grid), so the loads stay in straight-line code and each grid waits only
+  // for its own.
+  GridTap<C> ta, tb;
+  auto gidx = [&](int gi) { return gi < s.Mh ? hf * s.Mh + gi : s.M; };
+  grid_tap<C, GF16>(s, sG, F, gidx(0), x, y, z, valid, hR, ta);
   if constexpr (!BF) {
     const float* W1 = (const float*)swz;
-    for (int gi = 0; gi < s.Mh; ++gi) {
+    auto consume = [&](const GridTap<C>& t, int gi) {
       float e[C];
-      encode_grid<C, GF16>(s, sG, F, hf * s.Mh + gi, x, y, z, valid, hR, e);
+      grid_tap_value<C>(t, e);
 #pragma unroll
       for (int c = 0; c < C; ++c) {
-        const size_t t = (size_t)gi * C + c;
-        if constexpr (STY) tt_put<BF>(Ty, 32 * ((int)t >> 4) + 16 * hf + ((int)t & 15), lane & 31, e[c]);
+        const int k = gi * C + c;
+        if constexpr (STY) tt_put<BF>(Ty, 32 * (k >> 4) + 16 * hf + (k & 15), lane & 31, e[c]);
 #pragma unroll
-        for (int b = 0; b < NB; ++b) z1[b] = mma_f32(W1[((size_t)b * s.KHP + t) * 64 + lane], e[c], z1[b]);
+        for (int b = 0; b < NB; ++b) z1[b] = mma_f32(W1[(b * s.KHP + k) * 64 + lane], e[c], z1[b]);
       }
+    };
+    for (int gi = 0; gi < s.Mh; gi += 2) {
+      grid_tap<C, GF16>(s, sG, F, gidx(gi + 1), x, y, z, valid, hR, tb);
+      sched_barrier();   // keep the loads ahead of the consumer (no sinking under register pressure)
+      consume(ta, gi);
+      grid_tap<C, GF16>(s, sG, F, gidx(gi + 2), x, y, z, valid, hR, ta);
+      sched_barrier();
+      if (gi + 1 < s.Mh) consume(tb, gi + 1);
     }
   } else {
     const bf16x8* W1 = (const bf16x8*)swz;
-    constexpr int GPS = 8 / C;
+    constexpr int GPS = 8 / C;   // grids per 8-feature operand step (even for C = 1, 2, 4)
     const int S1 = s.KHP / 8;
     for (int st = 0; st < S1; ++st) {
       bf16x8 B;
 #pragma unroll
       for (int u = 0; u < GPS; ++u) {
         const int gi = st * GPS + u;
+        GridTap<C>& cur = (u & 1) ? tb : ta;
+        GridTap<C>& nxt = (u & 1) ? ta : tb;
+        grid_tap<C, GF16>(s, sG, F, gidx(gi + 1), x, y, z, valid, hR, nxt);
+        sched_barrier();
         float e[C];
-        encode_grid<C, GF16>(s, sG, F, gi < s.Mh ? hf * s.Mh + gi : s.M, x, y, z, valid, hR, e);
+        grid_tap_value<C>(cur, e);
 #pragma unroll
         for (int c = 0; c < C; ++c) {
           B[u * C + c] = (short)bf16_bits(e[c]);
@@ -159,7 +209,7 @@ __device__ inline void tile_fwd(const Shape& s, const float* sG, const void* F, 
         }
       }
 #pragma unroll
-      for (int b = 0; b < NB; ++b) z1[b] = mma_bf16(W1[((size_t)b * S1 + st) * 64 + lane], B, z1[b]);
+      for (int b = 0; b < NB; ++b) z1[b] = mma_bf16(W1[(b * S1 + st) * 64 + lane], B, z1[b]);
     }
   }
   // second layer

@@ -26,13 +26,29 @@ __device__ inline uint32_t bin_of(float x, float y, float z) {
   return (b[2] * kBinsPerAxis + b[1]) * kBinsPerAxis + b[0];
 }
 
-// keys[model][i] = bin of point i, vals = i.  pts SoA per model: [3][ld] at model * pts_stride.
-__global__ void k_bin_keys(const float* pts, int64_t ld, size_t pts_stride, int64_t n, uint32_t* keys,
-                           uint32_t* vals) {
+// The input points of the sort: SoA [3][ld] at model * pts_stride, or, when pts4 is set,
+// (x, y, z, _) records [model][n].
+struct SortIn {
+  const float* pts; int64_t ld; size_t pts_stride;
+  const float4* pts4;
+  __device__ inline void get(int model, int64_t n, int64_t i, float& x, float& y, float& z) const {
+    if (pts4) {
+      const float4 q = pts4[model * n + i];
+      x = q.x; y = q.y; z = q.z;
+    } else {
+      const float* P = pts + model * pts_stride;
+      x = P[i]; y = P[ld + i]; z = P[2 * ld + i];
+    }
+  }
+};
+
+// keys[model][i] = bin of point i, vals = i.
+__global__ void k_bin_keys(SortIn in, int64_t n, uint32_t* keys, uint32_t* vals) {
   const int model = blockIdx.y;
-  const float* P = pts + model * pts_stride;
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-    keys[model * n + i] = bin_of(P[i], P[ld + i], P[2 * ld + i]);
+    float x, y, z;
+    in.get(model, n, i, x, y, z);
+    keys[model * n + i] = bin_of(x, y, z);
     vals[model * n + i] = (uint32_t)i;
   }
 }
@@ -55,41 +71,52 @@ __global__ void __launch_bounds__(256) k_radix_hist(const uint32_t* keys, int64_
     hist[((size_t)model * kRadixDigits + d) * ntiles + tile] = h[d];
 }
 
-// Exclusive scan of hist[model][*] (digit-major, tile-minor) in place; one block of 1024
-// threads per model, in chunks of 4096 (each thread a vector of 4 consecutive counts).
-__global__ void __launch_bounds__(1024) k_radix_scan(uint32_t* hist, int len) {
-  __shared__ uint32_t wsum[16];
-  __shared__ uint32_t carry;
-  typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
-  uint32_t* H = hist + (size_t)blockIdx.x * len;
+// Exclusive scan of a 256-thread block's values; *total gets the block sum.
+__device__ inline uint32_t block_excl_scan256(uint32_t v, uint32_t* total) {
+  __shared__ uint32_t wsum[4];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  if (threadIdx.x == 0) carry = 0;
-  __syncthreads();
-  for (int base = 0; base < len; base += 4096) {
-    const int i = base + 4 * threadIdx.x;
-    u32x4 v = {0, 0, 0, 0};
-    if (i + 3 < len) v = *(const u32x4*)(H + i);
-    else for (int k = 0; k < 4; ++k) if (i + k < len) v[k] = H[i + k];
-    const uint32_t tot = v[0] + v[1] + v[2] + v[3];
-    // inclusive scan of the per-thread totals within the wave
-    uint32_t x = tot;
+  uint32_t x = v;
 #pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-      const uint32_t y = __shfl_up(x, o, 64);
-      if (lane >= o) x += y;
-    }
-    if (lane == 63) wsum[wave] = x;
-    __syncthreads();
-    uint32_t wpre = 0;
-    for (int w = 0; w < wave; ++w) wpre += wsum[w];
-    const uint32_t excl = carry + wpre + x - tot;
-    u32x4 o4;
-    o4[0] = excl; o4[1] = excl + v[0]; o4[2] = o4[1] + v[1]; o4[3] = o4[2] + v[2];
-    if (i + 3 < len) *(u32x4*)(H + i) = o4;
-    else for (int k = 0; k < 4; ++k) if (i + k < len) H[i + k] = o4[k];
-    __syncthreads();
-    if (threadIdx.x == 1023) carry = excl + tot;
-    __syncthreads();
+  for (int o = 1; o < 64; o <<= 1) {
+    const uint32_t y = __shfl_up(x, o, 64);
+    if (lane >= o) x += y;
+  }
+  if (lane == 63) wsum[wave] = x;
+  __syncthreads();
+  uint32_t pre = 0;
+  for (int w = 0; w < wave; ++w) pre += wsum[w];
+  *total = wsum[0] + wsum[1] + wsum[2] + wsum[3];
+  __syncthreads();
+  return pre + x - v;
+}
+
+// The digit-major, tile-minor exclusive scan of hist[model][digit][tile] in two steps:
+// each row (digit) is scanned in place and its total kept, then the totals are scanned
+// into dbase[model][digit]; the scatter adds the two.  Rows: grid (digits, models).
+__global__ void __launch_bounds__(256) k_radix_rowscan(uint32_t* hist, int ntiles, uint32_t* rowtot) {
+  const int model = blockIdx.y, d = blockIdx.x;
+  uint32_t* H = hist + ((size_t)model * kRadixDigits + d) * ntiles;
+  uint32_t carry = 0;
+  for (int base = 0; base < ntiles; base += 256) {
+    const int i = base + threadIdx.x;
+    const uint32_t v = i < ntiles ? H[i] : 0u;
+    uint32_t tot;
+    const uint32_t ex = block_excl_scan256(v, &tot);
+    if (i < ntiles) H[i] = carry + ex;
+    carry += tot;
+  }
+  if (threadIdx.x == 0) rowtot[(size_t)model * kRadixDigits + d] = carry;
+}
+
+__global__ void __launch_bounds__(256) k_radix_digitscan(const uint32_t* rowtot, uint32_t* dbase) {
+  const int model = blockIdx.x;
+  uint32_t carry = 0;
+  for (int base = 0; base < kRadixDigits; base += 256) {
+    const int d = base + threadIdx.x;
+    uint32_t tot;
+    const uint32_t ex = block_excl_scan256(rowtot[(size_t)model * kRadixDigits + d], &tot);
+    dbase[(size_t)model * kRadixDigits + d] = carry + ex;
+    carry += tot;
   }
 }
 
@@ -98,7 +125,7 @@ __global__ void __launch_bounds__(1024) k_radix_scan(uint32_t* hist, int len) {
 // by lane (lane order) among keys with the same digit.
 __global__ void __launch_bounds__(256) k_radix_scatter(const uint32_t* kin, const uint32_t* vin, uint32_t* kout,
                                                        uint32_t* vout, int64_t n, int shift, const uint32_t* offs,
-                                                       int ntiles) {
+                                                       const uint32_t* dbase, int ntiles) {
   __shared__ uint32_t running[kRadixDigits];
   __shared__ uint32_t wcnt[4][kRadixDigits];
   const int model = blockIdx.y, tile = blockIdx.x;
@@ -108,7 +135,7 @@ __global__ void __launch_bounds__(256) k_radix_scatter(const uint32_t* kin, cons
   uint32_t* Kout = kout + model * n;
   uint32_t* Vout = vout + model * n;
   for (int d = threadIdx.x; d < kRadixDigits; d += blockDim.x)
-    running[d] = offs[((size_t)model * kRadixDigits + d) * ntiles + tile];
+    running[d] = offs[((size_t)model * kRadixDigits + d) * ntiles + tile] + dbase[(size_t)model * kRadixDigits + d];
   const int64_t base = (int64_t)tile * kSortTile;
   const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
   for (int r = 0; r < kSortTile / 256; ++r) {
@@ -156,16 +183,18 @@ __global__ void k_bin_starts(const uint32_t* keys, int64_t n, uint32_t* start) {
   }
 }
 
-// out[model][3][n] = points in sorted order (perm = sorted vals); optional per-point
-// float arrays permuted alongside (src_f[perm[j]] -> dst_f[j]).
-__global__ void k_permute_points(const float* pts, int64_t ld, size_t pts_stride, int64_t n, const uint32_t* perm,
-                                 float* out, const float* src_f, float* dst_f) {
+// out[model][3][n] = points in sorted order (perm = sorted vals), also as (x, y, z, 0) records
+// in out4[model][n]; optional per-point float arrays permuted alongside (src_f[perm[j]] -> dst_f[j]).
+__global__ void k_permute_points(SortIn in, int64_t n, const uint32_t* perm, float* out, float4* out4,
+                                 const float* src_f, float* dst_f) {
   const int model = blockIdx.y;
-  const float* P = pts + model * pts_stride;
   float* O = out + (size_t)model * 3 * n;
   for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < n; j += (int64_t)gridDim.x * blockDim.x) {
     const uint32_t i = perm[model * n + j];
-    O[j] = P[i]; O[n + j] = P[ld + i]; O[2 * n + j] = P[2 * ld + i];
+    float x, y, z;
+    in.get(model, n, i, x, y, z);
+    O[j] = x; O[n + j] = y; O[2 * n + j] = z;
+    out4[model * n + j] = make_float4(x, y, z, 0.f);
     if (src_f) dst_f[model * n + j] = src_f[model * n + i];
   }
 }
