@@ -80,6 +80,11 @@ def measured_traffic():
     return fetch + write
 
 
+def progress(msg):
+    """A line on stderr after each finished phase (the JSON line stays alone on stdout)."""
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
 def hip():
     lib = ctypes.CDLL("libamdhip64.so")
     lib.hipEventCreate.argtypes = [ctypes.POINTER(ctypes.c_void_p)]
@@ -262,6 +267,7 @@ def main():
     tr, vol, host = make_trainer(A, torch, synth, A.F32, N)
     dt, kern_ms = time_steps(A, torch, tr, args.steps, args.warmup, hl)
     ms_step = dt * 1e3 / args.steps
+    progress(f"headline: {ms_step:.3f} ms per step")
     value = N * args.steps / dt
     flops = mlp_flops_fwd_bwd(M * C, H) * N
     achieved = flops / (kern_ms * 1e-3) / 1e12
@@ -283,12 +289,14 @@ def main():
     if not args.skip_extra:
         extra = {}
         extra["infer_pts_per_s_fp32"] = time_forward(A, torch, host, N)
+        progress("fp32 inference done")
         del tr
         torch.cuda.empty_cache()
         trb, _, _ = make_trainer(A, torch, synth, A.BF16, N)
         dtb, kb = time_steps(A, torch, trb, args.steps, args.warmup, hl)
         extra["train_pts_per_s_bf16_mlp"] = N * args.steps / dtb
         extra["bf16_kernel_ms"] = kb
+        progress("bf16-MLP step done")
         del trb
         torch.cuda.empty_cache()
         for name, fn in (("config1_tiny_fp32", extra_c1), ("config3_mixed_1024", extra_c3),
@@ -298,6 +306,7 @@ def main():
                     extra[name] = fn(A, torch, synth, hl)
                 except Exception as e:  # an extra figure never hides the headline line
                     extra[name] = {"error": repr(e)[:200]}
+                progress(f"{name} done")
                 torch.cuda.empty_cache()
         out["extra"] = extra
     if args.copy_probe:
@@ -309,6 +318,7 @@ def main():
         del src, dst
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(vol.cpu().numpy().astype("float64"), host, args.cpu_sample)
+        progress("cpu baseline done")
     print(json.dumps(out), flush=True)
 
 
