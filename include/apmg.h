@@ -75,7 +75,7 @@ typedef enum { APMG_F32 = 0, APMG_F16 = 1, APMG_BF16 = 2 } apmg_dtype;
 
 /* flags */
 #define APMG_ACCUMULATE     0x1u  /* add into the outputs instead of overwriting them */
-#define APMG_DETERMINISTIC  0x2u  /* bitwise-reproducible reductions (slower grid scatter) */
+#define APMG_DETERMINISTIC  0x2u  /* accepted; every reduction already has a fixed order */
 #define APMG_ADD_REC_DG     0x4u  /* training step: add L_rec's transform gradient to L_density's */
 #define APMG_ERR_ABS        0x8u  /* training step: h(x) = |f - v| instead of (f - v)^2 */
 
@@ -193,6 +193,20 @@ apmg_status apmg_assign_bricks(const apmg_brick_table* table, const float* pts, 
  * All per-model arrays are contiguous arenas indexed by model: model b's
  * block starts at b * (block size).  Adam moments and counters are device
  * memory the caller zero-initialises. */
+/* Launch shapes of the training step (fields of 0 take the defaults).
+ *   tile_blocks: blocks of the fused forward+adjoint tile kernel per model
+ *     (each block = 4 waves of 32-point tiles); default ceil(512 / nb), at most
+ *     4 times the default and at most the number of 4-tile groups.
+ *   cell_unroll: candidates per batch in the grid-gradient gather, 2, 4 or 8
+ *     (default 4).
+ * Results depend on tile_blocks through the order of the weight-gradient sums
+ * (each setting is bitwise reproducible run to run). */
+typedef struct apmg_tuning {
+  int32_t tile_blocks;
+  int32_t cell_unroll;
+  int32_t reserved[6];
+} apmg_tuning;
+
 typedef struct apmg_batch {
   int32_t nb;                 /* number of models */
   apmg_model shape;           /* M, C, R, n_layers, width, dtypes; pointers ignored */
@@ -217,10 +231,79 @@ typedef struct apmg_batch {
   int32_t p;                  /* flat-top strength (10) */
   uint32_t flags;
   double* losses;             /* [nb][2] output: L_rec, L_density */
+  const apmg_tuning* tuning;  /* HOST pointer, read when the call is made; NULL = defaults */
+  const int32_t* frozen;      /* [nb] or NULL: 1 = model retired, nothing of it changes */
+  const float* lr_scale;      /* [nb] or NULL: multiplies lr and lr_G of each model */
 } apmg_batch;
 
 apmg_status apmg_batched_step(const apmg_batch* batch, void* ws, size_t ws_bytes,
                               hipStream_t stream);
+
+/* Autotuner: times the training step's phases (points, sort, ground truth,
+ * tile kernel, grid-gradient gather, density passes; no Adam update, no
+ * counter change -- parameters, moments and the step counter are left as they
+ * are, the losses array is written) for candidate launch shapes around the
+ * defaults, and returns the fastest in *best (HOST) with its time in *best_ms.
+ * Needs the workspace of APMG_OP_BATCHED_STEP for this batch.  Synchronises
+ * `stream` (hipEvent timing), so it must not be called during graph capture.
+ * The caller keeps the result and passes it as batch->tuning. */
+apmg_status apmg_autotune_batched_step(const apmg_batch* batch, void* ws, size_t ws_bytes,
+                                       hipStream_t stream, apmg_tuning* best, float* best_ms);
+
+/* ---------------------------------------------------------------- training control
+ * On-device schedule of a training run (Sec. 4.3.2 "Delayed start" and
+ * "Early stopping"; Sec. 5.2 early stopping of brick models), applied after
+ * each training step to that step's losses, per model:
+ *   - delayed start: transforms are not trained during the first `delay`
+ *     iterations (500 in the paper);
+ *   - transform early stop: the mean of L_density over each block of
+ *     `ma_window` density iterations (1000) is compared with the previous
+ *     block's mean; when it is not lower by the relative amount `ma_rel`
+ *     (1e-4, "0.01%"), transform training stops for good; it also stops once
+ *     the next iteration would exceed stop_frac * total_iters (80%);
+ *   - plateau scheduler on L_rec: an iteration whose L_rec is below
+ *     best * (1 - plateau_rel) (1e-4) becomes the best and resets the count of
+ *     bad iterations; after more than `patience` (500) bad iterations in a
+ *     row the model's learning rates are multiplied by plateau_factor (0.1)
+ *     and the count restarts; the max_reductions-th (3rd) reduction retires
+ *     the model (frozen = 1).
+ * State per model is apmg_ctl_state (device, zero-initialised by the caller);
+ * density_active, frozen and lr_scale are the batch's arrays for the next
+ * step (initialise them to (delay == 0), 0 and 1).  A frozen model's state no
+ * longer changes.  Asynchronous and graph-capturable like the step. */
+typedef struct apmg_ctl_state {
+  int32_t iter;               /* iterations completed */
+  int32_t density_done;       /* transform training stopped */
+  int32_t ma_count;           /* density iterations in the current block */
+  int32_t have_prev;          /* a previous block mean exists */
+  int32_t bad;                /* plateau: bad iterations in a row */
+  int32_t reductions;         /* plateau: learning-rate reductions so far */
+  double ma_sum;              /* sum of L_density over the current block */
+  double ma_prev;             /* mean of the previous block */
+  double best;                /* plateau: best L_rec */
+} apmg_ctl_state;
+
+typedef struct apmg_control {
+  int32_t nb;
+  int32_t delay;              /* 500 */
+  int32_t total_iters;        /* length of the run */
+  int32_t ma_window;          /* 1000 */
+  int32_t patience;           /* 500 */
+  int32_t max_reductions;     /* 3 */
+  float stop_frac;            /* 0.8 */
+  float plateau_factor;       /* 0.1 */
+  double ma_rel;              /* 1e-4 */
+  double plateau_rel;         /* 1e-4 */
+  apmg_ctl_state* state;      /* [nb] */
+  int32_t* density_active;    /* [nb] written */
+  int32_t* frozen;            /* [nb] written */
+  float* lr_scale;            /* [nb] written */
+} apmg_control;
+
+/* losses: [nb][2] (L_rec, L_density) of the step just taken (the batch's
+ * losses array).  EINVAL for a NULL pointer, nb < 1, delay < 0, ma_window < 1,
+ * patience < 0, max_reductions < 1. */
+apmg_status apmg_train_control(const apmg_control* control, const double* losses, hipStream_t stream);
 
 /* ---------------------------------------------------------------- workspace
  * Bytes of workspace for `op` (one of the values below) on a model (or, for

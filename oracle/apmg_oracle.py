@@ -641,3 +641,77 @@ def zero_adam_state(model):
             "mG": np.zeros((np.asarray(model["G"]).shape[0], 3, 4)),
             "vG": np.zeros((np.asarray(model["G"]).shape[0], 3, 4)),
             "t": 0, "tG": 0}
+
+
+# --------------------------------------------------------------------------
+# Training schedule: Sec. 4.3.2 "Delayed start", "Early stopping"; Sec. 5.2
+# early stopping of brick models (plateau scheduler)
+# --------------------------------------------------------------------------
+
+CONTROL_DEFAULTS = {"delay": 500, "ma_window": 1000, "ma_rel": 1e-4, "stop_frac": 0.8, "patience": 500,
+                    "plateau_rel": 1e-4, "plateau_factor": 0.1, "max_reductions": 3}
+
+
+def control_initial(delay=CONTROL_DEFAULTS["delay"]):
+    """Per-model schedule state before the first iteration, and the flags of the first
+    iteration (transforms train in it only when delay is 0)."""
+    return {"iter": 0, "density_done": 0, "ma_count": 0, "have_prev": 0, "bad": 0, "reductions": 0,
+            "ma_sum": 0.0, "ma_prev": 0.0, "best": 0.0,
+            "density_active": 1 if delay == 0 else 0, "frozen": 0, "lr_scale": np.float32(1.0)}
+
+
+def control_update(st, L_rec, L_density, total_iters, **kw):
+    """The schedule after one iteration with losses (L_rec, L_density); returns the new state.
+
+    Readings:
+    * Delayed start: transforms are not trained in iterations 1..delay (the
+      paper's 500); iteration t trains them when t > delay.
+    * Transform early stop: the paper's "1000-iteration moving average has not
+      reduced by 0.01%" is read on consecutive non-overlapping blocks of
+      ma_window density iterations: when a block's mean L_density is not below
+      the previous block's mean times (1 - ma_rel), transform training stops for
+      good.  It also stops for iterations beyond stop_frac * total_iters (80%),
+      the product taken in float32 and truncated.
+    * Plateau scheduler (Sec. 5.2): an iteration whose L_rec is below
+      best * (1 - plateau_rel) becomes the best and resets the bad count;
+      otherwise the bad count grows; more than `patience` bad iterations in a
+      row multiply the learning rates by plateau_factor (float32) and restart
+      the count; the max_reductions-th reduction retires the model.
+    * A retired model's state no longer changes.
+    """
+    p = dict(CONTROL_DEFAULTS)
+    p.update(kw)
+    st = dict(st)
+    if st["frozen"]:
+        return st
+    it = st["iter"] + 1
+    if st["density_active"]:
+        st["ma_sum"] = st["ma_sum"] + float(L_density)
+        st["ma_count"] += 1
+        if st["ma_count"] == p["ma_window"]:
+            mean = st["ma_sum"] / float(p["ma_window"])
+            if st["have_prev"] and not (mean < st["ma_prev"] * (1.0 - p["ma_rel"])):
+                st["density_done"] = 1
+            st["ma_prev"] = mean
+            st["have_prev"] = 1
+            st["ma_sum"] = 0.0
+            st["ma_count"] = 0
+    limit = int(np.float32(p["stop_frac"]) * np.float32(total_iters))
+    if it + 1 > limit:
+        st["density_done"] = 1
+    if it == 1 or float(L_rec) < st["best"] * (1.0 - p["plateau_rel"]):
+        st["best"] = float(L_rec)
+        st["bad"] = 0
+    else:
+        st["bad"] += 1
+    frozen = 0
+    if st["bad"] > p["patience"]:
+        st["lr_scale"] = np.float32(np.float32(st["lr_scale"]) * np.float32(p["plateau_factor"]))
+        st["bad"] = 0
+        st["reductions"] += 1
+        if st["reductions"] >= p["max_reductions"]:
+            frozen = 1
+    st["iter"] = it
+    st["density_active"] = 1 if (not frozen and it >= p["delay"] and not st["density_done"]) else 0
+    st["frozen"] = frozen
+    return st

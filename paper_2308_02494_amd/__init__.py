@@ -47,13 +47,30 @@ class ApmgBrickTable(ctypes.Structure):
     _fields_ = [("dims", c_i32 * 3), ("vol", c_i32 * 3), ("B", c_i32), ("ghost", c_i32)]
 
 
+class ApmgTuning(ctypes.Structure):
+    _fields_ = [("tile_blocks", c_i32), ("cell_unroll", c_i32), ("reserved", c_i32 * 6)]
+
+
 class ApmgBatch(ctypes.Structure):
     _fields_ = [("nb", c_i32), ("shape", ApmgModel), ("G", c_p), ("F", c_p), ("F_lowp", c_p), ("W", c_p),
                 ("mG", c_p), ("vG", c_p), ("mF", c_p), ("vF", c_p), ("mW", c_p), ("vW", c_p),
                 ("t", c_p), ("tG", c_p), ("density_active", c_p), ("volume", c_p), ("bricks", c_p),
                 ("vol", c_i32 * 3), ("n", c_i64), ("seed", c_u64), ("step", c_p),
                 ("lr", c_f32), ("lr_G", c_f32), ("beta1", c_f32), ("beta2", c_f32), ("adam_eps", c_f32),
-                ("eps_density", c_f64), ("p", c_i32), ("flags", c_u32), ("losses", c_p)]
+                ("eps_density", c_f64), ("p", c_i32), ("flags", c_u32), ("losses", c_p),
+                ("tuning", ctypes.POINTER(ApmgTuning)), ("frozen", c_p), ("lr_scale", c_p)]
+
+
+class ApmgCtlState(ctypes.Structure):
+    _fields_ = [("iter", c_i32), ("density_done", c_i32), ("ma_count", c_i32), ("have_prev", c_i32),
+                ("bad", c_i32), ("reductions", c_i32), ("ma_sum", c_f64), ("ma_prev", c_f64), ("best", c_f64)]
+
+
+class ApmgControl(ctypes.Structure):
+    _fields_ = [("nb", c_i32), ("delay", c_i32), ("total_iters", c_i32), ("ma_window", c_i32),
+                ("patience", c_i32), ("max_reductions", c_i32), ("stop_frac", c_f32), ("plateau_factor", c_f32),
+                ("ma_rel", c_f64), ("plateau_rel", c_f64), ("state", c_p), ("density_active", c_p),
+                ("frozen", c_p), ("lr_scale", c_p)]
 
 
 _sigs = {
@@ -73,6 +90,9 @@ _sigs = {
     "apmg_uniform_points": [c_u64, c_u64, c_u32, c_i64, c_i64, c_p, c_i64, c_p],
     "apmg_gt_sample": [c_p, c_i32, c_i32, c_i32, c_p, c_i64, c_i64, c_p, c_p],
     "apmg_profile_events": [c_p, c_p],
+    "apmg_autotune_batched_step": [ctypes.POINTER(ApmgBatch), c_p, ctypes.c_size_t, c_p,
+                                   ctypes.POINTER(ApmgTuning), ctypes.POINTER(c_f32)],
+    "apmg_train_control": [ctypes.POINTER(ApmgControl), c_p, c_p],
 }
 for _name, _args in _sigs.items():
     _fn = getattr(_lib, _name)
@@ -304,7 +324,7 @@ class Trainer:
 
     def __init__(self, models_host, volume, bricks, n, seed=7, mlp_dtype=F32, grid_dtype=torch.float32,
                  lr=0.01, lr_G=0.001, betas=(0.9, 0.99), adam_eps=1e-8, eps_density=1e-12, p=10, flags=0,
-                 device="cuda"):
+                 device="cuda", control=None, tuning=None):
         nb = len(models_host)
         assert nb == len(bricks)
         dev = torch.device(device)
@@ -351,12 +371,82 @@ class Trainer:
         b.lr, b.lr_G, b.beta1, b.beta2, b.adam_eps = lr, lr_G, betas[0], betas[1], adam_eps
         b.eps_density, b.p, b.flags = eps_density, p, flags
         b.losses = self.losses.data_ptr()
+        self.frozen = torch.zeros(nb, dtype=torch.int32, device=dev)
+        self.lr_scale = torch.ones(nb, dtype=torch.float32, device=dev)
+        b.frozen = self.frozen.data_ptr()
+        b.lr_scale = self.lr_scale.data_ptr()
+        self.tuning = None
         self.batch = b
+        if tuning is not None:
+            self.set_tuning(tuning)
         self.ws = _workspace(OP_BATCHED_STEP, b, n, dev)
+        self.control = None
+        if control is not None:
+            self.enable_control(**control)
+
+    def set_tuning(self, tuning):
+        """Launch shapes for the step: an ApmgTuning, a dict (tile_blocks, cell_unroll) or None."""
+        if isinstance(tuning, dict):
+            t = ApmgTuning()
+            t.tile_blocks = tuning.get("tile_blocks", 0)
+            t.cell_unroll = tuning.get("cell_unroll", 0)
+            tuning = t
+        self.tuning = tuning
+        self.batch.tuning = ctypes.pointer(tuning) if tuning is not None else None
+
+    def autotune(self):
+        """Runs apmg_autotune_batched_step (synchronising; parameters unchanged) and adopts
+        the fastest launch shapes.  Returns (tuning dict, ms per step)."""
+        best = ApmgTuning()
+        ms = c_f32()
+        _check("apmg_autotune_batched_step",
+               _lib.apmg_autotune_batched_step(ctypes.byref(self.batch), _ptr(self.ws), self.ws.numel(),
+                                              _stream(self.device), ctypes.byref(best), ctypes.byref(ms)))
+        self.set_tuning(best)
+        return {"tile_blocks": best.tile_blocks, "cell_unroll": best.cell_unroll}, ms.value
+
+    def enable_control(self, total_iters, delay=500, ma_window=1000, ma_rel=1e-4, stop_frac=0.8, patience=500,
+                       plateau_rel=1e-4, plateau_factor=0.1, max_reductions=3):
+        """On-device training schedule (apmg_train_control) applied after every step: delayed
+        start of the transforms, their early stop, and the plateau scheduler that retires
+        models.  Defaults are the paper's values."""
+        nb = self.batch.nb
+        self.ctl_state = torch.zeros((nb, ctypes.sizeof(ApmgCtlState)), dtype=torch.uint8, device=self.device)
+        self.density_active.fill_(1 if delay == 0 else 0)
+        self.frozen.zero_()
+        self.lr_scale.fill_(1.0)
+        c = ApmgControl()
+        c.nb, c.delay, c.total_iters, c.ma_window = nb, delay, total_iters, ma_window
+        c.patience, c.max_reductions, c.stop_frac, c.plateau_factor = patience, max_reductions, stop_frac, plateau_factor
+        c.ma_rel, c.plateau_rel = ma_rel, plateau_rel
+        c.state = self.ctl_state.data_ptr()
+        c.density_active = self.density_active.data_ptr()
+        c.frozen = self.frozen.data_ptr()
+        c.lr_scale = self.lr_scale.data_ptr()
+        self.control = c
+
+    def control_state(self):
+        """Per-model control state as a list of dicts (copies to the host)."""
+        raw = self.ctl_state.cpu().numpy()
+        out = []
+        for row in raw:
+            st = ApmgCtlState.from_buffer_copy(row.tobytes())
+            out.append({k: getattr(st, k) for k, _ in ApmgCtlState._fields_})
+        return out
 
     def step(self):
+        st = _stream(self.device)
         _check("apmg_batched_step", _lib.apmg_batched_step(ctypes.byref(self.batch), _ptr(self.ws),
-                                                           self.ws.numel(), _stream(self.device)))
+                                                           self.ws.numel(), st))
+        if self.control is not None:
+            _check("apmg_train_control", _lib.apmg_train_control(ctypes.byref(self.control),
+                                                                 self.losses.data_ptr(), st))
+
+
+def train_control(control, losses):
+    """apmg_train_control on an ApmgControl and a [nb, 2] float64 device tensor of losses."""
+    _check("apmg_train_control", _lib.apmg_train_control(ctypes.byref(control), losses.data_ptr(),
+                                                         _stream(losses.device)))
 
 
 # ----------------------------------------------------------------------------- autograd

@@ -75,6 +75,31 @@ int tile_blocks(int64_t n) {
   return (int)std::max<int64_t>(1, std::min<int64_t>(b, kMaxTileBlocks));
 }
 
+// Training-step launch shapes (apmg_tuning): tile-kernel blocks per model, default
+// ceil(512 / nb) (about two blocks per CU over all models), at most 4x the default,
+// 1024, and the number of 4-tile groups; gather batch of 2, 4 or 8 candidates.
+struct Tune { int tile_blocks; int cell_unroll; };
+int step_groups(int64_t n) {
+  const int64_t tiles = (std::max<int64_t>(n, 1) + 31) / 32;
+  return (int)std::max<int64_t>(1, (tiles + kWavesPerBlock - 1) / kWavesPerBlock);
+}
+int step_default_blocks(int64_t n, int nb) {
+  return std::max(1, std::min((kMaxTileBlocks + nb - 1) / nb, step_groups(n)));
+}
+int step_max_blocks(int64_t n, int nb) {
+  return std::max(1, std::min(std::min(4 * step_default_blocks(n, nb), 1024), step_groups(n)));
+}
+bool resolve_tune(const apmg_tuning* t, int64_t n, int nb, Tune* out) {
+  out->tile_blocks = step_default_blocks(n, nb);
+  out->cell_unroll = 4;
+  if (!t) return true;
+  if (t->tile_blocks < 0 || t->tile_blocks > step_max_blocks(n, nb)) return false;
+  if (t->cell_unroll != 0 && t->cell_unroll != 2 && t->cell_unroll != 4 && t->cell_unroll != 8) return false;
+  if (t->tile_blocks > 0) out->tile_blocks = t->tile_blocks;
+  if (t->cell_unroll > 0) out->cell_unroll = t->cell_unroll;
+  return true;
+}
+
 // Adjoint passes: each accumulates a block of second-layer gradient rows and a slice of
 // first-layer gradient columns in LDS; the first pass also scatters dF, reduces dG and
 // the output-layer gradient.  Chosen so that every pass fits the LDS.
@@ -178,7 +203,7 @@ void take_cell(Carver& cv, const Shape& s, int64_t n, int nb, CellWs* o) {
 hipError_t launch_cells(const Shape& s, bool gf16, const float* G, size_t G_stride, const void* F, size_t F_stride,
                         const SortWs& sw, int64_t n, const CellWs& cw, float* dF, size_t dF_stride, int accumulate,
                         bool want_dG, double* dG, size_t dG_stride, int dG_accumulate, int nb,
-                        const int32_t* active, hipStream_t st) {
+                        const int32_t* active, hipStream_t st, int unroll = 4, const int32_t* dG_active = nullptr) {
   CellArgs c;
   memset(&c, 0, sizeof(c));
   c.s = s; c.G = G; c.G_stride = G_stride; c.F = F; c.F_stride = F_stride;
@@ -187,19 +212,25 @@ hipError_t launch_cells(const Shape& s, bool gf16, const float* G, size_t G_stri
   const int64_t nblocks = (int64_t)cell_blocks(s) * s.M * nb;
   if (nblocks > 0x7fffffff) return hipErrorInvalidValue;
   const dim3 grid((unsigned)nblocks);
+#define APMG_PULL(CC_, F16_, DG_)                                                                   \
+  {                                                                                                 \
+    if (unroll == 2) hipLaunchKernelGGL((k_cell_pull<CC_, F16_, DG_, 2>), grid, dim3(256), 0, st, c); \
+    else if (unroll == 8) hipLaunchKernelGGL((k_cell_pull<CC_, F16_, DG_, 8>), grid, dim3(256), 0, st, c); \
+    else hipLaunchKernelGGL((k_cell_pull<CC_, F16_, DG_, 4>), grid, dim3(256), 0, st, c);           \
+  }
 #define APMG_CELL(CC_, F16_)                                                                        \
   if (s.C == CC_ && gf16 == F16_) {                                                                 \
-    if (want_dG) hipLaunchKernelGGL((k_cell_pull<CC_, F16_, true>), grid, dim3(256), 0, st, c);       \
-    else hipLaunchKernelGGL((k_cell_pull<CC_, F16_, false>), grid, dim3(256), 0, st, c);              \
+    if (want_dG) APMG_PULL(CC_, F16_, true) else APMG_PULL(CC_, F16_, false)                         \
     if (dF) hipLaunchKernelGGL((k_cell_to_vertex<CC_>), dim3(grid1((int64_t)s.R * s.R * s.R, 1024), s.M, nb), \
                                dim3(256), 0, st, s, cw.CC, dF, dF_stride, accumulate, active);       \
   }
   APMG_CELL(1, false) APMG_CELL(2, false) APMG_CELL(4, false)
   APMG_CELL(1, true) APMG_CELL(2, true) APMG_CELL(4, true)
 #undef APMG_CELL
+#undef APMG_PULL
   if (dG)
     hipLaunchKernelGGL(k_reduce_cell_dG, dim3(1, nb), dim3(256), 0, st, cw.dGpart, s.M, cell_blocks(s), dG,
-                       dG_stride, dG_accumulate, active);
+                       dG_stride, dG_accumulate, dG_active ? dG_active : active);
   return hipGetLastError();
 }
 
@@ -288,6 +319,8 @@ struct StepWs {
   double* dG;     // [nb][12 M]  transform gradient used by Adam
   double* lrec;   // [nb] sum (f - v)^2
   double* part;   // adjoint partials
+  int32_t* live;  // [nb] models that train this step (not frozen)
+  int32_t* dlive; // [nb] models whose transforms train this step
   SortWs srt;
   CellWs cell;
   DenWs den;
@@ -312,7 +345,9 @@ size_t step_ws(const apmg_batch* b, const Shape& s, void* ws, StepWs* o) {
   w.dW = cv.take<float>((size_t)nb * w_elems(s));
   w.dG = cv.take<double>((size_t)nb * 12 * s.M);
   w.lrec = cv.take<double>((size_t)nb);
-  w.part = cv.take<double>((size_t)nb * tile_blocks(b->n) * max_part_len(s, bf));
+  w.part = cv.take<double>((size_t)nb * step_max_blocks(b->n, nb) * max_part_len(s, bf));
+  w.live = cv.take<int32_t>((size_t)nb);
+  w.dlive = cv.take<int32_t>((size_t)nb);
   take_sort(cv, b->n, nb, false, &w.srt);
   take_cell(cv, s, b->n, nb, &w.cell);
   size_t off = cv.off;
@@ -594,25 +629,32 @@ apmg_status apmg_convert_grids(int32_t M, int32_t C, int32_t R, const void* src,
 
 }  // extern "C"
 
-extern "C" apmg_status apmg_batched_step(const apmg_batch* b, void* ws, size_t ws_bytes, hipStream_t st) {
+namespace {
+
+apmg_status check_batch(const apmg_batch* b, Shape* s) {
   if (!b || b->nb < 1 || b->n < 0) return APMG_EINVAL;
-  Shape s;
-  apmg_status rc = check_model(&b->shape, false, &s);
+  apmg_status rc = check_model(&b->shape, false, s);
   if (rc != APMG_OK) return rc;
-  const bool bf = b->shape.mlp_dtype == APMG_BF16, gf16 = b->shape.grid_dtype == APMG_F16;
   if (!b->G || !b->F || !b->W || !b->mG || !b->vG || !b->mF || !b->vF || !b->mW || !b->vW || !b->t ||
       !b->tG || !b->density_active || !b->volume || !b->bricks || !b->step || !b->losses)
     return APMG_EINVAL;
-  if (gf16 && !b->F_lowp) return APMG_EINVAL;
+  if (b->shape.grid_dtype == APMG_F16 && !b->F_lowp) return APMG_EINVAL;
   for (int d = 0; d < 3; ++d) if (b->vol[d] < 2) return APMG_EINVAL;
   if (b->p < 1 || !(b->eps_density >= 0.0)) return APMG_EINVAL;
-  if (!ws || ws_bytes < step_ws(b, s, nullptr, nullptr)) return APMG_EWORKSPACE;
+  return APMG_OK;
+}
+
+// The phases of one training step; `update` adds the Adam updates and counter increments.
+apmg_status run_step(const apmg_batch* b, const Shape& s, void* ws, const Tune& tu, bool update, hipStream_t st) {
+  const bool bf = b->shape.mlp_dtype == APMG_BF16, gf16 = b->shape.grid_dtype == APMG_F16;
   const int nb = b->nb;
   const int64_t n = b->n;
   StepWs w;
   step_ws(b, s, ws, &w);
   const size_t nF = f_elems(s), nW = w_elems(s), nG = (size_t)12 * s.M;
   const size_t swz_stride = swz_sizes(s).total();
+  hipLaunchKernelGGL(k_live_masks, dim3((nb + 63) / 64), dim3(64), 0, st, b->frozen, b->density_active, w.live,
+                     w.dlive, nb);
 
   // 1. batch points, sorted by spatial bin, and the ground truth at the sorted points
   if (n > 0) {
@@ -632,7 +674,7 @@ extern "C" apmg_status apmg_batched_step(const apmg_batch* b, void* ws, size_t w
   if (n == 0) hipLaunchKernelGGL(k_fill_f32, dim3(grid1((int64_t)(nb * nF))), dim3(256), 0, st, w.dF, nb * nF, 0.f);
 
   // 3. forward + adjoint of L_rec (part 1 of the step)
-  const int nblk = tile_blocks(n);
+  const int nblk = tu.tile_blocks;
   const std::vector<Pass> passes = plan_passes(s, bf, true);
   if (passes.empty()) return APMG_EUNSUPPORTED;
   const int kb = passes.size() == 1 ? register_kb(s) : 0;
@@ -655,6 +697,7 @@ extern "C" apmg_status apmg_batched_step(const apmg_batch* b, void* ws, size_t w
     a.do_w3 = ps.first;
     a.want_loss = ps.first;
     a.part = w.part;
+    a.active = w.live;
     const int ncols = ps.c1_hi - ps.c1_lo, nrows = ps.w2_hi - ps.w2_lo;
     const PartLayout pl = part_layout(s, ncols, nrows);
     a.part_len = pl.len;
@@ -665,16 +708,16 @@ extern "C" apmg_status apmg_batched_step(const apmg_batch* b, void* ws, size_t w
     if (ncols > 0)
       hipLaunchKernelGGL(k_reduce_parts, dim3(red_blocks((int64_t)s.H * ncols), nb), dim3(256), 0, st, w.part, nblk,
                          pl.len, pl.o_w1, s.H * ncols, ncols, s.MC, ps.c1_lo, w.dW, (double*)nullptr, nW, 0,
-                         (const int32_t*)nullptr);
+                         (const int32_t*)w.live);
     if (nrows > 0)
       hipLaunchKernelGGL(k_reduce_parts, dim3(red_blocks((int64_t)s.H * nrows), nb), dim3(256), 0, st, w.part, nblk,
                          pl.len, pl.o_w2, s.H * nrows, s.H * nrows, 0, s.H * s.MC + ps.w2_lo * s.H, w.dW,
-                         (double*)nullptr, nW, 0, (const int32_t*)nullptr);
+                         (double*)nullptr, nW, 0, (const int32_t*)w.live);
     if (ps.first) {
       hipLaunchKernelGGL(k_reduce_parts, dim3(1, nb), dim3(256), 0, st, w.part, nblk, pl.len, pl.o_w3, s.H, s.H, 0,
-                         s.H * s.MC + s.H * s.H, w.dW, (double*)nullptr, nW, 0, (const int32_t*)nullptr);
+                         s.H * s.MC + s.H * s.H, w.dW, (double*)nullptr, nW, 0, (const int32_t*)w.live);
       hipLaunchKernelGGL(k_reduce_parts, dim3(1, nb), dim3(256), 0, st, w.part, nblk, pl.len, pl.o_loss, 1, 1, 0, 0,
-                         (float*)nullptr, w.lrec, (size_t)1, 0, (const int32_t*)nullptr);
+                         (float*)nullptr, w.lrec, (size_t)1, 0, (const int32_t*)w.live);
     }
   }
   if (n > 0)
@@ -685,29 +728,95 @@ extern "C" apmg_status apmg_batched_step(const apmg_batch* b, void* ws, size_t w
   // 4. grid gradient from the per-cell pass; L_rec's transform gradient only under APMG_ADD_REC_DG
   if (n > 0) {
     e = launch_cells(s, gf16, b->G, nG, gf16 ? (const void*)b->F_lowp : (const void*)b->F, nF, w.srt, n, w.cell,
-                     w.dF, nF, 0, rec_dG, nullptr, 0, 0, nb, nullptr, st);
+                     w.dF, nF, 0, rec_dG, nullptr, 0, 0, nb, w.live, st, tu.cell_unroll);
     if (e != hipSuccess) return APMG_EHIP;
   }
-  // 5. density loss and its transform gradient (part 2), for active models
+  // 5. density loss and its transform gradient (part 2), for models whose transforms train
   if (n > 0) {
     e = launch_density(s, b->G, nG, w.srt.spts, n, (size_t)3 * n, n, w.err, n, b->eps_density, b->p, b->losses + 1,
-                       2, w.dG, nG, 0, nullptr, w.den, nb, b->density_active, st);
+                       2, w.dG, nG, 0, nullptr, w.den, nb, w.dlive, st);
     if (e != hipSuccess) return APMG_EHIP;
     if (rec_dG)
       hipLaunchKernelGGL(k_reduce_cell_dG, dim3(1, nb), dim3(256), 0, st, w.cell.dGpart, s.M, cell_blocks(s), w.dG,
-                         nG, 1, b->density_active);
+                         nG, 1, w.dlive);
   }
+  if (!update) return hip_status(hipGetLastError());
 
-  // 5. Adam: grids and MLP every step, transforms while the density phase is active
+  // 6. Adam: grids and MLP every step, transforms while the density phase is active
   hipLaunchKernelGGL(k_adam, dim3(grid1((int64_t)nF), nb), dim3(256), 0, st, b->F, b->mF, b->vF, (const float*)w.dF,
-                     (const double*)nullptr, nF, (const int32_t*)b->t, (const int32_t*)nullptr, b->lr, b->beta1,
-                     b->beta2, b->adam_eps, gf16 ? (__half*)b->F_lowp : (__half*)nullptr);
+                     (const double*)nullptr, nF, (const int32_t*)b->t, (const int32_t*)w.live, b->lr, b->beta1,
+                     b->beta2, b->adam_eps, gf16 ? (__half*)b->F_lowp : (__half*)nullptr, b->lr_scale);
   hipLaunchKernelGGL(k_adam, dim3(grid1((int64_t)nW), nb), dim3(256), 0, st, b->W, b->mW, b->vW, (const float*)w.dW,
-                     (const double*)nullptr, nW, (const int32_t*)b->t, (const int32_t*)nullptr, b->lr, b->beta1,
-                     b->beta2, b->adam_eps, (__half*)nullptr);
+                     (const double*)nullptr, nW, (const int32_t*)b->t, (const int32_t*)w.live, b->lr, b->beta1,
+                     b->beta2, b->adam_eps, (__half*)nullptr, b->lr_scale);
   hipLaunchKernelGGL(k_adam, dim3(1, nb), dim3(256), 0, st, b->G, b->mG, b->vG, (const float*)nullptr,
-                     (const double*)w.dG, nG, (const int32_t*)b->tG, b->density_active, b->lr_G, b->beta1, b->beta2,
-                     b->adam_eps, (__half*)nullptr);
-  hipLaunchKernelGGL(k_step_counters, dim3((nb + 63) / 64), dim3(64), 0, st, b->t, b->tG, b->density_active, b->step, nb);
+                     (const double*)w.dG, nG, (const int32_t*)b->tG, (const int32_t*)w.dlive, b->lr_G, b->beta1,
+                     b->beta2, b->adam_eps, (__half*)nullptr, b->lr_scale);
+  hipLaunchKernelGGL(k_step_counters, dim3((nb + 63) / 64), dim3(64), 0, st, b->t, b->tG, (const int32_t*)w.live,
+                     (const int32_t*)w.dlive, b->step, nb);
+  return hip_status(hipGetLastError());
+}
+
+}  // namespace
+
+extern "C" apmg_status apmg_batched_step(const apmg_batch* b, void* ws, size_t ws_bytes, hipStream_t st) {
+  Shape s;
+  apmg_status rc = check_batch(b, &s);
+  if (rc != APMG_OK) return rc;
+  Tune tu;
+  if (!resolve_tune(b->tuning, b->n, b->nb, &tu)) return APMG_EINVAL;
+  if (!ws || ws_bytes < step_ws(b, s, nullptr, nullptr)) return APMG_EWORKSPACE;
+  return run_step(b, s, ws, tu, true, st);
+}
+
+extern "C" apmg_status apmg_autotune_batched_step(const apmg_batch* b, void* ws, size_t ws_bytes, hipStream_t st,
+                                                  apmg_tuning* best, float* best_ms) {
+  Shape s;
+  apmg_status rc = check_batch(b, &s);
+  if (rc != APMG_OK) return rc;
+  if (!best) return APMG_EINVAL;
+  if (!ws || ws_bytes < step_ws(b, s, nullptr, nullptr)) return APMG_EWORKSPACE;
+  const int d = step_default_blocks(b->n, b->nb), mx = step_max_blocks(b->n, b->nb);
+  std::vector<int> blocks;
+  for (int c : {d / 2, d, 2 * d, 4 * d}) {
+    const int v = std::max(1, std::min(c, mx));
+    if (std::find(blocks.begin(), blocks.end(), v) == blocks.end()) blocks.push_back(v);
+  }
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess) return APMG_EHIP;
+  if (hipEventCreate(&e1) != hipSuccess) { hipEventDestroy(e0); return APMG_EHIP; }
+  float best_t = -1.f;
+  Tune best_tu = {d, 4};
+  apmg_status out = APMG_OK;
+  for (int tb : blocks) {
+    for (int un : {2, 4, 8}) {
+      const Tune tu = {tb, un};
+      if ((rc = run_step(b, s, ws, tu, false, st)) != APMG_OK) { out = rc; break; }   // warm-up
+      if (hipEventRecord(e0, st) != hipSuccess) { out = APMG_EHIP; break; }
+      for (int r = 0; r < 3 && rc == APMG_OK; ++r) rc = run_step(b, s, ws, tu, false, st);
+      if (rc != APMG_OK) { out = rc; break; }
+      if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) { out = APMG_EHIP; break; }
+      float ms = 0.f;
+      if (hipEventElapsedTime(&ms, e0, e1) != hipSuccess) { out = APMG_EHIP; break; }
+      ms /= 3.f;
+      if (best_t < 0.f || ms < best_t) { best_t = ms; best_tu = tu; }
+    }
+    if (out != APMG_OK) break;
+  }
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  if (out != APMG_OK) return out;
+  memset(best, 0, sizeof(*best));
+  best->tile_blocks = best_tu.tile_blocks;
+  best->cell_unroll = best_tu.cell_unroll;
+  if (best_ms) *best_ms = best_t;
+  return APMG_OK;
+}
+
+extern "C" apmg_status apmg_train_control(const apmg_control* c, const double* losses, hipStream_t st) {
+  if (!c || !losses || c->nb < 1 || !c->state || !c->density_active || !c->frozen || !c->lr_scale) return APMG_EINVAL;
+  if (c->delay < 0 || c->ma_window < 1 || c->patience < 0 || c->max_reductions < 1 || c->total_iters < 0)
+    return APMG_EINVAL;
+  hipLaunchKernelGGL(k_train_control, dim3((c->nb + 63) / 64), dim3(64), 0, st, *c, losses);
   return hip_status(hipGetLastError());
 }

@@ -457,15 +457,17 @@ __global__ void k_density_grad(Shape s, const float* Gall, size_t G_stride, cons
 // ------------------------------------------------------------------ Adam
 // theta -= lr * mhat / (sqrt(vhat) + eps), bias-corrected with step t+1 (t read from
 // counters[model]).  Optional float16 shadow of theta.  gd (double) or gf (float) gradient.
+// active: per model, skip when 0 (NULL = all); lr_scale: per model multiplier of lr (NULL = 1).
 __global__ void k_adam(float* theta, float* m, float* v, const float* gf, const double* gd, size_t per_model,
                        const int32_t* counters, const int32_t* active, float lr, float b1, float b2,
-                       float eps, __half* shadow) {
+                       float eps, __half* shadow, const float* lr_scale) {
   const int model = blockIdx.y;
   if (active && !active[model]) return;
   const int t = counters[model] + 1;
   const float bc1 = (float)(1.0 - pow((double)b1, (double)t));
   const float bc2 = (float)(1.0 - pow((double)b2, (double)t));
-  const float step = lr / bc1, rb2 = 1.0f / sqrtf(bc2);
+  const float lrm = lr_scale ? lr * lr_scale[model] : lr;
+  const float step = lrm / bc1, rb2 = 1.0f / sqrtf(bc2);
   const size_t off = (size_t)model * per_model;
   for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < per_model; i += (size_t)gridDim.x * blockDim.x) {
     const size_t k = off + i;
@@ -481,13 +483,71 @@ __global__ void k_adam(float* theta, float* m, float* v, const float* gf, const 
 }
 
 // G is stored [M][3][4] float; its gradient is float64 of the same shape.
-__global__ void k_step_counters(int32_t* t, int32_t* tG, const int32_t* active, uint64_t* step, int nb) {
+// live: models that trained this step; dlive: models whose transforms trained.
+__global__ void k_step_counters(int32_t* t, int32_t* tG, const int32_t* live, const int32_t* dlive, uint64_t* step,
+                                int nb) {
   const int b = blockIdx.x * blockDim.x + threadIdx.x;
   if (b < nb) {
-    t[b] += 1;
-    if (active[b]) tG[b] += 1;
+    if (live[b]) t[b] += 1;
+    if (dlive[b]) tG[b] += 1;
   }
   if (b == 0) *step += 1;
+}
+
+// live[b] = !frozen[b]; dlive[b] = live[b] && density_active[b].
+__global__ void k_live_masks(const int32_t* frozen, const int32_t* density_active, int32_t* live, int32_t* dlive,
+                             int nb) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b < nb) {
+    const int32_t l = frozen ? (frozen[b] ? 0 : 1) : 1;
+    live[b] = l;
+    dlive[b] = (l && density_active[b]) ? 1 : 0;
+  }
+}
+
+// ------------------------------------------------------------------ training control
+// One thread per model: the schedule of Sec. 4.3.2 (delayed start, transform early stop)
+// and the plateau scheduler of Sec. 5.2, applied to the losses of the step just taken.
+__global__ void k_train_control(apmg_control c, const double* losses) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= c.nb) return;
+  if (c.frozen[b]) return;
+  apmg_ctl_state st = c.state[b];
+  const double lrec = losses[2 * b], lden = losses[2 * b + 1];
+  const int it = st.iter + 1;
+  // transform early stop over blocks of ma_window density iterations
+  if (c.density_active[b]) {
+    st.ma_sum += lden;
+    st.ma_count += 1;
+    if (st.ma_count == c.ma_window) {
+      const double mean = st.ma_sum / (double)c.ma_window;
+      if (st.have_prev && !(mean < st.ma_prev * (1.0 - c.ma_rel))) st.density_done = 1;
+      st.ma_prev = mean;
+      st.have_prev = 1;
+      st.ma_sum = 0.0;
+      st.ma_count = 0;
+    }
+  }
+  const int limit = (int)(c.stop_frac * (float)c.total_iters);
+  if (it + 1 > limit) st.density_done = 1;
+  // plateau scheduler on L_rec
+  if (it == 1 || lrec < st.best * (1.0 - c.plateau_rel)) {
+    st.best = lrec;
+    st.bad = 0;
+  } else {
+    st.bad += 1;
+  }
+  int frozen = 0;
+  if (st.bad > c.patience) {
+    c.lr_scale[b] = c.lr_scale[b] * c.plateau_factor;
+    st.bad = 0;
+    st.reductions += 1;
+    if (st.reductions >= c.max_reductions) frozen = 1;
+  }
+  st.iter = it;
+  c.state[b] = st;
+  c.density_active[b] = (!frozen && it >= c.delay && !st.density_done) ? 1 : 0;
+  c.frozen[b] = frozen;
 }
 
 }  // namespace apmg

@@ -34,13 +34,12 @@ __device__ inline int64_t xcd_logical(int64_t h, int64_t total) {
   return x * q + (x < r ? x : r) + k;
 }
 
-// Candidates are taken 4 at a time: their coordinates (and, for the accepted ones, dL/dy)
-// are loaded together, and a rejected candidate adds exact zeros, so the sums keep the
-// candidate order with no branch per point.
-constexpr int kCellUnroll = 4;
-
-template <int C, bool GF16, bool DG>
+// Candidates are taken U at a time (U = 2, 4 or 8, a launch-shape choice): their
+// coordinates (and, for the accepted ones, dL/dy) are loaded together, and a rejected
+// candidate adds exact zeros, so the sums keep the candidate order with no branch per point.
+template <int C, bool GF16, bool DG, int U>
 __global__ void __launch_bounds__(256) k_cell_pull(CellArgs a) {
+  constexpr int kCellUnroll = U;
   __shared__ float sG[12];
   __shared__ float sInv[9];
   __shared__ int sBad;

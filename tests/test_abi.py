@@ -137,3 +137,70 @@ def test_make_bricks_rejects_bad_arguments():
     assert A._lib.apmg_make_bricks(8, 8, 8, 2, -1, ctypes.byref(t), None, 0) == A.EINVAL
     arr = (A.ApmgBrick * 3)()
     assert A._lib.apmg_make_bricks(8, 8, 8, 2, 0, ctypes.byref(t), arr, 3) == A.EINVAL  # 64 bricks > cap
+
+
+_LAYOUT_SRC = r"""
+#include <cstdio>
+#include <cstddef>
+#include "apmg.h"
+#define F(T, f) std::printf(#T " " #f " %zu\n", offsetof(T, f));
+#define S(T) std::printf(#T " sizeof %zu\n", sizeof(T));
+int main() {
+  S(apmg_model) F(apmg_model, width) F(apmg_model, G) F(apmg_model, F) F(apmg_model, W) F(apmg_model, vmin)
+  S(apmg_brick) F(apmg_brick, e1) F(apmg_brick, vmax)
+  S(apmg_brick_table) F(apmg_brick_table, ghost)
+  S(apmg_tuning) F(apmg_tuning, cell_unroll)
+  S(apmg_batch) F(apmg_batch, shape) F(apmg_batch, G) F(apmg_batch, density_active) F(apmg_batch, vol)
+  F(apmg_batch, n) F(apmg_batch, step) F(apmg_batch, lr) F(apmg_batch, eps_density) F(apmg_batch, losses)
+  F(apmg_batch, tuning) F(apmg_batch, frozen) F(apmg_batch, lr_scale)
+  S(apmg_ctl_state) F(apmg_ctl_state, ma_sum) F(apmg_ctl_state, best)
+  S(apmg_control) F(apmg_control, stop_frac) F(apmg_control, ma_rel) F(apmg_control, state)
+  F(apmg_control, lr_scale)
+  return 0;
+}
+"""
+
+
+def test_struct_layouts_match_the_header(tmp_path):
+    """Every ctypes mirror has the size and field offsets the C compiler gives the header."""
+    import shutil
+    import subprocess
+    if shutil.which("g++") is None:
+        pytest.skip("g++ not available")
+    src = tmp_path / "layout.cpp"
+    src.write_text(_LAYOUT_SRC)
+    exe = tmp_path / "layout"
+    inc = os.path.dirname(HEADER)
+    r = subprocess.run(["g++", "-std=c++17", "-D__HIP_PLATFORM_AMD__", f"-I{inc}", "-I/opt/rocm/include",
+                        str(src), "-o", str(exe)], capture_output=True, text=True)
+    if r.returncode != 0:
+        pytest.skip("header does not compile with the host compiler here: " + r.stderr[:200])
+    out = subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split("\n")
+    mirrors = {"apmg_model": A.ApmgModel, "apmg_brick": A.ApmgBrick, "apmg_brick_table": A.ApmgBrickTable,
+               "apmg_tuning": A.ApmgTuning, "apmg_batch": A.ApmgBatch, "apmg_ctl_state": A.ApmgCtlState,
+               "apmg_control": A.ApmgControl}
+    checked = 0
+    for line in out:
+        if not line.strip():
+            continue
+        st, field, val = line.split()
+        py = mirrors[st]
+        got = ctypes.sizeof(py) if field == "sizeof" else getattr(py, field).offset
+        assert got == int(val), (st, field, got, val)
+        checked += 1
+    assert checked >= 25
+
+
+def test_new_entry_points_validate_without_gpu():
+    b = A.ApmgBatch()
+    t = A.ApmgTuning()
+    ms = ctypes.c_float()
+    # a batch with nb = 0 is rejected before anything is launched
+    assert A._lib.apmg_autotune_batched_step(ctypes.byref(b), None, 0, None, ctypes.byref(t),
+                                             ctypes.byref(ms)) == A.EINVAL
+    assert A._lib.apmg_autotune_batched_step(None, None, 0, None, ctypes.byref(t), ctypes.byref(ms)) == A.EINVAL
+    c = A.ApmgControl()
+    assert A._lib.apmg_train_control(None, None, None) == A.EINVAL
+    assert A._lib.apmg_train_control(ctypes.byref(c), None, None) == A.EINVAL
+    c.nb = 1
+    assert A._lib.apmg_train_control(ctypes.byref(c), 1, None) == A.EINVAL   # NULL state arrays
