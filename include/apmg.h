@@ -175,6 +175,31 @@ apmg_status apmg_make_bricks(int32_t nx, int32_t ny, int32_t nz, int32_t B, int3
 apmg_status apmg_assign_bricks(const apmg_brick_table* table, const float* pts, int64_t ld,
                                int64_t n, int32_t* brick, hipStream_t stream);
 
+/* ---------------------------------------------------------------- domain-decomposition inference
+ * Global-query inference across all brick models (Sec. 5.3): every global
+ * point p in [-1,1]^3 of the whole volume goes to its brick b by the hash of
+ * apmg_assign_bricks (table), is mapped into brick b's local frame, the
+ * inverse of the training map u = e0 + (l + 1)/2 (e1 - e0) over b's extended
+ * extent:
+ *   u_d = fma(p_d, (n_d-1)/2, (n_d-1)/2),
+ *   l_d = fma(u_d - e0_d, 2/(e1_d - e0_d), -1)   (float32, each operation
+ *                                                 rounded once),
+ * and evaluated by model b (f = m (vmax_b - vmin_b) + vmin_b with brick b's
+ * vmin/vmax).  f[i] is written in the input order.  One call evaluates every
+ * brick in one launch of the forward kernel.
+ * EINVAL also when nb != I*J*K of the table. */
+typedef struct apmg_dd_models {
+  int32_t nb;                 /* models, one per brick, in brick-id order */
+  apmg_model shape;           /* M, C, R, n_layers, width, dtypes; pointers ignored */
+  const float* G;             /* [nb][M][3][4] */
+  const void* F;              /* [nb][M][R][R][R][C] in shape.grid_dtype */
+  const float* W;             /* [nb][layers concatenated] float32 */
+  const apmg_brick* bricks;   /* [nb] device: extended extents, vmin, vmax */
+} apmg_dd_models;
+
+apmg_status apmg_dd_forward(const apmg_dd_models* models, const apmg_brick_table* table, const float* pts,
+                            int64_t ld, int64_t n, float* f, void* ws, size_t ws_bytes, hipStream_t stream);
+
 /* ---------------------------------------------------------------- training step
  * One training iteration (Sec. 4.3.2, Sec. 7) for nb independent models of
  * one shape, each trained on its own brick of one volume (nb = 1 with one
@@ -312,6 +337,7 @@ apmg_status apmg_train_control(const apmg_control* control, const double* losses
 #define APMG_OP_BACKWARD 1
 #define APMG_OP_DENSITY 2
 #define APMG_OP_BATCHED_STEP 3
+#define APMG_OP_DD_FORWARD 4     /* model_or_batch: an apmg_dd_models */
 size_t apmg_workspace_bytes(int op, const void* model_or_batch, int64_t n);
 
 const char* apmg_status_string(apmg_status status);

@@ -715,3 +715,47 @@ def control_update(st, L_rec, L_density, total_iters, **kw):
     st["density_active"] = 1 if (not frozen and it >= p["delay"] and not st["density_done"]) else 0
     st["frozen"] = frozen
     return st
+
+
+# --------------------------------------------------------------------------
+# Domain-decomposition inference: Sec. 5.3 (spatial hash, local frame)
+# --------------------------------------------------------------------------
+
+def dd_local_coords(x, shape_xyz, brick):
+    """A global point's coordinates in a brick model's frame: the inverse of
+    brick_local_to_voxel over the brick's extended extent.
+
+    Reading: the paper scales the global coordinate into the network's local
+    domain without giving the arithmetic; it is taken in float32, each step
+    rounded once, so that the grids' integer decisions downstream are exact:
+    u = fma(p, h, h) with h = (n - 1)/2 (the voxel coordinate of the hash),
+    l = fma(u - e0, 2/(e1 - e0), -1).  Returns float32 [N, 3].
+    """
+    x32 = np.asarray(x, np.float32)
+    out = np.empty_like(x32)
+    for d in range(3):
+        h = np.float32((shape_xyz[d] - 1) * 0.5)
+        with np.errstate(invalid="ignore"):
+            u = _fmaf(x32[:, d], h, h)
+            span = int(brick["e1"][d]) - int(brick["e0"][d])
+            sc = np.float32(2.0) / np.float32(span) if span > 0 else np.float32(0.0)
+            diff = (u - np.float32(brick["e0"][d])).astype(np.float32)
+            out[:, d] = _fmaf(diff, sc, np.float32(-1.0))
+    return out
+
+
+def dd_forward(models, bricks, shape_xyz, B, dims, x):
+    """f at global points x [N, 3] over a domain decomposition: each point is
+    hashed to its brick (brick_assign), mapped into that brick's frame
+    (dd_local_coords) and evaluated by the brick's model with the brick's
+    (vmin, vmax).  models[b]: a model dict; bricks[b]: dict with e0, e1, vmin,
+    vmax.  Returns (f [N] float64, brick ids [N])."""
+    ids = brick_assign(x, shape_xyz, B, dims)
+    f = np.zeros(len(ids))
+    for b in np.unique(ids):
+        sel = ids == b
+        lc = dd_local_coords(np.asarray(x)[sel], shape_xyz, bricks[b])
+        m = dict(models[b])
+        m["vmin"], m["vmax"] = float(bricks[b]["vmin"]), float(bricks[b]["vmax"])
+        f[sel], _ = forward(m, lc.astype(np.float64))
+    return f, ids

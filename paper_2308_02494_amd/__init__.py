@@ -25,7 +25,7 @@ _lib = ctypes.CDLL(LIB_PATH)
 OK, EINVAL, EUNSUPPORTED, EWORKSPACE, EHIP = 0, -1, -2, -3, -4
 F32, F16, BF16 = 0, 1, 2
 ACCUMULATE, DETERMINISTIC, ADD_REC_DG, ERR_ABS = 0x1, 0x2, 0x4, 0x8
-OP_FORWARD, OP_BACKWARD, OP_DENSITY, OP_BATCHED_STEP = 0, 1, 2, 3
+OP_FORWARD, OP_BACKWARD, OP_DENSITY, OP_BATCHED_STEP, OP_DD_FORWARD = 0, 1, 2, 3, 4
 MAX_LAYERS = 8
 
 c_i32, c_i64, c_u32, c_u64, c_f32, c_f64 = (ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32,
@@ -61,6 +61,10 @@ class ApmgBatch(ctypes.Structure):
                 ("tuning", ctypes.POINTER(ApmgTuning)), ("frozen", c_p), ("lr_scale", c_p)]
 
 
+class ApmgDdModels(ctypes.Structure):
+    _fields_ = [("nb", c_i32), ("shape", ApmgModel), ("G", c_p), ("F", c_p), ("W", c_p), ("bricks", c_p)]
+
+
 class ApmgCtlState(ctypes.Structure):
     _fields_ = [("iter", c_i32), ("density_done", c_i32), ("ma_count", c_i32), ("have_prev", c_i32),
                 ("bad", c_i32), ("reductions", c_i32), ("ma_sum", c_f64), ("ma_prev", c_f64), ("best", c_f64)]
@@ -93,6 +97,8 @@ _sigs = {
     "apmg_autotune_batched_step": [ctypes.POINTER(ApmgBatch), c_p, ctypes.c_size_t, c_p,
                                    ctypes.POINTER(ApmgTuning), ctypes.POINTER(c_f32)],
     "apmg_train_control": [ctypes.POINTER(ApmgControl), c_p, c_p],
+    "apmg_dd_forward": [ctypes.POINTER(ApmgDdModels), ctypes.POINTER(ApmgBrickTable), c_p, c_i64, c_i64, c_p, c_p,
+                        ctypes.c_size_t, c_p],
 }
 for _name, _args in _sigs.items():
     _fn = getattr(_lib, _name)
@@ -441,6 +447,44 @@ class Trainer:
         if self.control is not None:
             _check("apmg_train_control", _lib.apmg_train_control(ctypes.byref(self.control),
                                                                  self.losses.data_ptr(), st))
+
+
+class DDModels:
+    """The brick models of a domain decomposition for global-query inference
+    (apmg_dd_forward): arenas G [nb,M,3,4], F [nb,M,R,R,R,C] (float32 or float16),
+    W [nb, layers concatenated], the brick table and the device brick records."""
+
+    def __init__(self, G, F, W, widths, table, bricks, mlp_dtype=F32):
+        self.G, self.F, self.W = G.contiguous(), F.contiguous(), W.contiguous()
+        self.table, self.bricks_dev = table, brick_tensor(bricks, G.device)
+        d = ApmgDdModels()
+        d.nb = G.shape[0]
+        sh = d.shape
+        sh.M, sh.C, sh.R, sh.n_layers = G.shape[1], F.shape[5], F.shape[2], len(widths) - 1
+        for k, wd in enumerate(widths):
+            sh.width[k] = wd
+        sh.grid_dtype = F16 if F.dtype == torch.float16 else F32
+        sh.mlp_dtype = mlp_dtype
+        d.G, d.F, d.W, d.bricks = self.G.data_ptr(), self.F.data_ptr(), self.W.data_ptr(), self.bricks_dev.data_ptr()
+        self.struct = d
+
+    @classmethod
+    def from_trainer(cls, tr, table, bricks):
+        F = tr.F_lowp if tr.F_lowp is not None else tr.F
+        return cls(tr.G, F, tr.W, tr.widths, table, bricks, tr.batch.shape.mlp_dtype)
+
+
+def apmg_dd_forward(models, pts_soa, out=None, ws=None):
+    """f at global points pts_soa [3, n] over all bricks of `models` (a DDModels)."""
+    n = pts_soa.shape[1]
+    dev = pts_soa.device
+    f = out if out is not None else torch.empty(max(n, 1), dtype=torch.float32, device=dev)[:n]
+    if ws is None:
+        ws = _workspace(OP_DD_FORWARD, models.struct, n, dev)
+    _check("apmg_dd_forward", _lib.apmg_dd_forward(ctypes.byref(models.struct), ctypes.byref(models.table),
+                                                   _ptr(pts_soa), pts_soa.stride(0), n, _ptr(f), _ptr(ws),
+                                                   ws.numel(), _stream(dev)))
+    return f
 
 
 def train_control(control, losses):

@@ -373,6 +373,10 @@ void prof_end(hipStream_t st) {
 }
 
 // ======================================================================== ABI
+// domain-decomposition inference workspace (defined with its entry point below)
+struct DdWs;
+size_t dd_ws(const Shape& s, bool bf, int nb, int64_t n, void* ws, DdWs* o);
+
 extern "C" {
 
 apmg_status apmg_profile_events(hipEvent_t start, hipEvent_t stop) {
@@ -400,6 +404,12 @@ size_t apmg_workspace_bytes(int op, const void* mb, int64_t n) {
     Shape s;
     if (b->nb < 1 || b->n < 0 || check_model(&b->shape, false, &s) != APMG_OK) return 0;
     return step_ws(b, s, nullptr, nullptr);
+  }
+  if (op == APMG_OP_DD_FORWARD) {
+    const apmg_dd_models* d = (const apmg_dd_models*)mb;
+    Shape s;
+    if (d->nb < 1 || check_model(&d->shape, false, &s) != APMG_OK) return 0;
+    return dd_ws(s, d->shape.mlp_dtype == APMG_BF16, d->nb, n, nullptr, nullptr);
   }
   Shape s;
   const apmg_model* m = (const apmg_model*)mb;
@@ -820,3 +830,86 @@ extern "C" apmg_status apmg_train_control(const apmg_control* c, const double* l
   hipLaunchKernelGGL(k_train_control, dim3((c->nb + 63) / 64), dim3(64), 0, st, *c, losses);
   return hip_status(hipGetLastError());
 }
+
+// ---------------------------------------------------------------- domain-decomposition inference
+struct DdWs {
+  uint32_t *k0, *v0, *k1, *v1, *hist, *rowtot, *dbase, *seg;
+  float *lpts, *fs, *w3s, *scale;
+  void* swz;
+};
+int key_bits(int nseg) { int b = 1; while ((1 << b) < nseg) ++b; return b; }
+size_t dd_ws(const Shape& s, bool bf, int nb, int64_t n, void* ws, DdWs* o) {
+  Carver cv(ws);
+  const int64_t nn = std::max<int64_t>(n, 1);
+  DdWs w;
+  w.k0 = cv.take<uint32_t>(nn); w.v0 = cv.take<uint32_t>(nn);
+  w.k1 = cv.take<uint32_t>(nn); w.v1 = cv.take<uint32_t>(nn);
+  w.hist = cv.take<uint32_t>((size_t)kRadixDigits * sort_tiles(n));
+  w.rowtot = cv.take<uint32_t>(kRadixDigits);
+  w.dbase = cv.take<uint32_t>(kRadixDigits);
+  w.seg = cv.take<uint32_t>((size_t)nb + 1);
+  w.lpts = cv.take<float>((size_t)3 * nn);
+  w.fs = cv.take<float>(nn);
+  w.swz = cv.take<char>((size_t)nb * swz_sizes(s).total() * (bf ? 2 : 4));
+  w.w3s = cv.take<float>((size_t)nb * s.H);
+  w.scale = cv.take<float>((size_t)2 * nb);
+  if (o) *o = w;
+  return cv.off;
+}
+
+extern "C" apmg_status apmg_dd_forward(const apmg_dd_models* d, const apmg_brick_table* t, const float* pts,
+                                       int64_t ld, int64_t n, float* f, void* ws, size_t ws_bytes, hipStream_t st) {
+  if (!d || !t || d->nb < 1 || !d->G || !d->F || !d->W || !d->bricks) return APMG_EINVAL;
+  Shape s;
+  apmg_status rc = check_model(&d->shape, false, &s);
+  if (rc != APMG_OK) return rc;
+  if ((rc = check_points(pts, ld, n)) != APMG_OK) return rc;
+  if (n > 0 && !f) return APMG_EINVAL;
+  if (t->B < 1 || (int64_t)t->dims[0] * t->dims[1] * t->dims[2] != d->nb) return APMG_EINVAL;
+  for (int k = 0; k < 3; ++k) if (t->dims[k] < 1 || t->vol[k] < 2) return APMG_EINVAL;
+  if (n > 0xffffffffLL) return APMG_EUNSUPPORTED;
+  const bool bf = d->shape.mlp_dtype == APMG_BF16, gf16 = d->shape.grid_dtype == APMG_F16;
+  if (!ws || ws_bytes < dd_ws(s, bf, d->nb, n, nullptr, nullptr)) return APMG_EWORKSPACE;
+  if (n == 0) return APMG_OK;
+  DdWs w;
+  dd_ws(s, bf, d->nb, n, ws, &w);
+  const int nb = d->nb;
+  const size_t nF = f_elems(s), nW = w_elems(s), nG = (size_t)12 * s.M;
+  // brick ids, then a stable radix sort of the points by brick
+  hipLaunchKernelGGL(k_dd_keys, dim3(grid1(n)), dim3(256), 0, st, *t, pts, ld, n, w.k0, w.v0);
+  const int nt = sort_tiles(n);
+  uint32_t *ki = w.k0, *vi = w.v0, *ko = w.k1, *vo = w.v1;
+  for (int shift = 0; shift < key_bits(nb); shift += kRadixBits) {
+    hipLaunchKernelGGL(k_radix_hist, dim3(nt, 1), dim3(256), 0, st, ki, n, shift, w.hist, nt);
+    hipLaunchKernelGGL(k_radix_rowscan, dim3(kRadixDigits, 1), dim3(256), 0, st, w.hist, nt, w.rowtot);
+    hipLaunchKernelGGL(k_radix_digitscan, dim3(1), dim3(256), 0, st, w.rowtot, w.dbase);
+    hipLaunchKernelGGL(k_radix_scatter, dim3(nt, 1), dim3(256), 0, st, ki, vi, ko, vo, n, shift, w.hist, w.dbase, nt);
+    std::swap(ki, ko);
+    std::swap(vi, vo);
+  }
+  hipLaunchKernelGGL(k_seg_starts, dim3(grid1((int64_t)nb + 1)), dim3(256), 0, st, ki, n, nb, w.seg);
+  hipLaunchKernelGGL(k_dd_local, dim3(grid1(n)), dim3(256), 0, st, pts, ld, n, ki, vi, d->bricks, *t, w.lpts);
+  // every brick's model over its segment, one launch
+  hipError_t e = launch_swizzle(s, bf, d->W, d->W + (size_t)s.H * s.MC, d->W + (size_t)s.H * s.MC + (size_t)s.H * s.H,
+                                nW, w.swz, swz_sizes(s).total(), w.w3s, nb, st);
+  if (e != hipSuccess) return APMG_EHIP;
+  hipLaunchKernelGGL(k_brick_scale, dim3((nb + 63) / 64), dim3(64), 0, st, d->bricks, w.scale, nb);
+  TileArgs a;
+  memset(&a, 0, sizeof(a));
+  a.s = s;
+  a.G = d->G; a.G_stride = nG;
+  a.F = d->F; a.F_stride = nF;
+  a.swz = w.swz; a.swz_stride = swz_sizes(s).total(); a.w3s = w.w3s;
+  a.bscale = w.scale; a.boff = w.scale + nb;
+  a.pts = w.lpts; a.ld = n; a.pts_stride = 0; a.n = n;
+  a.seg = w.seg;
+  a.f = w.fs;
+  // blocks per brick: twice the even share of the tiles, at least one
+  const int64_t per = (n + nb - 1) / nb;
+  const int nblk = std::max(1, std::min(2 * tile_blocks(per), kMaxTileBlocks));
+  e = launch_tile(false, 0, a, gf16, bf, dim3(nblk, nb), forward_lds_bytes(s, bf), st);
+  if (e != hipSuccess) return APMG_EHIP;
+  hipLaunchKernelGGL(k_dd_scatter, dim3(grid1(n)), dim3(256), 0, st, w.fs, vi, n, f);
+  return hip_status(hipGetLastError());
+}
+

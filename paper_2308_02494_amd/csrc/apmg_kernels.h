@@ -43,6 +43,7 @@ struct TileArgs {
   const float* bscale;                    // per model (vmax - vmin) or NULL
   const float* boff;                      // per model vmin or NULL
   const float* pts; int64_t ld; size_t pts_stride; int64_t n;
+  const uint32_t* seg;                    // forward only: [models + 1] segment starts in one shared array, or NULL
   // forward
   float* f;
   // adjoint

@@ -10,5 +10,6 @@
 #include "apmg_mlp.hip"
 #include "apmg_misc.hip"
 #include "apmg_sort.hip"
+#include "apmg_dd.hip"
 #include "apmg_scatter.hip"
 #include "apmg_abi.hip"

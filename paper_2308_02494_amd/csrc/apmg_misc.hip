@@ -138,19 +138,12 @@ __global__ void k_cells(Shape s, const float* G, const float* pts, int64_t ld, i
   }
 }
 
+__device__ inline int brick_of(const apmg_brick_table& t, const float p[3]);
+
 __global__ void k_assign_bricks(apmg_brick_table t, const float* pts, int64_t ld, int64_t n, int32_t* brick) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-    int idx[3];
-    for (int d = 0; d < 3; ++d) {
-      const float h = 0.5f * (float)(t.vol[d] - 1);
-      float u = __builtin_fmaf(pts[d * ld + i], h, h);
-      if (!(fabsf(u) <= 3.0e38f)) u = 0.f;  // a non-finite coordinate goes to brick 0 on that axis
-      // floor(u) div B, clamped to [0, dims-1]
-      const float fl = fminf(fmaxf(floorf(u), 0.f), (float)t.vol[d]);
-      int k = (int)fl / t.B;
-      idx[d] = k < t.dims[d] - 1 ? k : t.dims[d] - 1;
-    }
-    brick[i] = idx[0] + t.dims[0] * (idx[1] + t.dims[1] * idx[2]);
+    const float p[3] = {pts[i], pts[ld + i], pts[2 * ld + i]};
+    brick[i] = brick_of(t, p);
   }
 }
 

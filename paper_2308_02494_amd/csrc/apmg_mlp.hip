@@ -285,19 +285,24 @@ __global__ void __launch_bounds__(kBlock) k_forward(TileArgs a) {
   const float* w3s = a.w3s + (size_t)model * H;
   const float vs = a.bscale ? a.bscale[model] : a.vscale;
   const float vo = a.boff ? a.boff[model] : a.voff;
-  const float* P = a.pts + model * a.pts_stride;
+  // points of this model: [model * pts_stride, + n) of its own arrays, or, with segments,
+  // [seg[model], seg[model + 1]) of one shared array (outputs at the same positions)
+  const int64_t base = a.seg ? (int64_t)a.seg[model] : 0;
+  const int64_t cnt = a.seg ? (int64_t)a.seg[model + 1] - base : a.n;
+  const float* P = a.seg ? a.pts + base : a.pts + model * a.pts_stride;
+  float* fo = a.seg ? a.f + base : a.f + (size_t)model * a.n;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, j = lane & 31;
-  const int64_t ntiles = (a.n + 31) / 32;
+  const int64_t ntiles = (cnt + 31) / 32;
   for (int64_t tile = (int64_t)blockIdx.x * kWavesPerBlock + wave; tile < ntiles;
        tile += (int64_t)gridDim.x * kWavesPerBlock) {
     const int64_t p = tile * 32 + j;
-    const bool valid = p < a.n;
+    const bool valid = p < cnt;
     float x = 0.f, y = 0.f, z = 0.f;
     if (valid) { x = P[p]; y = P[a.ld + p]; z = P[2 * a.ld + p]; }
     f32x16 z1[H / 32], z2[H / 32];
     float m;
     tile_fwd<C, H, GF16, BF>(s, sG, F, swz, w3s, x, y, z, valid, lane, z1, z2, m);
-    if (valid && lane < 32) a.f[(size_t)model * a.n + p] = __builtin_fmaf(m, vs, vo);
+    if (valid && lane < 32) fo[p] = __builtin_fmaf(m, vs, vo);
   }
 }
 

@@ -156,6 +156,7 @@ int main() {
   S(apmg_ctl_state) F(apmg_ctl_state, ma_sum) F(apmg_ctl_state, best)
   S(apmg_control) F(apmg_control, stop_frac) F(apmg_control, ma_rel) F(apmg_control, state)
   F(apmg_control, lr_scale)
+  S(apmg_dd_models) F(apmg_dd_models, shape) F(apmg_dd_models, G) F(apmg_dd_models, bricks)
   return 0;
 }
 """
@@ -178,7 +179,7 @@ def test_struct_layouts_match_the_header(tmp_path):
     out = subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split("\n")
     mirrors = {"apmg_model": A.ApmgModel, "apmg_brick": A.ApmgBrick, "apmg_brick_table": A.ApmgBrickTable,
                "apmg_tuning": A.ApmgTuning, "apmg_batch": A.ApmgBatch, "apmg_ctl_state": A.ApmgCtlState,
-               "apmg_control": A.ApmgControl}
+               "apmg_control": A.ApmgControl, "apmg_dd_models": A.ApmgDdModels}
     checked = 0
     for line in out:
         if not line.strip():
