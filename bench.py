@@ -182,15 +182,50 @@ def extra_c3(A, torch, synth, hl):
 
 def extra_c4(A, torch, synth, hl):
     """1000x1200x900 volume in 256^3 bricks with one ghost voxel (80 bricks), 16 grids at
-    32^3 x 2 per brick, MLP 32-64-64-1 in bf16, 2^17 points per brick; all bricks per step."""
+    32^3 x 2 per brick, MLP 32-64-64-1 in bf16, 2^17 points per brick; all bricks per step,
+    launch shapes from the autotuner, the step captured as a graph and replayed.  Then
+    global-query inference over all 80 brick models: 2^24 uniform points."""
     vol = synth.make_volume("blobs_turb", (900, 1200, 1000), device="cuda")
-    _, bricks = A.apmg_make_bricks(1000, 1200, 900, 256, 1)
+    table, bricks = A.apmg_make_bricks(1000, 1200, 900, 256, 1)
     hosts = [synth.init_model(16, 2, 32, [32, 64, 64, 1], seed=synth.SEED_MODEL + b) for b in range(len(bricks))]
     n = 1 << 17
     tr = A.Trainer(hosts, vol, bricks, n, seed=synth.SEED_POINTS, mlp_dtype=A.BF16)
     tr.density_active.fill_(1)
-    dt = _time_trainer(torch, tr, 5, 2)
-    return {"bricks": len(bricks), "train_pts_per_s": len(bricks) * n / dt, "ms_per_step": dt * 1e3}
+    dt_eager = _time_trainer(torch, tr, 3, 1)
+    tune, _ = tr.autotune()
+    tr.step()
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        with torch.cuda.graph(g, stream=s):
+            tr.step()
+    torch.cuda.synchronize()
+    g.replay()
+    torch.cuda.synchronize()
+    reps = 5
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        g.replay()
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / reps
+    out = {"bricks": len(bricks), "train_pts_per_s": len(bricks) * n / dt, "ms_per_step": dt * 1e3,
+           "ms_per_step_eager_default_shapes": dt_eager * 1e3, "tuning": tune, "graph": True}
+    dd = A.DDModels.from_trainer(tr, table, bricks)
+    m = 1 << 24
+    pts = A.apmg_uniform_points(99, 0, 0, 0, m)
+    ws = torch.empty(A._lib.apmg_workspace_bytes(A.OP_DD_FORWARD, ctypes.byref(dd.struct), m), dtype=torch.uint8,
+                     device="cuda")
+    f = torch.empty(m, device="cuda")
+    A.apmg_dd_forward(dd, pts, out=f, ws=ws)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(3):
+        A.apmg_dd_forward(dd, pts, out=f, ws=ws)
+    torch.cuda.synchronize()
+    out["dd_infer_pts_per_s"] = 3 * m / (time.perf_counter() - t0)
+    return out
 
 
 def extra_c5(A, torch, synth, hl):

@@ -222,14 +222,19 @@ apmg_status apmg_dd_forward(const apmg_dd_models* models, const apmg_brick_table
  *   tile_blocks: blocks of the fused forward+adjoint tile kernel per model
  *     (each block = 4 waves of 32-point tiles); default ceil(512 / nb), at most
  *     4 times the default and at most the number of 4-tile groups.
- *   cell_unroll: candidates per batch in the grid-gradient gather, 2, 4 or 8
- *     (default 4).
- * Results depend on tile_blocks through the order of the weight-gradient sums
- * (each setting is bitwise reproducible run to run). */
+ *   cell_kernel: grid-gradient gather, 1 = one wave per 4x4x4 block of cells
+ *     (the default; the wave reads each candidate point once), 2 = one thread
+ *     per cell (always used when L_rec's transform gradient is requested).
+ *   cell_unroll: candidates per batch of the one-thread-per-cell gather, 2, 4
+ *     or 8 (default 4).
+ * Both gathers add each cell's points in the same order with the same
+ * arithmetic.  Results depend on tile_blocks through the order of the
+ * weight-gradient sums (each setting is bitwise reproducible run to run). */
 typedef struct apmg_tuning {
   int32_t tile_blocks;
   int32_t cell_unroll;
-  int32_t reserved[6];
+  int32_t cell_kernel;
+  int32_t reserved[5];
 } apmg_tuning;
 
 typedef struct apmg_batch {

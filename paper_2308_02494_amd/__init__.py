@@ -48,7 +48,7 @@ class ApmgBrickTable(ctypes.Structure):
 
 
 class ApmgTuning(ctypes.Structure):
-    _fields_ = [("tile_blocks", c_i32), ("cell_unroll", c_i32), ("reserved", c_i32 * 6)]
+    _fields_ = [("tile_blocks", c_i32), ("cell_unroll", c_i32), ("cell_kernel", c_i32), ("reserved", c_i32 * 5)]
 
 
 class ApmgBatch(ctypes.Structure):
@@ -396,6 +396,7 @@ class Trainer:
             t = ApmgTuning()
             t.tile_blocks = tuning.get("tile_blocks", 0)
             t.cell_unroll = tuning.get("cell_unroll", 0)
+            t.cell_kernel = tuning.get("cell_kernel", 0)
             tuning = t
         self.tuning = tuning
         self.batch.tuning = ctypes.pointer(tuning) if tuning is not None else None
@@ -409,7 +410,8 @@ class Trainer:
                _lib.apmg_autotune_batched_step(ctypes.byref(self.batch), _ptr(self.ws), self.ws.numel(),
                                               _stream(self.device), ctypes.byref(best), ctypes.byref(ms)))
         self.set_tuning(best)
-        return {"tile_blocks": best.tile_blocks, "cell_unroll": best.cell_unroll}, ms.value
+        return {"tile_blocks": best.tile_blocks, "cell_unroll": best.cell_unroll,
+                "cell_kernel": best.cell_kernel}, ms.value
 
     def enable_control(self, total_iters, delay=500, ma_window=1000, ma_rel=1e-4, stop_frac=0.8, patience=500,
                        plateau_rel=1e-4, plateau_factor=0.1, max_reductions=3):

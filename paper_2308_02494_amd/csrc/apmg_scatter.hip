@@ -199,6 +199,204 @@ __global__ void __launch_bounds__(256) k_cell_pull(CellArgs a) {
   }
 }
 
+// The grid gradient without the transform gradient, one wave per 4 x 4 x 4 block of cells
+// of one grid.  The wave walks the rows of the bins that overlap the block's box (the
+// union of its cells' candidates, each point read once, 64 consecutive points per step),
+// every lane tests one point against the block, and a matching point's (w, dL/dy) record is
+// handed to the lane that owns its cell through LDS: each owner adds the records addressed
+// to it in lane order.  The accumulation per cell is in candidate order and has the same
+// arithmetic as k_cell_pull, so the corner sums are bitwise the same.
+constexpr int kBlk = 4;                      // cells per block edge
+template <int C, bool GF16>
+__global__ void __launch_bounds__(256) k_cell_pull_wave(CellArgs a) {
+  constexpr int RW = C <= 1 ? 1 : 2;         // float4 words per record: (w0, w1, w2, dy0), (dy1, ...)
+  __shared__ float4 sRec[4][64][RW];
+  __shared__ float sG[4][12];
+  __shared__ uint32_t sRow0[4][64];          // first sorted position of each row of the batch
+  __shared__ uint32_t sPre[4][64];           // exclusive prefix of the rows' lengths
+  const Shape s = a.s;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int R1 = s.R - 1;
+  const int nbx = (R1 + kBlk - 1) / kBlk;
+  const int64_t nblk_grid = (int64_t)nbx * nbx * nbx;            // cell blocks per grid
+  const int64_t groups = (nblk_grid + 3) / 4;                   // 4 waves per workgroup
+  const int64_t per_model = groups * s.M;
+  const int64_t L = xcd_logical(blockIdx.x, gridDim.x);
+  const int model = (int)(L / per_model);
+  const int64_t grp = (L % per_model) / s.M;
+  const int g = (int)(L % s.M);
+  const int64_t cb = grp * 4 + wave;                            // this wave's cell block
+  const bool act = (!a.active || a.active[model]) && cb < nblk_grid;
+  if (lane < 12) sG[wave][lane] = a.G[model * a.G_stride + 12 * g + lane];
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  const float* Gg = sG[wave];
+  const int bx = (int)(cb % nbx), by = (int)((cb / nbx) % nbx), bz = (int)(cb / ((int64_t)nbx * nbx));
+  const int cx = bx * kBlk + (lane & 3), cy = by * kBlk + ((lane >> 2) & 3), cz = bz * kBlk + (lane >> 4);
+  const bool own = act && cx < R1 && cy < R1 && cz < R1;
+  float acc[8][C];
+#pragma unroll
+  for (int q = 0; q < 8; ++q)
+#pragma unroll
+    for (int c = 0; c < C; ++c) acc[q][c] = 0.f;
+  if (act) {
+    // the block's box in global space (inverse of Eq. (1) applied to its local box)
+    double A[3][3];
+    for (int r = 0; r < 3; ++r) for (int c = 0; c < 3; ++c) A[r][c] = Gg[4 * r + c];
+    const double c00 = A[1][1] * A[2][2] - A[1][2] * A[2][1], c01 = A[1][2] * A[2][0] - A[1][0] * A[2][2];
+    const double c02 = A[1][0] * A[2][1] - A[1][1] * A[2][0];
+    const double det = A[0][0] * c00 + A[0][1] * c01 + A[0][2] * c02;
+    const double inv[9] = {c00, A[0][2] * A[2][1] - A[0][1] * A[2][2], A[0][1] * A[1][2] - A[0][2] * A[1][1],
+                           c01, A[0][0] * A[2][2] - A[0][2] * A[2][0], A[0][2] * A[1][0] - A[0][0] * A[1][2],
+                           c02, A[0][1] * A[2][0] - A[0][0] * A[2][1], A[0][0] * A[1][1] - A[0][1] * A[1][0]};
+    bool bad = !(fabs(det) > 1e-30);
+    float Ai[9];
+    for (int k = 0; k < 9; ++k) { Ai[k] = (float)(inv[k] / det); bad = bad || !isfinite(Ai[k]); }
+    int lo[3], hi[3];
+    const int b0[3] = {bx * kBlk, by * kBlk, bz * kBlk};
+    if (bad) {
+      for (int d = 0; d < 3; ++d) { lo[d] = 0; hi[d] = kBinsPerAxis - 1; }
+    } else {
+      float lm[3], hl[3];
+      for (int d = 0; d < 3; ++d) {
+        const int e = min(b0[d] + kBlk, R1);
+        lm[d] = -1.f + (float)(b0[d] + e) / R1 - Gg[4 * d + 3];   // box centre minus the translation
+        hl[d] = (float)(e - b0[d]) / R1;                           // box half-width (local units)
+      }
+      for (int d = 0; d < 3; ++d) {
+        const float wc = Ai[3 * d] * lm[0] + Ai[3 * d + 1] * lm[1] + Ai[3 * d + 2] * lm[2];
+        const float hw = fabsf(Ai[3 * d]) * hl[0] + fabsf(Ai[3 * d + 1]) * hl[1] + fabsf(Ai[3 * d + 2]) * hl[2];
+        const float f0 = floorf((wc - hw - 1e-4f + 1.f) * (0.5f * kBinsPerAxis));
+        const float f1 = floorf((wc + hw + 1e-4f + 1.f) * (0.5f * kBinsPerAxis));
+        lo[d] = (int)fminf(fmaxf(f0, 0.f), (float)(kBinsPerAxis - 1));
+        hi[d] = (int)fminf(fmaxf(f1, 0.f), (float)(kBinsPerAxis - 1));
+      }
+    }
+    const float4* P4 = a.pts4 + (size_t)model * a.n;
+    const float* dY = a.dY + ((size_t)model * s.M + g) * a.n * C;
+    const uint32_t* start = a.start + (size_t)model * (kBinsPerAxis * kBinsPerAxis * kBinsPerAxis + 1);
+    const float hR = 0.5f * (float)R1;
+    const int ny_r = hi[1] - lo[1] + 1, nz_r = hi[2] - lo[2] + 1;
+    const int nrows = ny_r * nz_r;
+    // A candidate: its point and dL/dy, loaded for every lane (a lane past the end loads
+    // point 0), so the loads of the next 64 candidates are in flight while these are used.
+    struct Cand { float4 q; float dy[C]; };
+    auto load = [&](uint32_t f, uint32_t total, Cand& cd) {
+      uint32_t p = 0;
+      if (f < total) {
+        // the row holding flat index f: the last row whose exclusive prefix is <= f
+        int r0 = 0, r1 = 63;
+        while (r0 < r1) {
+          const int mid = (r0 + r1 + 1) >> 1;
+          if (sPre[wave][mid] <= f) r0 = mid; else r1 = mid - 1;
+        }
+        p = sRow0[wave][r0] + (f - sPre[wave][r0]);
+      }
+      cd.q = P4[p];
+#pragma unroll
+      for (int c = 0; c < C; ++c) cd.dy[c] = dY[(size_t)p * C + c];
+    };
+    auto consume = [&](const Cand& cd, bool valid) {
+      int t = -1;
+      float4 r0 = make_float4(0.f, 0.f, 0.f, 0.f), r1 = r0;
+      if (valid) {
+        float l[3], w[3];
+        int i0[3];
+        local_coords(Gg, cd.q.x, cd.q.y, cd.q.z, l);
+        const bool in = cell_of(l, hR, s.R, i0, w);
+        const int ox = i0[0] - b0[0], oy = i0[1] - b0[1], oz = i0[2] - b0[2];
+        if (in && ox >= 0 && ox < kBlk && oy >= 0 && oy < kBlk && oz >= 0 && oz < kBlk) {
+          t = (oz * kBlk + oy) * kBlk + ox;
+          r0 = make_float4(w[0], w[1], w[2], cd.dy[0]);
+          if constexpr (C > 1) r1 = make_float4(cd.dy[1], C > 2 ? cd.dy[2] : 0.f, C > 3 ? cd.dy[3] : 0.f, 0.f);
+        }
+      }
+      sRec[wave][lane][0] = r0;
+      if constexpr (RW > 1) sRec[wave][lane][1] = r1;
+      // lanes whose point falls in my cell: agree on every bit of the target
+      const bool has = t >= 0;
+      uint64_t mask = __ballot(has);
+#pragma unroll
+      for (int b = 0; b < 6; ++b) {
+        const uint64_t bb = __ballot(has && ((t >> b) & 1));
+        mask &= ((lane >> b) & 1) ? bb : ~bb;
+      }
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      while (mask) {
+        const int k = __builtin_ctzll(mask);
+        mask &= mask - 1;
+        const float4 a0 = sRec[wave][k][0];
+        float dyv[C];
+        dyv[0] = a0.w;
+        if constexpr (C > 1) {
+          const float4 a1 = sRec[wave][k][RW - 1];
+          dyv[1] = a1.x;
+          if constexpr (C > 2) dyv[2] = a1.y;
+          if constexpr (C > 3) dyv[3] = a1.z;
+        }
+        const float w[3] = {a0.x, a0.y, a0.z};
+#pragma unroll
+        for (int qq = 0; qq < 8; ++qq) {
+          const float wq = ((qq & 1) ? w[0] : 1.f - w[0]) * ((qq & 2) ? w[1] : 1.f - w[1]) *
+                           ((qq & 4) ? w[2] : 1.f - w[2]);
+#pragma unroll
+          for (int c = 0; c < C; ++c) acc[qq][c] = __builtin_fmaf(wq, dyv[c], acc[qq][c]);
+        }
+      }
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    };
+    // rows (z outer, y inner) 64 at a time; each batch's points are one flat sequence
+    for (int rb = 0; rb < nrows; rb += 64) {
+      const int r = rb + lane;
+      uint32_t s0 = 0, len = 0;
+      if (r < nrows) {
+        const int yb = lo[1] + r % ny_r, zb = lo[2] + r / ny_r;
+        const int row = (zb * kBinsPerAxis + yb) * kBinsPerAxis;
+        s0 = start[row + lo[0]];
+        len = start[row + hi[0] + 1] - s0;
+      }
+      uint32_t x = len;
+#pragma unroll
+      for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t y = __shfl_up(x, o, 64);
+        if (lane >= o) x += y;
+      }
+      const uint32_t total = __shfl(x, 63, 64);
+      sRow0[wave][lane] = s0;
+      sPre[wave][lane] = x - len;
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      Cand ca, cbn;
+      load(lane, total, ca);
+      for (uint32_t base = 0; base < total; base += 128) {
+        load(base + 64 + lane, total, cbn);
+        sched_barrier();
+        consume(ca, base + lane < total);
+        load(base + 128 + lane, total, ca);
+        sched_barrier();
+        if (base + 64 < total) consume(cbn, base + 64 + lane < total);
+      }
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
+  }
+  if (own) {
+    const int64_t cell = ((int64_t)cz * R1 + cy) * R1 + cx;
+    const int64_t ncell = (int64_t)R1 * R1 * R1;
+    float* out = a.CC + (((size_t)model * s.M + g) * ncell + cell) * 8 * C;
+#pragma unroll
+    for (int q = 0; q < 8; ++q)
+#pragma unroll
+      for (int c = 0; c < C; ++c) out[q * C + c] = acc[q][c];
+  }
+}
+
 // dF[model][g][v][c] (+)= sum over the cells adjacent to vertex v of their corner sums.
 template <int C>
 __global__ void k_cell_to_vertex(Shape s, const float* CC, float* dF, size_t dF_stride, int accumulate,

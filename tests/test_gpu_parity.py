@@ -191,6 +191,24 @@ def test_backward_fp32(M, C, R, H):
         assert_close(f"dW{k + 1}", dW[k].cpu().numpy(), go["dW"][k])
 
 
+@pytest.mark.parametrize("M,C,R,H", SHAPES + [(32, 2, 8, 64), (7, 4, 5, 64)])
+def test_grid_gradient_gathers_agree_bitwise_and_match_oracle(M, C, R, H):
+    # without a transform gradient the grid gradient comes from the wave-cooperative gather,
+    # with it from the one-thread-per-cell gather: the same sums in the same order
+    host = host_model(M, C, R, H, extra_t=0.1)
+    x = make_points(6001)
+    df = np.random.default_rng(5).normal(size=x.shape[0]).astype(np.float32)
+    model = A().Model.from_host(host, DEV)
+    dF_w, _, _ = A().apmg_backward(model, soa(x), torch.from_numpy(df).to(DEV), want_dG=False)
+    dF_c, _, _ = A().apmg_backward(model, soa(x), torch.from_numpy(df).to(DEV), want_dG=True)
+    assert torch.equal(dF_w, dF_c)
+    xk = kink_free(host, x)
+    dfk = np.random.default_rng(6).normal(size=xk.shape[0]).astype(np.float32)
+    dF_k, _, _ = A().apmg_backward(model, soa(xk), torch.from_numpy(dfk).to(DEV), want_dG=False)
+    go = O.backward(f64(host), xk.astype(np.float64), dfk.astype(np.float64))
+    assert_close("dF (wave gather)", dF_k.cpu().numpy(), go["dF"].transpose(0, 2, 3, 4, 1))
+
+
 def test_backward_accumulate_and_partial_outputs():
     host = host_model(4, 2, 6, 64)
     x = kink_free(host, make_points(500))

@@ -168,7 +168,8 @@ def test_autotune_returns_a_valid_shape_and_leaves_parameters():
     tune, ms = tr.autotune()
     torch.cuda.synchronize()
     print("autotune:", tune, f"{ms:.3f} ms")
-    assert tune["cell_unroll"] in (2, 4, 8) and tune["tile_blocks"] >= 1 and ms > 0
+    assert tune["cell_unroll"] in (2, 4, 8) and tune["tile_blocks"] >= 1 and tune["cell_kernel"] in (1, 2)
+    assert ms > 0
     for x, y in zip(before, (tr.G, tr.F, tr.W, tr.mF, tr.t, tr.step_ctr)):
         assert torch.equal(x, y)
     # the tuned step against the default one: the same losses, and gradients (Adam's first
@@ -197,5 +198,21 @@ def test_bad_tuning_is_rejected_before_launch():
     tr.set_tuning({"tile_blocks": 1 << 20})
     with pytest.raises(A().ApmgError):
         tr.step()
+    tr.set_tuning({"cell_kernel": 3})
+    with pytest.raises(A().ApmgError):
+        tr.step()
     tr.set_tuning(None)
     tr.step()
+
+
+def test_both_gathers_give_the_same_step():
+    # the training step with the wave-cooperative gather and with the one-thread-per-cell
+    # gather (every batch size): bitwise the same parameters
+    ref = _bricks_trainer(nb=2, n=6000, tuning={"cell_kernel": 1})
+    ref.step()
+    for unroll in (2, 4, 8):
+        other = _bricks_trainer(nb=2, n=6000, tuning={"cell_kernel": 2, "cell_unroll": unroll})
+        other.step()
+        torch.cuda.synchronize()
+        for x, y in zip((ref.F, ref.W, ref.G, ref.mF), (other.F, other.W, other.G, other.mF)):
+            assert torch.equal(x, y), unroll
