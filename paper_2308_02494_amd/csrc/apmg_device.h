@@ -102,6 +102,18 @@ __device__ inline void uniform_point(uint64_t seed, uint64_t step, uint32_t stre
 }
 
 // ------------------------------------------------------------ encoder pieces
+// XCD-aware block order.  Workgroups are dispatched round-robin over the 8 XCDs (each with
+// its own L2), so hardware block h runs on XCD h % 8.  xcd_logical deals logical blocks out
+// so that XCD x runs the x-th contiguous eighth of the logical order: with spatially sorted
+// work in logical order, each XCD works on one slab and its L2 holds that slab's data.
+// A bijection for any total.
+constexpr int kXcds = 8;
+__device__ inline int64_t xcd_logical(int64_t h, int64_t total) {
+  const int64_t x = h % kXcds, k = h / kXcds;
+  const int64_t q = total / kXcds, r = total % kXcds;
+  return x * q + (x < r ? x : r) + k;
+}
+
 // Eq. (1) with a fixed fma order (the integer decisions depend on it).
 __device__ inline void local_coords(const float* Gg, float x, float y, float z, float l[3]) {
 #pragma unroll

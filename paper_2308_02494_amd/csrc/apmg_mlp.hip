@@ -265,7 +265,10 @@ __host__ __device__ inline size_t fwd_weight_bytes(const Shape& s, bool bf) {
 template <int C, int H, bool GF16, bool BF, bool WL>
 __global__ void __launch_bounds__(kBlock) k_forward(TileArgs a) {
   extern __shared__ float smem[];
-  const int model = blockIdx.y;
+  // logical block: models in order, each model's blocks over contiguous runs of its
+  // (spatially sorted) tiles, dealt to the XCDs in slabs
+  const int64_t lbl = xcd_logical(blockIdx.x + (int64_t)gridDim.x * blockIdx.y, (int64_t)gridDim.x * gridDim.y);
+  const int model = (int)(lbl / gridDim.x), lb = (int)(lbl % gridDim.x);
   if (a.active && !a.active[model]) return;
   const Shape s = a.s;
   float* sG = smem;
@@ -293,8 +296,9 @@ __global__ void __launch_bounds__(kBlock) k_forward(TileArgs a) {
   float* fo = a.seg ? a.f + base : a.f + (size_t)model * a.n;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, j = lane & 31;
   const int64_t ntiles = (cnt + 31) / 32;
-  for (int64_t tile = (int64_t)blockIdx.x * kWavesPerBlock + wave; tile < ntiles;
-       tile += (int64_t)gridDim.x * kWavesPerBlock) {
+  const int64_t per = (ntiles + gridDim.x - 1) / gridDim.x;
+  const int64_t t_end = min(ntiles, (lb + 1) * per);
+  for (int64_t tile = lb * per + wave; tile < t_end; tile += kWavesPerBlock) {
     const int64_t p = tile * 32 + j;
     const bool valid = p < cnt;
     float x = 0.f, y = 0.f, z = 0.f;
@@ -346,12 +350,15 @@ __global__ void __launch_bounds__(kBlock) k_backward(TileArgs a) {
   constexpr int NB = H / 32;
   constexpr int LDT = TT<BF>::LDT;
   constexpr bool REG = KB > 0;
-  const int model = blockIdx.y;
+  // logical block as in k_forward (the partial sums are indexed by it, so their fixed
+  // reduction order follows the tiles)
+  const int64_t lbl = xcd_logical(blockIdx.x + (int64_t)gridDim.x * blockIdx.y, (int64_t)gridDim.x * gridDim.y);
+  const int model = (int)(lbl / gridDim.x), lb = (int)(lbl % gridDim.x);
   const Shape s = a.s;
   const int ncols = a.c1_hi - a.c1_lo;
   const int nrows2 = a.w2_hi - a.w2_lo;
   const PartLayout pl = part_layout(s, ncols, nrows2);
-  double* part = a.part + ((size_t)model * gridDim.x + blockIdx.x) * pl.len;
+  double* part = a.part + ((size_t)model * gridDim.x + lb) * pl.len;
   const bool act = !a.active || a.active[model];
 
   // LDS: sG [12M] | sW3w [wave][H] | sLoss (double) | (REG) swizzled weights | per-wave
@@ -421,11 +428,15 @@ __global__ void __launch_bounds__(kBlock) k_backward(TileArgs a) {
     }
   }
   double loss = 0.0;
+  float w3acc[NB / 2];   // output-layer gradient: lane j of half hf holds rows 64 k + 32 (j / 16) + acc_row(j % 16, hf)
+#pragma unroll
+  for (int k = 0; k < NB / 2; ++k) w3acc[k] = 0.f;
   const int nblk = REG ? KB : s.KHP / 16;
 
   const int64_t ntiles = act ? (a.n + 31) / 32 : 0;
-  for (int64_t tile = (int64_t)blockIdx.x * kWavesPerBlock + wave; tile < ntiles;
-       tile += (int64_t)gridDim.x * kWavesPerBlock) {
+  const int64_t per = (ntiles + gridDim.x - 1) / gridDim.x;
+  const int64_t t_end = min(ntiles, (lb + 1) * per);
+  for (int64_t tile = lb * per + wave; tile < t_end; tile += kWavesPerBlock) {
     const int64_t p = tile * 32 + j;
     const bool valid = p < a.n;
     float x = 0.f, y = 0.f, z = 0.f;
@@ -453,13 +464,34 @@ __global__ void __launch_bounds__(kBlock) k_backward(TileArgs a) {
 
     // output layer: dW3 (reduced over the tile's points into this wave's row) and delta2
     if (a.do_w3) {
+      // dm * relu(z2) summed over the half's 32 points, for each pair of row blocks, by a
+      // transposing butterfly: each step halves the values a lane holds and adds the other
+      // half from the lane whose index differs in one bit (the pairs and the order of the
+      // sums of a plain butterfly), so lane j ends with value j summed over the 32 points;
+      // 31 shuffles per pair instead of 5 per value.  Per lane, tiles add up in order.
 #pragma unroll
-      for (int b = 0; b < NB; ++b)
+      for (int k = 0; k < NB / 2; ++k) {
+        // first step straight from the accumulators (16 values live, not 32)
+        float v[16];
+        const bool up16 = (j & 16) != 0;
 #pragma unroll
-        for (int r = 0; r < 16; ++r) {
-          const float t = half_sum(dm * fmaxf(z2[b][r], 0.f));
-          if (j == 0) sW3w[wave * H + 32 * b + acc_row(r, hf)] += t;
+        for (int i = 0; i < 16; ++i) {
+          const float lo = dm * fmaxf(z2[2 * k][i], 0.f), hi = dm * fmaxf(z2[2 * k + 1][i], 0.f);
+          v[i] = (up16 ? hi : lo) + __shfl_xor(up16 ? lo : hi, 16, 64);
         }
+#pragma unroll
+        for (int m = 16; m > 1; m >>= 1) {
+          const int o = m >> 1;
+          const bool up = (j & o) != 0;
+#pragma unroll
+          for (int i = 0; i < m / 2; ++i) {
+            const float keep = up ? v[i + m / 2] : v[i];
+            const float send = up ? v[i] : v[i + m / 2];
+            v[i] = keep + __shfl_xor(send, o, 64);
+          }
+        }
+        w3acc[k] += v[0];
+      }
     }
     f32x16 d2[NB];
 #pragma unroll
@@ -627,6 +659,10 @@ __global__ void __launch_bounds__(kBlock) k_backward(TileArgs a) {
     }
   }
 
+  if (a.do_w3) {
+#pragma unroll
+    for (int k = 0; k < NB / 2; ++k) sW3w[wave * H + 64 * k + 32 * (j >> 4) + acc_row(j & 15, hf)] = w3acc[k];
+  }
   if (a.want_loss) {
     const double t = wave_sum(loss);
     if (lane == 0) sLoss[wave] = t;

@@ -22,17 +22,23 @@ struct CellArgs {
   int nblk;                             // blocks of 256 cells per grid; launch nmodels * M * nblk blocks
 };
 
-// XCD-aware block order.  Workgroups are dispatched round-robin over the 8 XCDs (each with
-// its own L2), so hardware block h runs on XCD h % 8.  Logical blocks are dealt out so that
-// XCD x runs the x-th contiguous eighth of the logical order; with the order (model, cell
-// block, grid), an XCD works through a slab of cells for all grids at once and the points of
-// that slab stay in its L2 while every grid reads them.  A bijection for any total.
-constexpr int kXcds = 8;
-__device__ inline int64_t xcd_logical(int64_t h, int64_t total) {
-  const int64_t x = h % kXcds, k = h / kXcds;
-  const int64_t q = total / kXcds, r = total % kXcds;
-  return x * q + (x < r ? x : r) + k;
+// Corner weight q = a + 2b + 4c of the trilinear weights of offsets w.  Both gathers add
+// round(w_q * dL/dy) to the corner sums (a product, then a sum: no fused multiply-add), so
+// they produce the same bits.
+__device__ inline float corner_weight(int qq, const float w[3]) {
+  return ((qq & 1) ? w[0] : 1.f - w[0]) * ((qq & 2) ? w[1] : 1.f - w[1]) * ((qq & 4) ? w[2] : 1.f - w[2]);
 }
+__device__ inline float corner_product(float wq, float d) {
+#pragma clang fp contract(off)
+  return wq * d;
+}
+__device__ inline float add_rounded(float acc, float v) {
+#pragma clang fp contract(off)
+  return acc + v;
+}
+
+// Block order: xcd_logical over (model, cell block, grid), so an XCD works through a slab of
+// cells for all grids at once and the points of that slab stay in its L2.
 
 // Candidates are taken U at a time (U = 2, 4 or 8, a launch-shape choice): their
 // coordinates (and, for the accepted ones, dL/dy) are loaded together, and a rejected
@@ -143,10 +149,9 @@ __global__ void __launch_bounds__(256) k_cell_pull(CellArgs a) {
           for (int u = 0; u < kCellUnroll; ++u) {
 #pragma unroll
             for (int qq = 0; qq < 8; ++qq) {
-              const float wq = ((qq & 1) ? w[u][0] : 1.f - w[u][0]) * ((qq & 2) ? w[u][1] : 1.f - w[u][1]) *
-                               ((qq & 4) ? w[u][2] : 1.f - w[u][2]);
+              const float wq = corner_weight(qq, w[u]);
 #pragma unroll
-              for (int c = 0; c < C; ++c) acc[qq][c] = __builtin_fmaf(wq, dy[u][c], acc[qq][c]);
+              for (int c = 0; c < C; ++c) acc[qq][c] = add_rounded(acc[qq][c], corner_product(wq, dy[u][c]));
             }
             if constexpr (DG) {
               const float* wu = w[u];
@@ -209,7 +214,7 @@ __global__ void __launch_bounds__(256) k_cell_pull(CellArgs a) {
 constexpr int kBlk = 4;                      // cells per block edge
 template <int C, bool GF16>
 __global__ void __launch_bounds__(256) k_cell_pull_wave(CellArgs a) {
-  constexpr int RW = C <= 1 ? 1 : 2;         // float4 words per record: (w0, w1, w2, dy0), (dy1, ...)
+  constexpr int RW = 2 * C;                  // float4 words per record: the 8 C products w_q dL/dy_c
   __shared__ float4 sRec[4][64][RW];
   __shared__ float sG[4][12];
   __shared__ uint32_t sRow0[4][64];          // first sorted position of each row of the batch
@@ -281,16 +286,14 @@ __global__ void __launch_bounds__(256) k_cell_pull_wave(CellArgs a) {
     // A candidate: its point and dL/dy, loaded for every lane (a lane past the end loads
     // point 0), so the loads of the next 64 candidates are in flight while these are used.
     struct Cand { float4 q; float dy[C]; };
+    // each lane's flat index grows by 64 per step, so the row holding it (the last row whose
+    // exclusive prefix is <= f) is found by walking forward from the previous one
+    int rcur = 0;
     auto load = [&](uint32_t f, uint32_t total, Cand& cd) {
       uint32_t p = 0;
       if (f < total) {
-        // the row holding flat index f: the last row whose exclusive prefix is <= f
-        int r0 = 0, r1 = 63;
-        while (r0 < r1) {
-          const int mid = (r0 + r1 + 1) >> 1;
-          if (sPre[wave][mid] <= f) r0 = mid; else r1 = mid - 1;
-        }
-        p = sRow0[wave][r0] + (f - sPre[wave][r0]);
+        while (rcur < 63 && sPre[wave][rcur + 1] <= f) ++rcur;
+        p = sRow0[wave][rcur] + (f - sPre[wave][rcur]);
       }
       cd.q = P4[p];
 #pragma unroll
@@ -298,21 +301,28 @@ __global__ void __launch_bounds__(256) k_cell_pull_wave(CellArgs a) {
     };
     auto consume = [&](const Cand& cd, bool valid) {
       int t = -1;
-      float4 r0 = make_float4(0.f, 0.f, 0.f, 0.f), r1 = r0;
+      float w[3] = {0.f, 0.f, 0.f};
       if (valid) {
-        float l[3], w[3];
+        float l[3];
         int i0[3];
         local_coords(Gg, cd.q.x, cd.q.y, cd.q.z, l);
         const bool in = cell_of(l, hR, s.R, i0, w);
         const int ox = i0[0] - b0[0], oy = i0[1] - b0[1], oz = i0[2] - b0[2];
-        if (in && ox >= 0 && ox < kBlk && oy >= 0 && oy < kBlk && oz >= 0 && oz < kBlk) {
+        if (in && ox >= 0 && ox < kBlk && oy >= 0 && oy < kBlk && oz >= 0 && oz < kBlk)
           t = (oz * kBlk + oy) * kBlk + ox;
-          r0 = make_float4(w[0], w[1], w[2], cd.dy[0]);
-          if constexpr (C > 1) r1 = make_float4(cd.dy[1], C > 2 ? cd.dy[2] : 0.f, C > 3 ? cd.dy[3] : 0.f, 0.f);
-        }
       }
-      sRec[wave][lane][0] = r0;
-      if constexpr (RW > 1) sRec[wave][lane][1] = r1;
+      if (t >= 0) {
+        float pr[8 * C];
+#pragma unroll
+        for (int qq = 0; qq < 8; ++qq) {
+          const float wq = corner_weight(qq, w);
+#pragma unroll
+          for (int c = 0; c < C; ++c) pr[qq * C + c] = corner_product(wq, cd.dy[c]);
+        }
+#pragma unroll
+        for (int k = 0; k < RW; ++k)
+          sRec[wave][lane][k] = make_float4(pr[4 * k], pr[4 * k + 1], pr[4 * k + 2], pr[4 * k + 3]);
+      }
       // lanes whose point falls in my cell: agree on every bit of the target
       const bool has = t >= 0;
       uint64_t mask = __ballot(has);
@@ -327,22 +337,15 @@ __global__ void __launch_bounds__(256) k_cell_pull_wave(CellArgs a) {
       while (mask) {
         const int k = __builtin_ctzll(mask);
         mask &= mask - 1;
-        const float4 a0 = sRec[wave][k][0];
-        float dyv[C];
-        dyv[0] = a0.w;
-        if constexpr (C > 1) {
-          const float4 a1 = sRec[wave][k][RW - 1];
-          dyv[1] = a1.x;
-          if constexpr (C > 2) dyv[2] = a1.y;
-          if constexpr (C > 3) dyv[3] = a1.z;
-        }
-        const float w[3] = {a0.x, a0.y, a0.z};
 #pragma unroll
-        for (int qq = 0; qq < 8; ++qq) {
-          const float wq = ((qq & 1) ? w[0] : 1.f - w[0]) * ((qq & 2) ? w[1] : 1.f - w[1]) *
-                           ((qq & 4) ? w[2] : 1.f - w[2]);
+        for (int j4 = 0; j4 < RW; ++j4) {
+          const float4 v = sRec[wave][k][j4];
+          const float vv[4] = {v.x, v.y, v.z, v.w};
 #pragma unroll
-          for (int c = 0; c < C; ++c) acc[qq][c] = __builtin_fmaf(wq, dyv[c], acc[qq][c]);
+          for (int e = 0; e < 4; ++e) {
+            const int idx = 4 * j4 + e;
+            acc[idx / C][idx % C] = add_rounded(acc[idx / C][idx % C], vv[e]);
+          }
         }
       }
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -372,6 +375,7 @@ __global__ void __launch_bounds__(256) k_cell_pull_wave(CellArgs a) {
       __builtin_amdgcn_wave_barrier();
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
       Cand ca, cbn;
+      rcur = 0;
       load(lane, total, ca);
       for (uint32_t base = 0; base < total; base += 128) {
         load(base + 64 + lane, total, cbn);
