@@ -428,9 +428,6 @@ __global__ void __launch_bounds__(kBlock) k_backward(TileArgs a) {
     }
   }
   double loss = 0.0;
-  float w3acc[NB / 2];   // output-layer gradient: lane j of half hf holds rows 64 k + 32 (j / 16) + acc_row(j % 16, hf)
-#pragma unroll
-  for (int k = 0; k < NB / 2; ++k) w3acc[k] = 0.f;
   const int nblk = REG ? KB : s.KHP / 16;
 
   const int64_t ntiles = act ? (a.n + 31) / 32 : 0;
@@ -464,23 +461,23 @@ __global__ void __launch_bounds__(kBlock) k_backward(TileArgs a) {
 
     // output layer: dW3 (reduced over the tile's points into this wave's row) and delta2
     if (a.do_w3) {
-      // dm * relu(z2) summed over the half's 32 points, for each pair of row blocks, by a
+      // dm * relu(z2) summed over the half's 32 points, one row block at a time, by a
       // transposing butterfly: each step halves the values a lane holds and adds the other
-      // half from the lane whose index differs in one bit (the pairs and the order of the
-      // sums of a plain butterfly), so lane j ends with value j summed over the 32 points;
-      // 31 shuffles per pair instead of 5 per value.  Per lane, tiles add up in order.
+      // half from the lane whose index differs in one bit, so after offsets 8, 4, 2, 1 lane
+      // j holds value j % 16 summed over its 16-lane group, and one more shuffle adds the
+      // other group: 16 shuffles per block instead of 5 per value.  Lanes 0..15 of each half
+      // own one row each of the wave's LDS row and add the tiles in order.
 #pragma unroll
-      for (int k = 0; k < NB / 2; ++k) {
-        // first step straight from the accumulators (16 values live, not 32)
-        float v[16];
-        const bool up16 = (j & 16) != 0;
+      for (int b = 0; b < NB; ++b) {
+        float v[8];
+        const bool up8 = (j & 8) != 0;
 #pragma unroll
-        for (int i = 0; i < 16; ++i) {
-          const float lo = dm * fmaxf(z2[2 * k][i], 0.f), hi = dm * fmaxf(z2[2 * k + 1][i], 0.f);
-          v[i] = (up16 ? hi : lo) + __shfl_xor(up16 ? lo : hi, 16, 64);
+        for (int i = 0; i < 8; ++i) {
+          const float lo = dm * fmaxf(z2[b][i], 0.f), hi = dm * fmaxf(z2[b][i + 8], 0.f);
+          v[i] = (up8 ? hi : lo) + __shfl_xor(up8 ? lo : hi, 8, 64);
         }
 #pragma unroll
-        for (int m = 16; m > 1; m >>= 1) {
+        for (int m = 8; m > 1; m >>= 1) {
           const int o = m >> 1;
           const bool up = (j & o) != 0;
 #pragma unroll
@@ -490,7 +487,8 @@ __global__ void __launch_bounds__(kBlock) k_backward(TileArgs a) {
             v[i] = keep + __shfl_xor(send, o, 64);
           }
         }
-        w3acc[k] += v[0];
+        const float tot = v[0] + __shfl_xor(v[0], 16, 64);
+        if (j < 16) sW3w[wave * H + 32 * b + acc_row(j, hf)] += tot;   // one row per lane: no conflicts
       }
     }
     f32x16 d2[NB];
@@ -659,10 +657,6 @@ __global__ void __launch_bounds__(kBlock) k_backward(TileArgs a) {
     }
   }
 
-  if (a.do_w3) {
-#pragma unroll
-    for (int k = 0; k < NB / 2; ++k) sW3w[wave * H + 64 * k + 32 * (j >> 4) + acc_row(j & 15, hf)] = w3acc[k];
-  }
   if (a.want_loss) {
     const double t = wave_sum(loss);
     if (lane == 0) sLoss[wave] = t;
