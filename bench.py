@@ -246,7 +246,19 @@ def extra_c5(A, torch, synth, hl):
         A.apmg_forward(model, pts, out=out, ws=ws)
     torch.cuda.synchronize()
     dt = (time.perf_counter() - t0) / reps
-    return {"infer_pts_per_s": n / dt, "ms_per_frame": dt * 1e3, "points": n}
+    out = {"infer_pts_per_s": n / dt, "ms_per_frame": dt * 1e3, "points": n}
+    # the 2^20-point adjoint of the same model (dF, dG, dW), bf16 MLP
+    nb_ = 1 << 20
+    bp = A.apmg_uniform_points(13, 0, 0, 0, nb_)
+    dfb = torch.full((nb_,), 1.0 / nb_, device="cuda")
+    A.apmg_backward(model, bp, dfb)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(3):
+        A.apmg_backward(model, bp, dfb)
+    torch.cuda.synchronize()
+    out["backward_pts_per_s"] = 3 * nb_ / (time.perf_counter() - t0)
+    return out
 
 
 def cpu_baseline(vol_np, host, n_sample):
@@ -276,7 +288,7 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample", type=int, default=1 << 16)
+    ap.add_argument("--cpu-sample", type=int, default=1 << 18)
     ap.add_argument("--skip-extra", action="store_true")
     ap.add_argument("--configs", default="config1,config3,config4,config5",
                     help="extra workloads to time after the headline")

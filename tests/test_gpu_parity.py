@@ -535,3 +535,49 @@ def test_adjoint_2e20_points_sampled_vertices_and_partition():
         if checked == 8:
             break
     assert checked >= 6
+
+
+def test_render_shape_backward_2e20_points():
+    # the render workload's model (64 grids at 64^3 x 4 features, MLP 256-128-128-1) with a
+    # 2^20-point backward: FP32 MLP against the oracle on a slice and by batch partition,
+    # central differences along F on kink-free segments; the BF16 MLP's gradient error stated
+    host = synth.init_model(64, 4, 64, [256, 128, 128, 1], seed=5, grid_range=1.0, extra_translation=0.3)
+    n = 1 << 20
+    pts = A().apmg_uniform_points(23, 0, 0, 0, n, DEV)
+    x = pts.cpu().numpy().T.astype(np.float32).copy()
+    w = (np.random.default_rng(8).normal(size=n) / n).astype(np.float32)
+    model = A().Model.from_host(host, DEV)
+    dF, dG, dW = A().apmg_backward(model, pts, torch.from_numpy(w).to(DEV))
+    half = n // 2
+    p1 = A().apmg_backward(model, pts[:, :half].contiguous(), torch.from_numpy(w[:half]).to(DEV))
+    p2 = A().apmg_backward(model, pts[:, half:].contiguous(), torch.from_numpy(w[half:]).to(DEV))
+    assert_close("partition dF", dF.cpu().numpy(), (p1[0] + p2[0]).cpu().numpy())
+    assert_close("partition dG", dG.cpu().numpy(), (p1[1] + p2[1]).cpu().numpy())
+    for k in range(3):
+        assert_close(f"partition dW{k + 1}", dW[k].cpu().numpy(), (p1[2][k] + p2[2][k]).cpu().numpy())
+    s = 4096
+    keep = kink_free_mask(host, x[:s])
+    sub, ws_ = x[:s][keep], w[:s][keep]
+    g_ = A().apmg_backward(model, soa(sub), torch.from_numpy(ws_).to(DEV))
+    go = O.backward(f64(host), sub.astype(np.float64), ws_.astype(np.float64))
+    assert_close("slice dF", g_[0].cpu().numpy(), go["dF"].transpose(0, 2, 3, 4, 1))
+    assert_close("slice dG", g_[1].cpu().numpy(), go["dG"])
+    for k in range(3):
+        assert_close(f"slice dW{k + 1}", g_[2][k].cpu().numpy(), go["dW"][k])
+    rng = np.random.default_rng(31)
+    zero = {"G": np.zeros(host["G"].shape), "F": np.zeros(host["F"].shape),
+            "W": [np.zeros(wk.shape) for wk in host["W"]]}
+    _central_difference_check(host, dict(zero, F=0.3 * rng.normal(size=host["F"].shape)), 1e-3,
+                              synth.uniform_points_host(16384, seed=17), 4, 1e-3, "render F")
+    # BF16 operands (8-bit mantissas) through a 256-128-128 MLP: the error is stated, with a
+    # sanity bound only
+    mb = A().Model.from_host(host, DEV, mlp_dtype=A().BF16)
+    gb = A().apmg_backward(mb, soa(sub), torch.from_numpy(ws_).to(DEV))
+    for name, got, want in (("dF", gb[0].cpu().numpy(), go["dF"].transpose(0, 2, 3, 4, 1)),
+                            ("dG", gb[1].cpu().numpy(), go["dG"]),
+                            ("dW1", gb[2][0].cpu().numpy(), go["dW"][0]),
+                            ("dW2", gb[2][1].cpu().numpy(), go["dW"][1]),
+                            ("dW3", gb[2][2].cpu().numpy(), go["dW"][2])):
+        a, _ = errs(got, want)
+        print(f"render bf16 backward {name}: normwise {a:.2e}")
+        assert a < 0.2
