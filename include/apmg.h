@@ -227,14 +227,20 @@ apmg_status apmg_dd_forward(const apmg_dd_models* models, const apmg_brick_table
  *     per cell (always used when L_rec's transform gradient is requested).
  *   cell_unroll: candidates per batch of the one-thread-per-cell gather, 2, 4
  *     or 8 (default 4).
- * Both gathers add each cell's points in the same order with the same
- * arithmetic.  Results depend on tile_blocks through the order of the
- * weight-gradient sums (each setting is bitwise reproducible run to run). */
+ *   cell_group: lanes per candidate run of the wave gather, 1, 2, 4 or 8
+ *     (default 4): the wave splits its candidates into 64 / cell_group runs
+ *     and each group of lanes reads cell_group consecutive points per step.
+ * The two gathers add each cell's terms in different fixed orders (the
+ * per-cell thread in point order, the wave in its own step-then-lane order),
+ * so the grid gradients agree to float32 rounding; cell_unroll does not
+ * change the order, cell_group does.  Results also depend on tile_blocks through the order of
+ * the weight-gradient sums.  Each setting is bitwise reproducible run to run. */
 typedef struct apmg_tuning {
   int32_t tile_blocks;
   int32_t cell_unroll;
   int32_t cell_kernel;
-  int32_t reserved[5];
+  int32_t cell_group;
+  int32_t reserved[4];
 } apmg_tuning;
 
 typedef struct apmg_batch {

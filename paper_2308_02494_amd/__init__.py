@@ -48,7 +48,8 @@ class ApmgBrickTable(ctypes.Structure):
 
 
 class ApmgTuning(ctypes.Structure):
-    _fields_ = [("tile_blocks", c_i32), ("cell_unroll", c_i32), ("cell_kernel", c_i32), ("reserved", c_i32 * 5)]
+    _fields_ = [("tile_blocks", c_i32), ("cell_unroll", c_i32), ("cell_kernel", c_i32), ("cell_group", c_i32),
+                ("reserved", c_i32 * 4)]
 
 
 class ApmgBatch(ctypes.Structure):
@@ -391,12 +392,14 @@ class Trainer:
             self.enable_control(**control)
 
     def set_tuning(self, tuning):
-        """Launch shapes for the step: an ApmgTuning, a dict (tile_blocks, cell_unroll) or None."""
+        """Launch shapes for the step: an ApmgTuning, a dict (tile_blocks, cell_unroll, cell_kernel,
+        cell_group) or None."""
         if isinstance(tuning, dict):
             t = ApmgTuning()
             t.tile_blocks = tuning.get("tile_blocks", 0)
             t.cell_unroll = tuning.get("cell_unroll", 0)
             t.cell_kernel = tuning.get("cell_kernel", 0)
+            t.cell_group = tuning.get("cell_group", 0)
             tuning = t
         self.tuning = tuning
         self.batch.tuning = ctypes.pointer(tuning) if tuning is not None else None
@@ -411,7 +414,7 @@ class Trainer:
                                               _stream(self.device), ctypes.byref(best), ctypes.byref(ms)))
         self.set_tuning(best)
         return {"tile_blocks": best.tile_blocks, "cell_unroll": best.cell_unroll,
-                "cell_kernel": best.cell_kernel}, ms.value
+                "cell_kernel": best.cell_kernel, "cell_group": best.cell_group}, ms.value
 
     def enable_control(self, total_iters, delay=500, ma_window=1000, ma_rel=1e-4, stop_frac=0.8, patience=500,
                        plateau_rel=1e-4, plateau_factor=0.1, max_reductions=3):

@@ -77,8 +77,10 @@ int tile_blocks(int64_t n) {
 
 // Training-step launch shapes (apmg_tuning): tile-kernel blocks per model, default
 // ceil(512 / nb) (about two blocks per CU over all models), at most 4x the default,
-// 1024, and the number of 4-tile groups; gather batch of 2, 4 or 8 candidates.
-struct Tune { int tile_blocks; int cell_unroll; int cell_kernel; };
+// 1024, and the number of 4-tile groups; gather batch of 2, 4 or 8 candidates; lanes per
+// candidate run of the wave gather, 1, 2, 4 or 8.
+constexpr int kDefaultCellGroup = 4;
+struct Tune { int tile_blocks; int cell_unroll; int cell_kernel; int cell_group; };
 int step_groups(int64_t n) {
   const int64_t tiles = (std::max<int64_t>(n, 1) + 31) / 32;
   return (int)std::max<int64_t>(1, (tiles + kWavesPerBlock - 1) / kWavesPerBlock);
@@ -93,13 +95,17 @@ bool resolve_tune(const apmg_tuning* t, int64_t n, int nb, Tune* out) {
   out->tile_blocks = step_default_blocks(n, nb);
   out->cell_unroll = 4;
   out->cell_kernel = 0;
+  out->cell_group = kDefaultCellGroup;
   if (!t) return true;
   if (t->tile_blocks < 0 || t->tile_blocks > step_max_blocks(n, nb)) return false;
   if (t->cell_unroll != 0 && t->cell_unroll != 2 && t->cell_unroll != 4 && t->cell_unroll != 8) return false;
   if (t->cell_kernel < 0 || t->cell_kernel > 2) return false;
+  if (t->cell_group != 0 && t->cell_group != 1 && t->cell_group != 2 && t->cell_group != 4 && t->cell_group != 8)
+    return false;
   if (t->tile_blocks > 0) out->tile_blocks = t->tile_blocks;
   if (t->cell_unroll > 0) out->cell_unroll = t->cell_unroll;
   if (t->cell_kernel > 0) out->cell_kernel = t->cell_kernel - 1;
+  if (t->cell_group > 0) out->cell_group = t->cell_group;
   return true;
 }
 
@@ -207,7 +213,7 @@ hipError_t launch_cells(const Shape& s, bool gf16, const float* G, size_t G_stri
                         const SortWs& sw, int64_t n, const CellWs& cw, float* dF, size_t dF_stride, int accumulate,
                         bool want_dG, double* dG, size_t dG_stride, int dG_accumulate, int nb,
                         const int32_t* active, hipStream_t st, int unroll = 4, const int32_t* dG_active = nullptr,
-                        int cell_kernel = 0) {
+                        int cell_kernel = 0, int cell_group = kDefaultCellGroup) {
   CellArgs c;
   memset(&c, 0, sizeof(c));
   c.s = s; c.G = G; c.G_stride = G_stride; c.F = F; c.F_stride = F_stride;
@@ -229,9 +235,13 @@ hipError_t launch_cells(const Shape& s, bool gf16, const float* G, size_t G_stri
 #define APMG_CELL(CC_, F16_)                                                                        \
   if (s.C == CC_ && gf16 == F16_) {                                                                 \
     if (want_dG) APMG_PULL(CC_, F16_, true)                                                          \
-    else if (wave_kernel)                                                                           \
-      hipLaunchKernelGGL((k_cell_pull_wave<CC_, F16_>), dim3((unsigned)wgroups), dim3(256), 0, st, c); \
-    else APMG_PULL(CC_, F16_, false)                                                                 \
+    else if (wave_kernel) {                                                                         \
+      const dim3 wg((unsigned)wgroups);                                                             \
+      if (cell_group == 1) hipLaunchKernelGGL((k_cell_pull_wave<CC_, F16_, 1>), wg, dim3(256), 0, st, c); \
+      else if (cell_group == 2) hipLaunchKernelGGL((k_cell_pull_wave<CC_, F16_, 2>), wg, dim3(256), 0, st, c); \
+      else if (cell_group == 8) hipLaunchKernelGGL((k_cell_pull_wave<CC_, F16_, 8>), wg, dim3(256), 0, st, c); \
+      else hipLaunchKernelGGL((k_cell_pull_wave<CC_, F16_, 4>), wg, dim3(256), 0, st, c);           \
+    } else APMG_PULL(CC_, F16_, false)                                                               \
     if (dF) hipLaunchKernelGGL((k_cell_to_vertex<CC_>), dim3(grid1((int64_t)s.R * s.R * s.R, 1024), s.M, nb), \
                                dim3(256), 0, st, s, cw.CC, dF, dF_stride, accumulate, active);       \
   }
@@ -749,7 +759,7 @@ apmg_status run_step(const apmg_batch* b, const Shape& s, void* ws, const Tune& 
   // 4. grid gradient from the per-cell pass; L_rec's transform gradient only under APMG_ADD_REC_DG
   if (n > 0) {
     e = launch_cells(s, gf16, b->G, nG, gf16 ? (const void*)b->F_lowp : (const void*)b->F, nF, w.srt, n, w.cell,
-                     w.dF, nF, 0, rec_dG, nullptr, 0, 0, nb, w.live, st, tu.cell_unroll, nullptr, tu.cell_kernel);
+                     w.dF, nF, 0, rec_dG, nullptr, 0, 0, nb, w.live, st, tu.cell_unroll, nullptr, tu.cell_kernel, tu.cell_group);
     if (e != hipSuccess) return APMG_EHIP;
   }
   // 5. density loss and its transform gradient (part 2), for models whose transforms train
@@ -807,15 +817,19 @@ extern "C" apmg_status apmg_autotune_batched_step(const apmg_batch* b, void* ws,
   if (hipEventCreate(&e0) != hipSuccess) return APMG_EHIP;
   if (hipEventCreate(&e1) != hipSuccess) { hipEventDestroy(e0); return APMG_EHIP; }
   float best_t = -1.f;
-  Tune best_tu = {d, 4, 0};
+  Tune best_tu = {d, 4, 0, kDefaultCellGroup};
   apmg_status out = APMG_OK;
   const bool rec_dG = b->flags & APMG_ADD_REC_DG;
+  // gathers: the wave-cooperative one with 2, 4 or 8 lanes per candidate run, then one
+  // thread per cell with 2, 4 or 8 candidates per batch (the only gather when L_rec's
+  // transform gradient is requested)
+  struct Gather { int kernel, unroll, group; };
+  const Gather gathers[] = {{0, 4, 2}, {0, 4, 4}, {0, 4, 8}, {1, 2, kDefaultCellGroup},
+                            {1, 4, kDefaultCellGroup}, {1, 8, kDefaultCellGroup}};
   for (int tb : blocks) {
-    for (int variant = 0; variant < 4; ++variant) {
-      // variant 0: the wave-cooperative gather; 1..3: one thread per cell, 2/4/8 candidates
-      // per batch (the only gather when L_rec's transform gradient is requested)
-      if (variant == 0 && rec_dG) continue;
-      const Tune tu = {tb, variant == 0 ? 4 : (1 << variant), variant == 0 ? 0 : 1};
+    for (const Gather& ga : gathers) {
+      if (ga.kernel == 0 && rec_dG) continue;
+      const Tune tu = {tb, ga.unroll, ga.kernel, ga.group};
       if ((rc = run_step(b, s, ws, tu, false, st)) != APMG_OK) { out = rc; break; }   // warm-up
       if (hipEventRecord(e0, st) != hipSuccess) { out = APMG_EHIP; break; }
       for (int r = 0; r < 3 && rc == APMG_OK; ++r) rc = run_step(b, s, ws, tu, false, st);
@@ -835,6 +849,7 @@ extern "C" apmg_status apmg_autotune_batched_step(const apmg_batch* b, void* ws,
   best->tile_blocks = best_tu.tile_blocks;
   best->cell_unroll = best_tu.cell_unroll;
   best->cell_kernel = best_tu.cell_kernel + 1;
+  best->cell_group = best_tu.cell_group;
   if (best_ms) *best_ms = best_t;
   return APMG_OK;
 }

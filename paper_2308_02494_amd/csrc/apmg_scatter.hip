@@ -205,20 +205,27 @@ __global__ void __launch_bounds__(256) k_cell_pull(CellArgs a) {
 }
 
 // The grid gradient without the transform gradient, one wave per 4 x 4 x 4 block of cells
-// of one grid.  The wave walks the rows of the bins that overlap the block's box (the
-// union of its cells' candidates, each point read once, 64 consecutive points per step),
-// every lane tests one point against the block, and a matching point's (w, dL/dy) record is
-// handed to the lane that owns its cell through LDS: each owner adds the records addressed
-// to it in lane order.  The accumulation per cell is in candidate order and has the same
-// arithmetic as k_cell_pull, so the corner sums are bitwise the same.
+// of one grid.  The wave takes the rows of the bins that overlap the block's box (the union
+// of its cells' candidates, each point read once) 128 rows at a time and splits each batch's
+// points, as one flat sequence, into 64 / G contiguous runs of equal length, one per group
+// of G lanes.  At a step each group tests the next G points of its run against the block
+// (lane i of the group the i-th), so the points of a step come from all over the block's box
+// and few of them share a cell, while each group still reads G consecutive records.  A
+// matching point's (w, dL/dy) products are handed to the lane that owns its cell through
+// LDS, and each owner adds the records addressed to it in lane order.  Each cell's sum has a
+// fixed order (step, then lane) set by the candidate sequence and G: bitwise reproducible,
+// but not the plain candidate order of k_cell_pull.
 constexpr int kBlk = 4;                      // cells per block edge
-template <int C, bool GF16>
+constexpr int kRowBatch = 128;               // bin rows per batch (two per lane)
+template <int C, bool GF16, int G>
 __global__ void __launch_bounds__(256) k_cell_pull_wave(CellArgs a) {
+  static_assert(G == 1 || G == 2 || G == 4 || G == 8, "lanes per run");
+  constexpr int NR = 64 / G;                 // runs per batch
   constexpr int RW = 2 * C;                  // float4 words per record: the 8 C products w_q dL/dy_c
   __shared__ float4 sRec[4][64][RW];
   __shared__ float sG[4][12];
-  __shared__ uint32_t sRow0[4][64];          // first sorted position of each row of the batch
-  __shared__ uint32_t sPre[4][64];           // exclusive prefix of the rows' lengths
+  __shared__ uint32_t sRow0[4][kRowBatch];   // first sorted position of each row of the batch
+  __shared__ uint32_t sPre[4][kRowBatch + 1];  // exclusive prefix of the rows' lengths; [kRowBatch] = total
   const Shape s = a.s;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int R1 = s.R - 1;
@@ -283,26 +290,76 @@ __global__ void __launch_bounds__(256) k_cell_pull_wave(CellArgs a) {
     const float hR = 0.5f * (float)R1;
     const int ny_r = hi[1] - lo[1] + 1, nz_r = hi[2] - lo[2] + 1;
     const int nrows = ny_r * nz_r;
-    // A candidate: its point and dL/dy, loaded for every lane (a lane past the end loads
-    // point 0), so the loads of the next 64 candidates are in flight while these are used.
-    struct Cand { float4 q; float dy[C]; };
-    // each lane's flat index grows by 64 per step, so the row holding it (the last row whose
-    // exclusive prefix is <= f) is found by walking forward from the previous one
-    int rcur = 0;
-    auto load = [&](uint32_t f, uint32_t total, Cand& cd) {
-      uint32_t p = 0;
-      if (f < total) {
-        while (rcur < 63 && sPre[wave][rcur + 1] <= f) ++rcur;
-        p = sRow0[wave][rcur] + (f - sPre[wave][rcur]);
-      }
-      cd.q = P4[p];
+    // Tighter x-range of a bin row: the x for which some (y, z) of the row satisfies each of
+    // the three slab constraints of the block's local box, lo_d <= A_d . x + t_d <= hi_d,
+    // taken one slab at a time (a superset of the exact range).  float64, with the local box
+    // widened by 1e-4 and the row by 1e-5 (the float32 roundings of the cell decision and of
+    // the binning); the edge rows of the bin grid reach to infinity, because the binning
+    // clamps points outside the domain into them.  Returns false for an empty row.
+    double blo[3], bhi[3];
 #pragma unroll
-      for (int c = 0; c < C; ++c) cd.dy[c] = dY[(size_t)p * C + c];
+    for (int d = 0; d < 3; ++d) {
+      const int e = min(b0[d] + kBlk, R1);
+      blo[d] = -1.0 + 2.0 * b0[d] / R1 - 1e-4 - (double)Gg[4 * d + 3];
+      bhi[d] = -1.0 + 2.0 * e / R1 + 1e-4 - (double)Gg[4 * d + 3];
+    }
+    auto row_span = [&](int yb, int zb, int& x0, int& x1) -> bool {
+      constexpr double kInf = __builtin_inf(), kW = 2.0 / kBinsPerAxis;
+      const double ylo = yb == 0 ? -kInf : -1.0 + yb * kW - 1e-5;
+      const double yhi = yb == kBinsPerAxis - 1 ? kInf : -1.0 + (yb + 1) * kW + 1e-5;
+      const double zlo = zb == 0 ? -kInf : -1.0 + zb * kW - 1e-5;
+      const double zhi = zb == kBinsPerAxis - 1 ? kInf : -1.0 + (zb + 1) * kW + 1e-5;
+      double xl = -kInf, xh = kInf;
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        const double a0 = Gg[4 * d], a1 = Gg[4 * d + 1], a2 = Gg[4 * d + 2];
+        // range of a1 y + a2 z over the row (a zero coefficient contributes exactly 0)
+        const double m_lo = (a1 > 0 ? a1 * ylo : a1 < 0 ? a1 * yhi : 0.0) + (a2 > 0 ? a2 * zlo : a2 < 0 ? a2 * zhi : 0.0);
+        const double m_hi = (a1 > 0 ? a1 * yhi : a1 < 0 ? a1 * ylo : 0.0) + (a2 > 0 ? a2 * zhi : a2 < 0 ? a2 * zlo : 0.0);
+        const double P = blo[d] - m_hi, Q = bhi[d] - m_lo;      // P <= a0 x <= Q
+        if (a0 > 0) { xl = fmax(xl, P / a0); xh = fmin(xh, Q / a0); }
+        else if (a0 < 0) { xl = fmax(xl, Q / a0); xh = fmin(xh, P / a0); }
+        else if (P > 0.0 || Q < 0.0) return false;
+      }
+      if (!(xl <= xh)) return false;
+      const double f0 = floor((xl - 1e-4 + 1.0) * (0.5 * kBinsPerAxis));
+      const double f1 = floor((xh + 1e-4 + 1.0) * (0.5 * kBinsPerAxis));
+      x0 = (int)fmin(fmax(f0, (double)lo[0]), (double)hi[0]);
+      x1 = (int)fmin(fmax(f1, (double)lo[0]), (double)hi[0]);
+      return true;
     };
-    auto consume = [&](const Cand& cd, bool valid) {
+    // A candidate: its point and dL/dy, loaded for every lane (a lane past the end of its run
+    // loads point 0), so the loads of the next step are in flight while this one is used.
+    struct Cand { float4 q; float dy[C]; bool valid; };
+    // the lane's place in its run: flat index f (< fend), row r, sorted position p, and the
+    // points left in row r from p on
+    uint32_t f = 0, fend = 0, p = 0, rem = 0;
+    int r = 0;
+    auto load = [&](Cand& cd) {
+      cd.valid = f < fend;
+      const uint32_t pp = cd.valid ? p : 0u;
+      cd.q = P4[pp];
+#pragma unroll
+      for (int c = 0; c < C; ++c) cd.dy[c] = dY[(size_t)pp * C + c];
+      if (cd.valid) {
+        f += G;
+        if (f < fend) {                      // move G points on, across rows (the one holding f exists)
+          uint32_t k = G;
+          while (k >= rem) {
+            k -= rem;
+            do { ++r; } while (sPre[wave][r + 1] == sPre[wave][r]);
+            p = sRow0[wave][r];
+            rem = sPre[wave][r + 1] - sPre[wave][r];
+          }
+          p += k;
+          rem -= k;
+        }
+      }
+    };
+    auto consume = [&](const Cand& cd) {
       int t = -1;
       float w[3] = {0.f, 0.f, 0.f};
-      if (valid) {
+      if (cd.valid) {
         float l[3];
         int i0[3];
         local_coords(Gg, cd.q.x, cd.q.y, cd.q.z, l);
@@ -352,38 +409,62 @@ __global__ void __launch_bounds__(256) k_cell_pull_wave(CellArgs a) {
       __builtin_amdgcn_wave_barrier();
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     };
-    // rows (z outer, y inner) 64 at a time; each batch's points are one flat sequence
-    for (int rb = 0; rb < nrows; rb += 64) {
-      const int r = rb + lane;
-      uint32_t s0 = 0, len = 0;
-      if (r < nrows) {
-        const int yb = lo[1] + r % ny_r, zb = lo[2] + r / ny_r;
-        const int row = (zb * kBinsPerAxis + yb) * kBinsPerAxis;
-        s0 = start[row + lo[0]];
-        len = start[row + hi[0] + 1] - s0;
+    // rows (z outer, y inner) kRowBatch at a time; each batch's points are one flat sequence
+    for (int rb = 0; rb < nrows; rb += kRowBatch) {
+      uint32_t s0[2] = {0, 0}, len[2] = {0, 0};
+#pragma unroll
+      for (int k = 0; k < 2; ++k) {
+        const int rr = rb + 2 * lane + k;
+        int x0 = lo[0], x1 = hi[0];
+        if (rr < nrows) {
+          const int yb = lo[1] + rr % ny_r, zb = lo[2] + rr / ny_r;
+          if (bad || row_span(yb, zb, x0, x1)) {
+            const int row = (zb * kBinsPerAxis + yb) * kBinsPerAxis;
+            s0[k] = start[row + x0];
+            len[k] = start[row + x1 + 1] - s0[k];
+          }
+        }
       }
-      uint32_t x = len;
+      uint32_t x = len[0] + len[1];
 #pragma unroll
       for (int o = 1; o < 64; o <<= 1) {
         const uint32_t y = __shfl_up(x, o, 64);
         if (lane >= o) x += y;
       }
       const uint32_t total = __shfl(x, 63, 64);
-      sRow0[wave][lane] = s0;
-      sPre[wave][lane] = x - len;
+      const uint32_t ex = x - len[0] - len[1];
+      sRow0[wave][2 * lane] = s0[0];
+      sRow0[wave][2 * lane + 1] = s0[1];
+      sPre[wave][2 * lane] = ex;
+      sPre[wave][2 * lane + 1] = ex + len[0];
+      if (lane == 0) sPre[wave][kRowBatch] = total;
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
       __builtin_amdgcn_wave_barrier();
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      // runs of S points (a multiple of G; the last runs may be shorter), S / G steps
+      const uint32_t S = ((total + NR - 1) / NR + G - 1) / G * G;
+      const uint32_t f0 = min((uint32_t)(lane / G) * S, total);
+      fend = min(f0 + S, total);
+      f = f0 + (uint32_t)(lane % G);
+      if (f < fend) {
+        // the row holding f: the last row whose exclusive prefix is <= f (it is non-empty)
+        r = 0;
+#pragma unroll
+        for (int step = kRowBatch / 2; step >= 1; step >>= 1)
+          if (sPre[wave][r + step] <= f) r += step;
+        p = sRow0[wave][r] + (f - sPre[wave][r]);
+        rem = sPre[wave][r + 1] - f;
+      }
+      const uint32_t nsteps = S / G;
       Cand ca, cbn;
-      rcur = 0;
-      load(lane, total, ca);
-      for (uint32_t base = 0; base < total; base += 128) {
-        load(base + 64 + lane, total, cbn);
+      load(ca);
+      for (uint32_t st = 0; st < nsteps; st += 2) {
+        load(cbn);
         sched_barrier();
-        consume(ca, base + lane < total);
-        load(base + 128 + lane, total, ca);
+        consume(ca);
+        load(ca);
         sched_barrier();
-        if (base + 64 < total) consume(cbn, base + 64 + lane < total);
+        if (st + 1 < nsteps) consume(cbn);
       }
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
       __builtin_amdgcn_wave_barrier();

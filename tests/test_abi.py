@@ -149,7 +149,7 @@ int main() {
   S(apmg_model) F(apmg_model, width) F(apmg_model, G) F(apmg_model, F) F(apmg_model, W) F(apmg_model, vmin)
   S(apmg_brick) F(apmg_brick, e1) F(apmg_brick, vmax)
   S(apmg_brick_table) F(apmg_brick_table, ghost)
-  S(apmg_tuning) F(apmg_tuning, cell_unroll)
+  S(apmg_tuning) F(apmg_tuning, cell_unroll) F(apmg_tuning, cell_group)
   S(apmg_batch) F(apmg_batch, shape) F(apmg_batch, G) F(apmg_batch, density_active) F(apmg_batch, vol)
   F(apmg_batch, n) F(apmg_batch, step) F(apmg_batch, lr) F(apmg_batch, eps_density) F(apmg_batch, losses)
   F(apmg_batch, tuning) F(apmg_batch, frozen) F(apmg_batch, lr_scale)

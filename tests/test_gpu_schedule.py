@@ -169,6 +169,7 @@ def test_autotune_returns_a_valid_shape_and_leaves_parameters():
     torch.cuda.synchronize()
     print("autotune:", tune, f"{ms:.3f} ms")
     assert tune["cell_unroll"] in (2, 4, 8) and tune["tile_blocks"] >= 1 and tune["cell_kernel"] in (1, 2)
+    assert tune["cell_group"] in (1, 2, 4, 8)
     assert ms > 0
     for x, y in zip(before, (tr.G, tr.F, tr.W, tr.mF, tr.t, tr.step_ctr)):
         assert torch.equal(x, y)
@@ -201,18 +202,35 @@ def test_bad_tuning_is_rejected_before_launch():
     tr.set_tuning({"cell_kernel": 3})
     with pytest.raises(A().ApmgError):
         tr.step()
+    tr.set_tuning({"cell_group": 3})
+    with pytest.raises(A().ApmgError):
+        tr.step()
     tr.set_tuning(None)
     tr.step()
 
 
 def test_both_gathers_give_the_same_step():
-    # the training step with the wave-cooperative gather and with the one-thread-per-cell
-    # gather (every batch size): bitwise the same parameters
+    # one training step with the wave-cooperative gather and with the one-thread-per-cell
+    # gather (every batch size).  The grid gradient is the same terms summed in a different
+    # fixed order, so the grids' first moments (0.1 * gradient) agree to float32 rounding;
+    # the per-cell gather's batch size does not change its order (bitwise equal); the MLP
+    # and the transforms do not depend on the gather.
     ref = _bricks_trainer(nb=2, n=6000, tuning={"cell_kernel": 1})
+    F0 = ref.F.clone()
     ref.step()
+    first = None
     for unroll in (2, 4, 8):
         other = _bricks_trainer(nb=2, n=6000, tuning={"cell_kernel": 2, "cell_unroll": unroll})
         other.step()
         torch.cuda.synchronize()
-        for x, y in zip((ref.F, ref.W, ref.G, ref.mF), (other.F, other.W, other.G, other.mF)):
+        for x, y in zip((ref.W, ref.G), (other.W, other.G)):
             assert torch.equal(x, y), unroll
+        rel = ((ref.mF - other.mF).norm() / ref.mF.norm()).item()
+        assert rel < 1e-6, (unroll, rel)
+        dref, doth = ref.F - F0, other.F - F0
+        assert ((dref - doth).norm() / dref.norm()).item() < 1e-3, unroll
+        if first is None:
+            first = other
+        else:
+            for x, y in zip((first.F, first.mF), (other.F, other.mF)):
+                assert torch.equal(x, y), unroll
