@@ -37,6 +37,50 @@ __device__ inline float add_rounded(float acc, float v) {
   return acc + v;
 }
 
+// The local box of the cells [c0, c0 + w) (per axis, clipped to the grid) minus the
+// translation, widened by 1e-4 (covers the float32 rounding of the cell decision), in float64.
+__device__ inline void local_box(const float* Gg, const int c0[3], int w, int R1, double blo[3], double bhi[3]) {
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    const int e = min(c0[d] + w, R1);
+    blo[d] = -1.0 + 2.0 * c0[d] / R1 - 1e-4 - (double)Gg[4 * d + 3];
+    bhi[d] = -1.0 + 2.0 * e / R1 + 1e-4 - (double)Gg[4 * d + 3];
+  }
+}
+
+// Tighter x-range [x0, x1] (bins, within [lo0, hi0]) of the bin row (yb, zb) for a local box:
+// the x for which some (y, z) of the row satisfies each of the three slab constraints
+// blo_d <= A_d . x <= bhi_d, taken one slab at a time (a superset of the exact range), in
+// float64, with the row widened by 1e-5 (the float32 rounding of the binning) and the x-range
+// by 1e-4.  The edge rows of the bin grid reach to infinity, because the binning clamps points
+// outside the domain into them.  Returns false for an empty row.
+__device__ inline bool row_x_span(const float* Gg, const double blo[3], const double bhi[3], int lo0, int hi0,
+                                  int yb, int zb, int& x0, int& x1) {
+  constexpr double kInf = __builtin_inf(), kW = 2.0 / kBinsPerAxis;
+  const double ylo = yb == 0 ? -kInf : -1.0 + yb * kW - 1e-5;
+  const double yhi = yb == kBinsPerAxis - 1 ? kInf : -1.0 + (yb + 1) * kW + 1e-5;
+  const double zlo = zb == 0 ? -kInf : -1.0 + zb * kW - 1e-5;
+  const double zhi = zb == kBinsPerAxis - 1 ? kInf : -1.0 + (zb + 1) * kW + 1e-5;
+  double xl = -kInf, xh = kInf;
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    const double a0 = Gg[4 * d], a1 = Gg[4 * d + 1], a2 = Gg[4 * d + 2];
+    // range of a1 y + a2 z over the row (a zero coefficient contributes exactly 0)
+    const double m_lo = (a1 > 0 ? a1 * ylo : a1 < 0 ? a1 * yhi : 0.0) + (a2 > 0 ? a2 * zlo : a2 < 0 ? a2 * zhi : 0.0);
+    const double m_hi = (a1 > 0 ? a1 * yhi : a1 < 0 ? a1 * ylo : 0.0) + (a2 > 0 ? a2 * zhi : a2 < 0 ? a2 * zlo : 0.0);
+    const double P = blo[d] - m_hi, Q = bhi[d] - m_lo;      // P <= a0 x <= Q
+    if (a0 > 0) { xl = fmax(xl, P / a0); xh = fmin(xh, Q / a0); }
+    else if (a0 < 0) { xl = fmax(xl, Q / a0); xh = fmin(xh, P / a0); }
+    else if (P > 0.0 || Q < 0.0) return false;
+  }
+  if (!(xl <= xh)) return false;
+  const double f0 = floor((xl - 1e-4 + 1.0) * (0.5 * kBinsPerAxis));
+  const double f1 = floor((xh + 1e-4 + 1.0) * (0.5 * kBinsPerAxis));
+  x0 = (int)fmin(fmax(f0, (double)lo0), (double)hi0);
+  x1 = (int)fmin(fmax(f1, (double)lo0), (double)hi0);
+  return true;
+}
+
 // Block order: xcd_logical over (model, cell block, grid), so an XCD works through a slab of
 // cells for all grids at once and the points of that slab stay in its L2.
 
@@ -120,10 +164,15 @@ __global__ void __launch_bounds__(256) k_cell_pull(CellArgs a) {
                                 : (const void*)((const float*)a.F + model * a.F_stride),
                            g, s.R, me, val);
     }
+    double blo[3], bhi[3];
+    const int me0[3] = {cx, cy, cz};
+    local_box(sG, me0, 1, R1, blo, bhi);
     for (int bz = lo[2]; bz <= hi[2]; ++bz)
       for (int by = lo[1]; by <= hi[1]; ++by) {
+        int x0 = lo[0], x1 = hi[0];
+        if (!sBad && !row_x_span(sG, blo, bhi, lo[0], hi[0], by, bz, x0, x1)) continue;
         const int row = (bz * kBinsPerAxis + by) * kBinsPerAxis;
-        const uint32_t p0 = start[row + lo[0]], p1 = start[row + hi[0] + 1];
+        const uint32_t p0 = start[row + x0], p1 = start[row + x1 + 1];
         for (uint32_t p = p0; p < p1; p += kCellUnroll) {
           float4 q[kCellUnroll];
 #pragma unroll
@@ -290,44 +339,8 @@ __global__ void __launch_bounds__(256) k_cell_pull_wave(CellArgs a) {
     const float hR = 0.5f * (float)R1;
     const int ny_r = hi[1] - lo[1] + 1, nz_r = hi[2] - lo[2] + 1;
     const int nrows = ny_r * nz_r;
-    // Tighter x-range of a bin row: the x for which some (y, z) of the row satisfies each of
-    // the three slab constraints of the block's local box, lo_d <= A_d . x + t_d <= hi_d,
-    // taken one slab at a time (a superset of the exact range).  float64, with the local box
-    // widened by 1e-4 and the row by 1e-5 (the float32 roundings of the cell decision and of
-    // the binning); the edge rows of the bin grid reach to infinity, because the binning
-    // clamps points outside the domain into them.  Returns false for an empty row.
     double blo[3], bhi[3];
-#pragma unroll
-    for (int d = 0; d < 3; ++d) {
-      const int e = min(b0[d] + kBlk, R1);
-      blo[d] = -1.0 + 2.0 * b0[d] / R1 - 1e-4 - (double)Gg[4 * d + 3];
-      bhi[d] = -1.0 + 2.0 * e / R1 + 1e-4 - (double)Gg[4 * d + 3];
-    }
-    auto row_span = [&](int yb, int zb, int& x0, int& x1) -> bool {
-      constexpr double kInf = __builtin_inf(), kW = 2.0 / kBinsPerAxis;
-      const double ylo = yb == 0 ? -kInf : -1.0 + yb * kW - 1e-5;
-      const double yhi = yb == kBinsPerAxis - 1 ? kInf : -1.0 + (yb + 1) * kW + 1e-5;
-      const double zlo = zb == 0 ? -kInf : -1.0 + zb * kW - 1e-5;
-      const double zhi = zb == kBinsPerAxis - 1 ? kInf : -1.0 + (zb + 1) * kW + 1e-5;
-      double xl = -kInf, xh = kInf;
-#pragma unroll
-      for (int d = 0; d < 3; ++d) {
-        const double a0 = Gg[4 * d], a1 = Gg[4 * d + 1], a2 = Gg[4 * d + 2];
-        // range of a1 y + a2 z over the row (a zero coefficient contributes exactly 0)
-        const double m_lo = (a1 > 0 ? a1 * ylo : a1 < 0 ? a1 * yhi : 0.0) + (a2 > 0 ? a2 * zlo : a2 < 0 ? a2 * zhi : 0.0);
-        const double m_hi = (a1 > 0 ? a1 * yhi : a1 < 0 ? a1 * ylo : 0.0) + (a2 > 0 ? a2 * zhi : a2 < 0 ? a2 * zlo : 0.0);
-        const double P = blo[d] - m_hi, Q = bhi[d] - m_lo;      // P <= a0 x <= Q
-        if (a0 > 0) { xl = fmax(xl, P / a0); xh = fmin(xh, Q / a0); }
-        else if (a0 < 0) { xl = fmax(xl, Q / a0); xh = fmin(xh, P / a0); }
-        else if (P > 0.0 || Q < 0.0) return false;
-      }
-      if (!(xl <= xh)) return false;
-      const double f0 = floor((xl - 1e-4 + 1.0) * (0.5 * kBinsPerAxis));
-      const double f1 = floor((xh + 1e-4 + 1.0) * (0.5 * kBinsPerAxis));
-      x0 = (int)fmin(fmax(f0, (double)lo[0]), (double)hi[0]);
-      x1 = (int)fmin(fmax(f1, (double)lo[0]), (double)hi[0]);
-      return true;
-    };
+    local_box(Gg, b0, kBlk, R1, blo, bhi);
     // A candidate: its point and dL/dy, loaded for every lane (a lane past the end of its run
     // loads point 0), so the loads of the next step are in flight while this one is used.
     struct Cand { float4 q; float dy[C]; bool valid; };
@@ -418,7 +431,7 @@ __global__ void __launch_bounds__(256) k_cell_pull_wave(CellArgs a) {
         int x0 = lo[0], x1 = hi[0];
         if (rr < nrows) {
           const int yb = lo[1] + rr % ny_r, zb = lo[2] + rr / ny_r;
-          if (bad || row_span(yb, zb, x0, x1)) {
+          if (bad || row_x_span(Gg, blo, bhi, lo[0], hi[0], yb, zb, x0, x1)) {
             const int row = (zb * kBinsPerAxis + yb) * kBinsPerAxis;
             s0[k] = start[row + x0];
             len[k] = start[row + x1 + 1] - s0[k];
