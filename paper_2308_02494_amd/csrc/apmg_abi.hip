@@ -192,8 +192,7 @@ hipError_t launch_sort(const float* pts, int64_t ld, size_t pts_stride, const fl
   // after an even number of passes the sorted keys/values are back in k0/v0
   hipLaunchKernelGGL(k_permute_points, dim3(grid1(n), nb), dim3(256), 0, st, in, n, w.v0, w.spts, w.spts4,
                      src_f, w.sf);
-  hipLaunchKernelGGL(k_bin_starts, dim3(grid1(kBinsPerAxis * kBinsPerAxis * kBinsPerAxis + 1), nb), dim3(256), 0,
-                     st, w.k0, n, w.start);
+  hipLaunchKernelGGL(k_bin_starts, dim3(grid1(n + 1), nb), dim3(256), 0, st, w.k0, n, w.start);
   return hipGetLastError();
 }
 

@@ -12,7 +12,7 @@ constexpr int kBinsPerAxis = 64;          // NB
 constexpr int kBinBits = 18;              // 3 * log2(NB)
 constexpr int kRadixBits = 9;
 constexpr int kRadixDigits = 1 << kRadixBits;
-constexpr int kSortTile = 4096;           // keys per block of the histogram / scatter kernels
+constexpr int kSortTile = 1024;           // keys per block of the histogram / scatter kernels
 
 // Bin index of a point; coordinates outside [-1, 1) clamp to the edge bins, NaN to 0.
 __device__ inline uint32_t bin_of(float x, float y, float z) {
@@ -168,18 +168,18 @@ __global__ void __launch_bounds__(256) k_radix_scatter(const uint32_t* kin, cons
   }
 }
 
-// start[model][b] = first sorted position with key >= b, for b in [0, NB^3]; binary search.
+// start[model][b] = first sorted position with key >= b, for b in [0, NB^3]: position i
+// (0 < i < n) starts the bins (key[i-1], key[i]], position 0 the bins [0, key[0]] and the
+// end n the bins (key[n-1], NB^3]; every bin is written exactly once.
 __global__ void k_bin_starts(const uint32_t* keys, int64_t n, uint32_t* start) {
   const int model = blockIdx.y;
   const uint32_t nbins = (uint32_t)kBinsPerAxis * kBinsPerAxis * kBinsPerAxis;
   const uint32_t* K = keys + model * n;
-  for (uint32_t b = blockIdx.x * blockDim.x + threadIdx.x; b <= nbins; b += gridDim.x * blockDim.x) {
-    int64_t lo = 0, hi = n;
-    while (lo < hi) {
-      const int64_t mid = (lo + hi) >> 1;
-      if (K[mid] < b) lo = mid + 1; else hi = mid;
-    }
-    start[(size_t)model * (nbins + 1) + b] = (uint32_t)lo;
+  uint32_t* S = start + (size_t)model * (nbins + 1);
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i <= n; i += (int64_t)gridDim.x * blockDim.x) {
+    const uint32_t lo = i == 0 ? 0u : K[i - 1] + 1u;       // first bin this position starts
+    const uint32_t hi = i == n ? nbins : K[i];              // last bin this position starts
+    for (uint32_t b = lo; b <= hi; ++b) S[b] = (uint32_t)i;
   }
 }
 
