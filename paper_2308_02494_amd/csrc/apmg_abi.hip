@@ -173,13 +173,11 @@ void take_sort(Carver& cv, int64_t n, int nb, bool with_f, SortWs* o) {
   o->spts4 = cv.take<float4>((size_t)nb * nn);
 }
 
-hipError_t launch_sort(const float* pts, int64_t ld, size_t pts_stride, const float4* pts4, int64_t n, int nb,
-                       const SortWs& w, const float* src_f, hipStream_t st) {
-  const int nt = sort_tiles(n);
-  SortIn in;
-  in.pts = pts; in.ld = ld; in.pts_stride = pts_stride; in.pts4 = pts4;
-  hipLaunchKernelGGL(k_bin_keys, dim3(grid1(n), nb), dim3(256), 0, st, in, n, w.k0, w.v0);
+// LSD radix passes over the keys/values in k0/v0; after an even number of passes the sorted
+// keys/values are back in k0/v0.
+void radix_passes(int64_t n, int nb, int nt, const SortWs& w, hipStream_t st) {
   uint32_t *ki = w.k0, *vi = w.v0, *ko = w.k1, *vo = w.v1;
+  static_assert((kBinBits + kRadixBits - 1) / kRadixBits % 2 == 0, "an even number of passes");
   for (int shift = 0; shift < kBinBits; shift += kRadixBits) {
     hipLaunchKernelGGL(k_radix_hist, dim3(nt, nb), dim3(256), 0, st, ki, n, shift, w.hist, nt);
     hipLaunchKernelGGL(k_radix_rowscan, dim3(kRadixDigits, nb), dim3(256), 0, st, w.hist, nt, w.rowtot);
@@ -189,9 +187,30 @@ hipError_t launch_sort(const float* pts, int64_t ld, size_t pts_stride, const fl
     std::swap(ki, ko);
     std::swap(vi, vo);
   }
-  // after an even number of passes the sorted keys/values are back in k0/v0
+}
+
+hipError_t launch_sort(const float* pts, int64_t ld, size_t pts_stride, const float4* pts4, int64_t n, int nb,
+                       const SortWs& w, const float* src_f, hipStream_t st) {
+  const int nt = sort_tiles(n);
+  SortIn in;
+  in.pts = pts; in.ld = ld; in.pts_stride = pts_stride; in.pts4 = pts4;
+  hipLaunchKernelGGL(k_bin_keys, dim3(grid1(n), nb), dim3(256), 0, st, in, n, w.k0, w.v0);
+  radix_passes(n, nb, nt, w, st);
   hipLaunchKernelGGL(k_permute_points, dim3(grid1(n), nb), dim3(256), 0, st, in, n, w.v0, w.spts, w.spts4,
                      src_f, w.sf);
+  hipLaunchKernelGGL(k_bin_starts, dim3(grid1(n + 1), nb), dim3(256), 0, st, w.k0, n, w.start);
+  return hipGetLastError();
+}
+
+// The training batch: keys from the counter stream, the radix passes, then the points
+// regenerated in sorted order together with their ground truth (no gather of stored points).
+hipError_t launch_step_sort(uint64_t seed, const uint64_t* step_ctr, int64_t n, int nb, const SortWs& w,
+                            const float* vol, int vnx, int vny, const apmg_brick* bricks, float* v, hipStream_t st) {
+  const int nt = sort_tiles(n);
+  hipLaunchKernelGGL(k_batch_keys, dim3(grid1(n, 2048), nb), dim3(256), 0, st, seed, step_ctr, n, w.k0, w.v0);
+  radix_passes(n, nb, nt, w, st);
+  hipLaunchKernelGGL(k_batch_sorted, dim3(grid1(n, 2048), nb), dim3(256), 0, st, seed, step_ctr, n, w.v0, w.spts,
+                     w.spts4, vol, vnx, vny, bricks, v);
   hipLaunchKernelGGL(k_bin_starts, dim3(grid1(n + 1), nb), dim3(256), 0, st, w.k0, n, w.start);
   return hipGetLastError();
 }
@@ -328,7 +347,6 @@ hipError_t launch_density(const Shape& s, const float* G, size_t G_stride, const
 
 // ---------------------------------------------------------------- training step
 struct StepWs {
-  float4* pts4;   // [nb][n] generated (unsorted) as (x, y, z, 0)
   float* v;       // [nb][n] ground truth at the sorted points
   float* err;     // [nb][n]
   void* swz;      // [nb][swizzled weights]
@@ -355,7 +373,6 @@ size_t step_ws(const apmg_batch* b, const Shape& s, void* ws, StepWs* o) {
   const int nb = b->nb;
   const int64_t n = std::max<int64_t>(b->n, 1);
   StepWs w;
-  w.pts4 = cv.take<float4>((size_t)nb * n);
   w.v = cv.take<float>((size_t)nb * n);
   w.err = cv.take<float>((size_t)nb * n);
   w.swz = cv.take<char>((size_t)nb * swz_sizes(s).total() * (bf ? 2 : 4));
@@ -688,11 +705,9 @@ apmg_status run_step(const apmg_batch* b, const Shape& s, void* ws, const Tune& 
 
   // 1. batch points, sorted by spatial bin, and the ground truth at the sorted points
   if (n > 0) {
-    hipLaunchKernelGGL(k_batch_points, dim3(grid1(n, 2048), nb), dim3(256), 0, st, b->seed, b->step, n, w.pts4);
-    hipError_t e0 = launch_sort(nullptr, 0, 0, w.pts4, n, nb, w.srt, nullptr, st);
+    hipError_t e0 = launch_step_sort(b->seed, b->step, n, nb, w.srt, b->volume, b->vol[0], b->vol[1], b->bricks,
+                                     w.v, st);
     if (e0 != hipSuccess) return APMG_EHIP;
-    hipLaunchKernelGGL(k_batch_gt, dim3(grid1(n, 2048), nb), dim3(256), 0, st, w.srt.spts, n, b->volume, b->vol[0],
-                       b->vol[1], b->bricks, w.v);
   }
   // 2. operands of this step's weights, output scaling, zeroed gradients
   hipError_t e = launch_swizzle(s, bf, b->W, b->W + (size_t)s.H * s.MC, b->W + (size_t)s.H * s.MC + (size_t)s.H * s.H,
@@ -773,10 +788,10 @@ apmg_status run_step(const apmg_batch* b, const Shape& s, void* ws, const Tune& 
   if (!update) return hip_status(hipGetLastError());
 
   // 6. Adam: grids and MLP every step, transforms while the density phase is active
-  hipLaunchKernelGGL(k_adam, dim3(grid1((int64_t)nF), nb), dim3(256), 0, st, b->F, b->mF, b->vF, (const float*)w.dF,
+  hipLaunchKernelGGL(k_adam, dim3(grid1(((int64_t)nF + 3) / 4), nb), dim3(256), 0, st, b->F, b->mF, b->vF, (const float*)w.dF,
                      (const double*)nullptr, nF, (const int32_t*)b->t, (const int32_t*)w.live, b->lr, b->beta1,
                      b->beta2, b->adam_eps, gf16 ? (__half*)b->F_lowp : (__half*)nullptr, b->lr_scale);
-  hipLaunchKernelGGL(k_adam, dim3(grid1((int64_t)nW), nb), dim3(256), 0, st, b->W, b->mW, b->vW, (const float*)w.dW,
+  hipLaunchKernelGGL(k_adam, dim3(grid1(((int64_t)nW + 3) / 4), nb), dim3(256), 0, st, b->W, b->mW, b->vW, (const float*)w.dW,
                      (const double*)nullptr, nW, (const int32_t*)b->t, (const int32_t*)w.live, b->lr, b->beta1,
                      b->beta2, b->adam_eps, (__half*)nullptr, b->lr_scale);
   hipLaunchKernelGGL(k_adam, dim3(1, nb), dim3(256), 0, st, b->G, b->mG, b->vG, (const float*)nullptr,

@@ -94,32 +94,6 @@ __global__ void k_gt_sample(const float* vol, int nx, int ny, int nz, const floa
     v[i] = sample_volume(vol, nx, ny, e0, nn, pts[i], pts[ld + i], pts[2 * ld + i]);
 }
 
-// Training batch of every model: points from the counter stream as (x, y, z, 0) records
-// [model][n] (one 16-byte load per point for the spatial sort's gathers).
-__global__ void k_batch_points(uint64_t seed, const uint64_t* step_ctr, int64_t n, float4* pts4) {
-  const int model = blockIdx.y;
-  const uint64_t step = *step_ctr;
-  float4* P = pts4 + (size_t)model * n;
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-    float x, y, z;
-    uniform_point(seed, step, (uint32_t)model, (uint64_t)i, x, y, z);
-    P[i] = make_float4(x, y, z, 0.f);
-  }
-}
-
-// Ground truth of every model's (sorted) points: trilinear sample of the model's brick
-// (extended extent e0..e1 inclusive).
-__global__ void k_batch_gt(const float* pts, int64_t n, const float* vol, int vnx, int vny, const apmg_brick* bricks,
-                           float* v) {
-  const int model = blockIdx.y;
-  const apmg_brick br = bricks[model];
-  const int e0[3] = {br.e0[0], br.e0[1], br.e0[2]};
-  const int nn[3] = {br.e1[0] - br.e0[0] + 1, br.e1[1] - br.e0[1] + 1, br.e1[2] - br.e0[2] + 1};
-  const float* P = pts + (size_t)model * 3 * n;
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-    v[(size_t)model * n + i] = sample_volume(vol, vnx, vny, e0, nn, P[i], P[n + i], P[2 * n + i]);
-}
-
 // ------------------------------------------------------------------ cells / bricks
 __global__ void k_cells(Shape s, const float* G, const float* pts, int64_t ld, int64_t n,
                         int32_t* cell, uint8_t* inside) {
@@ -456,20 +430,51 @@ __global__ void k_adam(float* theta, float* m, float* v, const float* gf, const 
                        float eps, __half* shadow, const float* lr_scale) {
   const int model = blockIdx.y;
   if (active && !active[model]) return;
-  const int t = counters[model] + 1;
-  const float bc1 = (float)(1.0 - pow((double)b1, (double)t));
-  const float bc2 = (float)(1.0 - pow((double)b2, (double)t));
-  const float lrm = lr_scale ? lr * lr_scale[model] : lr;
-  const float step = lrm / bc1, rb2 = 1.0f / sqrtf(bc2);
+  // bias corrections in float64, once per block
+  __shared__ float sc[2];
+  if (threadIdx.x == 0) {
+    const int t = counters[model] + 1;
+    const float bc1 = (float)(1.0 - pow((double)b1, (double)t));
+    const float bc2 = (float)(1.0 - pow((double)b2, (double)t));
+    const float lrm = lr_scale ? lr * lr_scale[model] : lr;
+    sc[0] = lrm / bc1;
+    sc[1] = 1.0f / sqrtf(bc2);
+  }
+  __syncthreads();
+  const float step = sc[0], rb2 = sc[1];
   const size_t off = (size_t)model * per_model;
-  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < per_model; i += (size_t)gridDim.x * blockDim.x) {
+  auto one = [&](float g, float& mk, float& vk, float& th) {
+    mk = __builtin_fmaf(b1, mk, (1.f - b1) * g);
+    vk = __builtin_fmaf(b2, vk, (1.f - b2) * g * g);
+    th = th - step * mk / (sqrtf(vk) * rb2 + eps);
+  };
+  const size_t stride = (size_t)gridDim.x * blockDim.x;
+  size_t i0 = 0;
+  // four elements per thread with 16-byte accesses where every array allows it; the same
+  // arithmetic per element as the scalar loop that finishes the rest
+  if (gf && !shadow && ((uintptr_t)(theta + off) | (uintptr_t)(m + off) | (uintptr_t)(v + off) |
+                        (uintptr_t)(gf + off)) % 16 == 0) {
+    const size_t n4 = per_model / 4;
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n4; i += stride) {
+      const size_t k = off + 4 * i;
+      const float4 g4 = *(const float4*)(gf + k);
+      float4 m4 = *(float4*)(m + k), v4 = *(float4*)(v + k), t4 = *(float4*)(theta + k);
+      one(g4.x, m4.x, v4.x, t4.x);
+      one(g4.y, m4.y, v4.y, t4.y);
+      one(g4.z, m4.z, v4.z, t4.z);
+      one(g4.w, m4.w, v4.w, t4.w);
+      *(float4*)(m + k) = m4;
+      *(float4*)(v + k) = v4;
+      *(float4*)(theta + k) = t4;
+    }
+    i0 = 4 * n4;
+  }
+  for (size_t i = i0 + blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < per_model; i += stride) {
     const size_t k = off + i;
-    const float g = gf ? gf[k] : (float)gd[k];
-    const float mk = __builtin_fmaf(b1, m[k], (1.f - b1) * g);
-    const float vk = __builtin_fmaf(b2, v[k], (1.f - b2) * g * g);
+    float mk = m[k], vk = v[k], th = theta[k];
+    one(gf ? gf[k] : (float)gd[k], mk, vk, th);
     m[k] = mk;
     v[k] = vk;
-    const float th = theta[k] - step * mk / (sqrtf(vk) * rb2 + eps);
     theta[k] = th;
     if (shadow) shadow[k] = __float2half_rn(th);
   }

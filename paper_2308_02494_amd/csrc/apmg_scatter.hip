@@ -16,7 +16,7 @@ struct CellArgs {
   const float4* pts4; int64_t n;        // sorted points [model][n] as (x, y, z, 0)
   const uint32_t* start;                // [model][NB^3 + 1]
   const float* dY;                      // [model][M][n][C]
-  float* CC;                            // [model][M][(R-1)^3][8][C]
+  float* CC;                            // [model][M][8][(R-1)^3][C] (corner-major)
   double* dGpart;                       // [model][M][nblk][12] (DG)
   const int32_t* active;
   int nblk;                             // blocks of 256 cells per grid; launch nmodels * M * nblk blocks
@@ -232,11 +232,11 @@ __global__ void __launch_bounds__(256) k_cell_pull(CellArgs a) {
           }
         }
       }
-    float* out = a.CC + (((size_t)model * s.M + g) * ncell + cell) * 8 * C;
+    float* out = a.CC + ((size_t)model * s.M + g) * 8 * ncell * C + cell * C;
 #pragma unroll
     for (int q = 0; q < 8; ++q)
 #pragma unroll
-      for (int c = 0; c < C; ++c) out[q * C + c] = acc[q][c];
+      for (int c = 0; c < C; ++c) out[q * ncell * C + c] = acc[q][c];
   }
   if constexpr (DG) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -487,11 +487,11 @@ __global__ void __launch_bounds__(256) k_cell_pull_wave(CellArgs a) {
   if (own) {
     const int64_t cell = ((int64_t)cz * R1 + cy) * R1 + cx;
     const int64_t ncell = (int64_t)R1 * R1 * R1;
-    float* out = a.CC + (((size_t)model * s.M + g) * ncell + cell) * 8 * C;
+    float* out = a.CC + ((size_t)model * s.M + g) * 8 * ncell * C + cell * C;
 #pragma unroll
     for (int q = 0; q < 8; ++q)
 #pragma unroll
-      for (int c = 0; c < C; ++c) out[q * C + c] = acc[q][c];
+      for (int c = 0; c < C; ++c) out[q * ncell * C + c] = acc[q][c];
   }
 }
 
@@ -503,7 +503,7 @@ __global__ void k_cell_to_vertex(Shape s, const float* CC, float* dF, size_t dF_
   if (active && !active[model]) return;
   const int R = s.R, R1 = R - 1;
   const int64_t nv = (int64_t)R * R * R, ncell = (int64_t)R1 * R1 * R1;
-  const float* cc = CC + ((size_t)model * s.M + g) * ncell * 8 * C;
+  const float* cc = CC + ((size_t)model * s.M + g) * 8 * ncell * C;
   for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < nv; v += (int64_t)gridDim.x * blockDim.x) {
     const int vx = (int)(v % R), vy = (int)((v / R) % R), vz = (int)(v / ((int64_t)R * R));
     float sum[C];
@@ -513,7 +513,7 @@ __global__ void k_cell_to_vertex(Shape s, const float* CC, float* dF, size_t dF_
     for (int q = 0; q < 8; ++q) {
       const int cx = vx - (q & 1), cy = vy - ((q >> 1) & 1), cz = vz - (q >> 2);
       if (cx < 0 || cy < 0 || cz < 0 || cx >= R1 || cy >= R1 || cz >= R1) continue;
-      const float* src = cc + (((int64_t)cz * R1 + cy) * R1 + cx) * 8 * C + q * C;
+      const float* src = cc + ((q * ncell + ((int64_t)cz * R1 + cy) * R1 + cx)) * C;   // neighbours read neighbours
 #pragma unroll
       for (int c = 0; c < C; ++c) sum[c] += src[c];
     }
