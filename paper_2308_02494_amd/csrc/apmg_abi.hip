@@ -1,5 +1,6 @@
 // Host side of the C ABI declared in include/apmg.h: argument validation,
 // workspace layout and the launch sequence of every entry point.
+#include <mutex>
 #include <vector>
 
 using namespace apmg;
@@ -692,6 +693,28 @@ apmg_status check_batch(const apmg_batch* b, Shape* s) {
 }
 
 // The phases of one training step; `update` adds the Adam updates and counter increments.
+// A side stream per device (default priority, non-blocking) and its fork/join events,
+// created on the first training step that runs on that device outside graph capture; a
+// step captured before that runs all its phases on the caller's stream.
+struct SideStream { hipStream_t s = nullptr; hipEvent_t fork = nullptr, join = nullptr; bool ok = false; };
+constexpr int kMaxDevices = 64;
+std::mutex g_side_mu;
+SideStream g_side[kMaxDevices];
+SideStream* side_stream(hipStream_t st) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return nullptr;
+  SideStream& ss = g_side[dev];
+  if (!ss.ok) {
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(st, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) return nullptr;
+    if (!ss.s && hipStreamCreateWithFlags(&ss.s, hipStreamNonBlocking) != hipSuccess) { ss.s = nullptr; return nullptr; }
+    if (!ss.fork && hipEventCreateWithFlags(&ss.fork, hipEventDisableTiming) != hipSuccess) { ss.fork = nullptr; return nullptr; }
+    if (!ss.join && hipEventCreateWithFlags(&ss.join, hipEventDisableTiming) != hipSuccess) { ss.join = nullptr; return nullptr; }
+    ss.ok = true;
+  }
+  return &ss;
+}
+
 apmg_status run_step(const apmg_batch* b, const Shape& s, void* ws, const Tune& tu, bool update, hipStream_t st) {
   const bool bf = b->shape.mlp_dtype == APMG_BF16, gf16 = b->shape.grid_dtype == APMG_F16;
   const int nb = b->nb;
@@ -770,17 +793,27 @@ apmg_status run_step(const apmg_batch* b, const Shape& s, void* ws, const Tune& 
   else
     hipLaunchKernelGGL(k_fill_f64, dim3(1), dim3(256), 0, st, b->losses, (size_t)2 * nb, 0.0);
 
-  // 4. grid gradient from the per-cell pass; L_rec's transform gradient only under APMG_ADD_REC_DG
+  // 4. grid gradient from the per-cell pass (L_rec's transform gradient only under
+  // APMG_ADD_REC_DG) and 5. the density loss and its transform gradient (part 2) for models
+  // whose transforms train.  The two read the same inputs and write disjoint buffers, so the
+  // density passes run on the device's side stream, overlapping the gather.
   if (n > 0) {
-    e = launch_cells(s, gf16, b->G, nG, gf16 ? (const void*)b->F_lowp : (const void*)b->F, nF, w.srt, n, w.cell,
-                     w.dF, nF, 0, rec_dG, nullptr, 0, 0, nb, w.live, st, tu.cell_unroll, nullptr, tu.cell_kernel, tu.cell_group);
-    if (e != hipSuccess) return APMG_EHIP;
-  }
-  // 5. density loss and its transform gradient (part 2), for models whose transforms train
-  if (n > 0) {
-    e = launch_density(s, b->G, nG, w.srt.spts, n, (size_t)3 * n, n, w.err, n, b->eps_density, b->p, b->losses + 1,
-                       2, w.dG, nG, 0, nullptr, w.den, nb, w.dlive, st);
-    if (e != hipSuccess) return APMG_EHIP;
+    std::lock_guard<std::mutex> lk(g_side_mu);     // one fork..join at a time per process
+    SideStream* side = side_stream(st);
+    hipStream_t dst = st;
+    if (side && hipEventRecord(side->fork, st) == hipSuccess && hipStreamWaitEvent(side->s, side->fork, 0) == hipSuccess)
+      dst = side->s;
+    const hipError_t ed = launch_density(s, b->G, nG, w.srt.spts, n, (size_t)3 * n, n, w.err, n, b->eps_density,
+                                         b->p, b->losses + 1, 2, w.dG, nG, 0, nullptr, w.den, nb, w.dlive, dst);
+    const hipError_t ec = launch_cells(s, gf16, b->G, nG, gf16 ? (const void*)b->F_lowp : (const void*)b->F, nF,
+                                       w.srt, n, w.cell, w.dF, nF, 0, rec_dG, nullptr, 0, 0, nb, w.live, st,
+                                       tu.cell_unroll, nullptr, tu.cell_kernel, tu.cell_group);
+    hipError_t ej = hipSuccess;
+    if (dst != st) {
+      ej = hipEventRecord(side->join, dst);
+      if (ej == hipSuccess) ej = hipStreamWaitEvent(st, side->join, 0);
+    }
+    if (ed != hipSuccess || ec != hipSuccess || ej != hipSuccess) return APMG_EHIP;
     if (rec_dG)
       hipLaunchKernelGGL(k_reduce_cell_dG, dim3(1, nb), dim3(256), 0, st, w.cell.dGpart, s.M, cell_blocks(s), w.dG,
                          nG, 1, w.dlive);
