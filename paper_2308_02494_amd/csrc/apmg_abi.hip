@@ -747,6 +747,25 @@ apmg_status run_step(const apmg_batch* b, const Shape& s, void* ws, const Tune& 
   if (passes.empty()) return APMG_EUNSUPPORTED;
   const int kb = passes.size() == 1 ? register_kb(s) : 0;
   const bool rec_dG = b->flags & APMG_ADD_REC_DG;
+  // block partials of one pass -> dW (and, for the first pass, dW3 and the L_rec sum)
+  auto reduce_pass = [&](const Pass& ps, hipStream_t rs) {
+    const int ncols = ps.c1_hi - ps.c1_lo, nrows = ps.w2_hi - ps.w2_lo;
+    const PartLayout pl = part_layout(s, ncols, nrows);
+    if (ncols > 0)
+      hipLaunchKernelGGL(k_reduce_parts, dim3(red_blocks((int64_t)s.H * ncols), nb), dim3(256), 0, rs, w.part, nblk,
+                         pl.len, pl.o_w1, s.H * ncols, ncols, s.MC, ps.c1_lo, w.dW, (double*)nullptr, nW, 0,
+                         (const int32_t*)w.live);
+    if (nrows > 0)
+      hipLaunchKernelGGL(k_reduce_parts, dim3(red_blocks((int64_t)s.H * nrows), nb), dim3(256), 0, rs, w.part, nblk,
+                         pl.len, pl.o_w2, s.H * nrows, s.H * nrows, 0, s.H * s.MC + ps.w2_lo * s.H, w.dW,
+                         (double*)nullptr, nW, 0, (const int32_t*)w.live);
+    if (ps.first) {
+      hipLaunchKernelGGL(k_reduce_parts, dim3(1, nb), dim3(256), 0, rs, w.part, nblk, pl.len, pl.o_w3, s.H, s.H, 0,
+                         s.H * s.MC + s.H * s.H, w.dW, (double*)nullptr, nW, 0, (const int32_t*)w.live);
+      hipLaunchKernelGGL(k_reduce_parts, dim3(1, nb), dim3(256), 0, rs, w.part, nblk, pl.len, pl.o_loss, 1, 1, 0, 0,
+                         (float*)nullptr, w.lrec, (size_t)1, 0, (const int32_t*)w.live);
+    }
+  };
   for (size_t pi = 0; pi < passes.size() && n > 0; ++pi) {
     const Pass& ps = passes[pi];
     TileArgs a;
@@ -773,36 +792,26 @@ apmg_status run_step(const apmg_batch* b, const Shape& s, void* ws, const Tune& 
     e = launch_tile(true, kb, a, gf16, bf, dim3(nblk, nb), backward_lds_bytes(s, ncols, nrows, bf, kb), st);
     if (e != hipSuccess) return APMG_EHIP;
     if (pi + 1 == passes.size()) prof_end(st);
-    if (ncols > 0)
-      hipLaunchKernelGGL(k_reduce_parts, dim3(red_blocks((int64_t)s.H * ncols), nb), dim3(256), 0, st, w.part, nblk,
-                         pl.len, pl.o_w1, s.H * ncols, ncols, s.MC, ps.c1_lo, w.dW, (double*)nullptr, nW, 0,
-                         (const int32_t*)w.live);
-    if (nrows > 0)
-      hipLaunchKernelGGL(k_reduce_parts, dim3(red_blocks((int64_t)s.H * nrows), nb), dim3(256), 0, st, w.part, nblk,
-                         pl.len, pl.o_w2, s.H * nrows, s.H * nrows, 0, s.H * s.MC + ps.w2_lo * s.H, w.dW,
-                         (double*)nullptr, nW, 0, (const int32_t*)w.live);
-    if (ps.first) {
-      hipLaunchKernelGGL(k_reduce_parts, dim3(1, nb), dim3(256), 0, st, w.part, nblk, pl.len, pl.o_w3, s.H, s.H, 0,
-                         s.H * s.MC + s.H * s.H, w.dW, (double*)nullptr, nW, 0, (const int32_t*)w.live);
-      hipLaunchKernelGGL(k_reduce_parts, dim3(1, nb), dim3(256), 0, st, w.part, nblk, pl.len, pl.o_loss, 1, 1, 0, 0,
-                         (float*)nullptr, w.lrec, (size_t)1, 0, (const int32_t*)w.live);
-    }
+    // the last pass's reductions wait for the fork below (they overlap the gather)
+    if (pi + 1 < passes.size()) reduce_pass(ps, st);
   }
-  if (n > 0)
-    hipLaunchKernelGGL(k_copy_f64, dim3((nb + 63) / 64), dim3(64), 0, st, w.lrec, 1, b->losses, 2, nb, 1.0 / (double)n);
-  else
-    hipLaunchKernelGGL(k_fill_f64, dim3(1), dim3(256), 0, st, b->losses, (size_t)2 * nb, 0.0);
+  if (n == 0) hipLaunchKernelGGL(k_fill_f64, dim3(1), dim3(256), 0, st, b->losses, (size_t)2 * nb, 0.0);
 
   // 4. grid gradient from the per-cell pass (L_rec's transform gradient only under
   // APMG_ADD_REC_DG) and 5. the density loss and its transform gradient (part 2) for models
-  // whose transforms train.  The two read the same inputs and write disjoint buffers, so the
-  // density passes run on the device's side stream, overlapping the gather.
+  // whose transforms train.  The gather needs dL/dy only; the last pass's weight-gradient
+  // reductions, L_rec and the density passes need the adjoint's partials and errors and
+  // write buffers the gather does not touch, so they run on the device's side stream,
+  // overlapping the gather.
   if (n > 0) {
     std::lock_guard<std::mutex> lk(g_side_mu);     // one fork..join at a time per process
     SideStream* side = side_stream(st);
     hipStream_t dst = st;
     if (side && hipEventRecord(side->fork, st) == hipSuccess && hipStreamWaitEvent(side->s, side->fork, 0) == hipSuccess)
       dst = side->s;
+    reduce_pass(passes.back(), dst);
+    hipLaunchKernelGGL(k_copy_f64, dim3((nb + 63) / 64), dim3(64), 0, dst, w.lrec, 1, b->losses, 2, nb,
+                       1.0 / (double)n);
     const hipError_t ed = launch_density(s, b->G, nG, w.srt.spts, n, (size_t)3 * n, n, w.err, n, b->eps_density,
                                          b->p, b->losses + 1, 2, w.dG, nG, 0, nullptr, w.den, nb, w.dlive, dst);
     const hipError_t ec = launch_cells(s, gf16, b->G, nG, gf16 ? (const void*)b->F_lowp : (const void*)b->F, nF,
