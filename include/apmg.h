@@ -220,8 +220,9 @@ apmg_status apmg_dd_forward(const apmg_dd_models* models, const apmg_brick_table
  * memory the caller zero-initialises. */
 /* Launch shapes of the training step (fields of 0 take the defaults).
  *   tile_blocks: blocks of the fused forward+adjoint tile kernel per model
- *     (each block = 4 waves of 32-point tiles); default ceil(512 / nb), at most
- *     4 times the default and at most the number of 4-tile groups.
+ *     (each block = 4 waves of 32-point tiles); default CUs / nb when nb divides
+ *     the device's compute units (one round of blocks), else ceil(2 CUs / nb); at
+ *     most 4 times the default and at most the number of 4-tile groups.
  *   cell_kernel: grid-gradient gather, 1 = one wave per 4x4x4 block of cells
  *     (the default; the wave reads each candidate point once), 2 = one thread
  *     per cell (always used when L_rec's transform gradient is requested).

@@ -76,8 +76,8 @@ int tile_blocks(int64_t n) {
   return (int)std::max<int64_t>(1, std::min<int64_t>(b, kMaxTileBlocks));
 }
 
-// Training-step launch shapes (apmg_tuning): tile-kernel blocks per model, default
-// ceil(512 / nb) (about two blocks per CU over all models), at most 4x the default,
+// Training-step launch shapes (apmg_tuning): tile-kernel blocks per model, default one
+// per CU over all models when nb divides the CUs evenly, else about two per CU, at most 4x the default,
 // 1024, and the number of 4-tile groups; gather batch of 2, 4 or 8 candidates; lanes per
 // candidate run of the wave gather, 1, 2, 4 or 8.
 constexpr int kDefaultCellGroup = 4;
@@ -86,8 +86,20 @@ int step_groups(int64_t n) {
   const int64_t tiles = (std::max<int64_t>(n, 1) + 31) / 32;
   return (int)std::max<int64_t>(1, (tiles + kWavesPerBlock - 1) / kWavesPerBlock);
 }
+// The register-resident adjoint kernel runs one block per compute unit: one round of
+// blocks (one per CU) when the models share the CUs evenly, else about two per CU.
+int device_cus() {
+  int dev = 0, cus = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1)
+    return kMaxTileBlocks / 2;
+  return cus;
+}
 int step_default_blocks(int64_t n, int nb) {
-  return std::max(1, std::min((kMaxTileBlocks + nb - 1) / nb, step_groups(n)));
+  const int cus = device_cus();
+  const int one = (cus + nb - 1) / nb;
+  const int b = one * nb <= cus ? one : (2 * cus + nb - 1) / nb;
+  return std::max(1, std::min(b, step_groups(n)));
 }
 int step_max_blocks(int64_t n, int nb) {
   return std::max(1, std::min(std::min(4 * step_default_blocks(n, nb), 1024), step_groups(n)));
