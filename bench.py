@@ -157,6 +157,26 @@ def _time_trainer(torch, tr, steps, warmup):
     return (time.perf_counter() - t0) / steps
 
 
+def time_graph(torch, tr, reps):
+    """One training step captured as a HIP graph (after an eager step) and replayed: ms per step."""
+    tr.step()
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        with torch.cuda.graph(g, stream=s):
+            tr.step()
+    torch.cuda.synchronize()
+    g.replay()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        g.replay()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / reps * 1e3
+
+
 def extra_c1(A, torch, synth, hl):
     """64^3 blobs+sine volume, 16 grids at 16^3 x 2, MLP 32-64-64-1, 65,536 points, fp32."""
     vol = synth.make_volume("blobs_sine", (64, 64, 64), device="cuda")
@@ -193,23 +213,7 @@ def extra_c4(A, torch, synth, hl):
     tr.density_active.fill_(1)
     dt_eager = _time_trainer(torch, tr, 3, 1)
     tune, _ = tr.autotune()
-    tr.step()
-    torch.cuda.synchronize()
-    g = torch.cuda.CUDAGraph()
-    s = torch.cuda.Stream()
-    s.wait_stream(torch.cuda.current_stream())
-    with torch.cuda.stream(s):
-        with torch.cuda.graph(g, stream=s):
-            tr.step()
-    torch.cuda.synchronize()
-    g.replay()
-    torch.cuda.synchronize()
-    reps = 5
-    t0 = time.perf_counter()
-    for _ in range(reps):
-        g.replay()
-    torch.cuda.synchronize()
-    dt = (time.perf_counter() - t0) / reps
+    dt = time_graph(torch, tr, 5) * 1e-3
     out = {"bricks": len(bricks), "train_pts_per_s": len(bricks) * n / dt, "ms_per_step": dt * 1e3,
            "ms_per_step_eager_default_shapes": dt_eager * 1e3, "tuning": tune, "graph": True}
     dd = A.DDModels.from_trainer(tr, table, bricks)
@@ -337,6 +341,9 @@ def main():
         extra = {}
         extra["infer_pts_per_s_fp32"] = time_forward(A, torch, host, N)
         progress("fp32 inference done")
+        gms = time_graph(torch, tr, 20)
+        extra["headline_graph"] = {"ms_per_step": gms, "train_pts_per_s": N / (gms * 1e-3)}
+        progress("headline step as a replayed graph done")
         del tr
         torch.cuda.empty_cache()
         trb, _, _ = make_trainer(A, torch, synth, A.BF16, N)
