@@ -157,20 +157,33 @@ int max_part_len(const Shape& s, bool bf) {
 }
 
 // ---------------------------------------------------------------- workspace layouts
-struct FwdWs { void* swz; float* w3s; };
-size_t fwd_ws(const Shape& s, bool bf, void* ws, FwdWs* o) {
-  Carver cv(ws);
-  const size_t esz = bf ? 2 : 4;
-  void* swz = cv.take<char>(swz_sizes(s).total() * esz);
-  float* w3s = cv.take<float>(s.H);
-  if (o) { o->swz = swz; o->w3s = w3s; }
-  return cv.off;
-}
-
 // Spatial sort of nb models' points: keys/values ping-pong, digit histograms, bin starts,
 // sorted points and an optional permuted per-point array.
 struct SortWs { uint32_t *k0, *v0, *k1, *v1, *hist, *rowtot, *dbase, *start; float *spts, *sf; float4* spts4; };
 inline int sort_tiles(int64_t n) { return (int)std::max<int64_t>(1, (n + kSortTile - 1) / kSortTile); }
+void take_sort(Carver& cv, int64_t n, int nb, bool with_f, SortWs* o);
+
+// Forward operands; from kFwdSortMin points on, the points are first sorted into spatial
+// bins (neighbouring points of a wave then share grid cells in cache) and the outputs
+// scattered back to the caller's order.
+constexpr int64_t kFwdSortMin = (int64_t)1 << 15;
+struct FwdWs { void* swz; float* w3s; bool sorted; SortWs srt; float* fs; };
+size_t fwd_ws(const Shape& s, bool bf, int64_t n, void* ws, FwdWs* o) {
+  Carver cv(ws);
+  const size_t esz = bf ? 2 : 4;
+  FwdWs w;
+  w.swz = cv.take<char>(swz_sizes(s).total() * esz);
+  w.w3s = cv.take<float>(s.H);
+  w.sorted = n >= kFwdSortMin;
+  w.fs = nullptr;
+  if (w.sorted) {
+    take_sort(cv, n, 1, false, &w.srt);
+    w.fs = cv.take<float>((size_t)n);
+  }
+  if (o) *o = w;
+  return cv.off;
+}
+
 void take_sort(Carver& cv, int64_t n, int nb, bool with_f, SortWs* o) {
   const int64_t nn = std::max<int64_t>(n, 1);
   o->k0 = cv.take<uint32_t>((size_t)nb * nn);
@@ -466,7 +479,7 @@ size_t apmg_workspace_bytes(int op, const void* mb, int64_t n) {
   if (check_model(m, false, &s) != APMG_OK) return 0;
   const bool bf = m->mlp_dtype == APMG_BF16;
   switch (op) {
-    case APMG_OP_FORWARD: return fwd_ws(s, bf, nullptr, nullptr);
+    case APMG_OP_FORWARD: return fwd_ws(s, bf, n, nullptr, nullptr);
     case APMG_OP_BACKWARD: return bwd_ws(s, bf, n, nullptr, nullptr);
     case APMG_OP_DENSITY: return den_ws(s, n, 1, nullptr, nullptr);
   }
@@ -481,21 +494,27 @@ apmg_status apmg_forward(const apmg_model* m, const float* pts, int64_t ld, int6
   if ((rc = check_points(pts, ld, n)) != APMG_OK) return rc;
   if (n > 0 && !f) return APMG_EINVAL;
   const bool bf = m->mlp_dtype == APMG_BF16, gf16 = m->grid_dtype == APMG_F16;
-  if (ws_bytes < fwd_ws(s, bf, nullptr, nullptr) || !ws) return APMG_EWORKSPACE;
+  if (ws_bytes < fwd_ws(s, bf, n, nullptr, nullptr) || !ws) return APMG_EWORKSPACE;
   if (n == 0) return APMG_OK;
   FwdWs w;
-  fwd_ws(s, bf, ws, &w);
+  fwd_ws(s, bf, n, ws, &w);
   hipError_t e = launch_swizzle(s, bf, m->W[0], m->W[1], m->W[2], 0, w.swz, 0, w.w3s, 1, st);
   if (e != hipSuccess) return APMG_EHIP;
+  if (w.sorted && (e = launch_sort(pts, ld, 0, nullptr, n, 1, w.srt, nullptr, st)) != hipSuccess) return APMG_EHIP;
   TileArgs a;
   memset(&a, 0, sizeof(a));
   a.s = s;
   a.G = m->G; a.F = m->F; a.swz = w.swz; a.w3s = w.w3s;
   a.vscale = m->vmax - m->vmin; a.voff = m->vmin;
-  a.pts = pts; a.ld = ld; a.n = n; a.f = f;
+  if (w.sorted) { a.pts = w.srt.spts; a.ld = n; a.f = w.fs; }
+  else { a.pts = pts; a.ld = ld; a.f = f; }
+  a.n = n;
   const int64_t tiles = (n + 31) / 32;
   dim3 grid((unsigned)std::min<int64_t>((tiles + kWavesPerBlock - 1) / kWavesPerBlock, 8192), 1);
-  return hip_status(launch_tile(false, 0, a, gf16, bf, grid, forward_lds_bytes(s, bf), st));
+  e = launch_tile(false, 0, a, gf16, bf, grid, forward_lds_bytes(s, bf), st);
+  if (e != hipSuccess) return APMG_EHIP;
+  if (w.sorted) hipLaunchKernelGGL(k_dd_scatter, dim3(grid1(n)), dim3(256), 0, st, w.fs, w.srt.v0, n, f);
+  return hip_status(hipGetLastError());
 }
 
 apmg_status apmg_backward(const apmg_model* m, const float* pts, int64_t ld, int64_t n, const float* df,

@@ -149,6 +149,25 @@ def test_forward_edge_sizes():
     assert A().apmg_forward(model, empty).numel() == 0
 
 
+def test_forward_spatially_sorted_path_equals_direct_bitwise():
+    # from 2^15 points on the forward sorts the points into spatial bins first and scatters
+    # the outputs back: every point's arithmetic is unchanged, so the values are the same bits
+    # as chunks below the threshold; strided input (ld > n), NaN and outside points included
+    host = host_model(16, 2, 16, 64, extra_t=0.1)
+    model = A().Model.from_host(host, DEV)
+    n, ld = 40000, 40017
+    x = make_points(n)
+    x[7:1000] *= 1.4
+    pts = torch.zeros((3, ld), dtype=torch.float32, device=DEV)
+    pts[:, :n] = soa(x)
+    big = A().apmg_forward(model, pts, n=n, ld=ld)
+    parts = [A().apmg_forward(model, soa(x[i:i + 20000])) for i in range(0, n, 20000)]
+    assert torch.equal(big, torch.cat(parts))
+    idx = np.random.default_rng(3).choice(n, 3000, replace=False)
+    want, _ = O.forward(f64(host), x[idx].astype(np.float64))
+    assert_close("forward sorted path, sample", big.cpu().numpy()[idx], want)
+
+
 @pytest.mark.parametrize("grid16,bf", [(False, True), (True, False), (True, True)])
 def test_forward_mixed_precision_stated(grid16, bf):
     host = host_model(16, 2, 16, 64)
