@@ -225,7 +225,8 @@ apmg_status apmg_dd_forward(const apmg_dd_models* models, const apmg_brick_table
  *     most 4 times the default and at most the number of 4-tile groups.
  *   cell_kernel: grid-gradient gather, 1 = one wave per 4x4x4 block of cells
  *     (the default; the wave reads each candidate point once), 2 = one thread
- *     per cell (always used when L_rec's transform gradient is requested).
+ *     per cell.  Either also produces L_rec's transform gradient when it is
+ *     requested.
  *   cell_unroll: candidates per batch of the one-thread-per-cell gather, 2, 4
  *     or 8 (default 4).
  *   cell_group: lanes per candidate run of the wave gather, 1, 2, 4 or 8

@@ -245,10 +245,17 @@ hipError_t launch_step_sort(uint64_t seed, const uint64_t* step_ctr, int64_t n, 
 struct CellWs { float *dY, *CC; double* dGpart; };
 inline int64_t n_cells(const Shape& s) { return (int64_t)(s.R - 1) * (s.R - 1) * (s.R - 1); }
 inline int cell_blocks(const Shape& s) { return (int)((n_cells(s) + 255) / 256); }
+// workgroups per grid of the wave gather (4 waves, each a 4x4x4 block of cells)
+inline int wave_groups(const Shape& s) {
+  const int64_t nbx = (s.R - 1 + kBlk - 1) / kBlk;
+  return (int)((nbx * nbx * nbx + 3) / 4);
+}
+// transform-gradient partials per grid written by the gather cell_kernel selects
+inline int dg_parts(const Shape& s, int cell_kernel) { return cell_kernel != 1 ? wave_groups(s) : cell_blocks(s); }
 void take_cell(Carver& cv, const Shape& s, int64_t n, int nb, CellWs* o) {
   o->dY = cv.take<float>((size_t)nb * s.M * std::max<int64_t>(n, 1) * s.C);
   o->CC = cv.take<float>((size_t)nb * s.M * n_cells(s) * 8 * s.C);
-  o->dGpart = cv.take<double>((size_t)nb * s.M * cell_blocks(s) * 12);
+  o->dGpart = cv.take<double>((size_t)nb * s.M * std::max(cell_blocks(s), wave_groups(s)) * 12);
 }
 
 // Grid gradient (into dF when non-NULL) and, when want_dG, the per-block transform-gradient
@@ -272,29 +279,33 @@ hipError_t launch_cells(const Shape& s, bool gf16, const float* G, size_t G_stri
     else if (unroll == 8) hipLaunchKernelGGL((k_cell_pull<CC_, F16_, DG_, 8>), grid, dim3(256), 0, st, c); \
     else hipLaunchKernelGGL((k_cell_pull<CC_, F16_, DG_, 4>), grid, dim3(256), 0, st, c);           \
   }
-  const int nbx = (s.R - 1 + kBlk - 1) / kBlk;
-  const int64_t wgroups = ((int64_t)nbx * nbx * nbx + 3) / 4 * s.M * nb;
+  const int64_t wgroups = (int64_t)wave_groups(s) * s.M * nb;
   if (wgroups > 0x7fffffff) return hipErrorInvalidValue;
-  const bool wave_kernel = !want_dG && cell_kernel != 1;
+  const bool wave_kernel = cell_kernel != 1;
+#define APMG_WAVE(CC_, F16_, DG_)                                                                   \
+  {                                                                                                 \
+    const dim3 wg((unsigned)wgroups);                                                               \
+    if (cell_group == 1) hipLaunchKernelGGL((k_cell_pull_wave<CC_, F16_, 1, DG_>), wg, dim3(256), 0, st, c); \
+    else if (cell_group == 2) hipLaunchKernelGGL((k_cell_pull_wave<CC_, F16_, 2, DG_>), wg, dim3(256), 0, st, c); \
+    else if (cell_group == 8) hipLaunchKernelGGL((k_cell_pull_wave<CC_, F16_, 8, DG_>), wg, dim3(256), 0, st, c); \
+    else hipLaunchKernelGGL((k_cell_pull_wave<CC_, F16_, 4, DG_>), wg, dim3(256), 0, st, c);         \
+  }
 #define APMG_CELL(CC_, F16_)                                                                        \
   if (s.C == CC_ && gf16 == F16_) {                                                                 \
-    if (want_dG) APMG_PULL(CC_, F16_, true)                                                          \
-    else if (wave_kernel) {                                                                         \
-      const dim3 wg((unsigned)wgroups);                                                             \
-      if (cell_group == 1) hipLaunchKernelGGL((k_cell_pull_wave<CC_, F16_, 1>), wg, dim3(256), 0, st, c); \
-      else if (cell_group == 2) hipLaunchKernelGGL((k_cell_pull_wave<CC_, F16_, 2>), wg, dim3(256), 0, st, c); \
-      else if (cell_group == 8) hipLaunchKernelGGL((k_cell_pull_wave<CC_, F16_, 8>), wg, dim3(256), 0, st, c); \
-      else hipLaunchKernelGGL((k_cell_pull_wave<CC_, F16_, 4>), wg, dim3(256), 0, st, c);           \
-    } else APMG_PULL(CC_, F16_, false)                                                               \
+    if (wave_kernel) {                                                                              \
+      if (want_dG) APMG_WAVE(CC_, F16_, true) else APMG_WAVE(CC_, F16_, false)                      \
+    } else if (want_dG) APMG_PULL(CC_, F16_, true)                                                   \
+    else APMG_PULL(CC_, F16_, false)                                                                 \
     if (dF) hipLaunchKernelGGL((k_cell_to_vertex<CC_>), dim3(grid1((int64_t)s.R * s.R * s.R, 1024), s.M, nb), \
                                dim3(256), 0, st, s, cw.CC, dF, dF_stride, accumulate, active);       \
   }
   APMG_CELL(1, false) APMG_CELL(2, false) APMG_CELL(4, false)
   APMG_CELL(1, true) APMG_CELL(2, true) APMG_CELL(4, true)
 #undef APMG_CELL
+#undef APMG_WAVE
 #undef APMG_PULL
   if (dG)
-    hipLaunchKernelGGL(k_reduce_cell_dG, dim3(1, nb), dim3(256), 0, st, cw.dGpart, s.M, cell_blocks(s), dG,
+    hipLaunchKernelGGL(k_reduce_cell_dG, dim3(1, nb), dim3(256), 0, st, cw.dGpart, s.M, dg_parts(s, cell_kernel), dG,
                        dG_stride, dG_accumulate, dG_active ? dG_active : active);
   return hipGetLastError();
 }
@@ -855,8 +866,8 @@ apmg_status run_step(const apmg_batch* b, const Shape& s, void* ws, const Tune& 
     }
     if (ed != hipSuccess || ec != hipSuccess || ej != hipSuccess) return APMG_EHIP;
     if (rec_dG)
-      hipLaunchKernelGGL(k_reduce_cell_dG, dim3(1, nb), dim3(256), 0, st, w.cell.dGpart, s.M, cell_blocks(s), w.dG,
-                         nG, 1, w.dlive);
+      hipLaunchKernelGGL(k_reduce_cell_dG, dim3(1, nb), dim3(256), 0, st, w.cell.dGpart, s.M,
+                         dg_parts(s, tu.cell_kernel), w.dG, nG, 1, w.dlive);
   }
   if (!update) return hip_status(hipGetLastError());
 
@@ -906,16 +917,13 @@ extern "C" apmg_status apmg_autotune_batched_step(const apmg_batch* b, void* ws,
   float best_t = -1.f;
   Tune best_tu = {d, 4, 0, kDefaultCellGroup};
   apmg_status out = APMG_OK;
-  const bool rec_dG = b->flags & APMG_ADD_REC_DG;
   // gathers: the wave-cooperative one with 2, 4 or 8 lanes per candidate run, then one
-  // thread per cell with 2, 4 or 8 candidates per batch (the only gather when L_rec's
-  // transform gradient is requested)
+  // thread per cell with 2, 4 or 8 candidates per batch
   struct Gather { int kernel, unroll, group; };
   const Gather gathers[] = {{0, 4, 2}, {0, 4, 4}, {0, 4, 8}, {1, 2, kDefaultCellGroup},
                             {1, 4, kDefaultCellGroup}, {1, 8, kDefaultCellGroup}};
   for (int tb : blocks) {
     for (const Gather& ga : gathers) {
-      if (ga.kernel == 0 && rec_dG) continue;
       const Tune tu = {tb, ga.unroll, ga.kernel, ga.group};
       if ((rc = run_step(b, s, ws, tu, false, st)) != APMG_OK) { out = rc; break; }   // warm-up
       if (hipEventRecord(e0, st) != hipSuccess) { out = APMG_EHIP; break; }

@@ -81,6 +81,38 @@ __device__ inline bool row_x_span(const float* Gg, const double blo[3], const do
   return true;
 }
 
+// The adjoint of Eq. (2) with respect to the local coordinates for one point of a cell with
+// corner values val and offsets w: dl_d = sum_c dL/dy_c d(trilerp_c)/du_d, then the transform
+// gradient terms (dl h) x^T and (dl h) added to gacc (x masked to 0 for a rejected candidate,
+// which may be a NaN point and has dL/dy = 0).
+template <int C>
+__device__ inline void add_transform_grad(const float val[8][C], const float wu[3], const float dyv[C], float hR,
+                                          bool ok, float px, float py, float pz, float gacc[12]) {
+  float dl[3] = {0.f, 0.f, 0.f};
+#pragma unroll
+  for (int c = 0; c < C; ++c) {
+    const float ax00 = val[1][c] - val[0][c], ax10 = val[3][c] - val[2][c];
+    const float ax01 = val[5][c] - val[4][c], ax11 = val[7][c] - val[6][c];
+    const float gx = (1.f - wu[2]) * ((1.f - wu[1]) * ax00 + wu[1] * ax10) +
+                     wu[2] * ((1.f - wu[1]) * ax01 + wu[1] * ax11);
+    const float x00 = __builtin_fmaf(wu[0], ax00, val[0][c]);
+    const float x10 = __builtin_fmaf(wu[0], ax10, val[2][c]);
+    const float x01 = __builtin_fmaf(wu[0], ax01, val[4][c]);
+    const float x11 = __builtin_fmaf(wu[0], ax11, val[6][c]);
+    const float gy = (1.f - wu[2]) * (x10 - x00) + wu[2] * (x11 - x01);
+    const float y0 = __builtin_fmaf(wu[1], x10 - x00, x00);
+    const float y1 = __builtin_fmaf(wu[1], x11 - x01, x01);
+    dl[0] = __builtin_fmaf(dyv[c], gx, dl[0]);
+    dl[1] = __builtin_fmaf(dyv[c], gy, dl[1]);
+    dl[2] = __builtin_fmaf(dyv[c], y1 - y0, dl[2]);
+  }
+  const float xs[4] = {ok ? px : 0.f, ok ? py : 0.f, ok ? pz : 0.f, 1.f};
+#pragma unroll
+  for (int r = 0; r < 3; ++r)
+#pragma unroll
+    for (int k = 0; k < 4; ++k) gacc[4 * r + k] = __builtin_fmaf(dl[r] * hR, xs[k], gacc[4 * r + k]);
+}
+
 // Block order: xcd_logical over (model, cell block, grid), so an XCD works through a slab of
 // cells for all grids at once and the points of that slab stay in its L2.
 
@@ -202,33 +234,8 @@ __global__ void __launch_bounds__(256) k_cell_pull(CellArgs a) {
 #pragma unroll
               for (int c = 0; c < C; ++c) acc[qq][c] = add_rounded(acc[qq][c], corner_product(wq, dy[u][c]));
             }
-            if constexpr (DG) {
-              const float* wu = w[u];
-              float dl[3] = {0.f, 0.f, 0.f};
-#pragma unroll
-              for (int c = 0; c < C; ++c) {
-                const float ax00 = val[1][c] - val[0][c], ax10 = val[3][c] - val[2][c];
-                const float ax01 = val[5][c] - val[4][c], ax11 = val[7][c] - val[6][c];
-                const float gx = (1.f - wu[2]) * ((1.f - wu[1]) * ax00 + wu[1] * ax10) +
-                                 wu[2] * ((1.f - wu[1]) * ax01 + wu[1] * ax11);
-                const float x00 = __builtin_fmaf(wu[0], ax00, val[0][c]);
-                const float x10 = __builtin_fmaf(wu[0], ax10, val[2][c]);
-                const float x01 = __builtin_fmaf(wu[0], ax01, val[4][c]);
-                const float x11 = __builtin_fmaf(wu[0], ax11, val[6][c]);
-                const float gy = (1.f - wu[2]) * (x10 - x00) + wu[2] * (x11 - x01);
-                const float y0 = __builtin_fmaf(wu[1], x10 - x00, x00);
-                const float y1 = __builtin_fmaf(wu[1], x11 - x01, x01);
-                dl[0] = __builtin_fmaf(dy[u][c], gx, dl[0]);
-                dl[1] = __builtin_fmaf(dy[u][c], gy, dl[1]);
-                dl[2] = __builtin_fmaf(dy[u][c], y1 - y0, dl[2]);
-              }
-              // a rejected candidate may be a NaN point: its coordinates must not reach the sums
-              const float xs[4] = {ok[u] ? q[u].x : 0.f, ok[u] ? q[u].y : 0.f, ok[u] ? q[u].z : 0.f, 1.f};
-#pragma unroll
-              for (int r = 0; r < 3; ++r)
-#pragma unroll
-                for (int k = 0; k < 4; ++k) gacc[4 * r + k] = __builtin_fmaf(dl[r] * hR, xs[k], gacc[4 * r + k]);
-            }
+            if constexpr (DG)
+              add_transform_grad<C>(val, w[u], dy[u], hR, ok[u], q[u].x, q[u].y, q[u].z, gacc);
           }
         }
       }
@@ -266,7 +273,10 @@ __global__ void __launch_bounds__(256) k_cell_pull(CellArgs a) {
 // but not the plain candidate order of k_cell_pull.
 constexpr int kBlk = 4;                      // cells per block edge
 constexpr int kRowBatch = 128;               // bin rows per batch (two per lane)
-template <int C, bool GF16, int G>
+// DG: also the transform gradient of L_rec through the trilinear weights: every lane adds
+// the terms of the records it produces (in step order) to its own 12 sums, reduced per
+// workgroup in a fixed order into dGpart[model][g][group][12].
+template <int C, bool GF16, int G, bool DG>
 __global__ void __launch_bounds__(256) k_cell_pull_wave(CellArgs a) {
   static_assert(G == 1 || G == 2 || G == 4 || G == 8, "lanes per run");
   constexpr int NR = 64 / G;                 // runs per batch
@@ -275,6 +285,7 @@ __global__ void __launch_bounds__(256) k_cell_pull_wave(CellArgs a) {
   __shared__ float sG[4][12];
   __shared__ uint32_t sRow0[4][kRowBatch];   // first sorted position of each row of the batch
   __shared__ uint32_t sPre[4][kRowBatch + 1];  // exclusive prefix of the rows' lengths; [kRowBatch] = total
+  __shared__ double sDG[DG ? 4 : 1][12];
   const Shape s = a.s;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int R1 = s.R - 1;
@@ -300,6 +311,9 @@ __global__ void __launch_bounds__(256) k_cell_pull_wave(CellArgs a) {
   for (int q = 0; q < 8; ++q)
 #pragma unroll
     for (int c = 0; c < C; ++c) acc[q][c] = 0.f;
+  float gacc[DG ? 12 : 1];
+#pragma unroll
+  for (int k = 0; k < (DG ? 12 : 1); ++k) gacc[k] = 0.f;
   if (act) {
     // the block's box in global space (inverse of Eq. (1) applied to its local box)
     double A[3][3];
@@ -369,12 +383,14 @@ __global__ void __launch_bounds__(256) k_cell_pull_wave(CellArgs a) {
         }
       }
     };
+    const void* Fm = GF16 ? (const void*)((const __half*)a.F + model * a.F_stride)
+                          : (const void*)((const float*)a.F + model * a.F_stride);
     auto consume = [&](const Cand& cd) {
       int t = -1;
       float w[3] = {0.f, 0.f, 0.f};
+      int i0[3] = {0, 0, 0};
       if (cd.valid) {
         float l[3];
-        int i0[3];
         local_coords(Gg, cd.q.x, cd.q.y, cd.q.z, l);
         const bool in = cell_of(l, hR, s.R, i0, w);
         const int ox = i0[0] - b0[0], oy = i0[1] - b0[1], oz = i0[2] - b0[2];
@@ -392,6 +408,11 @@ __global__ void __launch_bounds__(256) k_cell_pull_wave(CellArgs a) {
 #pragma unroll
         for (int k = 0; k < RW; ++k)
           sRec[wave][lane][k] = make_float4(pr[4 * k], pr[4 * k + 1], pr[4 * k + 2], pr[4 * k + 3]);
+        if constexpr (DG) {
+          float val[8][C];
+          gather_cell<C, GF16>(Fm, g, s.R, i0, val);
+          add_transform_grad<C>(val, w, cd.dy, hR, true, cd.q.x, cd.q.y, cd.q.z, gacc);
+        }
       }
       // lanes whose point falls in my cell: agree on every bit of the target
       const bool has = t >= 0;
@@ -492,6 +513,18 @@ __global__ void __launch_bounds__(256) k_cell_pull_wave(CellArgs a) {
     for (int q = 0; q < 8; ++q)
 #pragma unroll
       for (int c = 0; c < C; ++c) out[q * ncell * C + c] = acc[q][c];
+  }
+  if constexpr (DG) {
+#pragma unroll
+    for (int k = 0; k < 12; ++k) {
+      const double t = wave_sum((double)gacc[k]);
+      if (lane == 0) sDG[wave][k] = t;
+    }
+    __syncthreads();
+    if (threadIdx.x < 12) {
+      const double t = sDG[0][threadIdx.x] + sDG[1][threadIdx.x] + sDG[2][threadIdx.x] + sDG[3][threadIdx.x];
+      a.dGpart[(((size_t)model * s.M + g) * groups + grp) * 12 + threadIdx.x] = t;
+    }
   }
 }
 

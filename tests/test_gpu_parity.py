@@ -212,9 +212,9 @@ def test_backward_fp32(M, C, R, H):
 
 @pytest.mark.parametrize("M,C,R,H", SHAPES + [(32, 2, 8, 64), (7, 4, 5, 64)])
 def test_grid_gradient_gathers_agree_and_match_oracle(M, C, R, H):
-    # without a transform gradient the grid gradient comes from the wave-cooperative gather,
-    # with it from the one-thread-per-cell gather: the same terms summed in different fixed
-    # orders, so they agree to float32 rounding and each is bitwise reproducible
+    # the wave gather with and without the transform gradient gives the same grid gradient
+    # bits, and is bitwise reproducible; the one-thread-per-cell gather is compared in the
+    # training-step tests (it sums the same terms in another fixed order)
     host = host_model(M, C, R, H, extra_t=0.1)
     x = make_points(6001)
     df = np.random.default_rng(5).normal(size=x.shape[0]).astype(np.float32)
@@ -223,7 +223,7 @@ def test_grid_gradient_gathers_agree_and_match_oracle(M, C, R, H):
     dF_w2, _, _ = A().apmg_backward(model, soa(x), torch.from_numpy(df).to(DEV), want_dG=False)
     dF_c, _, _ = A().apmg_backward(model, soa(x), torch.from_numpy(df).to(DEV), want_dG=True)
     assert torch.equal(dF_w, dF_w2)
-    assert_close("dF wave vs per-cell gather", dF_w.cpu().numpy(), dF_c.cpu().numpy(), 1e-6)
+    assert torch.equal(dF_w, dF_c)
     xk = kink_free(host, x)
     dfk = np.random.default_rng(6).normal(size=xk.shape[0]).astype(np.float32)
     dF_k, _, _ = A().apmg_backward(model, soa(xk), torch.from_numpy(dfk).to(DEV), want_dG=False)
@@ -260,12 +260,27 @@ def test_grid_gradient_under_rotated_scaled_sheared_transforms():
     model = A().Model.from_host(host, DEV)
     dF_w, _, _ = A().apmg_backward(model, soa(x), torch.from_numpy(df).to(DEV), want_dG=False)
     dF_c, _, _ = A().apmg_backward(model, soa(x), torch.from_numpy(df).to(DEV), want_dG=True)
-    assert_close("dF wave vs per-cell gather", dF_w.cpu().numpy(), dF_c.cpu().numpy(), 1e-6)
+    assert torch.equal(dF_w, dF_c)
     xk = kink_free(host, x)
     dfk = np.random.default_rng(9).normal(size=xk.shape[0]).astype(np.float32)
-    dF_k, _, _ = A().apmg_backward(model, soa(xk), torch.from_numpy(dfk).to(DEV), want_dG=False)
+    dF_k, dG_k, _ = A().apmg_backward(model, soa(xk), torch.from_numpy(dfk).to(DEV))
     go = O.backward(f64(host), xk.astype(np.float64), dfk.astype(np.float64))
     assert_close("dF (wave gather, turned grids)", dF_k.cpu().numpy(), go["dF"].transpose(0, 2, 3, 4, 1))
+    assert_close("dG (wave gather, turned grids)", dG_k.cpu().numpy(), go["dG"])
+    # the one-thread-per-cell gather (reached through the training step's launch shapes) on the
+    # same turned grids: the grids' first moments (0.1 * gradient) agree with the wave gather's
+    vol = synth.make_volume("blobs_sine", (30, 34, 38)).to(DEV)
+    nz, ny, nx = vol.shape
+    _, bricks = A().apmg_make_bricks(nx, ny, nz, max(nx, ny, nz), 0)
+    host["vmin"], host["vmax"] = np.float32(0.0), np.float32(1.0)
+    steps = []
+    for ck in (1, 2):
+        tr = A().Trainer([host], vol, bricks, 20000, seed=5, tuning={"cell_kernel": ck})
+        tr.step()
+        steps.append(tr)
+    torch.cuda.synchronize()
+    assert_close("mF wave vs per-cell gather (turned grids)", steps[0].mF.cpu().numpy(),
+                 steps[1].mF.cpu().numpy(), 1e-6)
 
 
 def test_backward_accumulate_and_partial_outputs():
@@ -388,6 +403,29 @@ def test_batched_step_matches_oracle(nb_shape):
         print(f"mG[{b}] rel err {a:.2e}")
         assert a < 1e-3
     assert int(tr.step_ctr.item()) == 1 and int(tr.t[0].item()) == 1 and int(tr.tG[0].item()) == 1
+
+
+@pytest.mark.parametrize("cell_kernel", [1, 2])
+def test_batched_step_with_rec_transform_gradient_matches_oracle(cell_kernel):
+    # APMG_ADD_REC_DG: L_rec's transform gradient (through the trilinear weights) is added to
+    # the density gradient, from the wave gather (1) or the one-thread-per-cell gather (2)
+    vol = synth.make_volume("blobs_sine", (48, 40, 36))
+    nz, ny, nx = vol.shape
+    _, bricks = A().apmg_make_bricks(nx, ny, nz, max(nx, ny, nz), 0)
+    host = host_model(8, 2, 8, 64, seed=12, grid_range=0.2, vmin=0.0, vmax=1.0, extra_t=0.1)
+    n = 3000
+    tr = A().Trainer([host], vol.to(DEV), bricks, n, seed=7, flags=A().ADD_REC_DG,
+                     tuning={"cell_kernel": cell_kernel})
+    tr.density_active.fill_(1)
+    tr.step()
+    torch.cuda.synchronize()
+    _, obricks = O.brick_partition((nx, ny, nz), max(nx, ny, nz), 0)
+    new_m, new_s, info = oracle_step(host, vol.numpy().astype(np.float64), obricks[0], 7, 0, 0, n, True,
+                                     flags_rec=True)
+    assert_close("mF", tr.mF[0].cpu().numpy(), new_s["mF"].transpose(0, 2, 3, 4, 1))
+    a, _ = errs(tr.mG[0].cpu().numpy(), new_s["mG"])
+    print(f"mG (density + L_rec transform gradient), gather {cell_kernel}: rel err {a:.2e}")
+    assert a < 1e-3
 
 
 # --------------------------------------------------------------------------- graphs, determinism
