@@ -95,6 +95,8 @@ int device_cus() {
     return kMaxTileBlocks / 2;
   return cus;
 }
+// apmg_backward: one round of the adjoint kernel's blocks (one per CU), at most one per 4 tiles.
+int bwd_blocks(int64_t n) { return std::max(1, std::min(tile_blocks(n), device_cus())); }
 int step_default_blocks(int64_t n, int nb) {
   const int cus = device_cus();
   const int one = (cus + nb - 1) / nb;
@@ -317,7 +319,7 @@ size_t bwd_ws(const Shape& s, bool bf, int64_t n, void* ws, BwdWs* o) {
   const size_t esz = bf ? 2 : 4;
   w.f.swz = cv.take<char>(swz_sizes(s).total() * esz);
   w.f.w3s = cv.take<float>(s.H);
-  w.part = cv.take<double>((size_t)tile_blocks(n) * max_part_len(s, bf));
+  w.part = cv.take<double>((size_t)bwd_blocks(n) * max_part_len(s, bf));
   take_sort(cv, n, 1, true, &w.srt);
   take_cell(cv, s, n, 1, &w.cell);
   if (o) *o = w;
@@ -562,7 +564,7 @@ apmg_status apmg_backward(const apmg_model* m, const float* pts, int64_t ld, int
   if (e != hipSuccess) return APMG_EHIP;
   e = launch_swizzle(s, bf, m->W[0], m->W[1], m->W[2], 0, w.f.swz, 0, w.f.w3s, 1, st);
   if (e != hipSuccess) return APMG_EHIP;
-  const int nblk = tile_blocks(n);
+  const int nblk = bwd_blocks(n);
   const bool want_cells = dF || dG;
   const int kb = passes.size() == 1 ? register_kb(s) : 0;
   for (const Pass& ps : passes) {
