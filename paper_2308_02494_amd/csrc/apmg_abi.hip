@@ -307,12 +307,20 @@ hipError_t launch_cells(const Shape& s, bool gf16, const float* G, size_t G_stri
 #undef APMG_WAVE
 #undef APMG_PULL
   if (dG)
-    hipLaunchKernelGGL(k_reduce_cell_dG, dim3(1, nb), dim3(256), 0, st, cw.dGpart, s.M, dg_parts(s, cell_kernel), dG,
+    hipLaunchKernelGGL(k_reduce_cell_dG, dim3(s.M, nb), dim3(256), 0, st, cw.dGpart, s.M, dg_parts(s, cell_kernel), dG,
                        dG_stride, dG_accumulate, dG_active ? dG_active : active);
   return hipGetLastError();
 }
 
-struct BwdWs { FwdWs f; double* part; SortWs srt; CellWs cell; };
+// Shapes outside the register-resident adjoint (H != 64 or more than 64 input features) take
+// their weight gradients from stored per-point activations and k_dw_gemm, in one adjoint pass
+// with no LDS accumulators (deterministic, no multi-pass recomputation of the forward).
+bool act_path(const Shape& s, bool bf) { return !(plan_passes(s, bf, true).size() == 1 && register_kb(s) > 0); }
+inline int64_t act_ld(int64_t n) { return (std::max<int64_t>(n, 1) + 31) / 32 * 32; }
+inline int gemm_chunks(int64_t n) { return (int)((act_ld(n) + kGemmChunk - 1) / kGemmChunk); }
+inline int gemm_part_len(const Shape& s) { return s.H * s.MC + s.H * s.H; }
+
+struct BwdWs { FwdWs f; double* part; SortWs srt; CellWs cell; void* act; double* gpart; };
 size_t bwd_ws(const Shape& s, bool bf, int64_t n, void* ws, BwdWs* o) {
   Carver cv(ws);
   BwdWs w;
@@ -322,6 +330,12 @@ size_t bwd_ws(const Shape& s, bool bf, int64_t n, void* ws, BwdWs* o) {
   w.part = cv.take<double>((size_t)bwd_blocks(n) * max_part_len(s, bf));
   take_sort(cv, n, 1, true, &w.srt);
   take_cell(cv, s, n, 1, &w.cell);
+  w.act = nullptr;
+  w.gpart = nullptr;
+  if (act_path(s, bf)) {
+    w.act = cv.take<char>((size_t)(s.MC + 3 * s.H) * act_ld(n) * esz);
+    w.gpart = cv.take<double>((size_t)gemm_chunks(n) * gemm_part_len(s));
+  }
   if (o) *o = w;
   return cv.off;
 }
@@ -541,7 +555,8 @@ apmg_status apmg_backward(const apmg_model* m, const float* pts, int64_t ld, int
   if (dW) for (int k = 0; k < m->n_layers; ++k) if (!dW[k]) return APMG_EINVAL;
   const bool bf = m->mlp_dtype == APMG_BF16, gf16 = m->grid_dtype == APMG_F16;
   if (ws_bytes < bwd_ws(s, bf, n, nullptr, nullptr) || !ws) return APMG_EWORKSPACE;
-  const std::vector<Pass> passes = plan_passes(s, bf, dW != nullptr);
+  const bool use_act = dW != nullptr && act_path(s, bf);
+  const std::vector<Pass> passes = use_act ? std::vector<Pass>{{0, 0, 0, 0, true}} : plan_passes(s, bf, dW != nullptr);
   if (passes.empty()) return APMG_EUNSUPPORTED;
   const bool acc = flags & APMG_ACCUMULATE;
   const size_t nF = (size_t)s.M * s.R * s.R * s.R * s.C;
@@ -566,12 +581,14 @@ apmg_status apmg_backward(const apmg_model* m, const float* pts, int64_t ld, int
   if (e != hipSuccess) return APMG_EHIP;
   const int nblk = bwd_blocks(n);
   const bool want_cells = dF || dG;
-  const int kb = passes.size() == 1 ? register_kb(s) : 0;
+  const int kb = (!use_act && passes.size() == 1) ? register_kb(s) : 0;
   for (const Pass& ps : passes) {
     TileArgs a;
     memset(&a, 0, sizeof(a));
     a.s = s;
     a.G = m->G; a.F = m->F; a.swz = w.f.swz; a.w3s = w.f.w3s;
+    a.act = use_act ? w.act : nullptr;
+    a.act_ld = act_ld(n);
     a.vscale = m->vmax - m->vmin; a.voff = m->vmin;
     a.pts = w.srt.spts; a.ld = n; a.n = n;
     a.df = w.srt.sf;
@@ -598,6 +615,31 @@ apmg_status apmg_backward(const apmg_model* m, const float* pts, int64_t ld, int
     if (a.do_w3)
       hipLaunchKernelGGL(k_reduce_parts, dim3(1, 1), dim3(256), 0, st, w.part, nblk, pl.len, pl.o_w3, s.H, s.H, 0,
                          0, dW[2], (double*)nullptr, (size_t)0, 1, (const int32_t*)nullptr);
+  }
+  if (use_act) {
+    // dW1 = sum_p delta1_p y_p^T and dW2 = sum_p delta2_p h1_p^T from the stored activations
+    const int64_t ld = act_ld(n);
+    const size_t esz = bf ? 2 : 4;
+    const char* act = (const char*)w.act;
+    const int nch = gemm_chunks(n), plen = gemm_part_len(s);
+    const void* Y = act;
+    const void* H1 = act + (size_t)s.MC * ld * esz;
+    const void* D1 = act + (size_t)(s.MC + s.H) * ld * esz;
+    const void* D2 = act + (size_t)(s.MC + 2 * s.H) * ld * esz;
+    const dim3 g1(nch, (s.H + 127) / 128, (s.MC + 127) / 128), g2(nch, (s.H + 127) / 128, (s.H + 127) / 128);
+    if (bf) {
+      hipLaunchKernelGGL(k_dw_gemm<true>, g1, dim3(256), 0, st, D1, Y, ld, s.H, s.MC, w.gpart, plen, 0);
+      hipLaunchKernelGGL(k_dw_gemm<true>, g2, dim3(256), 0, st, D2, H1, ld, s.H, s.H, w.gpart, plen, s.H * s.MC);
+    } else {
+      hipLaunchKernelGGL(k_dw_gemm<false>, g1, dim3(256), 0, st, D1, Y, ld, s.H, s.MC, w.gpart, plen, 0);
+      hipLaunchKernelGGL(k_dw_gemm<false>, g2, dim3(256), 0, st, D2, H1, ld, s.H, s.H, w.gpart, plen, s.H * s.MC);
+    }
+    hipLaunchKernelGGL(k_reduce_parts, dim3(red_blocks((int64_t)s.H * s.MC), 1), dim3(256), 0, st, w.gpart, nch,
+                       plen, 0, s.H * s.MC, s.MC, s.MC, 0, dW[0], (double*)nullptr, (size_t)0, 1,
+                       (const int32_t*)nullptr);
+    hipLaunchKernelGGL(k_reduce_parts, dim3(red_blocks((int64_t)s.H * s.H), 1), dim3(256), 0, st, w.gpart, nch,
+                       plen, s.H * s.MC, s.H * s.H, s.H, s.H, 0, dW[1], (double*)nullptr, (size_t)0, 1,
+                       (const int32_t*)nullptr);
   }
   if (want_cells) {
     e = launch_cells(s, gf16, m->G, 0, m->F, 0, w.srt, n, w.cell, dF, 0, acc ? 1 : 0, dG != nullptr, dG, 0,
@@ -868,7 +910,7 @@ apmg_status run_step(const apmg_batch* b, const Shape& s, void* ws, const Tune& 
     }
     if (ed != hipSuccess || ec != hipSuccess || ej != hipSuccess) return APMG_EHIP;
     if (rec_dG)
-      hipLaunchKernelGGL(k_reduce_cell_dG, dim3(1, nb), dim3(256), 0, st, w.cell.dGpart, s.M,
+      hipLaunchKernelGGL(k_reduce_cell_dG, dim3(s.M, nb), dim3(256), 0, st, w.cell.dGpart, s.M,
                          dg_parts(s, tu.cell_kernel), w.dG, nG, 1, w.dlive);
   }
   if (!update) return hip_status(hipGetLastError());

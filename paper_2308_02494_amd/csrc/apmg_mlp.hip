@@ -92,6 +92,12 @@ template <bool BF> struct TT {
 };
 
 template <bool BF>
+__device__ inline void act_put(void* act, size_t idx, float v) {
+  if constexpr (BF) ((uint16_t*)act)[idx] = bf16_bits(v);
+  else ((float*)act)[idx] = v;
+}
+
+template <bool BF>
 __device__ inline void tt_put(typename TT<BF>::T* t, int row, int j, float v) {
   if constexpr (BF) t[row * TT<BF>::LDT + j] = bf16_bits(v);
   else t[row * TT<BF>::LDT + j] = v;
@@ -150,7 +156,8 @@ template <int C, int H, bool GF16, bool BF, bool STY = false>
 __device__ inline void tile_fwd(const Shape& s, const float* sG, const void* F, const void* swz,
                                 const float* w3s, float x, float y, float z, bool valid, int lane,
                                 f32x16 (&z1)[H / 32], f32x16 (&z2)[H / 32], float& m,
-                                typename TT<BF>::T* Ty = nullptr) {
+                                typename TT<BF>::T* Ty = nullptr, void* yact = nullptr, int64_t yld = 0,
+                                int64_t ypa = 0) {
   constexpr int NB = H / 32;
   const int hf = lane >> 5;
   const float hR = 0.5f * (float)(s.R - 1);
@@ -170,6 +177,10 @@ __device__ inline void tile_fwd(const Shape& s, const float* sG, const void* F, 
     auto consume = [&](const GridTap<C>& t, int gi) {
       float e[C];
       grid_tap_value<C>(t, e);
+      if (yact && hf * s.Mh + gi < s.M) {
+#pragma unroll
+        for (int c = 0; c < C; ++c) act_put<BF>(yact, (size_t)((hf * s.Mh + gi) * C + c) * yld + ypa, e[c]);
+      }
 #pragma unroll
       for (int c = 0; c < C; ++c) {
         const int k = gi * C + c;
@@ -201,6 +212,10 @@ __device__ inline void tile_fwd(const Shape& s, const float* sG, const void* F, 
         sched_barrier();
         float e[C];
         grid_tap_value<C>(cur, e);
+        if (yact && gi < s.Mh && hf * s.Mh + gi < s.M) {
+#pragma unroll
+          for (int c = 0; c < C; ++c) act_put<BF>(yact, (size_t)((hf * s.Mh + gi) * C + c) * yld + ypa, e[c]);
+        }
 #pragma unroll
         for (int c = 0; c < C; ++c) {
           B[u * C + c] = (short)bf16_bits(e[c]);
@@ -440,7 +455,8 @@ __global__ void __launch_bounds__(kBlock) k_backward(TileArgs a) {
     if (valid) { x = P[p]; y = P[a.ld + p]; z = P[2 * a.ld + p]; }
     f32x16 z1[NB], z2[NB];
     float m;
-    tile_fwd<C, H, GF16, BF, REG>(s, sG, F, swz, w3s, x, y, z, valid, lane, z1, z2, m, Ty);
+    tile_fwd<C, H, GF16, BF, REG>(s, sG, F, swz, w3s, x, y, z, valid, lane, z1, z2, m, Ty,
+                                  REG ? nullptr : a.act, a.act_ld, tile * 32 + j);
 
     // dL/df for this point
     float df = 0.f;
@@ -496,6 +512,20 @@ __global__ void __launch_bounds__(kBlock) k_backward(TileArgs a) {
     for (int b = 0; b < NB; ++b)
 #pragma unroll
       for (int r = 0; r < 16; ++r) d2[b][r] = z2[b][r] > 0.f ? w3s[hf * (H / 2) + 16 * b + r] * dm : 0.f;
+
+    // stored activations: every lane of the tile writes (points past n write zeros)
+    const bool store_act = !REG && a.act != nullptr;
+    const int64_t pa = tile * 32 + j;
+    if (store_act) {
+#pragma unroll
+      for (int b = 0; b < NB; ++b)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+          const size_t row = 32 * b + acc_row(r, hf);
+          act_put<BF>(a.act, (s.MC + row) * a.act_ld + pa, fmaxf(z1[b][r], 0.f));
+          act_put<BF>(a.act, (s.MC + 2 * H + row) * a.act_ld + pa, d2[b][r]);
+        }
+    }
 
     // dW2 rows [w2_lo, w2_hi) = sum_j delta2_j h1_j^T, one 32-row block of h1 at a time
     if (nrows2 > 0) {
@@ -554,6 +584,13 @@ __global__ void __launch_bounds__(kBlock) k_backward(TileArgs a) {
     for (int b = 0; b < NB; ++b)
 #pragma unroll
       for (int r = 0; r < 16; ++r) d1[b][r] = z1[b][r] > 0.f ? d1[b][r] : 0.f;
+    if (store_act) {
+#pragma unroll
+      for (int b = 0; b < NB; ++b)
+#pragma unroll
+        for (int r = 0; r < 16; ++r)
+          act_put<BF>(a.act, (s.MC + H + 32 * b + acc_row(r, hf)) * (size_t)a.act_ld + pa, d1[b][r]);
+    }
 
     const bool any_w1 = ncols > 0;
     if (any_w1) {
@@ -668,6 +705,75 @@ __global__ void __launch_bounds__(kBlock) k_backward(TileArgs a) {
     for (int i = threadIdx.x; i < H; i += blockDim.x)
       part[pl.o_w3 + i] = (double)sW3w[i] + (double)sW3w[H + i] + (double)sW3w[2 * H + i] + (double)sW3w[3 * H + i];
   if (threadIdx.x == 0) part[pl.o_loss] = a.want_loss ? ((sLoss[0] + sLoss[1]) + sLoss[2]) + sLoss[3] : 0.0;
+}
+
+// Weight-gradient products from stored activations: part[chunk][off + i * cols + j] = sum over
+// the chunk's points p of A[i][p] B[j][p] (A: rows x ld, B: cols x ld, feature-major, float32
+// or bf16 as the MLP; ld a multiple of 32 with zeros past the last point).  A wave owns one
+// 32-row block and up to four 32-column blocks; the matrix-core k dimension runs over points
+// (lane half kh takes 16 (float32) or 8 (bf16) consecutive points of each step).  Partials are
+// float64, reduced over the chunks afterwards in a fixed order.
+constexpr int kGemmChunk = 2048;   // points per chunk (a multiple of 32)
+template <bool BF>
+__global__ void __launch_bounds__(256) k_dw_gemm(const void* A, const void* B, int64_t ld, int rows, int cols,
+                                                 double* part, int part_len, int part_off) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, i = lane & 31, kh = lane >> 5;
+  const int rb = blockIdx.y * 4 + wave;
+  if (32 * rb >= rows) return;
+  const int64_t p0 = (int64_t)blockIdx.x * kGemmChunk, p1 = min(ld, p0 + kGemmChunk);
+  const int row = 32 * rb + i;
+  int col[4];
+  bool cok[4];
+#pragma unroll
+  for (int c = 0; c < 4; ++c) { col[c] = 32 * (blockIdx.z * 4 + c) + i; cok[c] = col[c] < cols; }
+  f32x16 acc[4];
+#pragma unroll
+  for (int c = 0; c < 4; ++c)
+#pragma unroll
+    for (int r = 0; r < 16; ++r) acc[c][r] = 0.f;
+  for (int64_t base = p0; base < p1; base += 32) {
+    if constexpr (!BF) {
+      const f32x4* ar = (const f32x4*)((const float*)A + (size_t)row * ld + base + 16 * kh);
+      f32x4 av[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) av[q] = ar[q];
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        f32x4 bv[4];
+        if (cok[c]) {
+          const f32x4* br = (const f32x4*)((const float*)B + (size_t)col[c] * ld + base + 16 * kh);
+#pragma unroll
+          for (int q = 0; q < 4; ++q) bv[q] = br[q];
+        } else {
+#pragma unroll
+          for (int q = 0; q < 4; ++q) bv[q] = f32x4{0.f, 0.f, 0.f, 0.f};
+        }
+#pragma unroll
+        for (int st = 0; st < 16; ++st) acc[c] = mma_f32(av[st >> 2][st & 3], bv[st >> 2][st & 3], acc[c]);
+      }
+    } else {
+      const bf16x8* ar = (const bf16x8*)((const uint16_t*)A + (size_t)row * ld + base + 8 * kh);
+      const bf16x8 a0 = ar[0], a1 = ar[2];
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        bf16x8 b0 = bf16x8{0, 0, 0, 0, 0, 0, 0, 0}, b1 = b0;
+        if (cok[c]) {
+          const bf16x8* br = (const bf16x8*)((const uint16_t*)B + (size_t)col[c] * ld + base + 8 * kh);
+          b0 = br[0];
+          b1 = br[2];
+        }
+        acc[c] = mma_bf16(a0, b0, acc[c]);
+        acc[c] = mma_bf16(a1, b1, acc[c]);
+      }
+    }
+  }
+  double* out = part + (size_t)blockIdx.x * part_len + part_off;
+#pragma unroll
+  for (int c = 0; c < 4; ++c)
+    if (cok[c]) {
+#pragma unroll
+      for (int r = 0; r < 16; ++r) out[(size_t)(32 * rb + acc_row(r, kh)) * cols + col[c]] = (double)acc[c][r];
+    }
 }
 
 // ------------------------------------------------------------------ instantiation

@@ -556,17 +556,32 @@ __global__ void k_cell_to_vertex(Shape s, const float* CC, float* dF, size_t dF_
   }
 }
 
-// dG[model][g][k] (+)= sum over the cell blocks of grid g of the per-block partials, in block order.
-__global__ void k_reduce_cell_dG(const double* part, int M, int cb, double* dG, size_t dG_stride, int accumulate,
-                                 const int32_t* active) {
-  const int model = blockIdx.y;
+// dG[model][g][k] (+)= sum over the cb per-block partials of grid g: one workgroup per (grid,
+// model); thread t sums blocks t, t + 256, ... in order, then a fixed tree over the threads.
+__global__ void __launch_bounds__(256) k_reduce_cell_dG(const double* part, int M, int cb, double* dG,
+                                                        size_t dG_stride, int accumulate, const int32_t* active) {
+  __shared__ double sp[256][13];
+  const int g = blockIdx.x, model = blockIdx.y;
   if (active && !active[model]) return;
-  for (int e = threadIdx.x; e < 12 * M; e += blockDim.x) {
-    const int g = e / 12, k = e % 12;
-    double s = 0.0;
-    for (int b = 0; b < cb; ++b) s += part[(((size_t)model * M + g) * cb + b) * 12 + k];
-    double* o = dG + model * dG_stride + e;
-    *o = accumulate ? *o + s : s;
+  const double* P = part + ((size_t)model * M + g) * cb * 12;
+  double acc[12];
+#pragma unroll
+  for (int k = 0; k < 12; ++k) acc[k] = 0.0;
+  for (int b = threadIdx.x; b < cb; b += blockDim.x)
+#pragma unroll
+    for (int k = 0; k < 12; ++k) acc[k] += P[(size_t)b * 12 + k];
+#pragma unroll
+  for (int k = 0; k < 12; ++k) sp[threadIdx.x][k] = acc[k];
+  __syncthreads();
+  for (int w = 128; w >= 1; w >>= 1) {
+    if (threadIdx.x < w)
+#pragma unroll
+      for (int k = 0; k < 12; ++k) sp[threadIdx.x][k] += sp[threadIdx.x + w][k];
+    __syncthreads();
+  }
+  if (threadIdx.x < 12) {
+    double* o = dG + model * dG_stride + 12 * g + threadIdx.x;
+    *o = accumulate ? *o + sp[0][threadIdx.x] : sp[0][threadIdx.x];
   }
 }
 
