@@ -283,6 +283,21 @@ def test_grid_gradient_under_rotated_scaled_sheared_transforms():
                  steps[1].mF.cpu().numpy(), 1e-6)
 
 
+@pytest.mark.parametrize("bf", [False, True])
+def test_backward_activation_path_is_bitwise_reproducible(bf):
+    # H = 128 with 256 input features: weight gradients from stored activations and the
+    # chunked matrix-core products, no float atomics
+    host = host_model(64, 4, 9, 128, grid_range=0.3)
+    x = make_points(40000)
+    df = torch.from_numpy(np.random.default_rng(2).normal(size=x.shape[0]).astype(np.float32)).to(DEV)
+    model = A().Model.from_host(host, DEV, mlp_dtype=A().BF16 if bf else A().F32)
+    r1 = A().apmg_backward(model, soa(x), df)
+    r2 = A().apmg_backward(model, soa(x), df)
+    assert torch.equal(r1[0], r2[0]) and torch.equal(r1[1], r2[1])
+    for k in range(3):
+        assert torch.equal(r1[2][k], r2[2][k])
+
+
 def test_backward_accumulate_and_partial_outputs():
     host = host_model(4, 2, 6, 64)
     x = kink_free(host, make_points(500))
