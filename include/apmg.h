@@ -100,7 +100,9 @@ typedef struct apmg_model {
 
 /* ---------------------------------------------------------------- forward
  * f[n] = d(e(x_n)) for n points (Sec. 4.1, Eqs. (1)-(3) and the decoder).
- * f: [n] float32 output. */
+ * f: [n] float32 output.  From 2^15 points on, the points are first sorted
+ * into spatial bins (the workspace then grows with n) and the outputs are
+ * scattered back to the caller's order; each value is the same either way. */
 apmg_status apmg_forward(const apmg_model* model, const float* pts, int64_t ld, int64_t n,
                          float* f, void* ws, size_t ws_bytes, hipStream_t stream);
 
@@ -119,7 +121,10 @@ apmg_status apmg_forward(const apmg_model* model, const float* pts, int64_t ld, 
  * the points of the bins the cell overlaps, with no atomics, and every
  * reduction (dF, dG in float64, dW in float64 over per-block partials) runs
  * in a fixed order: results are bitwise reproducible, and
- * APMG_DETERMINISTIC is accepted but changes nothing. */
+ * APMG_DETERMINISTIC is accepted but changes nothing.  MLP shapes outside
+ * the register-resident adjoint (H != 64, or more than 64 input features)
+ * store the per-point activations in the workspace and form dW1 and dW2 as
+ * matrix products over the points. */
 apmg_status apmg_backward(const apmg_model* model, const float* pts, int64_t ld, int64_t n,
                           const float* df, float* dF, double* dG, float* const* dW,
                           uint32_t flags, void* ws, size_t ws_bytes, hipStream_t stream);
@@ -217,7 +222,13 @@ apmg_status apmg_dd_forward(const apmg_dd_models* models, const apmg_brick_table
  *   7. *step += 1 (device counter; a captured graph replays fresh batches).
  * All per-model arrays are contiguous arenas indexed by model: model b's
  * block starts at b * (block size).  Adam moments and counters are device
- * memory the caller zero-initialises. */
+ * memory the caller zero-initialises.
+ * The density passes (5) and the last weight-gradient reductions run on a
+ * side stream the library keeps per device (default priority), forked from
+ * and joined back into `stream` within the call, so the call stays ordered
+ * on `stream` and can be captured in a graph; concurrent calls take turns
+ * for the fork and join.  A step captured before any eager step on that
+ * device runs entirely on `stream`. */
 /* Launch shapes of the training step (fields of 0 take the defaults).
  *   tile_blocks: blocks of the fused forward+adjoint tile kernel per model
  *     (each block = 4 waves of 32-point tiles); default CUs / nb when nb divides
