@@ -588,7 +588,7 @@ apmg_status apmg_backward(const apmg_model* m, const float* pts, int64_t ld, int
     a.s = s;
     a.G = m->G; a.F = m->F; a.swz = w.f.swz; a.w3s = w.f.w3s;
     a.act = use_act ? w.act : nullptr;
-    a.act_ld = act_ld(n);
+    a.act_rows = s.MC + 3 * s.H;
     a.vscale = m->vmax - m->vmin; a.voff = m->vmin;
     a.pts = w.srt.spts; a.ld = n; a.n = n;
     a.df = w.srt.sf;
@@ -618,21 +618,21 @@ apmg_status apmg_backward(const apmg_model* m, const float* pts, int64_t ld, int
   }
   if (use_act) {
     // dW1 = sum_p delta1_p y_p^T and dW2 = sum_p delta2_p h1_p^T from the stored activations
-    const int64_t ld = act_ld(n);
-    const size_t esz = bf ? 2 : 4;
-    const char* act = (const char*)w.act;
+    // (rows of each tile's block: y [0, MC), h1 [MC, MC+H), delta1 [MC+H, ..), delta2 [MC+2H, ..))
+    const int64_t np = act_ld(n);
+    const int rows_tot = s.MC + 3 * s.H;
     const int nch = gemm_chunks(n), plen = gemm_part_len(s);
-    const void* Y = act;
-    const void* H1 = act + (size_t)s.MC * ld * esz;
-    const void* D1 = act + (size_t)(s.MC + s.H) * ld * esz;
-    const void* D2 = act + (size_t)(s.MC + 2 * s.H) * ld * esz;
     const dim3 g1(nch, (s.H + 127) / 128, (s.MC + 127) / 128), g2(nch, (s.H + 127) / 128, (s.H + 127) / 128);
     if (bf) {
-      hipLaunchKernelGGL(k_dw_gemm<true>, g1, dim3(256), 0, st, D1, Y, ld, s.H, s.MC, w.gpart, plen, 0);
-      hipLaunchKernelGGL(k_dw_gemm<true>, g2, dim3(256), 0, st, D2, H1, ld, s.H, s.H, w.gpart, plen, s.H * s.MC);
+      hipLaunchKernelGGL(k_dw_gemm<true>, g1, dim3(256), 0, st, w.act, rows_tot, s.MC + s.H, 0, np, s.H, s.MC,
+                         w.gpart, plen, 0);
+      hipLaunchKernelGGL(k_dw_gemm<true>, g2, dim3(256), 0, st, w.act, rows_tot, s.MC + 2 * s.H, s.MC, np, s.H, s.H,
+                         w.gpart, plen, s.H * s.MC);
     } else {
-      hipLaunchKernelGGL(k_dw_gemm<false>, g1, dim3(256), 0, st, D1, Y, ld, s.H, s.MC, w.gpart, plen, 0);
-      hipLaunchKernelGGL(k_dw_gemm<false>, g2, dim3(256), 0, st, D2, H1, ld, s.H, s.H, w.gpart, plen, s.H * s.MC);
+      hipLaunchKernelGGL(k_dw_gemm<false>, g1, dim3(256), 0, st, w.act, rows_tot, s.MC + s.H, 0, np, s.H, s.MC,
+                         w.gpart, plen, 0);
+      hipLaunchKernelGGL(k_dw_gemm<false>, g2, dim3(256), 0, st, w.act, rows_tot, s.MC + 2 * s.H, s.MC, np, s.H,
+                         s.H, w.gpart, plen, s.H * s.MC);
     }
     hipLaunchKernelGGL(k_reduce_parts, dim3(red_blocks((int64_t)s.H * s.MC), 1), dim3(256), 0, st, w.gpart, nch,
                        plen, 0, s.H * s.MC, s.MC, s.MC, 0, dW[0], (double*)nullptr, (size_t)0, 1,

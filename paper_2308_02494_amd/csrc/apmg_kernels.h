@@ -58,10 +58,10 @@ struct TileArgs {
   int want_loss;                          // accumulate sum (f - v)^2
   double* part; int part_len;             // per-block partials [model][block][part_len]
   const int32_t* active;                  // per model: skip the model when 0 (or NULL)
-  // per-tile LDS path only: when non-NULL, the per-point activations of the weight-gradient
-  // products are stored instead of accumulated, feature-major rows of act_ld points (float32,
-  // or bf16 with the bf16 MLP): y [MC rows] | h1 [H] | delta1 [H] | delta2 [H]
-  void* act; int64_t act_ld;
+  // activation path: when non-NULL, the per-point activations of the weight-gradient
+  // products are stored instead of accumulated (float32, or bf16 with the bf16 MLP), one block
+  // per 32-point tile of act_rows rows x 32 points, rows y [MC] | h1 [H] | delta1 [H] | delta2 [H]
+  void* act; int act_rows;
 };
 
 // Per-block partial sums of the adjoint, float64: [dW1 slice H x ncols]

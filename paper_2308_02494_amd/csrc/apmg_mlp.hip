@@ -358,8 +358,11 @@ __device__ inline f32x16 tt_mma(const typename TT<BF>::T* Ta, int ia, const type
 // KB > 0: register-resident weight-gradient accumulators (H = 64, KB = KHP/16 dy blocks,
 // every column and row in one launch).  KB == 0: per-tile LDS accumulation, any shape,
 // gradient rows/columns split across launches.
-template <int C, int H, bool GF16, bool BF, int KB>
+// ACT (KB == 0 only): the activation path, the per-point activations are stored (a.act) and
+// no weight gradient is accumulated in the kernel.
+template <int C, int H, bool GF16, bool BF, int KB, bool ACT>
 __global__ void __launch_bounds__(kBlock) k_backward(TileArgs a) {
+  static_assert(!ACT || KB == 0, "the activation path has no register accumulators");
   extern __shared__ float smem[];
   typedef typename TT<BF>::T TTy;
   constexpr int NB = H / 32;
@@ -455,8 +458,18 @@ __global__ void __launch_bounds__(kBlock) k_backward(TileArgs a) {
     if (valid) { x = P[p]; y = P[a.ld + p]; z = P[2 * a.ld + p]; }
     f32x16 z1[NB], z2[NB];
     float m;
+    // stored activations: every lane of the tile writes (points past n write zeros); row r of
+    // this lane's point is at pa + 32 r (row offsets are constants, not per-row registers)
+    const size_t pa = (size_t)tile * a.act_rows * 32 + j;
     tile_fwd<C, H, GF16, BF, REG>(s, sG, F, swz, w3s, x, y, z, valid, lane, z1, z2, m, Ty,
-                                  REG ? nullptr : a.act, a.act_ld, tile * 32 + j);
+                                  ACT ? a.act : nullptr, 32, (int64_t)pa);
+    if constexpr (ACT) {
+#pragma unroll
+      for (int b = 0; b < NB; ++b)
+#pragma unroll
+        for (int r = 0; r < 16; ++r)
+          act_put<BF>(a.act, pa + (size_t)(s.MC + 32 * b + acc_row(r, hf)) * 32, fmaxf(z1[b][r], 0.f));
+    }
 
     // dL/df for this point
     float df = 0.f;
@@ -513,22 +526,16 @@ __global__ void __launch_bounds__(kBlock) k_backward(TileArgs a) {
 #pragma unroll
       for (int r = 0; r < 16; ++r) d2[b][r] = z2[b][r] > 0.f ? w3s[hf * (H / 2) + 16 * b + r] * dm : 0.f;
 
-    // stored activations: every lane of the tile writes (points past n write zeros)
-    const bool store_act = !REG && a.act != nullptr;
-    const int64_t pa = tile * 32 + j;
-    if (store_act) {
+    if constexpr (ACT) {
 #pragma unroll
       for (int b = 0; b < NB; ++b)
 #pragma unroll
-        for (int r = 0; r < 16; ++r) {
-          const size_t row = 32 * b + acc_row(r, hf);
-          act_put<BF>(a.act, (s.MC + row) * a.act_ld + pa, fmaxf(z1[b][r], 0.f));
-          act_put<BF>(a.act, (s.MC + 2 * H + row) * a.act_ld + pa, d2[b][r]);
-        }
+        for (int r = 0; r < 16; ++r)
+          act_put<BF>(a.act, pa + (size_t)(s.MC + 2 * H + 32 * b + acc_row(r, hf)) * 32, d2[b][r]);
     }
 
     // dW2 rows [w2_lo, w2_hi) = sum_j delta2_j h1_j^T, one 32-row block of h1 at a time
-    if (nrows2 > 0) {
+    if (!ACT && nrows2 > 0) {
 #pragma unroll
       for (int b = 0; b < NB; ++b)
 #pragma unroll
@@ -584,15 +591,15 @@ __global__ void __launch_bounds__(kBlock) k_backward(TileArgs a) {
     for (int b = 0; b < NB; ++b)
 #pragma unroll
       for (int r = 0; r < 16; ++r) d1[b][r] = z1[b][r] > 0.f ? d1[b][r] : 0.f;
-    if (store_act) {
+    if constexpr (ACT) {
 #pragma unroll
       for (int b = 0; b < NB; ++b)
 #pragma unroll
         for (int r = 0; r < 16; ++r)
-          act_put<BF>(a.act, (s.MC + H + 32 * b + acc_row(r, hf)) * (size_t)a.act_ld + pa, d1[b][r]);
+          act_put<BF>(a.act, pa + (size_t)(s.MC + H + 32 * b + acc_row(r, hf)) * 32, d1[b][r]);
     }
 
-    const bool any_w1 = ncols > 0;
+    const bool any_w1 = !ACT && ncols > 0;
     if (any_w1) {
 #pragma unroll
       for (int b = 0; b < NB; ++b)
@@ -708,19 +715,20 @@ __global__ void __launch_bounds__(kBlock) k_backward(TileArgs a) {
 }
 
 // Weight-gradient products from stored activations: part[chunk][off + i * cols + j] = sum over
-// the chunk's points p of A[i][p] B[j][p] (A: rows x ld, B: cols x ld, feature-major, float32
-// or bf16 as the MLP; ld a multiple of 32 with zeros past the last point).  A wave owns one
-// 32-row block and up to four 32-column blocks; the matrix-core k dimension runs over points
-// (lane half kh takes 16 (float32) or 8 (bf16) consecutive points of each step).  Partials are
-// float64, reduced over the chunks afterwards in a fixed order.
+// the chunk's points p of A[i][p] B[j][p], where A is rows a_row0.. and B rows b_row0.. of the
+// activation blocks (act_rows x 32 points per tile, float32 or bf16 as the MLP, zeros past the
+// last point).  A wave owns one 32-row block and up to four 32-column blocks; the matrix-core
+// k dimension runs over points (lane half kh takes 16 (float32) or 8 (bf16) consecutive points
+// of each step).  Partials are float64, reduced over the chunks afterwards in a fixed order.
 constexpr int kGemmChunk = 2048;   // points per chunk (a multiple of 32)
 template <bool BF>
-__global__ void __launch_bounds__(256) k_dw_gemm(const void* A, const void* B, int64_t ld, int rows, int cols,
-                                                 double* part, int part_len, int part_off) {
+__global__ void __launch_bounds__(256) k_dw_gemm(const void* act, int act_rows, int a_row0, int b_row0,
+                                                 int64_t npad, int rows, int cols, double* part, int part_len,
+                                                 int part_off) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, i = lane & 31, kh = lane >> 5;
   const int rb = blockIdx.y * 4 + wave;
   if (32 * rb >= rows) return;
-  const int64_t p0 = (int64_t)blockIdx.x * kGemmChunk, p1 = min(ld, p0 + kGemmChunk);
+  const int64_t p0 = (int64_t)blockIdx.x * kGemmChunk, p1 = min(npad, p0 + kGemmChunk);
   const int row = 32 * rb + i;
   int col[4];
   bool cok[4];
@@ -732,8 +740,9 @@ __global__ void __launch_bounds__(256) k_dw_gemm(const void* A, const void* B, i
 #pragma unroll
     for (int r = 0; r < 16; ++r) acc[c][r] = 0.f;
   for (int64_t base = p0; base < p1; base += 32) {
+    const size_t tb = (size_t)(base / 32) * act_rows * 32;   // this tile's block
     if constexpr (!BF) {
-      const f32x4* ar = (const f32x4*)((const float*)A + (size_t)row * ld + base + 16 * kh);
+      const f32x4* ar = (const f32x4*)((const float*)act + tb + (size_t)(a_row0 + row) * 32 + 16 * kh);
       f32x4 av[4];
 #pragma unroll
       for (int q = 0; q < 4; ++q) av[q] = ar[q];
@@ -741,7 +750,7 @@ __global__ void __launch_bounds__(256) k_dw_gemm(const void* A, const void* B, i
       for (int c = 0; c < 4; ++c) {
         f32x4 bv[4];
         if (cok[c]) {
-          const f32x4* br = (const f32x4*)((const float*)B + (size_t)col[c] * ld + base + 16 * kh);
+          const f32x4* br = (const f32x4*)((const float*)act + tb + (size_t)(b_row0 + col[c]) * 32 + 16 * kh);
 #pragma unroll
           for (int q = 0; q < 4; ++q) bv[q] = br[q];
         } else {
@@ -752,13 +761,13 @@ __global__ void __launch_bounds__(256) k_dw_gemm(const void* A, const void* B, i
         for (int st = 0; st < 16; ++st) acc[c] = mma_f32(av[st >> 2][st & 3], bv[st >> 2][st & 3], acc[c]);
       }
     } else {
-      const bf16x8* ar = (const bf16x8*)((const uint16_t*)A + (size_t)row * ld + base + 8 * kh);
+      const bf16x8* ar = (const bf16x8*)((const uint16_t*)act + tb + (size_t)(a_row0 + row) * 32 + 8 * kh);
       const bf16x8 a0 = ar[0], a1 = ar[2];
 #pragma unroll
       for (int c = 0; c < 4; ++c) {
         bf16x8 b0 = bf16x8{0, 0, 0, 0, 0, 0, 0, 0}, b1 = b0;
         if (cok[c]) {
-          const bf16x8* br = (const bf16x8*)((const uint16_t*)B + (size_t)col[c] * ld + base + 8 * kh);
+          const bf16x8* br = (const bf16x8*)((const uint16_t*)act + tb + (size_t)(b_row0 + col[c]) * 32 + 8 * kh);
           b0 = br[0];
           b1 = br[2];
         }
@@ -787,12 +796,14 @@ hipError_t launch_tile_kernels(bool backward, int kb, const TileArgs& a, dim3 gr
       hipLaunchKernelGGL((k_forward<C, H, GF16, BF, true>), grid, dim3(kBlock), shmem, st, a);
     else
       hipLaunchKernelGGL((k_forward<C, H, GF16, BF, false>), grid, dim3(kBlock), shmem, st, a);
+  } else if (a.act) {
+    hipLaunchKernelGGL((k_backward<C, H, GF16, BF, 0, true>), grid, dim3(kBlock), shmem, st, a);
   } else if constexpr (H == 64) {
-    if (kb == 1) hipLaunchKernelGGL((k_backward<C, H, GF16, BF, 1>), grid, dim3(kBlock), shmem, st, a);
-    else if (kb == 2) hipLaunchKernelGGL((k_backward<C, H, GF16, BF, 2>), grid, dim3(kBlock), shmem, st, a);
-    else hipLaunchKernelGGL((k_backward<C, H, GF16, BF, 0>), grid, dim3(kBlock), shmem, st, a);
+    if (kb == 1) hipLaunchKernelGGL((k_backward<C, H, GF16, BF, 1, false>), grid, dim3(kBlock), shmem, st, a);
+    else if (kb == 2) hipLaunchKernelGGL((k_backward<C, H, GF16, BF, 2, false>), grid, dim3(kBlock), shmem, st, a);
+    else hipLaunchKernelGGL((k_backward<C, H, GF16, BF, 0, false>), grid, dim3(kBlock), shmem, st, a);
   } else {
-    hipLaunchKernelGGL((k_backward<C, H, GF16, BF, 0>), grid, dim3(kBlock), shmem, st, a);
+    hipLaunchKernelGGL((k_backward<C, H, GF16, BF, 0, false>), grid, dim3(kBlock), shmem, st, a);
   }
   return hipGetLastError();
 }
