@@ -234,3 +234,40 @@ def test_both_gathers_give_the_same_step():
         else:
             for x, y in zip((first.F, first.mF), (other.F, other.mF)):
                 assert torch.equal(x, y), unroll
+
+
+def test_steps_from_two_host_threads_match_sequential_steps():
+    # two trainers stepping at the same time from two host threads, each on its own stream:
+    # the library's per-device side stream is forked and joined under a lock, so each
+    # trainer's parameters equal those of the same steps run one trainer after the other
+    import threading
+    seq = [_bricks_trainer(nb=2, n=6000), _bricks_trainer(nb=1, n=5000)]
+    for tr in seq:
+        for _ in range(3):
+            tr.step()
+    torch.cuda.synchronize()
+    par = [_bricks_trainer(nb=2, n=6000), _bricks_trainer(nb=1, n=5000)]
+    streams = [torch.cuda.Stream(), torch.cuda.Stream()]
+    for st in streams:
+        st.wait_stream(torch.cuda.current_stream())
+    errors = []
+
+    def run(i):
+        try:
+            with torch.cuda.stream(streams[i]):
+                for _ in range(3):
+                    par[i].step()
+            streams[i].synchronize()
+        except Exception as e:  # surfaced in the main thread
+            errors.append(e)
+
+    threads = [threading.Thread(target=run, args=(i,)) for i in range(2)]
+    for t in threads:
+        t.start()
+    for t in threads:
+        t.join()
+    torch.cuda.synchronize()
+    assert not errors, errors
+    for a, b in zip(seq, par):
+        for x, y in zip((a.F, a.W, a.G, a.mF, a.losses), (b.F, b.W, b.G, b.mF, b.losses)):
+            assert torch.equal(x, y)
