@@ -415,6 +415,8 @@ struct StepWs {
   SortWs srt;
   CellWs cell;
   DenWs den;
+  void* act;      // activation path: [nb][tiles][MC + 3H][32] (float32 or bf16)
+  double* gpart;  // [nb][chunks][H*MC + H*H]
 };
 
 size_t w_elems(const Shape& s) { return (size_t)s.H * s.MC + (size_t)s.H * s.H + s.H; }
@@ -440,6 +442,12 @@ size_t step_ws(const apmg_batch* b, const Shape& s, void* ws, StepWs* o) {
   w.dlive = cv.take<int32_t>((size_t)nb);
   take_sort(cv, b->n, nb, false, &w.srt);
   take_cell(cv, s, b->n, nb, &w.cell);
+  w.act = nullptr;
+  w.gpart = nullptr;
+  if (act_path(s, bf)) {
+    w.act = cv.take<char>((size_t)nb * (s.MC + 3 * s.H) * act_ld(b->n) * (bf ? 2 : 4));
+    w.gpart = cv.take<double>((size_t)nb * gemm_chunks(b->n) * gemm_part_len(s));
+  }
   size_t off = cv.off;
   DenWs d;
   size_t dsz = den_ws(s, b->n, nb, ws ? (char*)ws + off : nullptr, &d);
@@ -829,10 +837,39 @@ apmg_status run_step(const apmg_batch* b, const Shape& s, void* ws, const Tune& 
 
   // 3. forward + adjoint of L_rec (part 1 of the step)
   const int nblk = tu.tile_blocks;
-  const std::vector<Pass> passes = plan_passes(s, bf, true);
+  const bool use_act = act_path(s, bf);
+  const std::vector<Pass> passes = use_act ? std::vector<Pass>{{0, 0, 0, 0, true}} : plan_passes(s, bf, true);
   if (passes.empty()) return APMG_EUNSUPPORTED;
-  const int kb = passes.size() == 1 ? register_kb(s) : 0;
+  const int kb = (!use_act && passes.size() == 1) ? register_kb(s) : 0;
   const bool rec_dG = b->flags & APMG_ADD_REC_DG;
+  const size_t act_stride = (size_t)(s.MC + 3 * s.H) * act_ld(n);
+  // activation path: dW1 and dW2 of every model from its stored activations
+  auto act_products = [&](hipStream_t rs) {
+    const int64_t np = act_ld(n);
+    const int rows_tot = s.MC + 3 * s.H, nch = gemm_chunks(n), plen = gemm_part_len(s);
+    const size_t esz = bf ? 2 : 4;
+    const dim3 g1(nch, (s.H + 127) / 128, (s.MC + 127) / 128), g2(nch, (s.H + 127) / 128, (s.H + 127) / 128);
+    for (int mb = 0; mb < nb; ++mb) {
+      const void* act = (const char*)w.act + (size_t)mb * act_stride * esz;
+      double* gp = w.gpart + (size_t)mb * nch * plen;
+      if (bf) {
+        hipLaunchKernelGGL(k_dw_gemm<true>, g1, dim3(256), 0, rs, act, rows_tot, s.MC + s.H, 0, np, s.H, s.MC, gp,
+                           plen, 0);
+        hipLaunchKernelGGL(k_dw_gemm<true>, g2, dim3(256), 0, rs, act, rows_tot, s.MC + 2 * s.H, s.MC, np, s.H, s.H,
+                           gp, plen, s.H * s.MC);
+      } else {
+        hipLaunchKernelGGL(k_dw_gemm<false>, g1, dim3(256), 0, rs, act, rows_tot, s.MC + s.H, 0, np, s.H, s.MC, gp,
+                           plen, 0);
+        hipLaunchKernelGGL(k_dw_gemm<false>, g2, dim3(256), 0, rs, act, rows_tot, s.MC + 2 * s.H, s.MC, np, s.H, s.H,
+                           gp, plen, s.H * s.MC);
+      }
+    }
+    hipLaunchKernelGGL(k_reduce_parts, dim3(red_blocks((int64_t)s.H * s.MC), nb), dim3(256), 0, rs, w.gpart, nch,
+                       plen, 0, s.H * s.MC, s.MC, s.MC, 0, w.dW, (double*)nullptr, nW, 0, (const int32_t*)w.live);
+    hipLaunchKernelGGL(k_reduce_parts, dim3(red_blocks((int64_t)s.H * s.H), nb), dim3(256), 0, rs, w.gpart, nch,
+                       plen, s.H * s.MC, s.H * s.H, s.H, s.H, s.H * s.MC, w.dW, (double*)nullptr, nW, 0,
+                       (const int32_t*)w.live);
+  };
   // block partials of one pass -> dW (and, for the first pass, dW3 and the L_rec sum)
   auto reduce_pass = [&](const Pass& ps, hipStream_t rs) {
     const int ncols = ps.c1_hi - ps.c1_lo, nrows = ps.w2_hi - ps.w2_lo;
@@ -871,6 +908,9 @@ apmg_status run_step(const apmg_batch* b, const Shape& s, void* ws, const Tune& 
     a.want_loss = ps.first;
     a.part = w.part;
     a.active = w.live;
+    a.act = use_act ? w.act : nullptr;
+    a.act_rows = s.MC + 3 * s.H;
+    a.act_stride = act_stride;
     const int ncols = ps.c1_hi - ps.c1_lo, nrows = ps.w2_hi - ps.w2_lo;
     const PartLayout pl = part_layout(s, ncols, nrows);
     a.part_len = pl.len;
@@ -896,6 +936,7 @@ apmg_status run_step(const apmg_batch* b, const Shape& s, void* ws, const Tune& 
     if (side && hipEventRecord(side->fork, st) == hipSuccess && hipStreamWaitEvent(side->s, side->fork, 0) == hipSuccess)
       dst = side->s;
     reduce_pass(passes.back(), dst);
+    if (use_act) act_products(dst);
     hipLaunchKernelGGL(k_copy_f64, dim3((nb + 63) / 64), dim3(64), 0, dst, w.lrec, 1, b->losses, 2, nb,
                        1.0 / (double)n);
     const hipError_t ed = launch_density(s, b->G, nG, w.srt.spts, n, (size_t)3 * n, n, w.err, n, b->eps_density,

@@ -61,7 +61,7 @@ struct TileArgs {
   // activation path: when non-NULL, the per-point activations of the weight-gradient
   // products are stored instead of accumulated (float32, or bf16 with the bf16 MLP), one block
   // per 32-point tile of act_rows rows x 32 points, rows y [MC] | h1 [H] | delta1 [H] | delta2 [H]
-  void* act; int act_rows;
+  void* act; int act_rows; size_t act_stride;   // act_stride: elements per model
 };
 
 // Per-block partial sums of the adjoint, float64: [dW1 slice H x ncols]

@@ -460,7 +460,7 @@ __global__ void __launch_bounds__(kBlock) k_backward(TileArgs a) {
     float m;
     // stored activations: every lane of the tile writes (points past n write zeros); row r of
     // this lane's point is at pa + 32 r (row offsets are constants, not per-row registers)
-    const size_t pa = (size_t)tile * a.act_rows * 32 + j;
+    const size_t pa = (size_t)model * a.act_stride + (size_t)tile * a.act_rows * 32 + j;
     tile_fwd<C, H, GF16, BF, REG>(s, sG, F, swz, w3s, x, y, z, valid, lane, z1, z2, m, Ty,
                                   ACT ? a.act : nullptr, 32, (int64_t)pa);
     if constexpr (ACT) {

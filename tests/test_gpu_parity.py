@@ -420,6 +420,38 @@ def test_batched_step_matches_oracle(nb_shape):
     assert int(tr.step_ctr.item()) == 1 and int(tr.t[0].item()) == 1 and int(tr.tG[0].item()) == 1
 
 
+def test_batched_step_activation_path_matches_oracle_and_is_reproducible():
+    # H = 128 with 32 input features: outside the register-resident adjoint, the step takes
+    # its weight gradients from stored activations and matrix-core products (two models)
+    vol = synth.make_volume("blobs_sine", (40, 44, 36))
+    nz, ny, nx = vol.shape
+    _, bricks = A().apmg_make_bricks(nx, ny, nz, 24, 1)
+    bricks = bricks[:2]
+    hosts = [host_model(8, 4, 8, 128, seed=30 + b, grid_range=0.2, vmin=0.0, vmax=1.0) for b in range(2)]
+    n = 2500
+    trs = []
+    for _ in range(2):
+        tr = A().Trainer(hosts, vol.to(DEV), bricks, n, seed=9)
+        tr.density_active.fill_(1)
+        tr.step()
+        trs.append(tr)
+    torch.cuda.synchronize()
+    for x, y in zip((trs[0].F, trs[0].W, trs[0].G, trs[0].mW), (trs[1].F, trs[1].W, trs[1].G, trs[1].mW)):
+        assert torch.equal(x, y)
+    tr = trs[0]
+    vol_np = vol.numpy().astype(np.float64)
+    _, obricks = O.brick_partition((nx, ny, nz), 24, 1)
+    for b in range(2):
+        new_m, new_s, info = oracle_step(hosts[b], vol_np, obricks[b], 9, 0, b, n, True)
+        assert_close(f"L_rec[{b}]", [tr.losses[b, 0].item()], [info["L_rec"]])
+        assert_close(f"mF[{b}]", tr.mF[b].cpu().numpy(), new_s["mF"].transpose(0, 2, 3, 4, 1))
+        mW = tr.mW[b].cpu().numpy()
+        o = 0
+        for k, w in enumerate(new_s["mW"]):
+            assert_close(f"mW{k + 1}[{b}]", mW[o:o + w.size].reshape(w.shape), w, 2e-5)
+            o += w.size
+
+
 @pytest.mark.parametrize("cell_kernel", [1, 2])
 def test_batched_step_with_rec_transform_gradient_matches_oracle(cell_kernel):
     # APMG_ADD_REC_DG: L_rec's transform gradient (through the trilinear weights) is added to
