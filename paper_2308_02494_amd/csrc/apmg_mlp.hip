@@ -103,22 +103,6 @@ __device__ inline void tt_put(typename TT<BF>::T* t, int row, int j, float v) {
   else t[row * TT<BF>::LDT + j] = v;
 }
 
-template <int C, bool GF16>
-__device__ inline void encode_grid(const Shape& s, const float* sG, const void* F, int g, float x,
-                                   float y, float z, bool valid, float hR, float e[C]) {
-#pragma unroll
-  for (int c = 0; c < C; ++c) e[c] = 0.f;
-  if (!valid || g >= s.M) return;
-  float l[3];
-  local_coords(sG + 12 * g, x, y, z, l);
-  int i0[3];
-  float w[3];
-  if (!cell_of(l, hR, s.R, i0, w)) return;
-  float val[8][C];
-  gather_cell<C, GF16>(F, g, s.R, i0, val);
-  trilerp<C>(val, w, e);
-}
-
 // One grid's contribution split in two so the gathers of the next grid can be in flight
 // while this one is consumed: grid_tap issues the 8 corner loads (always from a valid
 // address: cell 0 of grid 0 when the point is outside, invalid or past the last grid),
@@ -535,7 +519,8 @@ __global__ void __launch_bounds__(kBlock) k_backward(TileArgs a) {
     }
 
     // dW2 rows [w2_lo, w2_hi) = sum_j delta2_j h1_j^T, one 32-row block of h1 at a time
-    if (!ACT && nrows2 > 0) {
+    // (the register path only: other shapes take the activation path or want no dW)
+    if (REG && nrows2 > 0) {
 #pragma unroll
       for (int b = 0; b < NB; ++b)
 #pragma unroll
@@ -548,16 +533,6 @@ __global__ void __launch_bounds__(kBlock) k_backward(TileArgs a) {
         if constexpr (REG) {
 #pragma unroll
           for (int ib = 0; ib < NB; ++ib) aw2[ib][kb] = tt_mma<BF>(Ta, 32 * ib, Tb, 0, lane, aw2[ib][kb]);
-        } else {
-          for (int ib = a.w2_lo / 32; ib < a.w2_hi / 32; ++ib) {
-            f32x16 acc;
-#pragma unroll
-            for (int r = 0; r < 16; ++r) acc[r] = 0.f;
-            acc = tt_mma<BF>(Ta, 32 * ib, Tb, 0, lane, acc);
-#pragma unroll
-            for (int r = 0; r < 16; ++r)
-              atomicAdd(&sW2[(32 * ib + acc_row(r, hf) - a.w2_lo) * H + 32 * kb + j], acc[r]);
-          }
         }
         wave_lds_sync();
       }
@@ -599,7 +574,7 @@ __global__ void __launch_bounds__(kBlock) k_backward(TileArgs a) {
           act_put<BF>(a.act, pa + (size_t)(s.MC + H + 32 * b + acc_row(r, hf)) * 32, d1[b][r]);
     }
 
-    const bool any_w1 = !ACT && ncols > 0;
+    const bool any_w1 = REG && ncols > 0;
     if (any_w1) {
 #pragma unroll
       for (int b = 0; b < NB; ++b)
@@ -629,9 +604,7 @@ __global__ void __launch_bounds__(kBlock) k_backward(TileArgs a) {
           dy = mma_bf16(W1Tb[((size_t)blk * (H / 16) + st) * 64 + lane], B, dy);
         }
       }
-      const int lo0 = 16 * blk, lo1 = s.KH + 16 * blk;
-      const bool need_y = any_w1 && (REG || (lo0 < a.c1_hi && lo0 + 16 > a.c1_lo) ||
-                                     (lo1 < a.c1_hi && lo1 + 16 > a.c1_lo));
+      const bool need_y = any_w1;
 #pragma unroll
       for (int u = 0; u < 16 / C; ++u) {
         const int gi = 16 * blk / C + u;
@@ -642,12 +615,6 @@ __global__ void __launch_bounds__(kBlock) k_backward(TileArgs a) {
 #pragma unroll
           for (int c = 0; c < C; ++c) dst[c] = dy[u * C + c];
         }
-        if (!REG && need_y) {
-          float yv[C];
-          encode_grid<C, GF16>(s, sG, F, gvalid ? g : s.M, x, y, z, valid, hR, yv);
-#pragma unroll
-          for (int c = 0; c < C; ++c) tt_put<BF>(Tb, 16 * hf + u * C + c, j, yv[c]);
-        }
       }
       if (need_y) {
         wave_lds_sync();
@@ -655,21 +622,6 @@ __global__ void __launch_bounds__(kBlock) k_backward(TileArgs a) {
 #pragma unroll
           for (int ib = 0; ib < NB; ++ib)
             aw1[ib][blk] = tt_mma<BF>(Ta, 32 * ib, Ty + (size_t)32 * blk * LDT, 0, lane, aw1[ib][blk]);
-        } else {
-#pragma unroll
-          for (int ib = 0; ib < NB; ++ib) {
-            f32x16 acc;
-#pragma unroll
-            for (int r = 0; r < 16; ++r) acc[r] = 0.f;
-            acc = tt_mma<BF>(Ta, 32 * ib, Tb, 0, lane, acc);
-            const int col = (j >> 4) * s.KH + 16 * blk + (j & 15);
-            const bool ok = (16 * blk + (j & 15)) < s.KH && col < s.MC && col >= a.c1_lo && col < a.c1_hi;
-            if (ok) {
-#pragma unroll
-              for (int r = 0; r < 16; ++r)
-                atomicAdd(&sW1[(32 * ib + acc_row(r, hf)) * ncols + (col - a.c1_lo)], acc[r]);
-            }
-          }
         }
         wave_lds_sync();
       }
@@ -835,6 +787,8 @@ size_t forward_lds_bytes(const Shape& s, bool bf) {
 hipError_t launch_tile(bool backward, int kb, const TileArgs& a, bool grid_f16, bool mlp_bf16, dim3 grid,
                        size_t shmem, hipStream_t st) {
   const int C = a.s.C, H = a.s.H;
+  // only the register-resident adjoint accumulates weight gradients in the kernel
+  if (backward && kb == 0 && (a.c1_hi > a.c1_lo || a.w2_hi > a.w2_lo)) return hipErrorInvalidValue;
 #define APMG_DISPATCH(CC, HH)                                                                  \
   if (C == CC && H == HH) {                                                                    \
     if (!grid_f16 && !mlp_bf16) return launch_tile_kernels<CC, HH, false, false>(backward, kb, a, grid, shmem, st); \
