@@ -313,8 +313,9 @@ def test_backward_accumulate_and_partial_outputs():
     assert_close("dW2 alone", only_w[2][1].cpu().numpy(), dW[1].cpu().numpy(), 1e-6)
 
 
-def test_backward_wide_first_layer_multipass():
-    # 256 input features and 128 hidden: the first-layer gradient is split across passes
+def test_backward_wide_first_layer_activation_path():
+    # 256 input features and 128 hidden: outside the register-resident adjoint, so the weight
+    # gradients come from the stored activations and the matrix-core products
     host = host_model(64, 4, 5, 128, grid_range=0.3)
     x = kink_free(host, make_points(1500))
     df = np.random.default_rng(5).normal(size=x.shape[0]).astype(np.float32)
