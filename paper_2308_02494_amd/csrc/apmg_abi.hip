@@ -461,6 +461,28 @@ __global__ void k_brick_scale(const apmg_brick* bricks, float* scale, int nb) {
   if (b < nb) { scale[b] = bricks[b].vmax - bricks[b].vmin; scale[nb + b] = bricks[b].vmin; }
 }
 
+// A side stream per device (default priority, non-blocking) and its fork/join events,
+// created on the first training step that runs on that device outside graph capture; a
+// step captured before that runs all its phases on the caller's stream.
+struct SideStream { hipStream_t s = nullptr; hipEvent_t fork = nullptr, join = nullptr; bool ok = false; };
+constexpr int kMaxDevices = 64;
+std::mutex g_side_mu;
+SideStream g_side[kMaxDevices];
+SideStream* side_stream(hipStream_t st) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return nullptr;
+  SideStream& ss = g_side[dev];
+  if (!ss.ok) {
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(st, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) return nullptr;
+    if (!ss.s && hipStreamCreateWithFlags(&ss.s, hipStreamNonBlocking) != hipSuccess) { ss.s = nullptr; return nullptr; }
+    if (!ss.fork && hipEventCreateWithFlags(&ss.fork, hipEventDisableTiming) != hipSuccess) { ss.fork = nullptr; return nullptr; }
+    if (!ss.join && hipEventCreateWithFlags(&ss.join, hipEventDisableTiming) != hipSuccess) { ss.join = nullptr; return nullptr; }
+    ss.ok = true;
+  }
+  return &ss;
+}
+
 }  // namespace
 
 hipEvent_t g_prof_start = nullptr, g_prof_stop = nullptr;
@@ -624,6 +646,18 @@ apmg_status apmg_backward(const apmg_model* m, const float* pts, int64_t ld, int
       hipLaunchKernelGGL(k_reduce_parts, dim3(1, 1), dim3(256), 0, st, w.part, nblk, pl.len, pl.o_w3, s.H, s.H, 0,
                          0, dW[2], (double*)nullptr, (size_t)0, 1, (const int32_t*)nullptr);
   }
+  // the weight-gradient products (activation path) and the grid-gradient gather both read
+  // what the adjoint kernel wrote and write disjoint outputs: the products run on the
+  // device's side stream, overlapping the gather
+  std::unique_lock<std::mutex> lk(g_side_mu, std::defer_lock);
+  hipStream_t pst = st;
+  SideStream* side = nullptr;
+  if (use_act && want_cells) {
+    lk.lock();
+    side = side_stream(st);
+    if (side && hipEventRecord(side->fork, st) == hipSuccess && hipStreamWaitEvent(side->s, side->fork, 0) == hipSuccess)
+      pst = side->s;
+  }
   if (use_act) {
     // dW1 = sum_p delta1_p y_p^T and dW2 = sum_p delta2_p h1_p^T from the stored activations
     // (rows of each tile's block: y [0, MC), h1 [MC, MC+H), delta1 [MC+H, ..), delta2 [MC+2H, ..))
@@ -632,28 +666,33 @@ apmg_status apmg_backward(const apmg_model* m, const float* pts, int64_t ld, int
     const int nch = gemm_chunks(n), plen = gemm_part_len(s);
     const dim3 g1(nch, (s.H + 127) / 128, (s.MC + 127) / 128), g2(nch, (s.H + 127) / 128, (s.H + 127) / 128);
     if (bf) {
-      hipLaunchKernelGGL(k_dw_gemm<true>, g1, dim3(256), 0, st, w.act, rows_tot, s.MC + s.H, 0, np, s.H, s.MC,
+      hipLaunchKernelGGL(k_dw_gemm<true>, g1, dim3(256), 0, pst, w.act, rows_tot, s.MC + s.H, 0, np, s.H, s.MC,
                          w.gpart, plen, 0);
-      hipLaunchKernelGGL(k_dw_gemm<true>, g2, dim3(256), 0, st, w.act, rows_tot, s.MC + 2 * s.H, s.MC, np, s.H, s.H,
+      hipLaunchKernelGGL(k_dw_gemm<true>, g2, dim3(256), 0, pst, w.act, rows_tot, s.MC + 2 * s.H, s.MC, np, s.H, s.H,
                          w.gpart, plen, s.H * s.MC);
     } else {
-      hipLaunchKernelGGL(k_dw_gemm<false>, g1, dim3(256), 0, st, w.act, rows_tot, s.MC + s.H, 0, np, s.H, s.MC,
+      hipLaunchKernelGGL(k_dw_gemm<false>, g1, dim3(256), 0, pst, w.act, rows_tot, s.MC + s.H, 0, np, s.H, s.MC,
                          w.gpart, plen, 0);
-      hipLaunchKernelGGL(k_dw_gemm<false>, g2, dim3(256), 0, st, w.act, rows_tot, s.MC + 2 * s.H, s.MC, np, s.H,
+      hipLaunchKernelGGL(k_dw_gemm<false>, g2, dim3(256), 0, pst, w.act, rows_tot, s.MC + 2 * s.H, s.MC, np, s.H,
                          s.H, w.gpart, plen, s.H * s.MC);
     }
-    hipLaunchKernelGGL(k_reduce_parts, dim3(red_blocks((int64_t)s.H * s.MC), 1), dim3(256), 0, st, w.gpart, nch,
+    hipLaunchKernelGGL(k_reduce_parts, dim3(red_blocks((int64_t)s.H * s.MC), 1), dim3(256), 0, pst, w.gpart, nch,
                        plen, 0, s.H * s.MC, s.MC, s.MC, 0, dW[0], (double*)nullptr, (size_t)0, 1,
                        (const int32_t*)nullptr);
-    hipLaunchKernelGGL(k_reduce_parts, dim3(red_blocks((int64_t)s.H * s.H), 1), dim3(256), 0, st, w.gpart, nch,
+    hipLaunchKernelGGL(k_reduce_parts, dim3(red_blocks((int64_t)s.H * s.H), 1), dim3(256), 0, pst, w.gpart, nch,
                        plen, s.H * s.MC, s.H * s.H, s.H, s.H, 0, dW[1], (double*)nullptr, (size_t)0, 1,
                        (const int32_t*)nullptr);
   }
-  if (want_cells) {
-    e = launch_cells(s, gf16, m->G, 0, m->F, 0, w.srt, n, w.cell, dF, 0, acc ? 1 : 0, dG != nullptr, dG, 0,
-                     acc ? 1 : 0, 1, nullptr, st);
-    if (e != hipSuccess) return APMG_EHIP;
+  hipError_t ec = hipSuccess;
+  if (want_cells)
+    ec = launch_cells(s, gf16, m->G, 0, m->F, 0, w.srt, n, w.cell, dF, 0, acc ? 1 : 0, dG != nullptr, dG, 0,
+                      acc ? 1 : 0, 1, nullptr, st);
+  hipError_t ej = hipSuccess;
+  if (pst != st) {
+    ej = hipEventRecord(side->join, pst);
+    if (ej == hipSuccess) ej = hipStreamWaitEvent(st, side->join, 0);
   }
+  if (ec != hipSuccess || ej != hipSuccess) return APMG_EHIP;
   return hip_status(hipGetLastError());
 }
 
@@ -787,28 +826,6 @@ apmg_status check_batch(const apmg_batch* b, Shape* s) {
 }
 
 // The phases of one training step; `update` adds the Adam updates and counter increments.
-// A side stream per device (default priority, non-blocking) and its fork/join events,
-// created on the first training step that runs on that device outside graph capture; a
-// step captured before that runs all its phases on the caller's stream.
-struct SideStream { hipStream_t s = nullptr; hipEvent_t fork = nullptr, join = nullptr; bool ok = false; };
-constexpr int kMaxDevices = 64;
-std::mutex g_side_mu;
-SideStream g_side[kMaxDevices];
-SideStream* side_stream(hipStream_t st) {
-  int dev = 0;
-  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return nullptr;
-  SideStream& ss = g_side[dev];
-  if (!ss.ok) {
-    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
-    if (hipStreamIsCapturing(st, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) return nullptr;
-    if (!ss.s && hipStreamCreateWithFlags(&ss.s, hipStreamNonBlocking) != hipSuccess) { ss.s = nullptr; return nullptr; }
-    if (!ss.fork && hipEventCreateWithFlags(&ss.fork, hipEventDisableTiming) != hipSuccess) { ss.fork = nullptr; return nullptr; }
-    if (!ss.join && hipEventCreateWithFlags(&ss.join, hipEventDisableTiming) != hipSuccess) { ss.join = nullptr; return nullptr; }
-    ss.ok = true;
-  }
-  return &ss;
-}
-
 apmg_status run_step(const apmg_batch* b, const Shape& s, void* ws, const Tune& tu, bool update, hipStream_t st) {
   const bool bf = b->shape.mlp_dtype == APMG_BF16, gf16 = b->shape.grid_dtype == APMG_F16;
   const int nb = b->nb;
