@@ -264,6 +264,58 @@ def backward(model, x, df, cache=None):
     return {"dF": dF, "dG": dG, "dW": dW, "dy": dy.reshape(N, M * C)}
 
 
+def backward_magnitudes(model, x, df, cache=None, open_units=None):
+    """Per gradient entry, the sum of the absolute values of the terms that backward()
+    adds up: the same chain rule with every factor replaced by its absolute value.
+
+    These sums set the scale of the float32 rounding error of each entry of a gradient
+    that is reduced in float32 (the "noise level" of the rule for comparing Adam's
+    first updates).  Two more sums cover the float32 encoder, whose corner weights carry
+    an absolute error of a few (R-1) 2^-24 (u = (l + 1)(R-1)/2 is held to float32):
+      dF_unit  per vertex, sum |dL/dy| over the points of its cells (weights taken as 1);
+      dW_fabs  dW's sums with the features replaced by the interpolation of |F| (an upper
+               bound of |y| and the scale of its float32 error).
+    open_units: optional list, per hidden layer, of [N, H] boolean masks of units whose
+    ReLU derivative is taken as 1 whatever the sign of the pre-activation -- an envelope
+    of a point whose ReLU decisions a float32 forward pass may take either way.
+    Returns dict dF [M,C,R,R,R], dF_unit, dW list, dW_fabs list.
+    """
+    if cache is None:
+        _, cache = forward(model, x)
+    F = np.asarray(model["F"], np.float64)
+    M, C = F.shape[0], F.shape[1]
+    W = [np.abs(np.asarray(w, np.float64)) for w in model["W"]]
+    enc, z, a = cache["enc"], cache["z"], cache["a"]
+    xs = cache["x"]
+    N = xs.shape[0]
+    y_fabs = encode(model["G"], np.abs(F), xs)["y"]
+    scale = abs(float(model["vmax"]) - float(model["vmin"]))
+    delta = np.abs(np.asarray(df, np.float64) * scale)[:, None]
+    dW = [None] * len(W)
+    dW_fabs = [None] * len(W)
+    for k in range(len(W) - 1, -1, -1):
+        dW[k] = delta.T @ np.abs(a[k])
+        dW_fabs[k] = delta.T @ (y_fabs if k == 0 else np.abs(a[k]))
+        if k > 0:
+            on = z[k - 1] > 0.0
+            if open_units is not None:
+                on = on | open_units[k - 1]
+            delta = (delta @ W[k]) * on
+    dy = (delta @ W[0]).reshape(N, M, C)
+    dy = np.where(enc["inside"][..., None], dy, 0.0)
+    i0, cw = enc["i0"], _corner_weights(enc["w"])
+    dF = np.zeros_like(F)
+    dF_unit = np.zeros_like(F)
+    gidx = np.broadcast_to(np.arange(M)[None, :], (N, M))
+    for q in range(8):
+        a_, b_, c_ = q & 1, (q >> 1) & 1, (q >> 2) & 1
+        zi, yi, xi = i0[..., 2] + c_, i0[..., 1] + b_, i0[..., 0] + a_
+        for c in range(C):
+            np.add.at(dF, (gidx, c, zi, yi, xi), np.abs(cw[..., q]) * dy[..., c])
+            np.add.at(dF_unit, (gidx, c, zi, yi, xi), dy[..., c])
+    return {"dF": dF, "dF_unit": dF_unit, "dW": dW, "dW_fabs": dW_fabs}
+
+
 # --------------------------------------------------------------------------
 # Feature density and its loss: Sec. 4.2, Eqs. (7)-(9)
 # --------------------------------------------------------------------------
@@ -287,15 +339,21 @@ def _cofactor3(A):
     return cof
 
 
-def density_terms(G, x, p=P_FLATTOP, s_max=S_MAX_F64):
+def density_terms(G, x, p=P_FLATTOP, s_max=S_MAX_F64, abs_det=False):
     """Eq. (7): rho(x) = sum_i det(G_i[0:3,0:3]) exp(-sum_d l_d^{2p}).
 
     Reading: the determinant is signed, as written; no 1/2 or normaliser
     (Eq. (7) drops those of Eq. (6)); exp(-s) is exactly 0 when s > s_max or
-    s is NaN.  Returns (rho [N], phi [N, M], l [N, M, 3], det [M]).
+    s is NaN.  With abs_det the alternative reading |det| is used instead: a
+    grid's density is the number of its cells per unit of global volume
+    (Sec. 4.2), which does not change sign when the grid is reflected.
+    Returns (rho [N], phi [N, M], l [N, M, 3], det [M]) where det is the
+    factor actually used (signed or absolute).
     """
     G = np.asarray(G, np.float64)
     det = _det3(G[:, :3, :3])
+    if abs_det:
+        det = np.abs(det)
     l = local_coords(G, x)
     with np.errstate(over="ignore", invalid="ignore"):
         s = np.sum(l ** (2 * p), axis=-1)
@@ -305,7 +363,8 @@ def density_terms(G, x, p=P_FLATTOP, s_max=S_MAX_F64):
     return rho, phi, l, det
 
 
-def density_loss(G, x, h, eps=EPS_DENSITY, p=P_FLATTOP, s_max=S_MAX_F64):
+def density_loss(G, x, h, eps=EPS_DENSITY, p=P_FLATTOP, s_max=S_MAX_F64, abs_det=False,
+                 norm_target=False):
     """Eqs. (8)-(9) and the gradient of L_density with respect to G.
 
     h [N] is the per-point model error h(x).  Readings:
@@ -314,10 +373,14 @@ def density_loss(G, x, h, eps=EPS_DENSITY, p=P_FLATTOP, s_max=S_MAX_F64):
       * L = (1/N) sum rho* (log rho* - log(rho_scaled + eps)), the same eps
         inside the second log as in Eq. (8), and 0*log 0 := 0.      (Eq. (9))
       * rho* is a target: it is held constant in the gradient.
-    The gradient uses a(x) = dL/drho_scaled(x) = -rho*/(N (rho_scaled+eps)),
+    Alternative readings behind flags: abs_det takes |det| in Eq. (7) (see
+    density_terms); norm_target replaces rho* by rho* / sum_X rho* in Eq. (9),
+    so that both arguments of the divergence sum to one over the batch.
+    The gradient uses a(x) = dL/drho_scaled(x) = -target/(N (rho_scaled+eps)),
     Q = sum_x a rho_scaled, dL/drho(y) = (a(y) - Q)/S, chained through
-      d rho_i/dA = exp(-s_i) cof(A_i) - rho_i 2p (l^{2p-1}) x^T,
-      d rho_i/dt = -rho_i 2p l^{2p-1}.
+      d rho_i/dA = sgn exp(-s_i) cof(A_i) - rho_i 2p (l^{2p-1}) x^T,
+      d rho_i/dt = -rho_i 2p l^{2p-1},
+    with sgn = 1 (signed det) or sign(det(A_i)) (abs_det).
     Returns dict loss, dG [M,3,4], rho, rho_s, rho_star, S, h_bar.
     """
     G = np.asarray(G, np.float64)
@@ -328,7 +391,7 @@ def density_loss(G, x, h, eps=EPS_DENSITY, p=P_FLATTOP, s_max=S_MAX_F64):
     if N == 0:
         return {"loss": 0.0, "dG": np.zeros((M, 3, 4)), "rho": np.zeros(0),
                 "rho_s": np.zeros(0), "rho_star": np.zeros(0), "S": 0.0, "h_bar": 0.0}
-    rho, phi, l, det = density_terms(G, x, p, s_max)
+    rho, phi, l, det = density_terms(G, x, p, s_max, abs_det)
     S = rho.sum()
     if S == 0.0:
         # Reading: no grid has density at any point of the batch; the
@@ -340,13 +403,20 @@ def density_loss(G, x, h, eps=EPS_DENSITY, p=P_FLATTOP, s_max=S_MAX_F64):
     h_bar = h.mean()
     log_target = h_bar / (h + eps) * np.log(rho_s + eps)
     rho_star = np.exp(log_target)
-    terms = np.where(rho_star > 0.0, rho_star * (log_target - np.log(rho_s + eps)), 0.0)
+    target = rho_star
+    if norm_target:
+        Z = rho_star.sum()
+        target = rho_star / Z
+        log_target = log_target - np.log(Z)
+    terms = np.where(target > 0.0, target * (log_target - np.log(rho_s + eps)), 0.0)
     loss = terms.sum() / N
 
-    a = -rho_star / (N * (rho_s + eps))
+    a = -target / (N * (rho_s + eps))
     Q = np.sum(a * rho_s)
     dLdrho = (a - Q) / S                                     # [N]
     cof = _cofactor3(G[:, :3, :3])                           # [M, 3, 3]
+    if abs_det:
+        cof = cof * np.sign(_det3(G[:, :3, :3]))[:, None, None]
     rho_i = phi * det[None, :]                               # [N, M]
     with np.errstate(over="ignore", invalid="ignore"):
         q = np.where(phi[..., None] > 0.0, l ** (2 * p - 1), 0.0)   # [N, M, 3]
@@ -358,24 +428,25 @@ def density_loss(G, x, h, eps=EPS_DENSITY, p=P_FLATTOP, s_max=S_MAX_F64):
                     - np.einsum("nm,nmr,nk->mrk", coef, q, xs))
     dG[:, :, 3] = -np.einsum("nm,nmr->mr", coef, q)
     return {"loss": loss, "dG": dG, "rho": rho, "rho_s": rho_s, "rho_star": rho_star,
-            "S": S, "h_bar": h_bar, "Q": Q, "a": a}
+            "target": target, "S": S, "h_bar": h_bar, "Q": Q, "a": a}
 
 
-def density_grad_bruteforce(G, x, h, eps=EPS_DENSITY, p=P_FLATTOP):
+def density_grad_bruteforce(G, x, h, eps=EPS_DENSITY, p=P_FLATTOP, abs_det=False, norm_target=False):
     """The literal double sum sum_x sum_y dL/drho_s(x) drho_s(x)/drho(y) drho(y)/dG.
 
-    O(N^2): for tiny N only.  rho* held constant, as in density_loss().
+    O(N^2): for tiny N only.  The target held constant, as in density_loss().
     """
     G = np.asarray(G, np.float64)
     x = np.asarray(x, np.float64)
     N, M = x.shape[0], G.shape[0]
-    res = density_loss(G, x, h, eps, p)
-    rho, rho_s, rho_star, S = res["rho"], res["rho_s"], res["rho_star"], res["S"]
-    _, phi, l, det = density_terms(G, x, p)
+    res = density_loss(G, x, h, eps, p, abs_det=abs_det, norm_target=norm_target)
+    rho, rho_s, target, S = res["rho"], res["rho_s"], res["target"], res["S"]
+    _, phi, l, det = density_terms(G, x, p, abs_det=abs_det)
     cof = _cofactor3(G[:, :3, :3])
+    sgn = np.sign(_det3(G[:, :3, :3])) if abs_det else np.ones(M)
     dG = np.zeros((M, 3, 4))
     for xi in range(N):
-        dL_drhos = -rho_star[xi] / (N * (rho_s[xi] + eps))
+        dL_drhos = -target[xi] / (N * (rho_s[xi] + eps))
         for yi in range(N):
             drhos_drho = ((1.0 if xi == yi else 0.0) / S) - rho[xi] / S ** 2
             for i in range(M):
@@ -384,7 +455,7 @@ def density_grad_bruteforce(G, x, h, eps=EPS_DENSITY, p=P_FLATTOP):
                 for r in range(3):
                     qr = l[yi, i, r] ** (2 * p - 1)
                     for k in range(3):
-                        g[r, k] = phi[yi, i] * cof[i, r, k] - rho_i * 2 * p * qr * x[yi, k]
+                        g[r, k] = sgn[i] * phi[yi, i] * cof[i, r, k] - rho_i * 2 * p * qr * x[yi, k]
                     g[r, 3] = -rho_i * 2 * p * qr
                 dG[i] += dL_drhos * drhos_drho * g
     return dG
@@ -590,7 +661,7 @@ def brick_gt_sample(volume_zyx, brick, l):
 
 def train_step(model, state, x, v, density_active, add_rec_dG=False,
                eps=EPS_DENSITY, p=P_FLATTOP, lr=LR_DEFAULT, lr_G=LR_TRANSFORM,
-               betas=ADAM_BETAS, adam_eps=ADAM_EPS):
+               betas=ADAM_BETAS, adam_eps=ADAM_EPS, abs_det=False, norm_target=False):
     """Part (1): L_rec updates F and the MLP.  Part (2), when the density phase
     is active: L_density updates G only (L_rec gives G no gradient; its dG is
     added only when add_rec_dG is set).
@@ -619,7 +690,7 @@ def train_step(model, state, x, v, density_active, add_rec_dG=False,
         vWs.append(v_)
     new_model["W"], new_state["mW"], new_state["vW"] = Ws, mWs, vWs
     if density_active:
-        d = density_loss(model["G"], x, h, eps, p)
+        d = density_loss(model["G"], x, h, eps, p, abs_det=abs_det, norm_target=norm_target)
         info["L_density"] = d["loss"]
         info["dG_density"] = d["dG"]
         dG = d["dG"] + (g["dG"] if add_rec_dG else 0.0)

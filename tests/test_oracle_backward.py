@@ -5,6 +5,8 @@ are linear per axis inside a cell, transforms are affine, ReLU is piecewise
 linear), so central finite differences are exact up to rounding unless the
 stencil crosses a kink; crossings are detected and skipped."""
 import numpy as np
+
+import synth
 import torch
 
 from oracle import apmg_oracle as O
@@ -146,3 +148,31 @@ def test_outside_points_give_no_gradient():
     x = np.array([[3.0, 0.0, 0.0], [0.0, -2.5, 0.1], [np.nan, 0.2, 0.1]])
     g = O.backward(model, x, np.ones(3))
     assert np.all(g["dF"] == 0) and np.all(g["dG"] == 0)
+
+
+def test_backward_magnitudes_bound_and_equal_the_gradient_when_signs_agree():
+    rng = np.random.default_rng(60)
+    host = synth.init_model(3, 2, 4, [6, 8, 8, 1], seed=61, grid_range=0.5)
+    model = {"G": host["G"].astype(np.float64), "F": host["F"].astype(np.float64),
+             "W": [w.astype(np.float64) for w in host["W"]], "vmin": -1.0, "vmax": 2.0}
+    x = rng.uniform(-0.9, 0.9, size=(40, 3))
+    df = rng.normal(size=40)
+    g = O.backward(model, x, df)
+    mag = O.backward_magnitudes(model, x, df)
+    assert np.all(mag["dF"] >= np.abs(g["dF"]) - 1e-15)
+    for a, b in zip(mag["dW"], g["dW"]):
+        assert np.all(a >= np.abs(b) - 1e-15)
+    # opening every unit can only enlarge the envelope
+    _, cache = O.forward(model, x)
+    opened = O.backward_magnitudes(model, x, df, cache,
+                                   open_units=[np.ones_like(z, bool) for z in cache["z"][:-1]])
+    assert np.all(opened["dF"] >= mag["dF"] - 1e-15)
+    # one point, positive grids, weights and dL/df: every term is positive, so the sums of
+    # absolute values are the gradient itself
+    pos = dict(model, F=np.abs(model["F"]) + 0.1, W=[np.abs(w) + 0.01 for w in model["W"]], vmin=0.0, vmax=1.0)
+    x1 = np.array([[0.05, -0.1, 0.2]])
+    g1 = O.backward(pos, x1, np.array([0.7]))
+    m1 = O.backward_magnitudes(pos, x1, np.array([0.7]))
+    np.testing.assert_allclose(m1["dF"], g1["dF"], rtol=1e-14, atol=0)
+    for a, b in zip(m1["dW"], g1["dW"]):
+        np.testing.assert_allclose(a, b, rtol=1e-14, atol=0)

@@ -153,3 +153,113 @@ def test_all_points_outside_every_grid_is_zero():
     x = np.array([[0.9, 0.9, 0.9], [-0.8, 0.7, 0.95]])
     r = O.density_loss(G, x, np.array([0.1, 0.2]))
     assert r["loss"] == 0.0 and np.all(r["dG"] == 0)
+
+
+# ---------------------------------------------------------------- alternative readings
+# |det| in Eq. (7) (abs_det) and a target renormalised over the batch in Eq. (9)
+# (norm_target); the literal reading stays the default of every function.
+
+def _reflect_x(G):
+    """The same grid placement with its local x axis reversed: l' = diag(-1,1,1) l."""
+    Gr = G.copy()
+    Gr[:, 0, :] = -Gr[:, 0, :]
+    return Gr
+
+
+def test_abs_det_reflected_grid_has_the_same_density():
+    rng = np.random.default_rng(40)
+    G = _scaled_identity(1.2, M=3) + rng.normal(0, 0.1, (3, 3, 4))
+    x = rng.uniform(-1, 1, size=(100, 3))
+    Gr = _reflect_x(G)
+    rho_a, _, _, det_a = O.density_terms(G, x, abs_det=True)
+    rho_r, _, _, det_r = O.density_terms(Gr, x, abs_det=True)
+    np.testing.assert_allclose(rho_r, rho_a, rtol=1e-14)
+    assert np.all(det_a > 0) and np.all(det_r > 0)
+    # the literal (signed) reading negates the reflected grid's density
+    rho_s, _, _, _ = O.density_terms(Gr, x)
+    np.testing.assert_allclose(rho_s, -rho_a, rtol=1e-14)
+    # and the losses agree under |det| (h independent of the placement's handedness)
+    h = rng.uniform(0, 1, 100) ** 2
+    la = O.density_loss(G, x, h, abs_det=True)["loss"]
+    lr_ = O.density_loss(Gr, x, h, abs_det=True)["loss"]
+    np.testing.assert_allclose(lr_, la, rtol=1e-12)
+
+
+def test_abs_det_matches_signed_reading_for_positive_determinants():
+    rng = np.random.default_rng(41)
+    G = _scaled_identity(1.0, M=2) + rng.normal(0, 0.05, (2, 3, 4))
+    assert np.all(np.linalg.det(G[:, :, :3]) > 0)
+    x = rng.uniform(-1, 1, size=(60, 3))
+    h = rng.uniform(0, 1, 60) ** 2
+    r0 = O.density_loss(G, x, h)
+    r1 = O.density_loss(G, x, h, abs_det=True)
+    np.testing.assert_allclose(r1["loss"], r0["loss"], rtol=1e-14)
+    np.testing.assert_allclose(r1["dG"], r0["dG"], rtol=1e-13, atol=1e-16)
+
+
+def test_alternative_readings_uniform_error_gives_zero_loss_and_gradient():
+    rng = np.random.default_rng(42)
+    G = _scaled_identity(1.0, M=3) + rng.normal(0, 0.1, (3, 3, 4))
+    G = _reflect_x(G)                                       # negative determinants
+    x = rng.uniform(-1, 1, size=(64, 3))
+    h = np.full(64, 0.37)
+    for abs_det, norm in ((True, False), (False, True), (True, True)):
+        r = O.density_loss(G, x, h, eps=0.0, abs_det=abs_det, norm_target=norm)
+        assert abs(r["loss"]) < 1e-15, (abs_det, norm)
+        assert np.max(np.abs(r["dG"])) < 1e-13, (abs_det, norm)
+
+
+def test_normalised_target_loss_is_a_divergence():
+    # with eps = 0 both arguments sum to one over the batch: Gibbs' inequality gives L >= 0,
+    # and L equals the batch KL written out directly
+    rng = np.random.default_rng(43)
+    G = _scaled_identity(1.0, M=4) + rng.normal(0, 0.1, (4, 3, 4))
+    x = rng.uniform(-1, 1, size=(80, 3))
+    for trial in range(5):
+        h = rng.uniform(0, 1, 80) ** (1 + trial)
+        r = O.density_loss(G, x, h, eps=0.0, norm_target=True)
+        tn = r["target"]
+        np.testing.assert_allclose(tn.sum(), 1.0, rtol=1e-14)
+        pos = tn > 0.0                                       # 0 log 0 = 0
+        kl = np.sum(tn[pos] * np.log(tn[pos] / r["rho_s"][pos])) / 80
+        np.testing.assert_allclose(r["loss"], kl, rtol=1e-12)
+        assert r["loss"] >= 0.0
+
+
+def test_alternative_readings_single_pass_gradient_equals_bruteforce():
+    rng = np.random.default_rng(44)
+    G = _scaled_identity(1.0, M=3) + rng.normal(0, 0.15, (3, 3, 4))
+    G[1] = _reflect_x(G[1:2])[0]                             # one grid with det < 0
+    x = rng.uniform(-1, 1, size=(7, 3))
+    h = rng.uniform(0, 1, 7) ** 2
+    for abs_det, norm in ((True, False), (False, True), (True, True)):
+        r = O.density_loss(G, x, h, eps=1e-6, abs_det=abs_det, norm_target=norm)
+        bf = O.density_grad_bruteforce(G, x, h, eps=1e-6, abs_det=abs_det, norm_target=norm)
+        np.testing.assert_allclose(r["dG"], bf, rtol=1e-11, atol=1e-14)
+
+
+def test_alternative_readings_match_torch_autograd_with_detached_target():
+    rng = np.random.default_rng(45)
+    M, N, eps = 3, 40, 1e-9
+    G = _scaled_identity(1.0, M=M) + rng.normal(0, 0.1, (M, 3, 4))
+    G[0] = _reflect_x(G[0:1])[0]
+    x = rng.uniform(-1, 1, size=(N, 3))
+    h = rng.uniform(0, 1, N) ** 2
+    for abs_det, norm in ((True, False), (False, True), (True, True)):
+        r = O.density_loss(G, x, h, eps=eps, abs_det=abs_det, norm_target=norm)
+        Gt = torch.tensor(G, requires_grad=True)
+        xt, ht = torch.tensor(x), torch.tensor(h)
+        l = torch.einsum("mrk,nk->nmr", Gt[:, :, :3], xt) + Gt[None, :, :, 3]
+        det = torch.linalg.det(Gt[:, :, :3])
+        det = det.abs() if abs_det else det
+        rho = (det[None] * torch.exp(-(l ** 20).sum(-1))).sum(-1)
+        rs = rho / rho.sum()
+        target = torch.exp(ht.mean() / (ht + eps) * torch.log(rs + eps)).detach()
+        if norm:
+            target = target / target.sum()
+        safe = torch.where(target > 0, target, torch.ones_like(target))
+        L = torch.where(target > 0, target * (torch.log(safe) - torch.log(rs + eps)),
+                        torch.zeros_like(target)).mean()
+        L.backward()
+        np.testing.assert_allclose(r["loss"], L.item(), rtol=1e-12)
+        np.testing.assert_allclose(r["dG"], Gt.grad.numpy(), rtol=1e-9, atol=1e-14)
