@@ -32,12 +32,20 @@
  *   kernels).
  * - Points are structure-of-arrays: x at pts[0..n), y at pts[ld..ld+n),
  *   z at pts[2*ld..2*ld+n), with ld >= n.
- * - Grids are stored channel-last, [M][R][R][R][C] with axes (z, y, x, c),
- *   x fastest over vertices: F[i, c, z, y, x] of the paper's [M, C, D, H, W]
- *   tensor is at ((i*R + z)*R + y)*R + x)*C + c.  apmg_convert_grids()
- *   converts from and to the paper's [M][C][R][R][R] order.
- * - Transforms are the 12 free entries of each 4x4 matrix, [M][3][4]
- *   row-major float32 (row 3 is fixed to (0,0,0,1) by Eq. (1)).
+ * - Grids are the paper's encoder tensor [M, C, D, H, W] (Sec. 4.1.1) with
+ *   D = H = W = R, axes (z, y, x), x fastest: F[i, c, z, y, x] is at
+ *   (((i*C + c)*R + z)*R + y)*R + x (model.grid_layout = APMG_GRIDS_MCRRR,
+ *   the default).  Grid gradients are returned in the same order.  The
+ *   kernels gather from a channel-last mirror [M][R][R][R][C] (an x-adjacent
+ *   vertex pair is 2C contiguous values); with the default layout every call
+ *   builds that mirror in its workspace.  A caller that keeps its grids
+ *   channel-last already may say so with APMG_GRIDS_MRRRC (then F, and dF,
+ *   are [M][R][R][R][C]) and skip the copy; apmg_convert_grids() converts
+ *   between the two orders.
+ * - Transforms are the matrices of Eq. (1), float32 row-major: [M][3][4]
+ *   (rows 0..2, model.G_rows = 3, the default) or the full [M][4][4]
+ *   (model.G_rows = 4; row 3 is (0,0,0,1) by Eq. (1) and is never read).
+ *   Transform gradients are returned in the same shape (row 3 written as 0).
  * - MLP weights W_k are [width[k+1]][width[k]] row-major float32 (the
  *   master copy); mlp_dtype selects the arithmetic of the matrix products.
  * - Status: APMG_EINVAL for a NULL required pointer, n < 0, ld < n, or an
@@ -75,15 +83,32 @@ typedef enum { APMG_F32 = 0, APMG_F16 = 1, APMG_BF16 = 2 } apmg_dtype;
 
 /* flags */
 #define APMG_ACCUMULATE     0x1u  /* add into the outputs instead of overwriting them */
-#define APMG_DETERMINISTIC  0x2u  /* accepted; every reduction already has a fixed order */
+#define APMG_DETERMINISTIC  0x2u  /* reserved: accepted and ignored, since every reduction of
+                                     the library already runs in a fixed order (bitwise
+                                     reproducible results for a given launch shape) */
 #define APMG_ADD_REC_DG     0x4u  /* training step: add L_rec's transform gradient to L_density's */
 #define APMG_ERR_ABS        0x8u  /* training step: h(x) = |f - v| instead of (f - v)^2 */
+/* Readings of the feature density other than the literal one (apmg_density_loss and the
+ * training step).  Eq. (7) as printed weights grid i by its signed det(A_i); Sec. 4.2
+ * describes that factor as the grid's density, which grows as the grid shrinks and does
+ * not depend on its handedness:
+ *   APMG_DENSITY_ABS_DET: rho_i = |det(A_i)| exp(-sum_d l_d^{2p}).
+ * Eq. (9) compares an unnormalised target with the normalised rho_scaled:
+ *   APMG_DENSITY_NORM_TARGET: the target is rho* / sum_X rho*, so that both arguments
+ *   of the divergence sum to one over the batch. */
+#define APMG_DENSITY_ABS_DET     0x10u
+#define APMG_DENSITY_NORM_TARGET 0x20u
+
+/* grid layouts (apmg_model.grid_layout) */
+#define APMG_GRIDS_MCRRR 0   /* [M][C][R][R][R], the paper's order (default) */
+#define APMG_GRIDS_MRRRC 1   /* [M][R][R][R][C], channel-last */
 
 #define APMG_MAX_LAYERS 8
 
 /* One APMGSRN.  Supported by the built kernels: C in {1, 2, 4}; M*C <= 256;
  * n_layers == 3 with width = {M*C, H, H, 1} and H in {64, 128};
- * grid_dtype F32 or F16; mlp_dtype F32 or BF16. */
+ * grid_dtype F32 or F16; mlp_dtype F32 or BF16.  A zero-initialised struct
+ * has the default layouts (paper-order grids, [M][3][4] transforms). */
 typedef struct apmg_model {
   int32_t M;                        /* number of feature grids (>= 1) */
   int32_t C;                        /* feature channels per grid (>= 1) */
@@ -92,10 +117,12 @@ typedef struct apmg_model {
   int32_t width[APMG_MAX_LAYERS + 1]; /* width[0] = M*C, width[n_layers] = 1 */
   int32_t grid_dtype;               /* apmg_dtype of F */
   int32_t mlp_dtype;                /* apmg_dtype of the MLP products (F32 or BF16, fp32 accumulate) */
-  const float* G;                   /* [M][3][4] transforms, global -> local (Eq. (1)) */
-  const void* F;                    /* [M][R][R][R][C] grids, grid_dtype */
+  const float* G;                   /* [M][G_rows][4] transforms, global -> local (Eq. (1)) */
+  const void* F;                    /* grids in grid_layout order, grid_dtype */
   const float* W[APMG_MAX_LAYERS];  /* W_k: [width[k+1]][width[k]], no biases */
   float vmin, vmax;                 /* output scaling, Sec. 4.1.2 "Scaling" */
+  int32_t grid_layout;              /* APMG_GRIDS_MCRRR (0, default) or APMG_GRIDS_MRRRC */
+  int32_t G_rows;                   /* rows stored per transform: 3 (0 = 3, default) or 4 */
 } apmg_model;
 
 /* ---------------------------------------------------------------- forward
@@ -112,8 +139,10 @@ apmg_status apmg_forward(const apmg_model* model, const float* pts, int64_t ld, 
  * (ReLU'(0) = 0; the mask of Eq. (2) contributes no gradient; at a vertex
  * the one-sided derivative of the selected cell).
  *   df: [n] float32, dL/df.
- *   dF: [M][R][R][R][C] float32 (also when grids are F16) or NULL.
- *   dG: [M][3][4] float64 or NULL (gradient through the trilinear weights).
+ *   dF: float32 grids in model.grid_layout order (also when grids are F16),
+ *       or NULL.
+ *   dG: [M][G_rows][4] float64 or NULL (gradient through the trilinear
+ *       weights).
  *   dW: host array of n_layers device pointers, each [width[k+1]][width[k]]
  *       float32, or NULL for no MLP gradient.
  * Outputs are overwritten unless APMG_ACCUMULATE.  The points are first
@@ -138,9 +167,12 @@ apmg_status apmg_backward(const apmg_model* model, const float* pts, int64_t ld,
  * dG = d loss / dG with rho* held constant.  If sum_X rho == 0 the loss and
  * gradient are 0.
  *   err: [n] float32, the per-point error h(x).
- *   loss: [1] float64 output.  dG: [M][3][4] float64 or NULL.
+ *   loss: [1] float64 output.  dG: [M][G_rows][4] float64 or NULL.
  *   rho: [n] float32 output of Eq. (7), or NULL.
- * flags: APMG_ACCUMULATE adds into dG (loss is always overwritten).
+ * flags: APMG_ACCUMULATE adds into dG (loss is always overwritten);
+ * APMG_DENSITY_ABS_DET and APMG_DENSITY_NORM_TARGET select the alternative
+ * readings defined with the flags (the gradient of |det| is sign(det) times
+ * the cofactor matrix; the renormalised target is held constant too).
  * Per-point arithmetic is float32; all sums over points are float64. */
 apmg_status apmg_density_loss(const apmg_model* model, const float* pts, int64_t ld, int64_t n,
                               const float* err, double eps, int32_t p,
@@ -195,9 +227,9 @@ apmg_status apmg_assign_bricks(const apmg_brick_table* table, const float* pts, 
  * EINVAL also when nb != I*J*K of the table. */
 typedef struct apmg_dd_models {
   int32_t nb;                 /* models, one per brick, in brick-id order */
-  apmg_model shape;           /* M, C, R, n_layers, width, dtypes; pointers ignored */
-  const float* G;             /* [nb][M][3][4] */
-  const void* F;              /* [nb][M][R][R][R][C] in shape.grid_dtype */
+  apmg_model shape;           /* M, C, R, n_layers, width, dtypes, layouts; pointers ignored */
+  const float* G;             /* [nb][M][G_rows][4] */
+  const void* F;              /* [nb] grids in shape.grid_layout order, shape.grid_dtype */
   const float* W;             /* [nb][layers concatenated] float32 */
   const apmg_brick* bricks;   /* [nb] device: extended extents, vmin, vmax */
 } apmg_dd_models;
@@ -210,16 +242,24 @@ apmg_status apmg_dd_forward(const apmg_dd_models* models, const apmg_brick_table
  * one shape, each trained on its own brick of one volume (nb = 1 with one
  * brick spanning the volume is the single-model step).  For every model b:
  *   1. n uniform points in [-1,1)^3 from Philox4x64-10 (counter
- *      (j, step, b, 0), key (seed, 0x41504D47); coordinate = (w >> 40) 2^-23 - 1);
+ *      (j, step, stream0 + b, 0), key (seed, 0x41504D47); coordinate =
+ *      (w >> 40) 2^-23 - 1);
  *   2. v = trilinear sample of brick b's extended sub-volume;
  *   3. forward, L_rec = mean (f - v)^2, h = (f - v)^2 (or |f - v|);
  *   4. adjoint of L_rec into F and W;
  *   5. if density_active[b]: L_density and its transform gradient (+ L_rec's
  *      transform gradient under APMG_ADD_REC_DG);
  *   6. Adam (bias-corrected, float32 master weights): F and W with lr, every
- *      step; G with lr_G, only when density_active[b]; writes the F16 grid
- *      shadow when grid_dtype is F16.
+ *      step; G with lr_G, only when density_active[b].
  *   7. *step += 1 (device counter; a captured graph replays fresh batches).
+ * Grids F (and the moments mF, vF) are float32 master copies in
+ * shape.grid_layout order.  With grid_dtype F16 the encoder gathers from an
+ * F16 copy of the masters (round to nearest) that the step builds in its
+ * workspace at its start, while gradients and Adam stay float32; the same
+ * copy holds the channel-last mirror of paper-order grids.  Transforms are
+ * [nb][M][3][4] (shape.G_rows must be 3 or 0).
+ * flags: APMG_ADD_REC_DG, APMG_ERR_ABS, APMG_DENSITY_ABS_DET,
+ * APMG_DENSITY_NORM_TARGET.
  * All per-model arrays are contiguous arenas indexed by model: model b's
  * block starts at b * (block size).  Adam moments and counters are device
  * memory the caller zero-initialises.
@@ -260,8 +300,7 @@ typedef struct apmg_batch {
   int32_t nb;                 /* number of models */
   apmg_model shape;           /* M, C, R, n_layers, width, dtypes; pointers ignored */
   float* G;                   /* [nb][M][3][4] */
-  float* F;                   /* [nb][M][R][R][R][C] float32 master grids */
-  void* F_lowp;               /* [nb][M][R][R][R][C] F16 shadow (grid_dtype F16) or NULL */
+  float* F;                   /* [nb] float32 master grids in shape.grid_layout order */
   float* W;                   /* [nb][sum_k width[k+1]*width[k]], layers concatenated */
   float* mG; float* vG;       /* Adam moments, shapes of G */
   float* mF; float* vF;       /* shapes of F */
@@ -283,6 +322,9 @@ typedef struct apmg_batch {
   const apmg_tuning* tuning;  /* HOST pointer, read when the call is made; NULL = defaults */
   const int32_t* frozen;      /* [nb] or NULL: 1 = model retired, nothing of it changes */
   const float* lr_scale;      /* [nb] or NULL: multiplies lr and lr_G of each model */
+  uint32_t stream0;           /* model b draws its points from counter stream stream0 + b: a
+                                 subset of bricks stepped on its own (say one of several
+                                 devices) draws the same points as in the whole batch */
 } apmg_batch;
 
 apmg_status apmg_batched_step(const apmg_batch* batch, void* ws, size_t ws_bytes,

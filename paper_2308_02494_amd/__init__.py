@@ -25,6 +25,8 @@ _lib = ctypes.CDLL(LIB_PATH)
 OK, EINVAL, EUNSUPPORTED, EWORKSPACE, EHIP = 0, -1, -2, -3, -4
 F32, F16, BF16 = 0, 1, 2
 ACCUMULATE, DETERMINISTIC, ADD_REC_DG, ERR_ABS = 0x1, 0x2, 0x4, 0x8
+DENSITY_ABS_DET, DENSITY_NORM_TARGET = 0x10, 0x20
+GRIDS_MCRRR, GRIDS_MRRRC = 0, 1
 OP_FORWARD, OP_BACKWARD, OP_DENSITY, OP_BATCHED_STEP, OP_DD_FORWARD = 0, 1, 2, 3, 4
 MAX_LAYERS = 8
 
@@ -36,7 +38,8 @@ c_p = ctypes.c_void_p
 class ApmgModel(ctypes.Structure):
     _fields_ = [("M", c_i32), ("C", c_i32), ("R", c_i32), ("n_layers", c_i32),
                 ("width", c_i32 * (MAX_LAYERS + 1)), ("grid_dtype", c_i32), ("mlp_dtype", c_i32),
-                ("G", c_p), ("F", c_p), ("W", c_p * MAX_LAYERS), ("vmin", c_f32), ("vmax", c_f32)]
+                ("G", c_p), ("F", c_p), ("W", c_p * MAX_LAYERS), ("vmin", c_f32), ("vmax", c_f32),
+                ("grid_layout", c_i32), ("G_rows", c_i32)]
 
 
 class ApmgBrick(ctypes.Structure):
@@ -53,13 +56,13 @@ class ApmgTuning(ctypes.Structure):
 
 
 class ApmgBatch(ctypes.Structure):
-    _fields_ = [("nb", c_i32), ("shape", ApmgModel), ("G", c_p), ("F", c_p), ("F_lowp", c_p), ("W", c_p),
+    _fields_ = [("nb", c_i32), ("shape", ApmgModel), ("G", c_p), ("F", c_p), ("W", c_p),
                 ("mG", c_p), ("vG", c_p), ("mF", c_p), ("vF", c_p), ("mW", c_p), ("vW", c_p),
                 ("t", c_p), ("tG", c_p), ("density_active", c_p), ("volume", c_p), ("bricks", c_p),
                 ("vol", c_i32 * 3), ("n", c_i64), ("seed", c_u64), ("step", c_p),
                 ("lr", c_f32), ("lr_G", c_f32), ("beta1", c_f32), ("beta2", c_f32), ("adam_eps", c_f32),
                 ("eps_density", c_f64), ("p", c_i32), ("flags", c_u32), ("losses", c_p),
-                ("tuning", ctypes.POINTER(ApmgTuning)), ("frozen", c_p), ("lr_scale", c_p)]
+                ("tuning", ctypes.POINTER(ApmgTuning)), ("frozen", c_p), ("lr_scale", c_p), ("stream0", c_u32)]
 
 
 class ApmgDdModels(ctypes.Structure):
@@ -136,17 +139,20 @@ def _stream(device):
 
 # ----------------------------------------------------------------------------- model
 class Model:
-    """Device tensors of one APMGSRN in the library's layouts.
+    """Device tensors of one APMGSRN as the paper states the model (Sec. 4.1).
 
-    G [M,3,4] float32 (rows 0..2 of each transform), F [M,R,R,R,C] float32
-    or float16 (channel-last), W = [W1 [H,M*C], W2 [H,H], W3 [1,H]] float32,
-    vmin/vmax floats; mlp_dtype F32 or BF16.
+    G [M,3,4] or [M,4,4] float32 (the transforms of Eq. (1); row 3 of a 4x4 is
+    not read), F [M,C,R,R,R] float32 or float16 (the encoder tensor, axes z, y,
+    x), W = [W1 [H,M*C], W2 [H,H], W3 [1,H]] float32, vmin/vmax floats;
+    mlp_dtype F32 or BF16.  layout=GRIDS_MRRRC says F is channel-last
+    [M,R,R,R,C] instead (the order the kernels gather from).
     """
 
-    def __init__(self, G, F, W, vmin=0.0, vmax=1.0, mlp_dtype=F32):
+    def __init__(self, G, F, W, vmin=0.0, vmax=1.0, mlp_dtype=F32, layout=GRIDS_MCRRR):
         self.G, self.F, self.W = G, F, list(W)
         self.vmin, self.vmax = float(vmin), float(vmax)
         self.mlp_dtype = mlp_dtype
+        self.layout = layout
 
     @property
     def M(self):
@@ -154,11 +160,11 @@ class Model:
 
     @property
     def C(self):
-        return self.F.shape[4]
+        return self.F.shape[1] if self.layout == GRIDS_MCRRR else self.F.shape[4]
 
     @property
     def R(self):
-        return self.F.shape[1]
+        return self.F.shape[2] if self.layout == GRIDS_MCRRR else self.F.shape[1]
 
     def struct(self):
         m = ApmgModel()
@@ -174,15 +180,16 @@ class Model:
         for k, w in enumerate(self.W):
             m.W[k] = w.data_ptr()
         m.vmin, m.vmax = self.vmin, self.vmax
+        m.grid_layout = self.layout
+        m.G_rows = self.G.shape[1]
         return m
 
     @staticmethod
     def from_host(params, device="cuda", grid_dtype=torch.float32, mlp_dtype=F32):
-        """params: dict with G [M,3,4], F [M,C,R,R,R] (the paper's order), W list,
-        vmin, vmax (numpy or torch); converts F to the channel-last layout."""
-        G = torch.as_tensor(params["G"], dtype=torch.float32)[:, :3, :].contiguous().to(device)
-        F = torch.as_tensor(params["F"], dtype=torch.float32).permute(0, 2, 3, 4, 1).contiguous()
-        F = F.to(device=device, dtype=grid_dtype)
+        """params: dict with G [M,3,4] or [M,4,4], F [M,C,R,R,R] (the paper's order), W list,
+        vmin, vmax (numpy or torch), copied to the device as they are."""
+        G = torch.as_tensor(params["G"], dtype=torch.float32).contiguous().to(device)
+        F = torch.as_tensor(params["F"]).contiguous().to(device=device, dtype=grid_dtype)
         W = [torch.as_tensor(w, dtype=torch.float32).contiguous().to(device) for w in params["W"]]
         return Model(G, F, W, float(params.get("vmin", 0.0)), float(params.get("vmax", 1.0)), mlp_dtype)
 
@@ -215,7 +222,8 @@ def apmg_forward(model: Model, pts_soa, n=None, ld=None, out=None, ws=None):
 
 def apmg_backward(model: Model, pts_soa, df, want_dF=True, want_dG=True, want_dW=True, flags=0,
                   n=None, ld=None, dF=None, dG=None, dW=None, ws=None):
-    """Gradients of sum_n df[n] f(x_n): (dF [M,R,R,R,C] f32, dG [M,3,4] f64, [dW1, dW2, dW3])."""
+    """Gradients of sum_n df[n] f(x_n): (dF f32 in F's shape and layout, dG f64 in G's shape,
+    [dW1, dW2, dW3])."""
     n = pts_soa.shape[1] if n is None else n
     ld = pts_soa.shape[1] if ld is None else ld
     dev = model.G.device
@@ -223,7 +231,7 @@ def apmg_backward(model: Model, pts_soa, df, want_dF=True, want_dG=True, want_dW
     if want_dF and dF is None:
         dF = torch.empty(model.F.shape, dtype=torch.float32, device=dev)
     if want_dG and dG is None:
-        dG = torch.empty((model.M, 3, 4), dtype=torch.float64, device=dev)
+        dG = torch.empty(tuple(model.G.shape), dtype=torch.float64, device=dev)
     if want_dW and dW is None:
         dW = [torch.empty_like(w) for w in model.W]
     dw_arr = None
@@ -239,13 +247,14 @@ def apmg_backward(model: Model, pts_soa, df, want_dF=True, want_dG=True, want_dW
 
 def apmg_density_loss(model: Model, pts_soa, err, eps=1e-12, p=10, want_dG=True, want_rho=False, flags=0,
                       n=None, ld=None, ws=None):
-    """(loss [1] f64, dG [M,3,4] f64 or None, rho [n] f32 or None)."""
+    """(loss [1] f64, dG f64 in G's shape or None, rho [n] f32 or None).  flags: ACCUMULATE,
+    DENSITY_ABS_DET, DENSITY_NORM_TARGET."""
     n = pts_soa.shape[1] if n is None else n
     ld = pts_soa.shape[1] if ld is None else ld
     dev = model.G.device
     m = model.struct()
     loss = torch.empty(1, dtype=torch.float64, device=dev)
-    dG = torch.zeros((model.M, 3, 4), dtype=torch.float64, device=dev) if want_dG else None
+    dG = torch.zeros(tuple(model.G.shape), dtype=torch.float64, device=dev) if want_dG else None
     rho = torch.empty(max(n, 1), dtype=torch.float32, device=dev) if want_rho else None
     ws = _workspace(OP_DENSITY, m, n, dev) if ws is None else ws
     _check("apmg_density_loss", _lib.apmg_density_loss(
@@ -325,23 +334,26 @@ def brick_tensor(bricks, device):
 # ----------------------------------------------------------------------------- training step
 class Trainer:
     """Parameters, Adam state and counters of nb brick models, stepped by
-    apmg_batched_step.  Parameters are arenas: G [nb,M,3,4], F [nb,M,R,R,R,C]
-    (float32 master; float16 shadow when grid_dtype is float16), W [nb, sum of
-    layer sizes] (W1, W2, W3 concatenated)."""
+    apmg_batched_step.  Parameters are arenas: G [nb,M,3,4], F [nb,M,C,R,R,R]
+    (float32 masters in the paper's order; with grid_dtype float16 the encoder
+    gathers from an F16 copy the step makes), W [nb, sum of layer sizes] (W1, W2,
+    W3 concatenated).  flags: ADD_REC_DG, ERR_ABS, DENSITY_ABS_DET,
+    DENSITY_NORM_TARGET."""
 
     def __init__(self, models_host, volume, bricks, n, seed=7, mlp_dtype=F32, grid_dtype=torch.float32,
                  lr=0.01, lr_G=0.001, betas=(0.9, 0.99), adam_eps=1e-8, eps_density=1e-12, p=10, flags=0,
-                 device="cuda", control=None, tuning=None):
+                 device="cuda", control=None, tuning=None, stream0=0):
         nb = len(models_host)
         assert nb == len(bricks)
         dev = torch.device(device)
         self.device = dev
+        # the step's transform arena is [nb,M,3,4] (rows 0..2 of each matrix)
         G = torch.stack([torch.as_tensor(mh["G"], dtype=torch.float32)[:, :3, :] for mh in models_host])
-        F = torch.stack([torch.as_tensor(mh["F"], dtype=torch.float32).permute(0, 2, 3, 4, 1) for mh in models_host])
+        F = torch.stack([torch.as_tensor(mh["F"], dtype=torch.float32) for mh in models_host])
         W = torch.stack([torch.cat([torch.as_tensor(w, dtype=torch.float32).reshape(-1) for w in mh["W"]])
                          for mh in models_host])
         self.G, self.F, self.W = G.contiguous().to(dev), F.contiguous().to(dev), W.contiguous().to(dev)
-        self.F_lowp = self.F.to(torch.float16) if grid_dtype == torch.float16 else None
+        self.grid_dtype = grid_dtype
         z = torch.zeros_like
         self.mG, self.vG, self.mF, self.vF = z(self.G), z(self.G), z(self.F), z(self.F)
         self.mW, self.vW = z(self.W), z(self.W)
@@ -353,7 +365,7 @@ class Trainer:
         self.volume = volume
         self.bricks_dev = brick_tensor(bricks, dev)
         self.widths = [models_host[0]["W"][0].shape[1]] + [w.shape[0] for w in models_host[0]["W"]]
-        M, C, R = F.shape[1], F.shape[5], F.shape[2]
+        M, C, R = F.shape[1], F.shape[2], F.shape[3]
         b = ApmgBatch()
         b.nb = nb
         s = b.shape
@@ -363,7 +375,6 @@ class Trainer:
         s.grid_dtype = F16 if grid_dtype == torch.float16 else F32
         s.mlp_dtype = mlp_dtype
         b.G, b.F, b.W = self.G.data_ptr(), self.F.data_ptr(), self.W.data_ptr()
-        b.F_lowp = self.F_lowp.data_ptr() if self.F_lowp is not None else None
         b.mG, b.vG, b.mF, b.vF = self.mG.data_ptr(), self.vG.data_ptr(), self.mF.data_ptr(), self.vF.data_ptr()
         b.mW, b.vW = self.mW.data_ptr(), self.vW.data_ptr()
         b.t, b.tG = self.t.data_ptr(), self.tG.data_ptr()
@@ -382,6 +393,7 @@ class Trainer:
         self.lr_scale = torch.ones(nb, dtype=torch.float32, device=dev)
         b.frozen = self.frozen.data_ptr()
         b.lr_scale = self.lr_scale.data_ptr()
+        b.stream0 = stream0
         self.tuning = None
         self.batch = b
         if tuning is not None:
@@ -456,27 +468,37 @@ class Trainer:
 
 class DDModels:
     """The brick models of a domain decomposition for global-query inference
-    (apmg_dd_forward): arenas G [nb,M,3,4], F [nb,M,R,R,R,C] (float32 or float16),
-    W [nb, layers concatenated], the brick table and the device brick records."""
+    (apmg_dd_forward): arenas G [nb,M,3,4] or [nb,M,4,4], F [nb,M,C,R,R,R] (float32
+    or float16; [nb,M,R,R,R,C] with layout=GRIDS_MRRRC), W [nb, layers concatenated],
+    the brick table and the device brick records."""
 
-    def __init__(self, G, F, W, widths, table, bricks, mlp_dtype=F32):
+    def __init__(self, G, F, W, widths, table, bricks, mlp_dtype=F32, layout=GRIDS_MCRRR):
         self.G, self.F, self.W = G.contiguous(), F.contiguous(), W.contiguous()
         self.table, self.bricks_dev = table, brick_tensor(bricks, G.device)
         d = ApmgDdModels()
         d.nb = G.shape[0]
         sh = d.shape
-        sh.M, sh.C, sh.R, sh.n_layers = G.shape[1], F.shape[5], F.shape[2], len(widths) - 1
+        C, R = (F.shape[2], F.shape[3]) if layout == GRIDS_MCRRR else (F.shape[5], F.shape[2])
+        sh.M, sh.C, sh.R, sh.n_layers = G.shape[1], C, R, len(widths) - 1
         for k, wd in enumerate(widths):
             sh.width[k] = wd
         sh.grid_dtype = F16 if F.dtype == torch.float16 else F32
         sh.mlp_dtype = mlp_dtype
+        sh.grid_layout = layout
+        sh.G_rows = G.shape[2]
         d.G, d.F, d.W, d.bricks = self.G.data_ptr(), self.F.data_ptr(), self.W.data_ptr(), self.bricks_dev.data_ptr()
         self.struct = d
 
     @classmethod
     def from_trainer(cls, tr, table, bricks):
-        F = tr.F_lowp if tr.F_lowp is not None else tr.F
-        return cls(tr.G, F, tr.W, tr.widths, table, bricks, tr.batch.shape.mlp_dtype)
+        """The trainer's models as they were trained: with F16 gathers, the grids are given to
+        inference as their F16 copy (apmg_convert_grids, channel-last)."""
+        if tr.grid_dtype == torch.float16:
+            nb, M, C, R = tr.F.shape[0], tr.F.shape[1], tr.F.shape[2], tr.F.shape[3]
+            Fh = apmg_convert_grids(tr.F.view(nb * M, C, R, R, R), True, torch.float16)
+            return cls(tr.G, Fh.view(nb, M, R, R, R, C), tr.W, tr.widths, table, bricks, tr.batch.shape.mlp_dtype,
+                       GRIDS_MRRRC)
+        return cls(tr.G, tr.F, tr.W, tr.widths, table, bricks, tr.batch.shape.mlp_dtype)
 
 
 def apmg_dd_forward(models, pts_soa, out=None, ws=None):
@@ -502,8 +524,9 @@ def train_control(control, losses):
 class APMGFunction(torch.autograd.Function):
     """f = APMGSRN(pts) with the library's forward and hand-written adjoint.
 
-    apply(pts [N,3], G [M,3,4], F [M,R,R,R,C], W1, W2, W3, vmin, vmax, mlp_dtype)
-    Returns f [N].  Gradients for G (cast from float64), F, W1..W3; none for pts.
+    apply(pts [N,3], G [M,3,4] or [M,4,4], F [M,C,R,R,R], W1, W2, W3, vmin, vmax, mlp_dtype)
+    Returns f [N].  Gradients for G (cast from float64, G's shape, row 3 of a 4x4 zero), F
+    (the paper's order, cast to F's dtype), W1..W3; none for pts.
     """
 
     @staticmethod
@@ -533,24 +556,25 @@ class APMGFunction(torch.autograd.Function):
 
 class DensityLossFunction(torch.autograd.Function):
     """L_density(G) for points pts [N,3] and per-point error err [N] (Eqs. (7)-(9)),
-    with the target density held constant; gradient for G only."""
+    with the target density held constant; gradient for G only ([M,3,4] or [M,4,4]).
+    flags: DENSITY_ABS_DET, DENSITY_NORM_TARGET (alternative readings)."""
 
     @staticmethod
-    def forward(ctx, pts, G, err, eps, p):
+    def forward(ctx, pts, G, err, eps, p, flags=0):
         M = G.shape[0]
-        dummyF = torch.empty((M, 2, 2, 2, 1), dtype=torch.float32, device=G.device)
+        dummyF = torch.empty((M, 1, 2, 2, 2), dtype=torch.float32, device=G.device)
         model = Model(G.contiguous(), dummyF, [torch.empty((64, M), device=G.device),
                                                 torch.empty((64, 64), device=G.device),
                                                 torch.empty((1, 64), device=G.device)])
         loss, dG, _ = apmg_density_loss(model, _soa(pts), err.contiguous().to(torch.float32), eps, p,
-                                        want_dG=G.requires_grad)
+                                        want_dG=G.requires_grad, flags=flags)
         ctx.save_for_backward(dG if dG is not None else torch.empty(0))
         return loss.to(G.dtype)[0]
 
     @staticmethod
     def backward(ctx, g):
         (dG,) = ctx.saved_tensors
-        return None, (g * dG).to(torch.float32), None, None, None
+        return None, (g * dG).to(torch.float32), None, None, None, None
 
 
 def apmg_profile_events(start, stop):

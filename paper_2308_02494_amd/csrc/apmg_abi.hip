@@ -35,6 +35,8 @@ apmg_status check_model(const apmg_model* m, bool need_params, Shape* out) {
     if (!m->G || !m->F) return APMG_EINVAL;
     for (int k = 0; k < m->n_layers; ++k) if (!m->W[k]) return APMG_EINVAL;
   }
+  if (m->grid_layout != APMG_GRIDS_MCRRR && m->grid_layout != APMG_GRIDS_MRRRC) return APMG_EINVAL;
+  if (!(m->G_rows == 0 || m->G_rows == 3 || m->G_rows == 4)) return APMG_EINVAL;
   if (m->grid_dtype != APMG_F32 && m->grid_dtype != APMG_F16) return APMG_EUNSUPPORTED;
   if (m->mlp_dtype != APMG_F32 && m->mlp_dtype != APMG_BF16) return APMG_EUNSUPPORTED;
   if (!(m->C == 1 || m->C == 2 || m->C == 4)) return APMG_EUNSUPPORTED;
@@ -51,6 +53,10 @@ apmg_status check_model(const apmg_model* m, bool need_params, Shape* out) {
   if (out) *out = s;
   return APMG_OK;
 }
+
+inline int g_rows(const apmg_model* m) { return m->G_rows == 4 ? 4 : 3; }
+inline bool paper_grids(const apmg_model* m) { return m->grid_layout == APMG_GRIDS_MCRRR; }
+size_t f_elems(const Shape& s) { return (size_t)s.M * s.R * s.R * s.R * s.C; }
 
 apmg_status check_points(const float* pts, int64_t ld, int64_t n) {
   if (n < 0 || ld < n) return APMG_EINVAL;
@@ -158,6 +164,50 @@ int max_part_len(const Shape& s, bool bf) {
   return len;
 }
 
+// ---------------------------------------------------------------- model operands
+// What the kernels read: transforms as [model][M][3][4] and grids as a channel-last mirror
+// [model][M][R^3][C] in the dtype the encoder gathers.  Where the caller's arrays are not in
+// that form already (4-row transforms, paper-order grids, F16 gathers of float32 masters)
+// the copies live in the workspace and are rebuilt by every call.
+struct OpsWs { float* G; void* F; };
+void take_ops(Carver& cv, const Shape& s, int nb, bool pack_G, bool mirror, bool f16, OpsWs* o) {
+  o->G = pack_G ? cv.take<float>((size_t)nb * 12 * s.M) : nullptr;
+  o->F = mirror ? cv.take<char>((size_t)nb * f_elems(s) * (f16 ? 2 : 4)) : nullptr;
+}
+template <int C>
+void mirror_c(const Shape& s, int nb, const void* src, bool sf16, bool spaper, void* dst, bool df16, hipStream_t st) {
+  const int64_t nm = (int64_t)nb * s.M, R3 = (int64_t)s.R * s.R * s.R;
+  const dim3 g(grid1(nm * R3, 8192)), b(256);
+  if (!sf16 && !df16) {
+    if (spaper) hipLaunchKernelGGL((k_mirror_grids<C, float, float, true>), g, b, 0, st, nm, R3, (const float*)src, (float*)dst);
+    else hipLaunchKernelGGL((k_mirror_grids<C, float, float, false>), g, b, 0, st, nm, R3, (const float*)src, (float*)dst);
+  } else if (!sf16 && df16) {
+    if (spaper) hipLaunchKernelGGL((k_mirror_grids<C, float, uint16_t, true>), g, b, 0, st, nm, R3, (const float*)src, (uint16_t*)dst);
+    else hipLaunchKernelGGL((k_mirror_grids<C, float, uint16_t, false>), g, b, 0, st, nm, R3, (const float*)src, (uint16_t*)dst);
+  } else {   // F16 grids gathered as F16: only the order changes
+    hipLaunchKernelGGL((k_mirror_grids<C, uint16_t, uint16_t, true>), g, b, 0, st, nm, R3, (const uint16_t*)src, (uint16_t*)dst);
+  }
+}
+// Builds the copies of take_ops from the caller's G ([nb][M][grows][4]) and F (layout and
+// dtype as given) and returns the pointers the kernels take.
+hipError_t launch_ops(const Shape& s, int nb, const float* G, int grows, const void* F, bool sf16, bool spaper,
+                      const OpsWs& w, bool df16, hipStream_t st, const float** Gc, const void** Fc) {
+  *Gc = G;
+  if (Fc) *Fc = F;
+  if (w.G) {
+    hipLaunchKernelGGL(k_pack_G, dim3(grid1((int64_t)nb * 12 * s.M)), dim3(256), 0, st, (int64_t)nb * s.M, G, w.G);
+    *Gc = w.G;
+  }
+  if (w.F && Fc) {
+    if (s.C == 1) mirror_c<1>(s, nb, F, sf16, spaper, w.F, df16, st);
+    else if (s.C == 2) mirror_c<2>(s, nb, F, sf16, spaper, w.F, df16, st);
+    else mirror_c<4>(s, nb, F, sf16, spaper, w.F, df16, st);
+    *Fc = w.F;
+  }
+  (void)grows;
+  return hipGetLastError();
+}
+
 // ---------------------------------------------------------------- workspace layouts
 // Spatial sort of nb models' points: keys/values ping-pong, digit histograms, bin starts,
 // sorted points and an optional permuted per-point array.
@@ -169,11 +219,13 @@ void take_sort(Carver& cv, int64_t n, int nb, bool with_f, SortWs* o);
 // bins (neighbouring points of a wave then share grid cells in cache) and the outputs
 // scattered back to the caller's order.
 constexpr int64_t kFwdSortMin = (int64_t)1 << 15;
-struct FwdWs { void* swz; float* w3s; bool sorted; SortWs srt; float* fs; };
-size_t fwd_ws(const Shape& s, bool bf, int64_t n, void* ws, FwdWs* o) {
+struct FwdWs { void* swz; float* w3s; bool sorted; SortWs srt; float* fs; OpsWs ops; };
+size_t fwd_ws(const Shape& s, const apmg_model* m, int64_t n, void* ws, FwdWs* o) {
   Carver cv(ws);
+  const bool bf = m->mlp_dtype == APMG_BF16;
   const size_t esz = bf ? 2 : 4;
   FwdWs w;
+  take_ops(cv, s, 1, g_rows(m) == 4, paper_grids(m), m->grid_dtype == APMG_F16, &w.ops);
   w.swz = cv.take<char>(swz_sizes(s).total() * esz);
   w.w3s = cv.take<float>(s.H);
   w.sorted = n >= kFwdSortMin;
@@ -232,12 +284,15 @@ hipError_t launch_sort(const float* pts, int64_t ld, size_t pts_stride, const fl
 
 // The training batch: keys from the counter stream, the radix passes, then the points
 // regenerated in sorted order together with their ground truth (no gather of stored points).
-hipError_t launch_step_sort(uint64_t seed, const uint64_t* step_ctr, int64_t n, int nb, const SortWs& w,
-                            const float* vol, int vnx, int vny, const apmg_brick* bricks, float* v, hipStream_t st) {
+hipError_t launch_step_sort(uint64_t seed, const uint64_t* step_ctr, uint32_t stream0, int64_t n, int nb,
+                            const SortWs& w, const float* vol, int vnx, int vny, const apmg_brick* bricks, float* v,
+                            hipStream_t st) {
   const int nt = sort_tiles(n);
-  hipLaunchKernelGGL(k_batch_keys, dim3(grid1(n, 2048), nb), dim3(256), 0, st, seed, step_ctr, n, w.k0, w.v0);
+  hipLaunchKernelGGL(k_batch_keys, dim3(grid1(n, 2048), nb), dim3(256), 0, st, seed, step_ctr, stream0, n, w.k0,
+                     w.v0);
   radix_passes(n, nb, nt, w, st);
-  hipLaunchKernelGGL(k_batch_sorted, dim3(grid1(n, 2048), nb), dim3(256), 0, st, seed, step_ctr, n, w.v0, w.spts,
+  hipLaunchKernelGGL(k_batch_sorted, dim3(grid1(n, 2048), nb), dim3(256), 0, st, seed, step_ctr, stream0, n, w.v0,
+                     w.spts,
                      w.spts4, vol, vnx, vny, bricks, v);
   hipLaunchKernelGGL(k_bin_starts, dim3(grid1(n + 1), nb), dim3(256), 0, st, w.k0, n, w.start);
   return hipGetLastError();
@@ -263,8 +318,8 @@ void take_cell(Carver& cv, const Shape& s, int64_t n, int nb, CellWs* o) {
 // Grid gradient (into dF when non-NULL) and, when want_dG, the per-block transform-gradient
 // partials (reduced into dG when non-NULL; otherwise left for a later k_reduce_cell_dG).
 hipError_t launch_cells(const Shape& s, bool gf16, const float* G, size_t G_stride, const void* F, size_t F_stride,
-                        const SortWs& sw, int64_t n, const CellWs& cw, float* dF, size_t dF_stride, int accumulate,
-                        bool want_dG, double* dG, size_t dG_stride, int dG_accumulate, int nb,
+                        const SortWs& sw, int64_t n, const CellWs& cw, float* dF, size_t dF_stride, int dF_paper,
+                        int accumulate, bool want_dG, double* dG, size_t dG_stride, int dG_rows, int dG_accumulate, int nb,
                         const int32_t* active, hipStream_t st, int unroll = 4, const int32_t* dG_active = nullptr,
                         int cell_kernel = 0, int cell_group = kDefaultCellGroup) {
   CellArgs c;
@@ -299,7 +354,7 @@ hipError_t launch_cells(const Shape& s, bool gf16, const float* G, size_t G_stri
     } else if (want_dG) APMG_PULL(CC_, F16_, true)                                                   \
     else APMG_PULL(CC_, F16_, false)                                                                 \
     if (dF) hipLaunchKernelGGL((k_cell_to_vertex<CC_>), dim3(grid1((int64_t)s.R * s.R * s.R, 1024), s.M, nb), \
-                               dim3(256), 0, st, s, cw.CC, dF, dF_stride, accumulate, active);       \
+                               dim3(256), 0, st, s, cw.CC, dF, dF_stride, dF_paper, accumulate, active); \
   }
   APMG_CELL(1, false) APMG_CELL(2, false) APMG_CELL(4, false)
   APMG_CELL(1, true) APMG_CELL(2, true) APMG_CELL(4, true)
@@ -308,7 +363,7 @@ hipError_t launch_cells(const Shape& s, bool gf16, const float* G, size_t G_stri
 #undef APMG_PULL
   if (dG)
     hipLaunchKernelGGL(k_reduce_cell_dG, dim3(s.M, nb), dim3(256), 0, st, cw.dGpart, s.M, dg_parts(s, cell_kernel), dG,
-                       dG_stride, dG_accumulate, dG_active ? dG_active : active);
+                       dG_stride, dG_rows, dG_accumulate, dG_active ? dG_active : active);
   return hipGetLastError();
 }
 
@@ -320,11 +375,13 @@ inline int64_t act_ld(int64_t n) { return (std::max<int64_t>(n, 1) + 31) / 32 * 
 inline int gemm_chunks(int64_t n) { return (int)((act_ld(n) + kGemmChunk - 1) / kGemmChunk); }
 inline int gemm_part_len(const Shape& s) { return s.H * s.MC + s.H * s.H; }
 
-struct BwdWs { FwdWs f; double* part; SortWs srt; CellWs cell; void* act; double* gpart; };
-size_t bwd_ws(const Shape& s, bool bf, int64_t n, void* ws, BwdWs* o) {
+struct BwdWs { FwdWs f; double* part; SortWs srt; CellWs cell; void* act; double* gpart; OpsWs ops; };
+size_t bwd_ws(const Shape& s, const apmg_model* m, int64_t n, void* ws, BwdWs* o) {
   Carver cv(ws);
   BwdWs w;
+  const bool bf = m->mlp_dtype == APMG_BF16;
   const size_t esz = bf ? 2 : 4;
+  take_ops(cv, s, 1, g_rows(m) == 4, paper_grids(m), m->grid_dtype == APMG_F16, &w.ops);
   w.f.swz = cv.take<char>(swz_sizes(s).total() * esz);
   w.f.w3s = cv.take<float>(s.H);
   w.part = cv.take<double>((size_t)bwd_blocks(n) * max_part_len(s, bf));
@@ -351,34 +408,48 @@ size_t den_ws(const Shape& s, int64_t n, int nb, void* ws, DenWs* o) {
   d.coef = cv.take<float>((size_t)nb * std::max<int64_t>(n, 1));
   d.pa = cv.take<double>((size_t)nb * kDensBlocks * 2);
   d.sums = cv.take<double>((size_t)nb * 2);
-  d.pb1 = cv.take<double>((size_t)nb * kDensBlocks * 2);
-  d.lq = cv.take<double>((size_t)nb * 2);
+  d.pb1 = cv.take<double>((size_t)nb * kDensBlocks * 3);
+  d.lq = cv.take<double>((size_t)nb * 3);
   d.pb2 = cv.take<double>((size_t)nb * dens_chunks(n) * 13 * s.M);
   d.U = cv.take<double>((size_t)nb * 13 * s.M);
   if (o) *o = d;
   return cv.off;
 }
 
+// apmg_density_loss: the packed transforms (4-row input) and the density buffers.
+size_t den_model_ws(const Shape& s, const apmg_model* m, int64_t n, void* ws, OpsWs* ops, DenWs* o) {
+  Carver cv(ws);
+  OpsWs w;
+  take_ops(cv, s, 1, g_rows(m) == 4, false, false, &w);
+  const size_t off = cv.off;
+  const size_t dsz = den_ws(s, n, 1, ws ? (char*)ws + off : nullptr, o);
+  if (ops) *ops = w;
+  return off + dsz;
+}
+
 // Density loss launch sequence for nb models sharing one shape.  pts/err/rho are per
 // model with the given strides; outputs loss (stride lstride) and dG (stride dG_stride).
+// flags: APMG_DENSITY_ABS_DET, APMG_DENSITY_NORM_TARGET; dG has dG_rows rows per transform.
 hipError_t launch_density(const Shape& s, const float* G, size_t G_stride, const float* pts, int64_t ld,
                           size_t pts_stride, int64_t n, const float* err, size_t err_stride, double eps,
-                          int p, double* loss, int lstride, double* dG, size_t dG_stride, int accumulate,
-                          float* rho_user, const DenWs& w, int nb, const int32_t* active, hipStream_t st) {
+                          int p, uint32_t flags, double* loss, int lstride, double* dG, size_t dG_stride, int dG_rows,
+                          int accumulate, float* rho_user, const DenWs& w, int nb, const int32_t* active,
+                          hipStream_t st) {
+  const int abs_det = (flags & APMG_DENSITY_ABS_DET) ? 1 : 0, norm = (flags & APMG_DENSITY_NORM_TARGET) ? 1 : 0;
   float* rho = rho_user ? rho_user : w.rho;
   const size_t rho_stride = rho_user ? (size_t)n : (size_t)std::max<int64_t>(n, 1);
   const int ba = dens_blocks(n), nch = dens_chunks(n);
   const size_t shA = 64 + (size_t)13 * s.M * 4;
   if (p == 10)
     hipLaunchKernelGGL(k_density_a<10>, dim3(ba, nb), dim3(256), shA, st, s, G, G_stride, pts, ld, pts_stride, n,
-                       err, err_stride, p, rho, rho_stride, w.pa, active);
+                       err, err_stride, p, abs_det, rho, rho_stride, w.pa, active);
   else
     hipLaunchKernelGGL(k_density_a<0>, dim3(ba, nb), dim3(256), shA, st, s, G, G_stride, pts, ld, pts_stride, n,
-                       err, err_stride, p, rho, rho_stride, w.pa, active);
+                       err, err_stride, p, abs_det, rho, rho_stride, w.pa, active);
   hipLaunchKernelGGL(k_density_sums, dim3(nb), dim3(256), 0, st, w.pa, ba, w.sums, nb);
   hipLaunchKernelGGL(k_density_b1, dim3(ba, nb), dim3(256), 0, st, rho, rho_stride, err, err_stride, n,
                      w.sums, eps, w.pb1, active);
-  hipLaunchKernelGGL(k_density_lq, dim3(nb), dim3(256), 0, st, w.pb1, ba, n, w.lq, nb);
+  hipLaunchKernelGGL(k_density_lq, dim3(nb), dim3(256), 0, st, w.pb1, ba, n, w.lq, nb, norm);
   if (dG) {
     const size_t cstride = (size_t)std::max<int64_t>(n, 1);
     hipLaunchKernelGGL(k_density_coef, dim3(grid1(n, 2048), nb), dim3(256), 0, st, rho, rho_stride, err, err_stride, n,
@@ -391,10 +462,10 @@ hipError_t launch_density(const Shape& s, const float* G, size_t G_stride, const
                          ld, pts_stride, n, w.coef, cstride, p, w.pb2, active);
     hipLaunchKernelGGL(k_density_b2_reduce, dim3(s.M, nb), dim3(256), 0, st, w.pb2, s.M, nch, w.U,
                        active);
-    hipLaunchKernelGGL(k_density_grad, dim3(1, nb), dim3(64), 0, st, s, G, G_stride, w.U, p, dG, dG_stride,
-                       accumulate, w.sums, active);
+    hipLaunchKernelGGL(k_density_grad, dim3(1, nb), dim3(64), 0, st, s, G, G_stride, w.U, p, abs_det, dG, dG_stride,
+                       dG_rows, accumulate, w.sums, active);
   }
-  if (loss) hipLaunchKernelGGL(k_copy_f64, dim3((nb + 63) / 64), dim3(64), 0, st, w.lq, 2, loss, lstride, nb, 1.0);
+  if (loss) hipLaunchKernelGGL(k_copy_f64, dim3((nb + 63) / 64), dim3(64), 0, st, w.lq, 3, loss, lstride, nb, 1.0);
   return hipGetLastError();
 }
 
@@ -417,10 +488,10 @@ struct StepWs {
   DenWs den;
   void* act;      // activation path: [nb][tiles][MC + 3H][32] (float32 or bf16)
   double* gpart;  // [nb][chunks][H*MC + H*H]
+  OpsWs ops;      // gather mirror of the grids (paper order or F16 gathers), else unused
 };
 
 size_t w_elems(const Shape& s) { return (size_t)s.H * s.MC + (size_t)s.H * s.H + s.H; }
-size_t f_elems(const Shape& s) { return (size_t)s.M * s.R * s.R * s.R * s.C; }
 
 size_t step_ws(const apmg_batch* b, const Shape& s, void* ws, StepWs* o) {
   Carver cv(ws);
@@ -428,6 +499,8 @@ size_t step_ws(const apmg_batch* b, const Shape& s, void* ws, StepWs* o) {
   const int nb = b->nb;
   const int64_t n = std::max<int64_t>(b->n, 1);
   StepWs w;
+  take_ops(cv, s, nb, false, paper_grids(&b->shape) || b->shape.grid_dtype == APMG_F16,
+           b->shape.grid_dtype == APMG_F16, &w.ops);
   w.v = cv.take<float>((size_t)nb * n);
   w.err = cv.take<float>((size_t)nb * n);
   w.swz = cv.take<char>((size_t)nb * swz_sizes(s).total() * (bf ? 2 : 4));
@@ -495,7 +568,7 @@ void prof_end(hipStream_t st) {
 // ======================================================================== ABI
 // domain-decomposition inference workspace (defined with its entry point below)
 struct DdWs;
-size_t dd_ws(const Shape& s, bool bf, int nb, int64_t n, void* ws, DdWs* o);
+size_t dd_ws(const Shape& s, const apmg_model* shape, int nb, int64_t n, void* ws, DdWs* o);
 
 extern "C" {
 
@@ -529,16 +602,15 @@ size_t apmg_workspace_bytes(int op, const void* mb, int64_t n) {
     const apmg_dd_models* d = (const apmg_dd_models*)mb;
     Shape s;
     if (d->nb < 1 || check_model(&d->shape, false, &s) != APMG_OK) return 0;
-    return dd_ws(s, d->shape.mlp_dtype == APMG_BF16, d->nb, n, nullptr, nullptr);
+    return dd_ws(s, &d->shape, d->nb, n, nullptr, nullptr);
   }
   Shape s;
   const apmg_model* m = (const apmg_model*)mb;
   if (check_model(m, false, &s) != APMG_OK) return 0;
-  const bool bf = m->mlp_dtype == APMG_BF16;
   switch (op) {
-    case APMG_OP_FORWARD: return fwd_ws(s, bf, n, nullptr, nullptr);
-    case APMG_OP_BACKWARD: return bwd_ws(s, bf, n, nullptr, nullptr);
-    case APMG_OP_DENSITY: return den_ws(s, n, 1, nullptr, nullptr);
+    case APMG_OP_FORWARD: return fwd_ws(s, m, n, nullptr, nullptr);
+    case APMG_OP_BACKWARD: return bwd_ws(s, m, n, nullptr, nullptr);
+    case APMG_OP_DENSITY: return den_model_ws(s, m, n, nullptr, nullptr, nullptr);
   }
   return 0;
 }
@@ -551,17 +623,21 @@ apmg_status apmg_forward(const apmg_model* m, const float* pts, int64_t ld, int6
   if ((rc = check_points(pts, ld, n)) != APMG_OK) return rc;
   if (n > 0 && !f) return APMG_EINVAL;
   const bool bf = m->mlp_dtype == APMG_BF16, gf16 = m->grid_dtype == APMG_F16;
-  if (ws_bytes < fwd_ws(s, bf, n, nullptr, nullptr) || !ws) return APMG_EWORKSPACE;
+  if (ws_bytes < fwd_ws(s, m, n, nullptr, nullptr) || !ws) return APMG_EWORKSPACE;
   if (n == 0) return APMG_OK;
   FwdWs w;
-  fwd_ws(s, bf, n, ws, &w);
-  hipError_t e = launch_swizzle(s, bf, m->W[0], m->W[1], m->W[2], 0, w.swz, 0, w.w3s, 1, st);
+  fwd_ws(s, m, n, ws, &w);
+  const float* Gc;
+  const void* Fc;
+  hipError_t e = launch_ops(s, 1, m->G, g_rows(m), m->F, gf16, paper_grids(m), w.ops, gf16, st, &Gc, &Fc);
+  if (e != hipSuccess) return APMG_EHIP;
+  e = launch_swizzle(s, bf, m->W[0], m->W[1], m->W[2], 0, w.swz, 0, w.w3s, 1, st);
   if (e != hipSuccess) return APMG_EHIP;
   if (w.sorted && (e = launch_sort(pts, ld, 0, nullptr, n, 1, w.srt, nullptr, st)) != hipSuccess) return APMG_EHIP;
   TileArgs a;
   memset(&a, 0, sizeof(a));
   a.s = s;
-  a.G = m->G; a.F = m->F; a.swz = w.swz; a.w3s = w.w3s;
+  a.G = Gc; a.F = Fc; a.swz = w.swz; a.w3s = w.w3s;
   a.vscale = m->vmax - m->vmin; a.voff = m->vmin;
   if (w.sorted) { a.pts = w.srt.spts; a.ld = n; a.f = w.fs; }
   else { a.pts = pts; a.ld = ld; a.f = f; }
@@ -584,7 +660,8 @@ apmg_status apmg_backward(const apmg_model* m, const float* pts, int64_t ld, int
   if (n > 0 && !df) return APMG_EINVAL;
   if (dW) for (int k = 0; k < m->n_layers; ++k) if (!dW[k]) return APMG_EINVAL;
   const bool bf = m->mlp_dtype == APMG_BF16, gf16 = m->grid_dtype == APMG_F16;
-  if (ws_bytes < bwd_ws(s, bf, n, nullptr, nullptr) || !ws) return APMG_EWORKSPACE;
+  if (ws_bytes < bwd_ws(s, m, n, nullptr, nullptr) || !ws) return APMG_EWORKSPACE;
+  const int grows = g_rows(m);
   const bool use_act = dW != nullptr && act_path(s, bf);
   const std::vector<Pass> passes = use_act ? std::vector<Pass>{{0, 0, 0, 0, true}} : plan_passes(s, bf, dW != nullptr);
   if (passes.empty()) return APMG_EUNSUPPORTED;
@@ -598,14 +675,18 @@ apmg_status apmg_backward(const apmg_model* m, const float* pts, int64_t ld, int
     }
     if (n == 0) {
       if (dF) hipLaunchKernelGGL(k_fill_f32, dim3(grid1(nF)), dim3(256), 0, st, dF, nF, 0.f);
-      if (dG) hipLaunchKernelGGL(k_fill_f64, dim3(1), dim3(256), 0, st, dG, (size_t)12 * s.M, 0.0);
+      if (dG) hipLaunchKernelGGL(k_fill_f64, dim3(1), dim3(256), 0, st, dG, (size_t)4 * grows * s.M, 0.0);
     }
   }
   if (n == 0) return hip_status(hipGetLastError());
   BwdWs w;
-  bwd_ws(s, bf, n, ws, &w);
+  bwd_ws(s, m, n, ws, &w);
+  const float* Gc;
+  const void* Fc;
+  hipError_t e = launch_ops(s, 1, m->G, grows, m->F, gf16, paper_grids(m), w.ops, gf16, st, &Gc, &Fc);
+  if (e != hipSuccess) return APMG_EHIP;
   // points (and dL/df) in spatial-bin order
-  hipError_t e = launch_sort(pts, ld, 0, nullptr, n, 1, w.srt, df, st);
+  e = launch_sort(pts, ld, 0, nullptr, n, 1, w.srt, df, st);
   if (e != hipSuccess) return APMG_EHIP;
   e = launch_swizzle(s, bf, m->W[0], m->W[1], m->W[2], 0, w.f.swz, 0, w.f.w3s, 1, st);
   if (e != hipSuccess) return APMG_EHIP;
@@ -616,7 +697,7 @@ apmg_status apmg_backward(const apmg_model* m, const float* pts, int64_t ld, int
     TileArgs a;
     memset(&a, 0, sizeof(a));
     a.s = s;
-    a.G = m->G; a.F = m->F; a.swz = w.f.swz; a.w3s = w.f.w3s;
+    a.G = Gc; a.F = Fc; a.swz = w.f.swz; a.w3s = w.f.w3s;
     a.act = use_act ? w.act : nullptr;
     a.act_rows = s.MC + 3 * s.H;
     a.vscale = m->vmax - m->vmin; a.voff = m->vmin;
@@ -685,8 +766,8 @@ apmg_status apmg_backward(const apmg_model* m, const float* pts, int64_t ld, int
   }
   hipError_t ec = hipSuccess;
   if (want_cells)
-    ec = launch_cells(s, gf16, m->G, 0, m->F, 0, w.srt, n, w.cell, dF, 0, acc ? 1 : 0, dG != nullptr, dG, 0,
-                      acc ? 1 : 0, 1, nullptr, st);
+    ec = launch_cells(s, gf16, Gc, 0, Fc, 0, w.srt, n, w.cell, dF, 0, paper_grids(m) ? 1 : 0, acc ? 1 : 0,
+                      dG != nullptr, dG, 0, grows, acc ? 1 : 0, 1, nullptr, st);
   hipError_t ej = hipSuccess;
   if (pst != st) {
     ej = hipEventRecord(side->join, pst);
@@ -705,17 +786,22 @@ apmg_status apmg_density_loss(const apmg_model* m, const float* pts, int64_t ld,
   if (rc != APMG_OK) return rc;
   if ((rc = check_points(pts, ld, n)) != APMG_OK) return rc;
   if (!loss || (n > 0 && !err) || p < 1 || !(eps >= 0.0)) return APMG_EINVAL;
-  if (ws_bytes < den_ws(s, n, 1, nullptr, nullptr) || !ws) return APMG_EWORKSPACE;
+  if (ws_bytes < den_model_ws(s, m, n, nullptr, nullptr, nullptr) || !ws) return APMG_EWORKSPACE;
   const bool acc = flags & APMG_ACCUMULATE;
+  const int grows = g_rows(m);
   if (n == 0) {
     hipLaunchKernelGGL(k_fill_f64, dim3(1), dim3(64), 0, st, loss, (size_t)1, 0.0);
-    if (dG && !acc) hipLaunchKernelGGL(k_fill_f64, dim3(1), dim3(256), 0, st, dG, (size_t)12 * s.M, 0.0);
+    if (dG && !acc) hipLaunchKernelGGL(k_fill_f64, dim3(1), dim3(256), 0, st, dG, (size_t)4 * grows * s.M, 0.0);
     return hip_status(hipGetLastError());
   }
   DenWs w;
-  den_ws(s, n, 1, ws, &w);
-  return hip_status(launch_density(s, m->G, 0, pts, ld, 0, n, err, 0, eps, p, loss, 1, dG, 0, acc ? 1 : 0,
-                                   rho, w, 1, nullptr, st));
+  OpsWs ops;
+  den_model_ws(s, m, n, ws, &ops, &w);
+  const float* Gc;
+  if (launch_ops(s, 1, m->G, grows, nullptr, false, false, ops, false, st, &Gc, nullptr) != hipSuccess)
+    return APMG_EHIP;
+  return hip_status(launch_density(s, Gc, 0, pts, ld, 0, n, err, 0, eps, p, flags, loss, 1, dG, 0, grows,
+                                   acc ? 1 : 0, rho, w, 1, nullptr, st));
 }
 
 apmg_status apmg_cells(const apmg_model* m, const float* pts, int64_t ld, int64_t n, int32_t* cell,
@@ -727,8 +813,9 @@ apmg_status apmg_cells(const apmg_model* m, const float* pts, int64_t ld, int64_
   if (rc != APMG_OK) return rc;
   if (n == 0) return APMG_OK;
   if (!cell && !inside) return APMG_EINVAL;
+  if (!(m->G_rows == 0 || m->G_rows == 3 || m->G_rows == 4)) return APMG_EINVAL;
   s.M = m->M; s.C = m->C; s.R = m->R;
-  hipLaunchKernelGGL(k_cells, dim3(grid1(n * m->M)), dim3(256), 0, st, s, m->G, pts, ld, n, cell, inside);
+  hipLaunchKernelGGL(k_cells, dim3(grid1(n * m->M)), dim3(256), 0, st, s, m->G, g_rows(m), pts, ld, n, cell, inside);
   return hip_status(hipGetLastError());
 }
 
@@ -819,7 +906,7 @@ apmg_status check_batch(const apmg_batch* b, Shape* s) {
   if (!b->G || !b->F || !b->W || !b->mG || !b->vG || !b->mF || !b->vF || !b->mW || !b->vW || !b->t ||
       !b->tG || !b->density_active || !b->volume || !b->bricks || !b->step || !b->losses)
     return APMG_EINVAL;
-  if (b->shape.grid_dtype == APMG_F16 && !b->F_lowp) return APMG_EINVAL;
+  if (b->shape.G_rows == 4) return APMG_EUNSUPPORTED;
   for (int d = 0; d < 3; ++d) if (b->vol[d] < 2) return APMG_EINVAL;
   if (b->p < 1 || !(b->eps_density >= 0.0)) return APMG_EINVAL;
   return APMG_OK;
@@ -836,11 +923,18 @@ apmg_status run_step(const apmg_batch* b, const Shape& s, void* ws, const Tune& 
   const size_t swz_stride = swz_sizes(s).total();
   hipLaunchKernelGGL(k_live_masks, dim3((nb + 63) / 64), dim3(64), 0, st, b->frozen, b->density_active, w.live,
                      w.dlive, nb);
+  // the grids the encoder gathers: the masters themselves (channel-last float32) or their
+  // mirror (paper order, or F16 gathers)
+  const bool paper = paper_grids(&b->shape);
+  const float* Gc;
+  const void* Fg;
+  if (launch_ops(s, nb, b->G, 3, b->F, false, paper, w.ops, gf16, st, &Gc, &Fg) != hipSuccess) return APMG_EHIP;
+  (void)Gc;   // the step's transforms are [nb][M][3][4] already
 
   // 1. batch points, sorted by spatial bin, and the ground truth at the sorted points
   if (n > 0) {
-    hipError_t e0 = launch_step_sort(b->seed, b->step, n, nb, w.srt, b->volume, b->vol[0], b->vol[1], b->bricks,
-                                     w.v, st);
+    hipError_t e0 = launch_step_sort(b->seed, b->step, b->stream0, n, nb, w.srt, b->volume, b->vol[0], b->vol[1],
+                                     b->bricks, w.v, st);
     if (e0 != hipSuccess) return APMG_EHIP;
   }
   // 2. operands of this step's weights, output scaling, zeroed gradients
@@ -912,7 +1006,7 @@ apmg_status run_step(const apmg_batch* b, const Shape& s, void* ws, const Tune& 
     memset(&a, 0, sizeof(a));
     a.s = s;
     a.G = b->G; a.G_stride = nG;
-    a.F = gf16 ? (const void*)b->F_lowp : (const void*)b->F; a.F_stride = nF;
+    a.F = Fg; a.F_stride = nF;
     a.swz = w.swz; a.swz_stride = swz_stride; a.w3s = w.w3s;
     a.bscale = w.scale; a.boff = w.scale + nb;
     a.pts = w.srt.spts; a.ld = n; a.pts_stride = (size_t)3 * n; a.n = n;
@@ -957,10 +1051,11 @@ apmg_status run_step(const apmg_batch* b, const Shape& s, void* ws, const Tune& 
     hipLaunchKernelGGL(k_copy_f64, dim3((nb + 63) / 64), dim3(64), 0, dst, w.lrec, 1, b->losses, 2, nb,
                        1.0 / (double)n);
     const hipError_t ed = launch_density(s, b->G, nG, w.srt.spts, n, (size_t)3 * n, n, w.err, n, b->eps_density,
-                                         b->p, b->losses + 1, 2, w.dG, nG, 0, nullptr, w.den, nb, w.dlive, dst);
-    const hipError_t ec = launch_cells(s, gf16, b->G, nG, gf16 ? (const void*)b->F_lowp : (const void*)b->F, nF,
-                                       w.srt, n, w.cell, w.dF, nF, 0, rec_dG, nullptr, 0, 0, nb, w.live, st,
-                                       tu.cell_unroll, nullptr, tu.cell_kernel, tu.cell_group);
+                                         b->p, b->flags, b->losses + 1, 2, w.dG, nG, 3, 0, nullptr, w.den, nb,
+                                         w.dlive, dst);
+    const hipError_t ec = launch_cells(s, gf16, b->G, nG, Fg, nF, w.srt, n, w.cell, w.dF, nF, paper ? 1 : 0, 0,
+                                       rec_dG, nullptr, 0, 3, 0, nb, w.live, st, tu.cell_unroll, nullptr,
+                                       tu.cell_kernel, tu.cell_group);
     hipError_t ej = hipSuccess;
     if (dst != st) {
       ej = hipEventRecord(side->join, dst);
@@ -969,20 +1064,20 @@ apmg_status run_step(const apmg_batch* b, const Shape& s, void* ws, const Tune& 
     if (ed != hipSuccess || ec != hipSuccess || ej != hipSuccess) return APMG_EHIP;
     if (rec_dG)
       hipLaunchKernelGGL(k_reduce_cell_dG, dim3(s.M, nb), dim3(256), 0, st, w.cell.dGpart, s.M,
-                         dg_parts(s, tu.cell_kernel), w.dG, nG, 1, w.dlive);
+                         dg_parts(s, tu.cell_kernel), w.dG, nG, 3, 1, w.dlive);
   }
   if (!update) return hip_status(hipGetLastError());
 
   // 6. Adam: grids and MLP every step, transforms while the density phase is active
   hipLaunchKernelGGL(k_adam, dim3(grid1(((int64_t)nF + 3) / 4), nb), dim3(256), 0, st, b->F, b->mF, b->vF, (const float*)w.dF,
                      (const double*)nullptr, nF, (const int32_t*)b->t, (const int32_t*)w.live, b->lr, b->beta1,
-                     b->beta2, b->adam_eps, gf16 ? (__half*)b->F_lowp : (__half*)nullptr, b->lr_scale);
+                     b->beta2, b->adam_eps, b->lr_scale);
   hipLaunchKernelGGL(k_adam, dim3(grid1(((int64_t)nW + 3) / 4), nb), dim3(256), 0, st, b->W, b->mW, b->vW, (const float*)w.dW,
                      (const double*)nullptr, nW, (const int32_t*)b->t, (const int32_t*)w.live, b->lr, b->beta1,
-                     b->beta2, b->adam_eps, (__half*)nullptr, b->lr_scale);
+                     b->beta2, b->adam_eps, b->lr_scale);
   hipLaunchKernelGGL(k_adam, dim3(1, nb), dim3(256), 0, st, b->G, b->mG, b->vG, (const float*)nullptr,
                      (const double*)w.dG, nG, (const int32_t*)b->tG, (const int32_t*)w.dlive, b->lr_G, b->beta1,
-                     b->beta2, b->adam_eps, (__half*)nullptr, b->lr_scale);
+                     b->beta2, b->adam_eps, b->lr_scale);
   hipLaunchKernelGGL(k_step_counters, dim3((nb + 63) / 64), dim3(64), 0, st, b->t, b->tG, (const int32_t*)w.live,
                      (const int32_t*)w.dlive, b->step, nb);
   return hip_status(hipGetLastError());
@@ -1064,12 +1159,15 @@ struct DdWs {
   uint32_t *k0, *v0, *k1, *v1, *hist, *rowtot, *dbase, *seg;
   float *lpts, *fs, *w3s, *scale;
   void* swz;
+  OpsWs ops;
 };
 int key_bits(int nseg) { int b = 1; while ((1 << b) < nseg) ++b; return b; }
-size_t dd_ws(const Shape& s, bool bf, int nb, int64_t n, void* ws, DdWs* o) {
+size_t dd_ws(const Shape& s, const apmg_model* shape, int nb, int64_t n, void* ws, DdWs* o) {
   Carver cv(ws);
+  const bool bf = shape->mlp_dtype == APMG_BF16;
   const int64_t nn = std::max<int64_t>(n, 1);
   DdWs w;
+  take_ops(cv, s, nb, g_rows(shape) == 4, paper_grids(shape), shape->grid_dtype == APMG_F16, &w.ops);
   w.k0 = cv.take<uint32_t>(nn); w.v0 = cv.take<uint32_t>(nn);
   w.k1 = cv.take<uint32_t>(nn); w.v1 = cv.take<uint32_t>(nn);
   w.hist = cv.take<uint32_t>((size_t)kRadixDigits * sort_tiles(n));
@@ -1097,12 +1195,17 @@ extern "C" apmg_status apmg_dd_forward(const apmg_dd_models* d, const apmg_brick
   for (int k = 0; k < 3; ++k) if (t->dims[k] < 1 || t->vol[k] < 2) return APMG_EINVAL;
   if (n > 0xffffffffLL) return APMG_EUNSUPPORTED;
   const bool bf = d->shape.mlp_dtype == APMG_BF16, gf16 = d->shape.grid_dtype == APMG_F16;
-  if (!ws || ws_bytes < dd_ws(s, bf, d->nb, n, nullptr, nullptr)) return APMG_EWORKSPACE;
+  if (!ws || ws_bytes < dd_ws(s, &d->shape, d->nb, n, nullptr, nullptr)) return APMG_EWORKSPACE;
   if (n == 0) return APMG_OK;
   DdWs w;
-  dd_ws(s, bf, d->nb, n, ws, &w);
+  dd_ws(s, &d->shape, d->nb, n, ws, &w);
   const int nb = d->nb;
   const size_t nF = f_elems(s), nW = w_elems(s), nG = (size_t)12 * s.M;
+  const float* Gc;
+  const void* Fc;
+  if (launch_ops(s, nb, d->G, g_rows(&d->shape), d->F, gf16, paper_grids(&d->shape), w.ops, gf16, st, &Gc, &Fc) !=
+      hipSuccess)
+    return APMG_EHIP;
   // brick ids, then a stable radix sort of the points by brick
   hipLaunchKernelGGL(k_dd_keys, dim3(grid1(n)), dim3(256), 0, st, *t, pts, ld, n, w.k0, w.v0);
   const int nt = sort_tiles(n);
@@ -1125,8 +1228,8 @@ extern "C" apmg_status apmg_dd_forward(const apmg_dd_models* d, const apmg_brick
   TileArgs a;
   memset(&a, 0, sizeof(a));
   a.s = s;
-  a.G = d->G; a.G_stride = nG;
-  a.F = d->F; a.F_stride = nF;
+  a.G = Gc; a.G_stride = nG;
+  a.F = Fc; a.F_stride = nF;
   a.swz = w.swz; a.swz_stride = swz_sizes(s).total(); a.w3s = w.w3s;
   a.bscale = w.scale; a.boff = w.scale + nb;
   a.pts = w.lpts; a.ld = n; a.pts_stride = 0; a.n = n;

@@ -95,7 +95,8 @@ __global__ void k_gt_sample(const float* vol, int nx, int ny, int nz, const floa
 }
 
 // ------------------------------------------------------------------ cells / bricks
-__global__ void k_cells(Shape s, const float* G, const float* pts, int64_t ld, int64_t n,
+// G: [M][grows][4] (rows 0..2 read).
+__global__ void k_cells(Shape s, const float* G, int grows, const float* pts, int64_t ld, int64_t n,
                         int32_t* cell, uint8_t* inside) {
   const float hR = 0.5f * (float)(s.R - 1);
   const int64_t total = n * s.M;
@@ -103,7 +104,7 @@ __global__ void k_cells(Shape s, const float* G, const float* pts, int64_t ld, i
     const int64_t p = i / s.M;
     const int g = (int)(i % s.M);
     float l[3];
-    local_coords(G + 12 * g, pts[p], pts[ld + p], pts[2 * ld + p], l);
+    local_coords(G + 4 * grows * g, pts[p], pts[ld + p], pts[2 * ld + p], l);
     int i0[3];
     float w[3];
     const bool in = cell_of(l, hR, s.R, i0, w);
@@ -139,6 +140,36 @@ __global__ void k_convert(int M, int C, int R, const TS* src, TD* dst, int to_cl
     if constexpr (sizeof(TS) == 2) val = __half2float(*(const __half*)&src[si]); else val = (float)src[si];
     if constexpr (sizeof(TD) == 2) { __half hv = __float2half_rn(val); dst[i] = *(TD*)&hv; } else dst[i] = (TD)val;
   }
+}
+
+// Gather mirror of nm grids (all models of a batch, one after another): dst is channel-last
+// [nm][R^3][C] in TD; src is [nm][C][R^3] (SRC_PAPER) or [nm][R^3][C], in TS.  One thread per
+// vertex: with the paper's order every channel plane is read coalesced and the C values of a
+// vertex are stored together.  float -> half rounds to nearest even.
+template <int C, typename TS, typename TD, bool SRC_PAPER>
+__global__ void k_mirror_grids(int64_t nm, int64_t R3, const TS* __restrict__ src, TD* __restrict__ dst) {
+  const int64_t total = nm * R3;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t g = i / R3, v = i - g * R3;
+    float val[C];
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+      const TS x = SRC_PAPER ? src[(g * C + c) * R3 + v] : src[i * C + c];
+      if constexpr (sizeof(TS) == 2) val[c] = __half2float(*(const __half*)&x);
+      else val[c] = (float)x;
+    }
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+      if constexpr (sizeof(TD) == 2) { const __half h = __float2half_rn(val[c]); dst[i * C + c] = *(const TD*)&h; }
+      else dst[i * C + c] = (TD)val[c];
+    }
+  }
+}
+
+// Rows 0..2 of ng transforms stored [ng][4][4] -> compact [ng][3][4].
+__global__ void k_pack_G(int64_t ng, const float* __restrict__ src, float* __restrict__ dst) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < 12 * ng; i += (int64_t)gridDim.x * blockDim.x)
+    dst[i] = src[(i / 12) * 16 + i % 12];
 }
 
 // ------------------------------------------------------------------ feature density
@@ -194,7 +225,7 @@ __device__ inline void flat_pow2(float l, int p, float& e2p, float& e2pm1) {
 template <int PF>
 __global__ void __launch_bounds__(256) k_density_a(Shape s, const float* Gall, size_t G_stride,
     const float* pts, int64_t ld, size_t pts_stride, int64_t n, const float* err, size_t err_stride,
-    int p, float* rho, size_t rho_stride, double* part, const int32_t* active) {
+    int p, int abs_det, float* rho, size_t rho_stride, double* part, const int32_t* active) {
   extern __shared__ float smem[];
   const int model = blockIdx.y;
   double* spart = (double*)smem;   // [wave][2]
@@ -204,7 +235,11 @@ __global__ void __launch_bounds__(256) k_density_a(Shape s, const float* Gall, s
   const float* G = Gall + model * G_stride;
   for (int i = threadIdx.x; i < 12 * s.M; i += blockDim.x) sG[i] = G[i];
   __syncthreads();
-  for (int g = threadIdx.x; g < s.M; g += blockDim.x) { double dc[10]; det_cof(sG + 12 * g, dc); sdet[g] = (float)dc[0]; }
+  for (int g = threadIdx.x; g < s.M; g += blockDim.x) {
+    double dc[10];
+    det_cof(sG + 12 * g, dc);
+    sdet[g] = (float)(abs_det ? fabs(dc[0]) : dc[0]);
+  }
   __syncthreads();
   double srho = 0.0, serr = 0.0;
   const float* P = pts + model * pts_stride;
@@ -232,91 +267,115 @@ __global__ void __launch_bounds__(256) k_density_a(Shape s, const float* Gall, s
         ((spart[threadIdx.x] + spart[2 + threadIdx.x]) + spart[4 + threadIdx.x]) + spart[6 + threadIdx.x];
 }
 
-// Fixed-order block sum of the pairs part[model][k][2], k < nblk: out = {sum_k [0], sum_k [1]}.
+// Fixed-order block sum of the K-tuples part[model][k][K], k < nblk: out[q] = sum_k [q].
 // Thread t sums the contiguous range [t*per, (t+1)*per); the 256 range sums are then added
 // by a fixed tree.  One block per model.
-__device__ inline void pair_sum(const double* part, int nblk, double& a, double& b) {
-  __shared__ double sa[256], sb[256];
+template <int K>
+__device__ inline void tuple_sum(const double* part, int nblk, double out[K]) {
+  __shared__ double sh[K][256];
   const int per = (nblk + 255) / 256;
   const int k0 = threadIdx.x * per, k1 = min(nblk, k0 + per);
-  double x = 0.0, y = 0.0;
-  for (int k = k0; k < k1; ++k) { x += part[2 * (size_t)k]; y += part[2 * (size_t)k + 1]; }
-  sa[threadIdx.x] = x;
-  sb[threadIdx.x] = y;
+  double x[K];
+#pragma unroll
+  for (int q = 0; q < K; ++q) x[q] = 0.0;
+  for (int k = k0; k < k1; ++k)
+#pragma unroll
+    for (int q = 0; q < K; ++q) x[q] += part[K * (size_t)k + q];
+#pragma unroll
+  for (int q = 0; q < K; ++q) sh[q][threadIdx.x] = x[q];
   __syncthreads();
   for (int w = 128; w > 0; w >>= 1) {
-    if ((int)threadIdx.x < w) { sa[threadIdx.x] += sa[threadIdx.x + w]; sb[threadIdx.x] += sb[threadIdx.x + w]; }
+    if ((int)threadIdx.x < w)
+#pragma unroll
+      for (int q = 0; q < K; ++q) sh[q][threadIdx.x] += sh[q][threadIdx.x + w];
     __syncthreads();
   }
-  a = sa[0];
-  b = sb[0];
+#pragma unroll
+  for (int q = 0; q < K; ++q) out[q] = sh[q][0];
 }
 
 // Reduce pass-A partials: sums[model] = {S, sum err}.
 __global__ void __launch_bounds__(256) k_density_sums(const double* part, int nblk, double* sums, int nmodels) {
   const int model = blockIdx.x;
-  double a, b;
-  pair_sum(part + (size_t)model * nblk * 2, nblk, a, b);
-  if (threadIdx.x == 0) { sums[2 * model] = a; sums[2 * model + 1] = b; }
+  double o[2];
+  tuple_sum<2>(part + (size_t)model * nblk * 2, nblk, o);
+  if (threadIdx.x == 0) { sums[2 * model] = o[0]; sums[2 * model + 1] = o[1]; }
 }
 
-// Target density and loss summand for one point, float64 (Eqs. (8), (9)).
+// Target density and loss summand for one point, float64 (Eqs. (8), (9)): rho_s, the
+// target rho* and, with it unnormalised, the loss summand and a = dL/drho_s.
 __device__ inline void target_terms(double rho, double S, double hbar, double h, double eps, double N,
-                                    double& term, double& a, double& rho_s) {
+                                    double& term, double& a, double& rho_s, double& target) {
   rho_s = rho / S;
   const double lg = log(rho_s + eps);
   const double lt = hbar / (h + eps) * lg;
   const double rs = exp(lt);
   term = rs > 0.0 ? rs * (lt - lg) : 0.0;
   a = -rs / (N * (rho_s + eps));
+  target = rs;
 }
 
-// Pass B1: loss and Q = sum a rho_s.  part: [model][block][2] = {loss sum, Q}
+// Pass B1: per block, {sum of loss summands, Q = sum a rho_s, sum rho*} (a and the loss
+// summands with the unnormalised target).  part: [model][block][3]
 __global__ void __launch_bounds__(256) k_density_b1(const float* rho, size_t rho_stride, const float* err,
     size_t err_stride, int64_t n, const double* sums, double eps, double* part, const int32_t* active) {
-  __shared__ double spart[8];   // [wave][2]
+  __shared__ double spart[12];   // [wave][3]
   const int model = blockIdx.y;
   const bool act = (!active || active[model]) && sums[2 * model] != 0.0;
-  double sl = 0.0, sq = 0.0;
+  double sl = 0.0, sq = 0.0, sz = 0.0;
   if (act) {
     const double S = sums[2 * model], hbar = sums[2 * model + 1] / (double)n;
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-      double term, a, rs;
-      target_terms(rho[model * rho_stride + i], S, hbar, err[model * err_stride + i], eps, (double)n, term, a, rs);
+      double term, a, rs, tg;
+      target_terms(rho[model * rho_stride + i], S, hbar, err[model * err_stride + i], eps, (double)n, term, a, rs, tg);
       sl += term;
       sq += a * rs;
+      sz += tg;
     }
   }
   sl = wave_sum(sl);
   sq = wave_sum(sq);
-  if ((threadIdx.x & 63) == 0) { spart[2 * (threadIdx.x >> 6)] = sl; spart[2 * (threadIdx.x >> 6) + 1] = sq; }
+  sz = wave_sum(sz);
+  const int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) { spart[3 * w] = sl; spart[3 * w + 1] = sq; spart[3 * w + 2] = sz; }
   __syncthreads();
-  if (threadIdx.x < 2)
-    part[((size_t)model * gridDim.x + blockIdx.x) * 2 + threadIdx.x] =
-        ((spart[threadIdx.x] + spart[2 + threadIdx.x]) + spart[4 + threadIdx.x]) + spart[6 + threadIdx.x];
+  if (threadIdx.x < 3)
+    part[((size_t)model * gridDim.x + blockIdx.x) * 3 + threadIdx.x] =
+        ((spart[threadIdx.x] + spart[3 + threadIdx.x]) + spart[6 + threadIdx.x]) + spart[9 + threadIdx.x];
 }
 
-// Reduce pass-B1 partials into lq[model] = {loss, Q}
-__global__ void __launch_bounds__(256) k_density_lq(const double* part, int nblk, int64_t n, double* lq, int nmodels) {
+// Reduce pass-B1 partials into lq[model] = {loss, Q, Z}: Z = 1 for the literal target, and
+// Z = sum rho* for the renormalised one (target rho*/Z), for which
+// loss = (sum of summands) / (n Z) - log(Z) / n and Q = Q_raw / Z.
+__global__ void __launch_bounds__(256) k_density_lq(const double* part, int nblk, int64_t n, double* lq, int nmodels,
+                                                    int norm_target) {
   const int model = blockIdx.x;
-  double a, b;
-  pair_sum(part + (size_t)model * nblk * 2, nblk, a, b);
-  if (threadIdx.x == 0) { lq[2 * model] = n > 0 ? a / (double)n : 0.0; lq[2 * model + 1] = b; }
+  double o[3];
+  tuple_sum<3>(part + (size_t)model * nblk * 3, nblk, o);
+  if (threadIdx.x == 0) {
+    const double Z = (norm_target && o[2] > 0.0) ? o[2] : 1.0;
+    double loss = n > 0 ? o[0] / ((double)n * Z) : 0.0;
+    if (norm_target && n > 0) loss -= log(Z) / (double)n;
+    lq[3 * model] = loss;
+    lq[3 * model + 1] = o[1] / Z;
+    lq[3 * model + 2] = Z;
+  }
 }
 
-// Per-point coefficient c(x) = dL/drho(x) = (a(x) - Q)/S (float64 arithmetic, stored float32).
+// Per-point coefficient c(x) = dL/drho(x) = (a(x)/Z - Q)/S (float64 arithmetic, stored float32).
 __global__ void k_density_coef(const float* rho, size_t rho_stride, const float* err, size_t err_stride, int64_t n,
                                const double* sums, const double* lq, double eps, float* coef, size_t coef_stride,
                                const int32_t* active) {
   const int model = blockIdx.y;
   const bool act = (!active || active[model]) && sums[2 * model] != 0.0;
-  const double S = sums[2 * model], hbar = sums[2 * model + 1] / (double)n, Q = lq[2 * model + 1];
+  const double S = sums[2 * model], hbar = sums[2 * model + 1] / (double)n;
+  const double Q = lq[3 * model + 1], Z = lq[3 * model + 2];
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
     float c = 0.f;
     if (act) {
-      double term, a, rs;
-      target_terms(rho[model * rho_stride + i], S, hbar, err[model * err_stride + i], eps, (double)n, term, a, rs);
-      c = (float)((a - Q) / S);
+      double term, a, rs, tg;
+      target_terms(rho[model * rho_stride + i], S, hbar, err[model * err_stride + i], eps, (double)n, term, a, rs, tg);
+      c = (float)((a / Z - Q) / S);
     }
     coef[model * coef_stride + i] = c;
   }
@@ -399,8 +458,11 @@ __global__ void __launch_bounds__(256) k_density_b2_reduce(const double* part, i
 }
 
 // Assemble dG_i = cof_i U0 - 2p det_i [U1 | U2] from the reduced pass-B2 sums.
-__global__ void k_density_grad(Shape s, const float* Gall, size_t G_stride, const double* U, int p,
-                               double* dG, size_t dG_stride, int accumulate, const double* sums,
+// Assemble dG_i = sgn_i cof_i U0 - 2p det_i [U1 | U2] from the reduced pass-B2 sums, where
+// det_i and sgn_i are det(A_i) and 1 (signed reading) or |det(A_i)| and sign(det(A_i))
+// (abs_det).  dG rows per transform: grows (3, or 4 with row 3 written as 0).
+__global__ void k_density_grad(Shape s, const float* Gall, size_t G_stride, const double* U, int p, int abs_det,
+                               double* dG, size_t dG_stride, int grows, int accumulate, const double* sums,
                                const int32_t* active) {
   const int model = blockIdx.y;
   if (active && !active[model]) return;
@@ -408,26 +470,30 @@ __global__ void k_density_grad(Shape s, const float* Gall, size_t G_stride, cons
   for (int g = blockIdx.x * blockDim.x + threadIdx.x; g < s.M; g += gridDim.x * blockDim.x) {
     double dc[10];
     det_cof(Gall + model * G_stride + 12 * g, dc);
+    const double sgn = abs_det ? (dc[0] > 0.0 ? 1.0 : (dc[0] < 0.0 ? -1.0 : 0.0)) : 1.0;
+    const double det = abs_det ? fabs(dc[0]) : dc[0];
     const double* u = U + (size_t)model * 13 * s.M + 13 * g;
-    double* o = dG + model * dG_stride + 12 * g;
+    double* o = dG + model * dG_stride + 4 * grows * g;
     for (int r = 0; r < 3; ++r) {
       for (int k = 0; k < 3; ++k) {
-        const double v = zero ? 0.0 : dc[1 + 3 * r + k] * u[0] - 2.0 * p * dc[0] * u[1 + 3 * r + k];
+        const double v = zero ? 0.0 : sgn * dc[1 + 3 * r + k] * u[0] - 2.0 * p * det * u[1 + 3 * r + k];
         o[4 * r + k] = accumulate ? o[4 * r + k] + v : v;
       }
-      const double v = zero ? 0.0 : -2.0 * p * dc[0] * u[10 + r];
+      const double v = zero ? 0.0 : -2.0 * p * det * u[10 + r];
       o[4 * r + 3] = accumulate ? o[4 * r + 3] + v : v;
     }
+    if (grows == 4 && !accumulate)
+      for (int k = 0; k < 4; ++k) o[12 + k] = 0.0;
   }
 }
 
 // ------------------------------------------------------------------ Adam
 // theta -= lr * mhat / (sqrt(vhat) + eps), bias-corrected with step t+1 (t read from
-// counters[model]).  Optional float16 shadow of theta.  gd (double) or gf (float) gradient.
+// counters[model]).  gd (double) or gf (float) gradient.
 // active: per model, skip when 0 (NULL = all); lr_scale: per model multiplier of lr (NULL = 1).
 __global__ void k_adam(float* theta, float* m, float* v, const float* gf, const double* gd, size_t per_model,
                        const int32_t* counters, const int32_t* active, float lr, float b1, float b2,
-                       float eps, __half* shadow, const float* lr_scale) {
+                       float eps, const float* lr_scale) {
   const int model = blockIdx.y;
   if (active && !active[model]) return;
   // bias corrections in float64, once per block
@@ -452,7 +518,7 @@ __global__ void k_adam(float* theta, float* m, float* v, const float* gf, const 
   size_t i0 = 0;
   // four elements per thread with 16-byte accesses where every array allows it; the same
   // arithmetic per element as the scalar loop that finishes the rest
-  if (gf && !shadow && ((uintptr_t)(theta + off) | (uintptr_t)(m + off) | (uintptr_t)(v + off) |
+  if (gf && ((uintptr_t)(theta + off) | (uintptr_t)(m + off) | (uintptr_t)(v + off) |
                         (uintptr_t)(gf + off)) % 16 == 0) {
     const size_t n4 = per_model / 4;
     for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n4; i += stride) {
@@ -476,7 +542,6 @@ __global__ void k_adam(float* theta, float* m, float* v, const float* gf, const 
     m[k] = mk;
     v[k] = vk;
     theta[k] = th;
-    if (shadow) shadow[k] = __float2half_rn(th);
   }
 }
 

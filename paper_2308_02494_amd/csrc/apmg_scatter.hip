@@ -530,7 +530,8 @@ __global__ void __launch_bounds__(256) k_cell_pull_wave(CellArgs a) {
 
 // dF[model][g][v][c] (+)= sum over the cells adjacent to vertex v of their corner sums.
 template <int C>
-__global__ void k_cell_to_vertex(Shape s, const float* CC, float* dF, size_t dF_stride, int accumulate,
+// dF in the paper's order [M][C][R^3] when paper != 0, else channel-last [M][R^3][C].
+__global__ void k_cell_to_vertex(Shape s, const float* CC, float* dF, size_t dF_stride, int paper, int accumulate,
                                  const int32_t* active) {
   const int model = blockIdx.z, g = blockIdx.y;
   if (active && !active[model]) return;
@@ -550,16 +551,19 @@ __global__ void k_cell_to_vertex(Shape s, const float* CC, float* dF, size_t dF_
 #pragma unroll
       for (int c = 0; c < C; ++c) sum[c] += src[c];
     }
-    float* dst = dF + model * dF_stride + ((size_t)g * nv + v) * C;
+    float* dst = dF + model * dF_stride + (paper ? (size_t)g * C * nv + v : ((size_t)g * nv + v) * C);
+    const size_t cs = paper ? (size_t)nv : 1;
 #pragma unroll
-    for (int c = 0; c < C; ++c) dst[c] = accumulate ? dst[c] + sum[c] : sum[c];
+    for (int c = 0; c < C; ++c) dst[c * cs] = accumulate ? dst[c * cs] + sum[c] : sum[c];
   }
 }
 
 // dG[model][g][k] (+)= sum over the cb per-block partials of grid g: one workgroup per (grid,
 // model); thread t sums blocks t, t + 256, ... in order, then a fixed tree over the threads.
+// dG rows per transform: grows (3, or 4 with row 3 written as 0).
 __global__ void __launch_bounds__(256) k_reduce_cell_dG(const double* part, int M, int cb, double* dG,
-                                                        size_t dG_stride, int accumulate, const int32_t* active) {
+                                                        size_t dG_stride, int grows, int accumulate,
+                                                        const int32_t* active) {
   __shared__ double sp[256][13];
   const int g = blockIdx.x, model = blockIdx.y;
   if (active && !active[model]) return;
@@ -580,8 +584,10 @@ __global__ void __launch_bounds__(256) k_reduce_cell_dG(const double* part, int 
     __syncthreads();
   }
   if (threadIdx.x < 12) {
-    double* o = dG + model * dG_stride + 12 * g + threadIdx.x;
+    double* o = dG + model * dG_stride + 4 * grows * g + threadIdx.x;
     *o = accumulate ? *o + sp[0][threadIdx.x] : sp[0][threadIdx.x];
+  } else if (grows == 4 && threadIdx.x < 16 && !accumulate) {
+    dG[model * dG_stride + 4 * grows * g + threadIdx.x] = 0.0;
   }
 }
 

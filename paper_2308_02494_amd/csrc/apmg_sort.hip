@@ -185,13 +185,14 @@ __global__ void k_bin_starts(const uint32_t* keys, int64_t n, uint32_t* start) {
 
 // The training batch's sort keys straight from the counter stream: point i of every model
 // is generated and binned (the points themselves are not stored; they are regenerated in
-// sorted order below).
-__global__ void k_batch_keys(uint64_t seed, const uint64_t* step_ctr, int64_t n, uint32_t* keys, uint32_t* vals) {
+// sorted order below).  Model b draws from stream stream0 + b.
+__global__ void k_batch_keys(uint64_t seed, const uint64_t* step_ctr, uint32_t stream0, int64_t n, uint32_t* keys,
+                             uint32_t* vals) {
   const int model = blockIdx.y;
   const uint64_t step = *step_ctr;
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
     float x, y, z;
-    uniform_point(seed, step, (uint32_t)model, (uint64_t)i, x, y, z);
+    uniform_point(seed, step, stream0 + (uint32_t)model, (uint64_t)i, x, y, z);
     keys[model * n + i] = bin_of(x, y, z);
     vals[model * n + i] = (uint32_t)i;
   }
@@ -200,7 +201,7 @@ __global__ void k_batch_keys(uint64_t seed, const uint64_t* step_ctr, int64_t n,
 // Sorted position j of every model gets point perm[j] regenerated from the counter stream
 // (the same bits as at key time), written as [model][3][n] and (x, y, z, 0) records, and
 // the ground truth there: a trilinear sample of the model's brick (extended extent e0..e1).
-__global__ void k_batch_sorted(uint64_t seed, const uint64_t* step_ctr, int64_t n, const uint32_t* perm, float* out,
+__global__ void k_batch_sorted(uint64_t seed, const uint64_t* step_ctr, uint32_t stream0, int64_t n, const uint32_t* perm, float* out,
                                float4* out4, const float* vol, int vnx, int vny, const apmg_brick* bricks, float* v) {
   const int model = blockIdx.y;
   const uint64_t step = *step_ctr;
@@ -210,7 +211,7 @@ __global__ void k_batch_sorted(uint64_t seed, const uint64_t* step_ctr, int64_t 
   float* O = out + (size_t)model * 3 * n;
   for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < n; j += (int64_t)gridDim.x * blockDim.x) {
     float x, y, z;
-    uniform_point(seed, step, (uint32_t)model, (uint64_t)perm[model * n + j], x, y, z);
+    uniform_point(seed, step, stream0 + (uint32_t)model, (uint64_t)perm[model * n + j], x, y, z);
     O[j] = x; O[n + j] = y; O[2 * n + j] = z;
     out4[model * n + j] = make_float4(x, y, z, 0.f);
     v[(size_t)model * n + j] = sample_volume(vol, vnx, vny, e0, nn, x, y, z);

@@ -168,21 +168,3 @@ def ray_points(width=1920, height=1080, samples=8, aspect_half=0.5625):
     pz = (-1.0 + (2.0 * np.arange(samples) + 1.0) / samples).astype(np.float32)
     Y, X, Z = np.meshgrid(py, px, pz, indexing="ij")
     return np.stack([X.ravel(), Y.ravel(), Z.ravel()], axis=-1)
-
-
-# --------------------------------------------------------------------------
-# the workloads (sizes of the five benchmark configurations)
-# --------------------------------------------------------------------------
-
-WORKLOADS = {
-    "c1_tiny_fp32": dict(volume=("blobs_sine", (64, 64, 64)), M=16, C=2, R=16,
-                         widths=[32, 64, 64, 1], n=65536),
-    "c2_train_fp32": dict(volume=("blobs_turb", (256, 256, 256)), M=32, C=2, R=32,
-                          widths=[64, 64, 64, 1], n=1 << 20),
-    "c3_train_mixed": dict(volume=("blobs_turb", (1024, 1024, 1024)), M=32, C=2, R=32,
-                           widths=[64, 64, 64, 1], n=1 << 21),
-    "c4_bricks": dict(volume=("blobs_turb", (900, 1200, 1000)), M=16, C=2, R=32,
-                      widths=[32, 64, 64, 1], n=1 << 17, brick=256, ghost=1),
-    "c5_render": dict(M=64, C=4, R=64, widths=[256, 128, 128, 1], n=1920 * 1080 * 8,
-                      n_backward=1 << 20),
-}

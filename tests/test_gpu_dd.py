@@ -30,7 +30,7 @@ def _setup(M=8, C=2, R=12, H=64, mlp=None, seed=0):
         bricks[b].vmin, bricks[b].vmax = float(rng.uniform(-1, 0)), float(rng.uniform(1, 2))
         hosts.append(h)
     G = torch.stack([torch.from_numpy(h["G"]) for h in hosts]).to(DEV)
-    F = torch.stack([torch.from_numpy(h["F"]).permute(0, 2, 3, 4, 1) for h in hosts]).contiguous().to(DEV)
+    F = torch.stack([torch.from_numpy(h["F"]) for h in hosts]).contiguous().to(DEV)
     W = torch.stack([torch.cat([torch.from_numpy(w).reshape(-1) for w in h["W"]]) for h in hosts]).to(DEV)
     models = A_.DDModels(G, F, W, [M * C, H, H, 1], table, bricks, A_.F32 if mlp is None else mlp)
     obricks = [{"e0": list(br.e0), "e1": list(br.e1), "vmin": br.vmin, "vmax": br.vmax} for br in bricks]

@@ -204,7 +204,7 @@ def test_backward_fp32(M, C, R, H):
     model = A().Model.from_host(host, DEV)
     dF, dG, dW = A().apmg_backward(model, soa(x), torch.from_numpy(df).to(DEV))
     go = O.backward(f64(host), x.astype(np.float64), df.astype(np.float64))
-    assert_close("dF", dF.cpu().numpy(), go["dF"].transpose(0, 2, 3, 4, 1))
+    assert_close("dF", dF.cpu().numpy(), go["dF"])
     assert_close("dG", dG.cpu().numpy(), go["dG"])
     for k in range(3):
         assert_close(f"dW{k + 1}", dW[k].cpu().numpy(), go["dW"][k])
@@ -228,7 +228,7 @@ def test_grid_gradient_gathers_agree_and_match_oracle(M, C, R, H):
     dfk = np.random.default_rng(6).normal(size=xk.shape[0]).astype(np.float32)
     dF_k, _, _ = A().apmg_backward(model, soa(xk), torch.from_numpy(dfk).to(DEV), want_dG=False)
     go = O.backward(f64(host), xk.astype(np.float64), dfk.astype(np.float64))
-    assert_close("dF (wave gather)", dF_k.cpu().numpy(), go["dF"].transpose(0, 2, 3, 4, 1))
+    assert_close("dF (wave gather)", dF_k.cpu().numpy(), go["dF"])
 
 
 def _rotation(rng):
@@ -265,7 +265,7 @@ def test_grid_gradient_under_rotated_scaled_sheared_transforms():
     dfk = np.random.default_rng(9).normal(size=xk.shape[0]).astype(np.float32)
     dF_k, dG_k, _ = A().apmg_backward(model, soa(xk), torch.from_numpy(dfk).to(DEV))
     go = O.backward(f64(host), xk.astype(np.float64), dfk.astype(np.float64))
-    assert_close("dF (wave gather, turned grids)", dF_k.cpu().numpy(), go["dF"].transpose(0, 2, 3, 4, 1))
+    assert_close("dF (wave gather, turned grids)", dF_k.cpu().numpy(), go["dF"])
     assert_close("dG (wave gather, turned grids)", dG_k.cpu().numpy(), go["dG"])
     # the one-thread-per-cell gather (reached through the training step's launch shapes) on the
     # same turned grids: the grids' first moments (0.1 * gradient) agree with the wave gather's
@@ -322,7 +322,7 @@ def test_backward_wide_first_layer_activation_path():
     model = A().Model.from_host(host, DEV, mlp_dtype=A().F32)
     dF, dG, dW = A().apmg_backward(model, soa(x), torch.from_numpy(df).to(DEV))
     go = O.backward(f64(host), x.astype(np.float64), df.astype(np.float64))
-    assert_close("dF", dF.cpu().numpy(), go["dF"].transpose(0, 2, 3, 4, 1))
+    assert_close("dF", dF.cpu().numpy(), go["dF"])
     assert_close("dG", dG.cpu().numpy(), go["dG"])
     for k in range(3):
         assert_close(f"dW{k + 1}", dW[k].cpu().numpy(), go["dW"][k])
@@ -340,7 +340,7 @@ def test_autograd_function_matches_oracle():
     (f * wts).sum().backward()
     go = O.backward(f64(host), x.astype(np.float64), wts.cpu().numpy().astype(np.float64))
     assert_close("autograd dG", G.grad.cpu().numpy(), go["dG"])
-    assert_close("autograd dF", F.grad.cpu().numpy(), go["dF"].transpose(0, 2, 3, 4, 1))
+    assert_close("autograd dF", F.grad.cpu().numpy(), go["dF"])
     assert_close("autograd dW1", Ws[0].grad.cpu().numpy(), go["dW"][0])
 
 
@@ -409,11 +409,11 @@ def test_batched_step_matches_oracle(nb_shape):
         print(f"L_density[{b}] rel err {a:.2e}")
         assert a < 1e-3
         # Adam first moments are (1 - beta1) * gradient
-        assert_close(f"mF[{b}]", tr.mF[b].cpu().numpy(), new_s["mF"].transpose(0, 2, 3, 4, 1))
+        assert_close(f"mF[{b}]", tr.mF[b].cpu().numpy(), new_s["mF"])
         mW = tr.mW[b].cpu().numpy()
         o = 0
         for k, w in enumerate(new_s["mW"]):
-            assert_close(f"mW{k + 1}[{b}]", mW[o:o + w.size].reshape(w.shape), w, 2e-5)
+            assert_close(f"mW{k + 1}[{b}]", mW[o:o + w.size].reshape(w.shape), w)
             o += w.size
         a, _ = errs(tr.mG[b].cpu().numpy(), new_s["mG"])
         print(f"mG[{b}] rel err {a:.2e}")
@@ -445,11 +445,11 @@ def test_batched_step_activation_path_matches_oracle_and_is_reproducible():
     for b in range(2):
         new_m, new_s, info = oracle_step(hosts[b], vol_np, obricks[b], 9, 0, b, n, True)
         assert_close(f"L_rec[{b}]", [tr.losses[b, 0].item()], [info["L_rec"]])
-        assert_close(f"mF[{b}]", tr.mF[b].cpu().numpy(), new_s["mF"].transpose(0, 2, 3, 4, 1))
+        assert_close(f"mF[{b}]", tr.mF[b].cpu().numpy(), new_s["mF"])
         mW = tr.mW[b].cpu().numpy()
         o = 0
         for k, w in enumerate(new_s["mW"]):
-            assert_close(f"mW{k + 1}[{b}]", mW[o:o + w.size].reshape(w.shape), w, 2e-5)
+            assert_close(f"mW{k + 1}[{b}]", mW[o:o + w.size].reshape(w.shape), w)
             o += w.size
 
 
@@ -470,7 +470,7 @@ def test_batched_step_with_rec_transform_gradient_matches_oracle(cell_kernel):
     _, obricks = O.brick_partition((nx, ny, nz), max(nx, ny, nz), 0)
     new_m, new_s, info = oracle_step(host, vol.numpy().astype(np.float64), obricks[0], 7, 0, 0, n, True,
                                      flags_rec=True)
-    assert_close("mF", tr.mF[0].cpu().numpy(), new_s["mF"].transpose(0, 2, 3, 4, 1))
+    assert_close("mF", tr.mF[0].cpu().numpy(), new_s["mF"])
     a, _ = errs(tr.mG[0].cpu().numpy(), new_s["mG"])
     print(f"mG (density + L_rec transform gradient), gather {cell_kernel}: rel err {a:.2e}")
     assert a < 1e-3
@@ -591,7 +591,7 @@ def _central_difference_check(host, dirs, h, x, wts_seed, tol, name):
     step = {"G": hp["G"].astype(np.float64) - hm["G"], "F": hp["F"].astype(np.float64) - hm["F"],
             "W": [a.astype(np.float64) - b for a, b in zip(hp["W"], hm["W"])]}
     pred = float((dG.cpu().numpy().astype(np.float64) * step["G"]).sum()
-                 + (dF.cpu().numpy().transpose(0, 4, 1, 2, 3).astype(np.float64) * step["F"]).sum()
+                 + (dF.cpu().numpy().astype(np.float64) * step["F"]).sum()
                  + sum((g.cpu().numpy().astype(np.float64) * d).sum() for g, d in zip(dW, step["W"])))
 
     def L(hh):
@@ -651,7 +651,7 @@ def test_adjoint_2e20_points_sampled_vertices_and_partition():
     sub = x[:s][keep]
     dFs, dGs, dWs = A().apmg_backward(model, soa(sub), torch.from_numpy(wa[:s][keep]).to(DEV))
     go = O.backward(f64(host), sub.astype(np.float64), wa[:s][keep].astype(np.float64))
-    assert_close("slice dF", dFs.cpu().numpy(), go["dF"].transpose(0, 2, 3, 4, 1))
+    assert_close("slice dF", dFs.cpu().numpy(), go["dF"])
     assert_close("slice dG", dGs.cpu().numpy(), go["dG"])
     for k in range(3):
         assert_close(f"slice dW{k + 1}", dWs[k].cpu().numpy(), go["dW"][k])
@@ -672,7 +672,7 @@ def test_adjoint_2e20_points_sampled_vertices_and_partition():
             continue                                # a pre-activation within float32 reach of 0
         go = O.backward(f64(host), sub.astype(np.float64), wa[sel].astype(np.float64), cache)
         want = go["dF"][g, :, v[2], v[1], v[0]]
-        got = dF[g, v[2], v[1], v[0], :]
+        got = dF[g, :, v[2], v[1], v[0]]
         err = np.max(np.abs(got - want))
         print(f"vertex g={g} v={tuple(v)} points={sel.sum()} want={want} err={err:.2e}")
         assert err <= 1e-5 * max(np.max(np.abs(want)), 1e-2 * scale)
@@ -705,7 +705,7 @@ def test_render_shape_backward_2e20_points():
     sub, ws_ = x[:s][keep], w[:s][keep]
     g_ = A().apmg_backward(model, soa(sub), torch.from_numpy(ws_).to(DEV))
     go = O.backward(f64(host), sub.astype(np.float64), ws_.astype(np.float64))
-    assert_close("slice dF", g_[0].cpu().numpy(), go["dF"].transpose(0, 2, 3, 4, 1))
+    assert_close("slice dF", g_[0].cpu().numpy(), go["dF"])
     assert_close("slice dG", g_[1].cpu().numpy(), go["dG"])
     for k in range(3):
         assert_close(f"slice dW{k + 1}", g_[2][k].cpu().numpy(), go["dW"][k])
@@ -718,7 +718,7 @@ def test_render_shape_backward_2e20_points():
     # sanity bound only
     mb = A().Model.from_host(host, DEV, mlp_dtype=A().BF16)
     gb = A().apmg_backward(mb, soa(sub), torch.from_numpy(ws_).to(DEV))
-    for name, got, want in (("dF", gb[0].cpu().numpy(), go["dF"].transpose(0, 2, 3, 4, 1)),
+    for name, got, want in (("dF", gb[0].cpu().numpy(), go["dF"]),
                             ("dG", gb[1].cpu().numpy(), go["dG"]),
                             ("dW1", gb[2][0].cpu().numpy(), go["dW"][0]),
                             ("dW2", gb[2][1].cpu().numpy(), go["dW"][1]),
@@ -726,3 +726,58 @@ def test_render_shape_backward_2e20_points():
         a, _ = errs(got, want)
         print(f"render bf16 backward {name}: normwise {a:.2e}")
         assert a < 0.2
+
+
+# --------------------------------------------------------------------------- boundary layouts
+def test_abi_paper_order_grids_and_4x4_transforms():
+    # The boundary takes the encoder tensor in the paper's [M, C, D, H, W] order (Sec. 4.1.1)
+    # and the full 4x4 matrices of Eq. (1) (row 3 is never read: filled with junk here), and
+    # returns dF and dG in those shapes (row 3 of dG zero).  A caller that keeps its grids
+    # channel-last and its transforms as 3x4 gets bitwise the same values.
+    A_ = A()
+    host = host_model(8, 2, 8, 64, extra_t=0.1)
+    x = kink_free(host, make_points(3001))
+    n = x.shape[0]
+    df = np.random.default_rng(41).normal(size=n).astype(np.float32)
+    G4 = np.zeros((8, 4, 4), np.float32)
+    G4[:, :3, :] = host["G"]
+    G4[:, 3, :] = [7.0, -3.0, np.nan, 2.0]
+    W = [torch.from_numpy(w).to(DEV) for w in host["W"]]
+    F = torch.from_numpy(host["F"]).to(DEV)
+    m4 = A_.Model(torch.from_numpy(G4).to(DEV), F, W, host["vmin"], host["vmax"])
+    pts, dft = soa(x), torch.from_numpy(df).to(DEV)
+    f = A_.apmg_forward(m4, pts)
+    want, _ = O.forward(f64(host), x.astype(np.float64))
+    assert_close("forward (paper order, 4x4)", f.cpu().numpy(), want)
+    dF, dG, dW = A_.apmg_backward(m4, pts, dft)
+    assert tuple(dF.shape) == (8, 2, 8, 8, 8) and tuple(dG.shape) == (8, 4, 4)
+    assert torch.all(dG[:, 3, :] == 0)
+    go = O.backward(f64(host), x.astype(np.float64), df.astype(np.float64))
+    assert_close("dF (paper order)", dF.cpu().numpy(), go["dF"])
+    assert_close("dG (4x4)", dG[:, :3, :].cpu().numpy(), go["dG"])
+    for k in range(3):
+        assert_close(f"dW{k + 1}", dW[k].cpu().numpy(), go["dW"][k])
+    # channel-last grids, 3x4 transforms
+    Fcl = A_.apmg_convert_grids(F, True)
+    mcl = A_.Model(torch.from_numpy(host["G"]).to(DEV), Fcl, W, host["vmin"], host["vmax"], layout=A_.GRIDS_MRRRC)
+    assert torch.equal(A_.apmg_forward(mcl, pts), f)
+    dF2, dG2, dW2 = A_.apmg_backward(mcl, pts, dft)
+    assert torch.equal(A_.apmg_convert_grids(dF2, False), dF)
+    assert torch.equal(dG2, dG[:, :3, :])
+    for k in range(3):
+        assert torch.equal(dW2[k], dW[k])
+    # the density loss with 4x4 transforms
+    err = torch.from_numpy((np.random.default_rng(42).uniform(0, 1, n) ** 2).astype(np.float32)).to(DEV)
+    l4, g4, _ = A_.apmg_density_loss(m4, pts, err)
+    l3, g3, _ = A_.apmg_density_loss(mcl, pts, err)
+    assert l4.item() == l3.item()
+    assert torch.equal(g4[:, :3, :], g3) and torch.all(g4[:, 3, :] == 0)
+    # autograd with paper-order grids and 4x4 transforms
+    Gp = torch.from_numpy(G4).to(DEV).requires_grad_(True)
+    Fp = F.clone().requires_grad_(True)
+    Wp = [w.clone().requires_grad_(True) for w in W]
+    out = A_.APMGFunction.apply(torch.from_numpy(x).to(DEV), Gp, Fp, *Wp, float(host["vmin"]),
+                                float(host["vmax"]), A_.F32)
+    (out * dft).sum().backward()
+    assert torch.equal(Fp.grad, dF) and torch.all(Gp.grad[:, 3, :] == 0)
+    assert_close("autograd dG (4x4)", Gp.grad[:, :3, :].cpu().numpy(), go["dG"])
