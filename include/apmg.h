@@ -133,6 +133,23 @@ typedef struct apmg_model {
 apmg_status apmg_forward(const apmg_model* model, const float* pts, int64_t ld, int64_t n,
                          float* f, void* ws, size_t ws_bytes, hipStream_t stream);
 
+/* ---------------------------------------------------------------- forward without a workspace
+ * For callers that cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): apmg_forward with no workspace
+ * argument.  Its scratch (swizzled MLP operands, and for paper-order grids or 4x4
+ * transforms their gather copies) lives in one static device array per GPU of
+ * apmg_forward_noalloc_scratch_bytes() = 16 MiB, held until the process ends; the call
+ * allocates nothing.  It takes the direct tile path for every n (no spatial sort), so
+ * each output is bitwise the value apmg_forward gives.  APMG_EWORKSPACE when the model's
+ * scratch exceeds the array (for example paper-order grids of more than about 15 MiB:
+ * pass them channel-last, APMG_GRIDS_MRRRC, which needs no copy); APMG_EHIP when the
+ * array's device address cannot be had.  Every call on one GPU shares that GPU's array:
+ * calls that overlap on one GPU (two streams, two host threads) race and must be
+ * serialised by the caller.  Other arguments and errors as apmg_forward. */
+apmg_status apmg_forward_noalloc(const apmg_model* model, const float* pts, int64_t ld, int64_t n,
+                                 float* f, hipStream_t stream);
+size_t apmg_forward_noalloc_scratch_bytes(void);
+
 /* ---------------------------------------------------------------- adjoint
  * Gradients of L = sum_n df[n] * f(x_n), computed by recomputing the
  * forward pass for each tile of points and back-propagating by hand

@@ -83,6 +83,8 @@ class ApmgControl(ctypes.Structure):
 
 _sigs = {
     "apmg_forward": [ctypes.POINTER(ApmgModel), c_p, c_i64, c_i64, c_p, c_p, ctypes.c_size_t, c_p],
+    "apmg_forward_noalloc": [ctypes.POINTER(ApmgModel), c_p, c_i64, c_i64, c_p, c_p],
+    "apmg_forward_noalloc_scratch_bytes": [],
     "apmg_backward": [ctypes.POINTER(ApmgModel), c_p, c_i64, c_i64, c_p, c_p, c_p, c_p, c_u32, c_p,
                       ctypes.c_size_t, c_p],
     "apmg_density_loss": [ctypes.POINTER(ApmgModel), c_p, c_i64, c_i64, c_p, c_f64, c_i32, c_p, c_p, c_p,
@@ -109,6 +111,7 @@ for _name, _args in _sigs.items():
     _fn.argtypes = _args
     _fn.restype = ctypes.c_int
 _lib.apmg_workspace_bytes.restype = ctypes.c_size_t
+_lib.apmg_forward_noalloc_scratch_bytes.restype = ctypes.c_size_t
 _lib.apmg_status_string.restype = ctypes.c_char_p
 
 EXPORTS = tuple(_sigs)
@@ -217,6 +220,18 @@ def apmg_forward(model: Model, pts_soa, n=None, ld=None, out=None, ws=None):
     ws = _workspace(OP_FORWARD, m, n, dev) if ws is None else ws
     _check("apmg_forward", _lib.apmg_forward(ctypes.byref(m), _ptr(pts_soa), ld, n, _ptr(f), _ptr(ws),
                                              ws.numel(), _stream(dev)))
+    return f
+
+
+def apmg_forward_noalloc(model: Model, pts_soa, n=None, ld=None, out=None):
+    """apmg_forward without a workspace (the library's static per-device scratch); f[n]."""
+    n = pts_soa.shape[1] if n is None else n
+    ld = pts_soa.shape[1] if ld is None else ld
+    dev = model.G.device
+    m = model.struct()
+    f = torch.empty(n, dtype=torch.float32, device=dev) if out is None else out
+    _check("apmg_forward_noalloc", _lib.apmg_forward_noalloc(ctypes.byref(m), _ptr(pts_soa), ld, n, _ptr(f),
+                                                             _stream(dev)))
     return f
 
 

@@ -220,7 +220,9 @@ void take_sort(Carver& cv, int64_t n, int nb, bool with_f, SortWs* o);
 // scattered back to the caller's order.
 constexpr int64_t kFwdSortMin = (int64_t)1 << 15;
 struct FwdWs { void* swz; float* w3s; bool sorted; SortWs srt; float* fs; OpsWs ops; };
-size_t fwd_ws(const Shape& s, const apmg_model* m, int64_t n, void* ws, FwdWs* o) {
+// sortable = false: the direct tile path for every n (the sort only orders the work; each
+// output is bitwise the same either way)
+size_t fwd_ws(const Shape& s, const apmg_model* m, int64_t n, void* ws, FwdWs* o, bool sortable = true) {
   Carver cv(ws);
   const bool bf = m->mlp_dtype == APMG_BF16;
   const size_t esz = bf ? 2 : 4;
@@ -228,7 +230,7 @@ size_t fwd_ws(const Shape& s, const apmg_model* m, int64_t n, void* ws, FwdWs* o
   take_ops(cv, s, 1, g_rows(m) == 4, paper_grids(m), m->grid_dtype == APMG_F16, &w.ops);
   w.swz = cv.take<char>(swz_sizes(s).total() * esz);
   w.w3s = cv.take<float>(s.H);
-  w.sorted = n >= kFwdSortMin;
+  w.sorted = sortable && n >= kFwdSortMin;
   w.fs = nullptr;
   if (w.sorted) {
     take_sort(cv, n, 1, false, &w.srt);
@@ -615,18 +617,29 @@ size_t apmg_workspace_bytes(int op, const void* mb, int64_t n) {
   return 0;
 }
 
-apmg_status apmg_forward(const apmg_model* m, const float* pts, int64_t ld, int64_t n, float* f, void* ws,
-                         size_t ws_bytes, hipStream_t st) {
+}  // extern "C"
+
+// The forward pass's scratch for callers that cannot allocate: one array per device, held
+// until the process ends.  In host code `scratch` names a host-side stand-in; the device
+// address comes from hipGetSymbolAddress, once per device with that device current, and
+// only that address is passed on.
+constexpr size_t kScratchBytes = (size_t)16 << 20;
+static __device__ __align__(256) char scratch[kScratchBytes];
+
+namespace {
+// apmg_forward on a given workspace; sortable = false keeps to the direct tile path.
+apmg_status forward_impl(const apmg_model* m, const float* pts, int64_t ld, int64_t n, float* f, void* ws,
+                         size_t ws_bytes, hipStream_t st, bool sortable) {
   Shape s;
   apmg_status rc = check_model(m, true, &s);
   if (rc != APMG_OK) return rc;
   if ((rc = check_points(pts, ld, n)) != APMG_OK) return rc;
   if (n > 0 && !f) return APMG_EINVAL;
   const bool bf = m->mlp_dtype == APMG_BF16, gf16 = m->grid_dtype == APMG_F16;
-  if (ws_bytes < fwd_ws(s, m, n, nullptr, nullptr) || !ws) return APMG_EWORKSPACE;
+  if (ws_bytes < fwd_ws(s, m, n, nullptr, nullptr, sortable) || !ws) return APMG_EWORKSPACE;
   if (n == 0) return APMG_OK;
   FwdWs w;
-  fwd_ws(s, m, n, ws, &w);
+  fwd_ws(s, m, n, ws, &w, sortable);
   const float* Gc;
   const void* Fc;
   hipError_t e = launch_ops(s, 1, m->G, g_rows(m), m->F, gf16, paper_grids(m), w.ops, gf16, st, &Gc, &Fc);
@@ -649,6 +662,41 @@ apmg_status apmg_forward(const apmg_model* m, const float* pts, int64_t ld, int6
   if (w.sorted) hipLaunchKernelGGL(k_dd_scatter, dim3(grid1(n)), dim3(256), 0, st, w.fs, w.srt.v0, n, f);
   return hip_status(hipGetLastError());
 }
+
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+void* device_scratch() {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return nullptr;
+    g_scratch_ptr[dev] = ptr;
+  }
+  return g_scratch_ptr[dev];
+}
+}  // namespace
+
+extern "C" {
+
+apmg_status apmg_forward(const apmg_model* m, const float* pts, int64_t ld, int64_t n, float* f, void* ws,
+                         size_t ws_bytes, hipStream_t st) {
+  return forward_impl(m, pts, ld, n, f, ws, ws_bytes, st, true);
+}
+
+apmg_status apmg_forward_noalloc(const apmg_model* m, const float* pts, int64_t ld, int64_t n, float* f,
+                                 hipStream_t st) {
+  Shape s;
+  apmg_status rc = check_model(m, true, &s);
+  if (rc != APMG_OK) return rc;
+  if (fwd_ws(s, m, n, nullptr, nullptr, false) > kScratchBytes) return APMG_EWORKSPACE;
+  void* ws = device_scratch();
+  if (!ws) return APMG_EHIP;
+  return forward_impl(m, pts, ld, n, f, ws, kScratchBytes, st, false);
+}
+
+size_t apmg_forward_noalloc_scratch_bytes(void) { return kScratchBytes; }
 
 apmg_status apmg_backward(const apmg_model* m, const float* pts, int64_t ld, int64_t n, const float* df,
                           float* dF, double* dG, float* const* dW, uint32_t flags, void* ws, size_t ws_bytes,
