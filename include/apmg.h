@@ -288,7 +288,7 @@ apmg_status apmg_dd_forward(const apmg_dd_models* models, const apmg_brick_table
  * device runs entirely on `stream`. */
 /* Launch shapes of the training step (fields of 0 take the defaults).
  *   tile_blocks: blocks of the fused forward+adjoint tile kernel per model
- *     (each block = 4 waves of 32-point tiles); default CUs / nb when nb divides
+ *     (each block = 8 or 4 waves of 32-point tiles); default CUs / nb when nb divides
  *     the device's compute units (one round of blocks), else ceil(2 CUs / nb); at
  *     most 4 times the default and at most the number of 4-tile groups.
  *   cell_kernel: grid-gradient gather, 1 = one wave per 4x4x4 block of cells
@@ -300,17 +300,24 @@ apmg_status apmg_dd_forward(const apmg_dd_models* models, const apmg_brick_table
  *   cell_group: lanes per candidate run of the wave gather, 1, 2, 4 or 8
  *     (default 4): the wave splits its candidates into 64 / cell_group runs
  *     and each group of lanes reads cell_group consecutive points per step.
+ *   adjoint_kernel: the fused forward + adjoint tile kernel for shapes with hidden
+ *     width 64 and at most 64 input features, 1 = eight waves per block, two per
+ *     SIMD, each wave accumulating one block of the weight gradients over the
+ *     tiles of the whole block (the default), 2 = four waves per block, one per
+ *     SIMD, each wave accumulating all of them over its own tiles.
  * The two gathers add each cell's terms in different fixed orders (the
  * per-cell thread in point order, the wave in its own step-then-lane order),
  * so the grid gradients agree to float32 rounding; cell_unroll does not
- * change the order, cell_group does.  Results also depend on tile_blocks through the order of
- * the weight-gradient sums.  Each setting is bitwise reproducible run to run. */
+ * change the order, cell_group does.  Results also depend on tile_blocks and
+ * adjoint_kernel through the order of the weight-gradient sums.  Each setting is
+ * bitwise reproducible run to run. */
 typedef struct apmg_tuning {
   int32_t tile_blocks;
   int32_t cell_unroll;
   int32_t cell_kernel;
   int32_t cell_group;
-  int32_t reserved[4];
+  int32_t adjoint_kernel;
+  int32_t reserved[3];
 } apmg_tuning;
 
 typedef struct apmg_batch {

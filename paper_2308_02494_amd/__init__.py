@@ -52,7 +52,7 @@ class ApmgBrickTable(ctypes.Structure):
 
 class ApmgTuning(ctypes.Structure):
     _fields_ = [("tile_blocks", c_i32), ("cell_unroll", c_i32), ("cell_kernel", c_i32), ("cell_group", c_i32),
-                ("reserved", c_i32 * 4)]
+                ("adjoint_kernel", c_i32), ("reserved", c_i32 * 3)]
 
 
 class ApmgBatch(ctypes.Structure):
@@ -427,6 +427,7 @@ class Trainer:
             t.cell_unroll = tuning.get("cell_unroll", 0)
             t.cell_kernel = tuning.get("cell_kernel", 0)
             t.cell_group = tuning.get("cell_group", 0)
+            t.adjoint_kernel = tuning.get("adjoint_kernel", 0)
             tuning = t
         self.tuning = tuning
         self.batch.tuning = ctypes.pointer(tuning) if tuning is not None else None

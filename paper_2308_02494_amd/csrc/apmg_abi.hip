@@ -87,7 +87,7 @@ int tile_blocks(int64_t n) {
 // 1024, and the number of 4-tile groups; gather batch of 2, 4 or 8 candidates; lanes per
 // candidate run of the wave gather, 1, 2, 4 or 8.
 constexpr int kDefaultCellGroup = 4;
-struct Tune { int tile_blocks; int cell_unroll; int cell_kernel; int cell_group; };
+struct Tune { int tile_blocks; int cell_unroll; int cell_kernel; int cell_group; int adjoint; };
 int step_groups(int64_t n) {
   const int64_t tiles = (std::max<int64_t>(n, 1) + 31) / 32;
   return (int)std::max<int64_t>(1, (tiles + kWavesPerBlock - 1) / kWavesPerBlock);
@@ -117,6 +117,7 @@ bool resolve_tune(const apmg_tuning* t, int64_t n, int nb, Tune* out) {
   out->cell_unroll = 4;
   out->cell_kernel = 0;
   out->cell_group = kDefaultCellGroup;
+  out->adjoint = 0;
   if (!t) return true;
   if (t->tile_blocks < 0 || t->tile_blocks > step_max_blocks(n, nb)) return false;
   if (t->cell_unroll != 0 && t->cell_unroll != 2 && t->cell_unroll != 4 && t->cell_unroll != 8) return false;
@@ -127,6 +128,8 @@ bool resolve_tune(const apmg_tuning* t, int64_t n, int nb, Tune* out) {
   if (t->cell_unroll > 0) out->cell_unroll = t->cell_unroll;
   if (t->cell_kernel > 0) out->cell_kernel = t->cell_kernel - 1;
   if (t->cell_group > 0) out->cell_group = t->cell_group;
+  if (t->adjoint_kernel < 0 || t->adjoint_kernel > 2) return false;
+  out->adjoint = t->adjoint_kernel == 2 ? 1 : 0;
   return true;
 }
 
@@ -760,7 +763,8 @@ apmg_status apmg_backward(const apmg_model* m, const float* pts, int64_t ld, int
     const PartLayout pl = part_layout(s, ncols, nrows);
     a.part_len = pl.len;
     if (ps.first) prof_begin(st);
-    e = launch_tile(true, kb, a, gf16, bf, dim3(nblk, 1), backward_lds_bytes(s, ncols, nrows, bf, kb), st);
+    e = kb > 0 ? launch_adjoint(a, gf16, bf, dim3(nblk, 1), st)
+               : launch_tile(true, kb, a, gf16, bf, dim3(nblk, 1), backward_lds_bytes(s, ncols, nrows, bf, kb), st);
     if (e != hipSuccess) return APMG_EHIP;
     if (&ps == &passes.back()) prof_end(st);
     if (ncols > 0)
@@ -1074,7 +1078,9 @@ apmg_status run_step(const apmg_batch* b, const Shape& s, void* ws, const Tune& 
     const PartLayout pl = part_layout(s, ncols, nrows);
     a.part_len = pl.len;
     if (pi == 0) prof_begin(st);
-    e = launch_tile(true, kb, a, gf16, bf, dim3(nblk, nb), backward_lds_bytes(s, ncols, nrows, bf, kb), st);
+    e = (kb > 0 && tu.adjoint == 0)
+            ? launch_adjoint(a, gf16, bf, dim3(nblk, nb), st)
+            : launch_tile(true, kb, a, gf16, bf, dim3(nblk, nb), backward_lds_bytes(s, ncols, nrows, bf, kb), st);
     if (e != hipSuccess) return APMG_EHIP;
     if (pi + 1 == passes.size()) prof_end(st);
     // the last pass's reductions wait for the fork below (they overlap the gather)
@@ -1160,7 +1166,7 @@ extern "C" apmg_status apmg_autotune_batched_step(const apmg_batch* b, void* ws,
   if (hipEventCreate(&e0) != hipSuccess) return APMG_EHIP;
   if (hipEventCreate(&e1) != hipSuccess) { hipEventDestroy(e0); return APMG_EHIP; }
   float best_t = -1.f;
-  Tune best_tu = {d, 4, 0, kDefaultCellGroup};
+  Tune best_tu = {d, 4, 0, kDefaultCellGroup, 0};
   apmg_status out = APMG_OK;
   // gathers: the wave-cooperative one with 2, 4 or 8 lanes per candidate run, then one
   // thread per cell with 2, 4 or 8 candidates per batch
@@ -1169,7 +1175,7 @@ extern "C" apmg_status apmg_autotune_batched_step(const apmg_batch* b, void* ws,
                             {1, 4, kDefaultCellGroup}, {1, 8, kDefaultCellGroup}};
   for (int tb : blocks) {
     for (const Gather& ga : gathers) {
-      const Tune tu = {tb, ga.unroll, ga.kernel, ga.group};
+      const Tune tu = {tb, ga.unroll, ga.kernel, ga.group, 0};
       if ((rc = run_step(b, s, ws, tu, false, st)) != APMG_OK) { out = rc; break; }   // warm-up
       if (hipEventRecord(e0, st) != hipSuccess) { out = APMG_EHIP; break; }
       for (int r = 0; r < 3 && rc == APMG_OK; ++r) rc = run_step(b, s, ws, tu, false, st);
@@ -1190,6 +1196,7 @@ extern "C" apmg_status apmg_autotune_batched_step(const apmg_batch* b, void* ws,
   best->cell_unroll = best_tu.cell_unroll;
   best->cell_kernel = best_tu.cell_kernel + 1;
   best->cell_group = best_tu.cell_group;
+  best->adjoint_kernel = best_tu.adjoint + 1;
   if (best_ms) *best_ms = best_t;
   return APMG_OK;
 }

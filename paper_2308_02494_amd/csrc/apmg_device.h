@@ -20,13 +20,22 @@ constexpr int kWavesPerBlock = kBlock / kWave;
 constexpr float kSMax = 87.0f;  // exp(-s) is taken as 0 above this (float32 range)
 
 // ------------------------------------------------------------ bf16
-__device__ inline uint16_t bf16_bits(float f) {
-  uint32_t u = __float_as_uint(f);
-  if ((u & 0x7f800000u) == 0x7f800000u) return (uint16_t)((u >> 16) | ((u & 0xffff) ? 0x40 : 0));
-  u += 0x7fffu + ((u >> 16) & 1u);  // round to nearest even
-  return (uint16_t)(u >> 16);
+// float -> bf16, round to nearest even (NaN stays NaN): gfx950's v_cvt_pk_bf16_f32, which
+// converts two values per instruction.
+typedef __bf16 bf16x2n __attribute__((ext_vector_type(2)));
+typedef float f32x2n __attribute__((ext_vector_type(2)));
+__device__ inline uint16_t bf16_bits(float f) { return __builtin_bit_cast(uint16_t, (__bf16)f); }
+__device__ inline uint32_t bf16_pack2(float a, float b) {
+  const f32x2n x = {a, b};
+  return __builtin_bit_cast(uint32_t, __builtin_convertvector(x, bf16x2n));   // a in the low half
 }
 __device__ inline float bf16_to_f32(uint16_t b) { return __uint_as_float(((uint32_t)b) << 16); }
+// Eight floats as an MFMA bf16 operand (element e in bits 16(e%2).. of word e/2).
+__device__ inline bf16x8 bf16_pack8(const float v[8]) {
+  typedef uint32_t u32x4n __attribute__((ext_vector_type(4)));
+  const u32x4n w = {bf16_pack2(v[0], v[1]), bf16_pack2(v[2], v[3]), bf16_pack2(v[4], v[5]), bf16_pack2(v[6], v[7])};
+  return __builtin_bit_cast(bf16x8, w);
+}
 
 // ------------------------------------------------------------ MFMA wrappers
 // v_mfma_f32_32x32x2_f32: A[i][k] in lane i + 32k, B[k][j] in lane j + 32k,

@@ -8,6 +8,7 @@
 #include "apmg_kernels.h"
 
 #include "apmg_mlp.hip"
+#include "apmg_adjoint.hip"
 #include "apmg_misc.hip"
 #include "apmg_sort.hip"
 #include "apmg_dd.hip"

@@ -186,7 +186,7 @@ __device__ inline void tile_fwd(const Shape& s, const float* sG, const void* F, 
     constexpr int GPS = 8 / C;   // grids per 8-feature operand step (even for C = 1, 2, 4)
     const int S1 = s.KHP / 8;
     for (int st = 0; st < S1; ++st) {
-      bf16x8 B;
+      float Bv[8];
 #pragma unroll
       for (int u = 0; u < GPS; ++u) {
         const int gi = st * GPS + u;
@@ -202,11 +202,12 @@ __device__ inline void tile_fwd(const Shape& s, const float* sG, const void* F, 
         }
 #pragma unroll
         for (int c = 0; c < C; ++c) {
-          B[u * C + c] = (short)bf16_bits(e[c]);
+          Bv[u * C + c] = e[c];
           const int t = 8 * st + u * C + c;
           if constexpr (STY) tt_put<BF>(Ty, 32 * (t >> 4) + 16 * hf + (t & 15), lane & 31, e[c]);
         }
       }
+      const bf16x8 B = bf16_pack8(Bv);
 #pragma unroll
       for (int b = 0; b < NB; ++b) z1[b] = mma_bf16(W1[(b * S1 + st) * 64 + lane], B, z1[b]);
     }
@@ -229,9 +230,10 @@ __device__ inline void tile_fwd(const Shape& s, const float* sG, const void* F, 
     const bf16x8* W2 = (const bf16x8*)((const uint16_t*)swz + (size_t)2 * H * s.KHP);
 #pragma unroll
     for (int st = 0; st < H / 16; ++st) {
-      bf16x8 B;
+      float Bv[8];
 #pragma unroll
-      for (int e = 0; e < 8; ++e) B[e] = (short)bf16_bits(fmaxf(z1[st >> 1][8 * (st & 1) + e], 0.f));
+      for (int e = 0; e < 8; ++e) Bv[e] = fmaxf(z1[st >> 1][8 * (st & 1) + e], 0.f);
+      const bf16x8 B = bf16_pack8(Bv);
 #pragma unroll
       for (int b = 0; b < NB; ++b) z2[b] = mma_bf16(W2[((size_t)b * (H / 16) + st) * 64 + lane], B, z2[b]);
     }
@@ -555,9 +557,10 @@ __global__ void __launch_bounds__(kBlock) k_backward(TileArgs a) {
     } else {
 #pragma unroll
       for (int st = 0; st < H / 16; ++st) {
-        bf16x8 B;
+        float Bv[8];
 #pragma unroll
-        for (int e = 0; e < 8; ++e) B[e] = (short)bf16_bits(d2[st >> 1][8 * (st & 1) + e]);
+        for (int e = 0; e < 8; ++e) Bv[e] = d2[st >> 1][8 * (st & 1) + e];
+        const bf16x8 B = bf16_pack8(Bv);
 #pragma unroll
         for (int b = 0; b < NB; ++b) d1[b] = mma_bf16(W2Tb[((size_t)b * (H / 16) + st) * 64 + lane], B, d1[b]);
       }
@@ -598,9 +601,10 @@ __global__ void __launch_bounds__(kBlock) k_backward(TileArgs a) {
       } else {
 #pragma unroll
         for (int st = 0; st < H / 16; ++st) {
-          bf16x8 B;
+          float Bv[8];
 #pragma unroll
-          for (int e = 0; e < 8; ++e) B[e] = (short)bf16_bits(d1[st >> 1][8 * (st & 1) + e]);
+          for (int e = 0; e < 8; ++e) Bv[e] = d1[st >> 1][8 * (st & 1) + e];
+          const bf16x8 B = bf16_pack8(Bv);
           dy = mma_bf16(W1Tb[((size_t)blk * (H / 16) + st) * 64 + lane], B, dy);
         }
       }
