@@ -301,10 +301,12 @@ apmg_status apmg_dd_forward(const apmg_dd_models* models, const apmg_brick_table
  *     (default 4): the wave splits its candidates into 64 / cell_group runs
  *     and each group of lanes reads cell_group consecutive points per step.
  *   adjoint_kernel: the fused forward + adjoint tile kernel for shapes with hidden
- *     width 64 and at most 64 input features, 1 = eight waves per block, two per
- *     SIMD, each wave accumulating one block of the weight gradients over the
- *     tiles of the whole block (the default), 2 = four waves per block, one per
- *     SIMD, each wave accumulating all of them over its own tiles.
+ *     width 64 and at most 64 input features.  The tiled kernels (each wave keeps
+ *     one 32x32 block of dW1 and of dW2 and accumulates it over the tiles of its
+ *     whole block, two waves per SIMD): 1 = eight waves per block, one block per
+ *     CU; 2 = four waves per block, two blocks per CU (bf16: its LDS allows it);
+ *     0 (default) = 1 for a float32 MLP, 2 for bf16.  3 = four waves per block,
+ *     one per SIMD, each wave accumulating all of dW1 and dW2 over its own tiles.
  * The two gathers add each cell's terms in different fixed orders (the
  * per-cell thread in point order, the wave in its own step-then-lane order),
  * so the grid gradients agree to float32 rounding; cell_unroll does not

@@ -87,6 +87,8 @@ int tile_blocks(int64_t n) {
 // 1024, and the number of 4-tile groups; gather batch of 2, 4 or 8 candidates; lanes per
 // candidate run of the wave gather, 1, 2, 4 or 8.
 constexpr int kDefaultCellGroup = 4;
+// adjoint: 0 = tiled adjoint, waves per block by dtype; 1 = eight waves; 2 = four waves;
+// 3 = the one-wave-per-SIMD register kernel.
 struct Tune { int tile_blocks; int cell_unroll; int cell_kernel; int cell_group; int adjoint; };
 int step_groups(int64_t n) {
   const int64_t tiles = (std::max<int64_t>(n, 1) + 31) / 32;
@@ -102,7 +104,11 @@ int device_cus() {
   return cus;
 }
 // apmg_backward: one round of the adjoint kernel's blocks (one per CU), at most one per 4 tiles.
-int bwd_blocks(int64_t n) { return std::max(1, std::min(tile_blocks(n), device_cus())); }
+// (two rounds when the tiled adjoint runs four-wave blocks, two per CU)
+int bwd_blocks(int64_t n, bool bf) {
+  const int cap = adjoint_waves(0, bf) == 4 ? 2 * device_cus() : device_cus();
+  return std::max(1, std::min(tile_blocks(n), cap));
+}
 int step_default_blocks(int64_t n, int nb) {
   const int cus = device_cus();
   const int one = (cus + nb - 1) / nb;
@@ -112,13 +118,21 @@ int step_default_blocks(int64_t n, int nb) {
 int step_max_blocks(int64_t n, int nb) {
   return std::max(1, std::min(std::min(4 * step_default_blocks(n, nb), 1024), step_groups(n)));
 }
-bool resolve_tune(const apmg_tuning* t, int64_t n, int nb, Tune* out) {
+bool resolve_tune(const apmg_tuning* t, int64_t n, int nb, bool bf, Tune* out) {
   out->tile_blocks = step_default_blocks(n, nb);
   out->cell_unroll = 4;
   out->cell_kernel = 0;
   out->cell_group = kDefaultCellGroup;
   out->adjoint = 0;
-  if (!t) return true;
+  // four-wave tiled adjoint blocks run two per compute unit
+  const auto two_per_cu = [&]() {
+    if (out->adjoint < 3 && adjoint_waves(out->adjoint, bf) == 4)
+      out->tile_blocks = std::min(2 * out->tile_blocks, step_max_blocks(n, nb));
+  };
+  if (!t) {
+    two_per_cu();
+    return true;
+  }
   if (t->tile_blocks < 0 || t->tile_blocks > step_max_blocks(n, nb)) return false;
   if (t->cell_unroll != 0 && t->cell_unroll != 2 && t->cell_unroll != 4 && t->cell_unroll != 8) return false;
   if (t->cell_kernel < 0 || t->cell_kernel > 2) return false;
@@ -128,8 +142,9 @@ bool resolve_tune(const apmg_tuning* t, int64_t n, int nb, Tune* out) {
   if (t->cell_unroll > 0) out->cell_unroll = t->cell_unroll;
   if (t->cell_kernel > 0) out->cell_kernel = t->cell_kernel - 1;
   if (t->cell_group > 0) out->cell_group = t->cell_group;
-  if (t->adjoint_kernel < 0 || t->adjoint_kernel > 2) return false;
-  out->adjoint = t->adjoint_kernel == 2 ? 1 : 0;
+  if (t->adjoint_kernel < 0 || t->adjoint_kernel > 3) return false;
+  out->adjoint = t->adjoint_kernel;
+  if (t->tile_blocks == 0) two_per_cu();
   return true;
 }
 
@@ -389,7 +404,7 @@ size_t bwd_ws(const Shape& s, const apmg_model* m, int64_t n, void* ws, BwdWs* o
   take_ops(cv, s, 1, g_rows(m) == 4, paper_grids(m), m->grid_dtype == APMG_F16, &w.ops);
   w.f.swz = cv.take<char>(swz_sizes(s).total() * esz);
   w.f.w3s = cv.take<float>(s.H);
-  w.part = cv.take<double>((size_t)bwd_blocks(n) * max_part_len(s, bf));
+  w.part = cv.take<double>((size_t)bwd_blocks(n, bf) * max_part_len(s, bf));
   take_sort(cv, n, 1, true, &w.srt);
   take_cell(cv, s, n, 1, &w.cell);
   w.act = nullptr;
@@ -741,7 +756,7 @@ apmg_status apmg_backward(const apmg_model* m, const float* pts, int64_t ld, int
   if (e != hipSuccess) return APMG_EHIP;
   e = launch_swizzle(s, bf, m->W[0], m->W[1], m->W[2], 0, w.f.swz, 0, w.f.w3s, 1, st);
   if (e != hipSuccess) return APMG_EHIP;
-  const int nblk = bwd_blocks(n);
+  const int nblk = bwd_blocks(n, bf);
   const bool want_cells = dF || dG;
   const int kb = (!use_act && passes.size() == 1) ? register_kb(s) : 0;
   for (const Pass& ps : passes) {
@@ -763,7 +778,7 @@ apmg_status apmg_backward(const apmg_model* m, const float* pts, int64_t ld, int
     const PartLayout pl = part_layout(s, ncols, nrows);
     a.part_len = pl.len;
     if (ps.first) prof_begin(st);
-    e = kb > 0 ? launch_adjoint(a, gf16, bf, dim3(nblk, 1), st)
+    e = kb > 0 ? launch_adjoint(a, gf16, bf, 0, dim3(nblk, 1), st)
                : launch_tile(true, kb, a, gf16, bf, dim3(nblk, 1), backward_lds_bytes(s, ncols, nrows, bf, kb), st);
     if (e != hipSuccess) return APMG_EHIP;
     if (&ps == &passes.back()) prof_end(st);
@@ -1078,8 +1093,8 @@ apmg_status run_step(const apmg_batch* b, const Shape& s, void* ws, const Tune& 
     const PartLayout pl = part_layout(s, ncols, nrows);
     a.part_len = pl.len;
     if (pi == 0) prof_begin(st);
-    e = (kb > 0 && tu.adjoint == 0)
-            ? launch_adjoint(a, gf16, bf, dim3(nblk, nb), st)
+    e = (kb > 0 && tu.adjoint < 3)
+            ? launch_adjoint(a, gf16, bf, tu.adjoint, dim3(nblk, nb), st)
             : launch_tile(true, kb, a, gf16, bf, dim3(nblk, nb), backward_lds_bytes(s, ncols, nrows, bf, kb), st);
     if (e != hipSuccess) return APMG_EHIP;
     if (pi + 1 == passes.size()) prof_end(st);
@@ -1144,7 +1159,7 @@ extern "C" apmg_status apmg_batched_step(const apmg_batch* b, void* ws, size_t w
   apmg_status rc = check_batch(b, &s);
   if (rc != APMG_OK) return rc;
   Tune tu;
-  if (!resolve_tune(b->tuning, b->n, b->nb, &tu)) return APMG_EINVAL;
+  if (!resolve_tune(b->tuning, b->n, b->nb, b->shape.mlp_dtype == APMG_BF16, &tu)) return APMG_EINVAL;
   if (!ws || ws_bytes < step_ws(b, s, nullptr, nullptr)) return APMG_EWORKSPACE;
   return run_step(b, s, ws, tu, true, st);
 }
@@ -1196,7 +1211,7 @@ extern "C" apmg_status apmg_autotune_batched_step(const apmg_batch* b, void* ws,
   best->cell_unroll = best_tu.cell_unroll;
   best->cell_kernel = best_tu.cell_kernel + 1;
   best->cell_group = best_tu.cell_group;
-  best->adjoint_kernel = best_tu.adjoint + 1;
+  best->adjoint_kernel = best_tu.adjoint;
   if (best_ms) *best_ms = best_t;
   return APMG_OK;
 }

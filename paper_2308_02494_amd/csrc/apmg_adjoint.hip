@@ -17,8 +17,6 @@
 
 namespace apmg {
 
-constexpr int kAdjWaves = 8;                     // waves per block
-constexpr int kAdjThreads = kAdjWaves * kWave;   // 512
 constexpr int kAdjPub = 4;                       // tiles published per sub-round
 constexpr int kAdjPts = kAdjPub * 32;            // points per published set
 
@@ -30,14 +28,16 @@ template <bool BF> struct AdjT {
   typedef typename std::conditional<BF, uint16_t, float>::type T;
 };
 
-// Forward pass of one tile that also keeps the tile's features (yv[t] = feature
-// hf * KH + t of this lane's point) for the first-layer weight gradient.  The grids of a
-// half are unrolled at compile time (at most 32 features per half); gathers run PD - 1
-// grids ahead of the grid being interpolated.
+// Forward pass of one tile that also keeps the tile's features for the first-layer weight
+// gradient: float32, yv[t] = feature hf * KH + t of this lane's point; bf16, the packed
+// first-layer operands yb[st] (features 8 st .. 8 st + 7) and the packed second-layer
+// operands hb[st] (h1 = relu(z1) in accumulator row order).  The grids of a half are
+// unrolled at compile time (at most 32 features per half); gathers run PD - 1 grids ahead
+// of the grid being interpolated.
 template <int C, bool GF16, bool BF, int PD>
 __device__ inline void adj_fwd(const Shape& s, const float* sG, const void* F, const void* swz, const float* w3s,
                                float x, float y, float z, bool valid, int lane, f32x16 (&z1)[2], f32x16 (&z2)[2],
-                               float& m, float (&yv)[32]) {
+                               float& m, float (&yv)[32], bf16x8 (&yb)[4], bf16x8 (&hb)[4]) {
   constexpr int GMAX = 32 / C;
   constexpr int H = 64, NB = 2;
   const int hf = lane >> 5;
@@ -46,8 +46,13 @@ __device__ inline void adj_fwd(const Shape& s, const float* sG, const void* F, c
   for (int b = 0; b < NB; ++b)
 #pragma unroll
     for (int r = 0; r < 16; ++r) z1[b][r] = 0.f;
+  if constexpr (!BF) {
 #pragma unroll
-  for (int t = 0; t < 32; ++t) yv[t] = 0.f;
+    for (int t = 0; t < 32; ++t) yv[t] = 0.f;
+  } else {
+#pragma unroll
+    for (int st = 0; st < 4; ++st) yb[st] = bf16x8{0, 0, 0, 0, 0, 0, 0, 0};
+  }
   GridTap<C> tp[PD];
   auto gidx = [&](int gi) { return gi < s.Mh ? hf * s.Mh + gi : s.M; };
 #pragma unroll
@@ -86,12 +91,10 @@ __device__ inline void adj_fwd(const Shape& s, const float* sG, const void* F, c
           float e[C];
           grid_tap_value<C>(tp[gi % PD], e);
 #pragma unroll
-          for (int c = 0; c < C; ++c) {
-            Bv[u * C + c] = e[c];
-            yv[gi * C + c] = e[c];
-          }
+          for (int c = 0; c < C; ++c) Bv[u * C + c] = e[c];
         }
         const bf16x8 B = bf16_pack8(Bv);
+        yb[st] = B;
 #pragma unroll
         for (int b = 0; b < NB; ++b) z1[b] = mma_bf16(W1[(b * S1 + st) * 64 + lane], B, z1[b]);
       }
@@ -119,6 +122,7 @@ __device__ inline void adj_fwd(const Shape& s, const float* sG, const void* F, c
 #pragma unroll
       for (int e = 0; e < 8; ++e) Bv[e] = fmaxf(z1[st >> 1][8 * (st & 1) + e], 0.f);
       const bf16x8 B = bf16_pack8(Bv);
+      hb[st] = B;
 #pragma unroll
       for (int b = 0; b < NB; ++b) z2[b] = mma_bf16(W2[((size_t)b * (H / 16) + st) * 64 + lane], B, z2[b]);
     }
@@ -163,13 +167,22 @@ __device__ inline void adj_put(typename AdjT<BF>::T* T, int row, int col, float 
   else T[(size_t)row * AdjT<BF>::P + col] = v;
 }
 
-template <int C, bool GF16, bool BF>
-__global__ void __launch_bounds__(kAdjThreads, 2) k_adjoint(TileArgs a) {
+// NW waves per block: 8 (one block per compute unit, two sub-rounds of four published
+// tiles per round) or 4 (two blocks per compute unit when the LDS allows it -- bf16 --,
+// one sub-round per round; the two blocks' barriers are independent, so the two waves of a
+// SIMD drift into different phases).  The swizzled weights are staged in LDS.  (Measured
+// at the headline workload: a deeper gather prefetch, PD = 3, changes nothing; float32
+// weights read from global memory instead of LDS, to fit two four-wave blocks per CU,
+// take twice as long.)
+template <int C, bool GF16, bool BF, int NW>
+__global__ void __launch_bounds__(NW * kWave, 8 / NW) k_adjoint(TileArgs a) {
   extern __shared__ float smem[];
   typedef typename AdjT<BF>::T TT_;
   constexpr int P = AdjT<BF>::P;
   constexpr int H = 64, NB = 2;
   constexpr int PD = 2;
+  constexpr int kAdjWaves = NW;
+  constexpr int NSUB = NW / kAdjPub;
   // logical block as in k_backward (partials indexed by it, in tile order)
   const int64_t lbl = xcd_logical(blockIdx.x + (int64_t)gridDim.x * blockIdx.y, (int64_t)gridDim.x * gridDim.y);
   const int model = (int)(lbl / gridDim.x), lb = (int)(lbl % gridDim.x);
@@ -208,19 +221,14 @@ __global__ void __launch_bounds__(kAdjThreads, 2) k_adjoint(TileArgs a) {
   const float vo = a.boff ? a.boff[model] : a.voff;
   const float* Pp = a.pts + model * a.pts_stride;
   float* dY = a.dY ? a.dY + (size_t)model * s.M * a.n * C : nullptr;
-  const float* W2T = nullptr; const bf16x8* W2Tb = nullptr;
-  const float* W1T = nullptr; const bf16x8* W1Tb = nullptr;
-  {
-    const size_t o2t = (size_t)2 * H * s.KHP + (size_t)H * H, o1t = o2t + (size_t)H * H;
-    if (BF) { W2Tb = (const bf16x8*)((const uint16_t*)swz + o2t); W1Tb = (const bf16x8*)((const uint16_t*)swz + o1t); }
-    else { W2T = (const float*)swz + o2t; W1T = (const float*)swz + o1t; }
-  }
+  const size_t o2t = (size_t)2 * H * s.KHP + (size_t)H * H, o1t = o2t + (size_t)H * H;
 
   // this wave's weight-gradient blocks: dW2 block (ib2, kb2) over published points
-  // [64 part2, +64); dW1 block (ib1, kb1) over [k1len part1, +k1len)
+  // [k2len part2, +k2len); dW1 block (ib1, kb1) over [k1len part1, +k1len)
   const int nkb1 = (s.MC + 31) / 32;
   const int B1 = 2 * nkb1, S1 = kAdjWaves / B1, k1len = kAdjPts / S1;
   const int b1 = wave % B1, part1 = wave / B1, ib1 = b1 / nkb1, kb1 = b1 % nkb1;
+  constexpr int S2 = kAdjWaves / 4, k2len = kAdjPts / S2;
   const int b2 = wave & 3, part2 = wave >> 2, ib2 = b2 >> 1, kb2 = b2 & 1;
   f32x16 acc1, acc2;
 #pragma unroll
@@ -232,6 +240,10 @@ __global__ void __launch_bounds__(kAdjThreads, 2) k_adjoint(TileArgs a) {
   const int64_t per = (ntiles + gridDim.x - 1) / gridDim.x;
   const int64_t t_beg = lb * per, t_end = min(ntiles, (lb + 1) * per);
   for (int64_t rbase = t_beg; rbase < t_end; rbase += kAdjWaves) {
+    const float* W2T = BF ? nullptr : (const float*)swz + o2t;
+    const float* W1T = BF ? nullptr : (const float*)swz + o1t;
+    const bf16x8* W2Tb = BF ? (const bf16x8*)((const uint16_t*)swz + o2t) : nullptr;
+    const bf16x8* W1Tb = BF ? (const bf16x8*)((const uint16_t*)swz + o1t) : nullptr;
     const int64_t tile = rbase + wave;
     const int64_t p = tile * 32 + j;
     const bool valid = tile < t_end && p < a.n;
@@ -240,7 +252,8 @@ __global__ void __launch_bounds__(kAdjThreads, 2) k_adjoint(TileArgs a) {
     f32x16 z1[NB], z2[NB];
     float m;
     float yv[32];
-    adj_fwd<C, GF16, BF, PD>(s, sG, F, swz, w3s, x, y, z, valid, lane, z1, z2, m, yv);
+    bf16x8 yb[4], hb[4];
+    adj_fwd<C, GF16, BF, PD>(s, sG, F, swz, w3s, x, y, z, valid, lane, z1, z2, m, yv, yb, hb);
 
     float df = 0.f;
     if (valid) {
@@ -290,6 +303,23 @@ __global__ void __launch_bounds__(kAdjThreads, 2) k_adjoint(TileArgs a) {
     for (int b = 0; b < NB; ++b)
 #pragma unroll
       for (int r = 0; r < 16; ++r) d2[b][r] = z2[b][r] > 0.f ? w3s[hf * (H / 2) + 16 * b + r] * dm : 0.f;
+    // bf16: the packed operands stand in for delta2, h1, delta1 and y from here on (the
+    // published values are bf16 as well); the ReLU pattern of z1 is kept as a bit mask
+    bf16x8 d2b[4], d1b[4];
+    uint32_t zmask = 0;
+    if constexpr (BF) {
+#pragma unroll
+      for (int st = 0; st < 4; ++st) {
+        float Bv[8];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) Bv[e] = d2[st >> 1][8 * (st & 1) + e];
+        d2b[st] = bf16_pack8(Bv);
+      }
+#pragma unroll
+      for (int b = 0; b < NB; ++b)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) zmask |= (z1[b][r] > 0.f ? 1u : 0u) << (16 * b + r);
+    }
 
     // delta1 = (W2^T delta2) * [z1 > 0]
     f32x16 d1[NB];
@@ -308,18 +338,27 @@ __global__ void __launch_bounds__(kAdjThreads, 2) k_adjoint(TileArgs a) {
     } else {
 #pragma unroll
       for (int st = 0; st < H / 16; ++st) {
-        float Bv[8];
 #pragma unroll
-        for (int e = 0; e < 8; ++e) Bv[e] = d2[st >> 1][8 * (st & 1) + e];
-        const bf16x8 B = bf16_pack8(Bv);
-#pragma unroll
-        for (int b = 0; b < NB; ++b) d1[b] = mma_bf16(W2Tb[((size_t)b * (H / 16) + st) * 64 + lane], B, d1[b]);
+        for (int b = 0; b < NB; ++b) d1[b] = mma_bf16(W2Tb[((size_t)b * (H / 16) + st) * 64 + lane], d2b[st], d1[b]);
       }
     }
+    if constexpr (!BF) {
 #pragma unroll
-    for (int b = 0; b < NB; ++b)
+      for (int b = 0; b < NB; ++b)
 #pragma unroll
-      for (int r = 0; r < 16; ++r) d1[b][r] = z1[b][r] > 0.f ? d1[b][r] : 0.f;
+        for (int r = 0; r < 16; ++r) d1[b][r] = z1[b][r] > 0.f ? d1[b][r] : 0.f;
+    } else {
+#pragma unroll
+      for (int st = 0; st < 4; ++st) {
+        float Bv[8];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+          const int b = st >> 1, r = 8 * (st & 1) + e;
+          Bv[e] = ((zmask >> (16 * b + r)) & 1u) ? d1[b][r] : 0.f;
+        }
+        d1b[st] = bf16_pack8(Bv);
+      }
+    }
 
     // dL/dy per block of 16 features of each half, stored per grid for the cell gather
     if (dY) {
@@ -337,12 +376,7 @@ __global__ void __launch_bounds__(kAdjThreads, 2) k_adjoint(TileArgs a) {
             }
           } else {
 #pragma unroll
-            for (int st = 0; st < H / 16; ++st) {
-              float Bv[8];
-#pragma unroll
-              for (int e = 0; e < 8; ++e) Bv[e] = d1[st >> 1][8 * (st & 1) + e];
-              dy = mma_bf16(W1Tb[((size_t)blk * (H / 16) + st) * 64 + lane], bf16_pack8(Bv), dy);
-            }
+            for (int st = 0; st < H / 16; ++st) dy = mma_bf16(W1Tb[((size_t)blk * (H / 16) + st) * 64 + lane], d1b[st], dy);
           }
 #pragma unroll
           for (int u = 0; u < 16 / C; ++u) {
@@ -358,32 +392,55 @@ __global__ void __launch_bounds__(kAdjThreads, 2) k_adjoint(TileArgs a) {
       }
     }
 
-    // weight gradients: two sub-rounds, each publishing four tiles (waves 4 sub .. 4 sub + 3)
+    // weight gradients: NSUB sub-rounds, each publishing four tiles (waves 4 sub .. 4 sub + 3)
     const int slot = wave & 3;
 #pragma unroll 1
-    for (int sub = 0; sub < 2; ++sub) {
+    for (int sub = 0; sub < NSUB; ++sub) {
       const bool pub = (wave >> 2) == sub;
       if (pub) {
+        if constexpr (!BF) {
 #pragma unroll
-        for (int b = 0; b < NB; ++b)
+          for (int b = 0; b < NB; ++b)
 #pragma unroll
-          for (int r = 0; r < 16; ++r) {
-            adj_put<BF>(TD, 32 * b + acc_row(r, hf), 32 * slot + j, d2[b][r]);
-            adj_put<BF>(TY, 32 * b + acc_row(r, hf), 32 * slot + j, fmaxf(z1[b][r], 0.f));
-          }
+            for (int r = 0; r < 16; ++r) {
+              adj_put<BF>(TD, 32 * b + acc_row(r, hf), 32 * slot + j, d2[b][r]);
+              adj_put<BF>(TY, 32 * b + acc_row(r, hf), 32 * slot + j, fmaxf(z1[b][r], 0.f));
+            }
+        } else {
+#pragma unroll
+          for (int st = 0; st < 4; ++st)
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+              const int row = 32 * (st >> 1) + acc_row(8 * (st & 1) + e, hf);
+              TD[(size_t)row * P + 32 * slot + j] = (uint16_t)d2b[st][e];
+              TY[(size_t)row * P + 32 * slot + j] = (uint16_t)hb[st][e];
+            }
+        }
       }
       __syncthreads();
-      acc2 = adj_dw<BF>(TD, 32 * ib2, TY, 32 * kb2, 64 * part2, 64, lane, acc2);
+      acc2 = adj_dw<BF>(TD, 32 * ib2, TY, 32 * kb2, k2len * part2, k2len, lane, acc2);
       __syncthreads();
       if (pub) {
+        if constexpr (!BF) {
 #pragma unroll
-        for (int b = 0; b < NB; ++b)
+          for (int b = 0; b < NB; ++b)
 #pragma unroll
-          for (int r = 0; r < 16; ++r) adj_put<BF>(TD, 32 * b + acc_row(r, hf), 32 * slot + j, d1[b][r]);
+            for (int r = 0; r < 16; ++r) adj_put<BF>(TD, 32 * b + acc_row(r, hf), 32 * slot + j, d1[b][r]);
 #pragma unroll
-        for (int t = 0; t < 32; ++t) {
-          const int k = hf * s.KH + t;
-          if (t < s.KH && k < s.MC) adj_put<BF>(TY, k, 32 * slot + j, yv[t]);
+          for (int t = 0; t < 32; ++t) {
+            const int k = hf * s.KH + t;
+            if (t < s.KH && k < s.MC) adj_put<BF>(TY, k, 32 * slot + j, yv[t]);
+          }
+        } else {
+#pragma unroll
+          for (int st = 0; st < 4; ++st)
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+              const int row = 32 * (st >> 1) + acc_row(8 * (st & 1) + e, hf);
+              TD[(size_t)row * P + 32 * slot + j] = (uint16_t)d1b[st][e];
+              const int t = 8 * st + e, k = hf * s.KH + t;
+              if (t < s.KH && k < s.MC) TY[(size_t)k * P + 32 * slot + j] = (uint16_t)yb[st][e];
+            }
         }
       }
       __syncthreads();
@@ -427,11 +484,11 @@ __global__ void __launch_bounds__(kAdjThreads, 2) k_adjoint(TileArgs a) {
   }
 }
 
-// LDS bytes of k_adjoint.
-size_t adjoint_lds_bytes(const Shape& s, bool bf) {
-  size_t b = (size_t)(12 * s.M + kAdjWaves * s.H) * 4;
+// LDS bytes of k_adjoint with nw waves per block.
+size_t adjoint_lds_bytes(const Shape& s, bool bf, int nw) {
+  size_t b = (size_t)(12 * s.M + nw * s.H) * 4;
   b = (b + 7) & ~(size_t)7;
-  b += 8 * kAdjWaves;
+  b += 8 * nw;
   b = (b + 15) & ~(size_t)15;
   const size_t esz = bf ? 2 : 4;
   b += swz_sizes(s).total() * esz;
@@ -441,25 +498,35 @@ size_t adjoint_lds_bytes(const Shape& s, bool bf) {
   return b;
 }
 
-// The eight-wave adjoint applies to the register-resident shapes: hidden width 64 and at
-// most 64 input features (two blocks of 16 per half).
+// The tiled adjoint applies to the register-resident shapes: hidden width 64 and at most
+// 64 input features (two blocks of 16 per half).
 bool adjoint_applies(const Shape& s) { return s.H == 64 && s.KHP <= 32; }
 
-hipError_t launch_adjoint(const TileArgs& a, bool grid_f16, bool mlp_bf16, dim3 grid, hipStream_t st) {
+// waves per block of the tiled adjoint: variant 1 = eight, 2 = four, 0 = the faster one
+// measured for the MLP dtype (eight for float32, whose 64 KB of staged weights leave room
+// for one block per CU; four for bf16, two blocks per CU).
+int adjoint_waves(int variant, bool bf) { return variant == 1 ? 8 : variant == 2 ? 4 : (bf ? 4 : 8); }
+
+hipError_t launch_adjoint(const TileArgs& a, bool grid_f16, bool mlp_bf16, int variant, dim3 grid, hipStream_t st) {
   if (!adjoint_applies(a.s)) return hipErrorInvalidValue;
-  const size_t shmem = adjoint_lds_bytes(a.s, mlp_bf16);
+  const int nw = adjoint_waves(variant, mlp_bf16);
+  const size_t shmem = adjoint_lds_bytes(a.s, mlp_bf16, nw);
+#define APMG_ADJ_V(CC, G16, B16)                                                                                   \
+  if (nw == 4) hipLaunchKernelGGL((k_adjoint<CC, G16, B16, 4>), grid, dim3(4 * kWave), shmem, st, a);              \
+  else hipLaunchKernelGGL((k_adjoint<CC, G16, B16, 8>), grid, dim3(8 * kWave), shmem, st, a);
 #define APMG_ADJ(CC)                                                                                              \
   if (a.s.C == CC) {                                                                                              \
-    if (!grid_f16 && !mlp_bf16) hipLaunchKernelGGL((k_adjoint<CC, false, false>), grid, dim3(kAdjThreads), shmem, st, a); \
-    else if (!grid_f16 && mlp_bf16) hipLaunchKernelGGL((k_adjoint<CC, false, true>), grid, dim3(kAdjThreads), shmem, st, a); \
-    else if (grid_f16 && !mlp_bf16) hipLaunchKernelGGL((k_adjoint<CC, true, false>), grid, dim3(kAdjThreads), shmem, st, a); \
-    else hipLaunchKernelGGL((k_adjoint<CC, true, true>), grid, dim3(kAdjThreads), shmem, st, a);                  \
+    if (!grid_f16 && !mlp_bf16) { APMG_ADJ_V(CC, false, false) }                                                  \
+    else if (!grid_f16 && mlp_bf16) { APMG_ADJ_V(CC, false, true) }                                               \
+    else if (grid_f16 && !mlp_bf16) { APMG_ADJ_V(CC, true, false) }                                               \
+    else { APMG_ADJ_V(CC, true, true) }                                                                           \
     return hipGetLastError();                                                                                     \
   }
   APMG_ADJ(1)
   APMG_ADJ(2)
   APMG_ADJ(4)
 #undef APMG_ADJ
+#undef APMG_ADJ_V
   return hipErrorInvalidValue;
 }
 

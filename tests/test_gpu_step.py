@@ -487,3 +487,32 @@ def test_step_with_density_readings_matches_oracle():
     a, _ = errs(got["mG"], ost["mG"])
     print(f"mG (|det|, renormalised target): normwise {a:.2e} (stated)")
     assert a < 1e-3
+
+
+@pytest.mark.parametrize("variant", [1, 2, 3])
+def test_step_adjoint_kernel_variants_match_oracle(variant):
+    # every fused-adjoint variant (eight-wave and four-wave tiled kernels, the one-wave-per-
+    # SIMD register kernel) against the oracle's step, float32 MLP, two bricks with a ragged
+    # tile count (3001 points) and 24 features (a partial dW1 column block)
+    vol = synth.make_volume("blobs_sine", (40, 44, 36))
+    bricks, obricks = brick_setup(vol, 2, 24, 1)
+    hosts = [synth.init_model(12, 2, 8, [24, 64, 64, 1], seed=97 + b, grid_range=0.2) for b in range(2)]
+    n = 3001
+    tr = A().Trainer(hosts, vol.to(DEV), bricks, n, seed=13, tuning={"adjoint_kernel": variant})
+    tr.density_active.fill_(0)
+    tr.step()
+    torch.cuda.synchronize()
+    vol_np = vol.numpy().astype(np.float64)
+    for b in range(2):
+        got = snapshot(tr, b)
+        model = f64(hosts[b])
+        x = O.uniform_points(13, 0, b, n)
+        v = O.brick_gt_sample(vol_np, obricks[b], x)
+        nl = noise_levels(model, x, v)
+        om, ost, info = O.train_step(model, O.zero_adam_state(model), x, v, density_active=False)
+        trk = Track(model["F"].size, sum(w.size for w in model["W"]))
+        trk.add(info["dF"].ravel(), flat_w(info["dW"]), nl, ost)
+        tag = f"[variant {variant}, model {b}]"
+        assert_close("L_rec " + tag, [got["losses"][0]], [info["L_rec"]])
+        check_env("mF " + tag, got["mF"], ost["mF"], trk.amF)
+        check_env("mW " + tag, got["mW"], flat_w(ost["mW"]), trk.amW)
