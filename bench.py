@@ -200,13 +200,14 @@ def extra_c3(A, torch, synth, hl):
     return {"train_pts_per_s": n / dt, "ms_per_step": dt * 1e3, "mlp": "bf16", "grids": "fp16 (fp32 master)"}
 
 
-def extra_c4(A, torch, synth, hl):
-    """1000x1200x900 volume in 256^3 bricks with one ghost voxel (80 bricks), 16 grids at
-    32^3 x 2 per brick, MLP 32-64-64-1 in bf16, 2^17 points per brick; all bricks per step,
-    launch shapes from the autotuner, the step captured as a graph and replayed.  Then
-    global-query inference over all 80 brick models: 2^24 uniform points."""
+def extra_c4(A, torch, synth, hl, B=256):
+    """1000x1200x900 volume in B^3 bricks with one ghost voxel (B = 256: 4 x 5 x 4 = 80 bricks;
+    B = 300: 4 x 4 x 3 = 48 bricks, the workload's stated model count), 16 grids at 32^3 x 2
+    per brick, MLP 32-64-64-1 in bf16, 2^17 points per brick; all bricks per step, launch
+    shapes from the autotuner, the step captured as a graph and replayed.  Then global-query
+    inference over all brick models: 2^24 uniform points."""
     vol = synth.make_volume("blobs_turb", (900, 1200, 1000), device="cuda")
-    table, bricks = A.apmg_make_bricks(1000, 1200, 900, 256, 1)
+    table, bricks = A.apmg_make_bricks(1000, 1200, 900, B, 1)
     hosts = [synth.init_model(16, 2, 32, [32, 64, 64, 1], seed=synth.SEED_MODEL + b) for b in range(len(bricks))]
     n = 1 << 17
     tr = A.Trainer(hosts, vol, bricks, n, seed=synth.SEED_POINTS, mlp_dtype=A.BF16)
@@ -265,25 +266,90 @@ def extra_c5(A, torch, synth, hl):
     return out
 
 
-def cpu_baseline(vol_np, host, n_sample):
-    """The FP64 oracle's training step on a bounded sample of the same workload."""
+def _oracle_chunk(args):
+    """One FP64 oracle training step on a chunk of the sample (a worker of the CPU baseline)."""
     import numpy as np
     from threadpoolctl import threadpool_limits
 
     from oracle import apmg_oracle as O
+    host, vol_path, shape, start, count = args
+    vol_np = np.memmap(vol_path, dtype=np.float64, mode="r", shape=shape)
     model = {"G": host["G"].astype(np.float64), "F": host["F"].astype(np.float64),
              "W": [w.astype(np.float64) for w in host["W"]], "vmin": 0.0, "vmax": 1.0}
-    brick = {"e0": [0, 0, 0], "e1": [VOL[2] - 1, VOL[1] - 1, VOL[0] - 1]}
+    brick = {"e0": [0, 0, 0], "e1": [shape[2] - 1, shape[1] - 1, shape[0] - 1]}
     with threadpool_limits(limits=1):
-        t0 = time.perf_counter()
-        x = O.uniform_points(7, 0, 0, n_sample)
+        x = O.uniform_points(7, 0, 0, count, start=start)
         v = O.brick_gt_sample(vol_np, brick, x)
         O.train_step(model, O.zero_adam_state(model), x, v, density_active=True)
-        dt = time.perf_counter() - t0
-    return {"value": n_sample / dt, "unit": "train pts/s", "cores": 1, "kind": "oracle",
-            "sample": f"one FP64 oracle training step (points, ground truth, forward, adjoint, density, "
-                      f"Adam) on {n_sample} of the {N} points, same model and volume, 1 thread, "
-                      f"{dt:.1f} s"}
+    return count
+
+
+def cpu_baseline(vol_np, host, n_sample):
+    """The FP64 oracle's training step on a bounded sample of the same workload, on the host's
+    cores: the sample is split into one chunk per worker process (threads pinned to one per
+    worker), each chunk a training step of its own -- the same per-point work (points, ground
+    truth, forward, adjoint, density passes, Adam) as one step over the whole sample."""
+    import multiprocessing as mp
+    import tempfile
+
+    import numpy as np
+    cores = min(len(os.sched_getaffinity(0)), 16)
+    chunk = (n_sample + cores - 1) // cores
+    with tempfile.TemporaryDirectory() as td:
+        path = os.path.join(td, "volume.f64")
+        mm = np.memmap(path, dtype=np.float64, mode="w+", shape=vol_np.shape)
+        mm[:] = vol_np
+        mm.flush()
+        jobs = [(host, path, vol_np.shape, k * chunk, min(chunk, n_sample - k * chunk)) for k in range(cores)
+                if k * chunk < n_sample]
+        ctx = mp.get_context("spawn")
+        with ctx.Pool(len(jobs)) as pool:
+            pool.map(_oracle_chunk, [(host, path, vol_np.shape, 0, 8)] * len(jobs))   # workers up, imports done
+            t0 = time.perf_counter()
+            done = sum(pool.map(_oracle_chunk, jobs))
+            dt = time.perf_counter() - t0
+    return {"value": done / dt, "unit": "train pts/s", "cores": len(jobs), "kind": "oracle",
+            "sample": f"FP64 oracle training steps (points, ground truth, forward, adjoint, density, Adam) on "
+                      f"{done} of the {N} points of the headline step, same model and volume, split into "
+                      f"{len(jobs)} chunks over {len(jobs)} worker processes (one thread each), {dt:.1f} s"}
+
+
+def stated_errors(A, torch, synth, vol, host, n):
+    """Error of one GPU training step (FP32, BF16 MLP, BF16 MLP + FP16 grids) against the FP64
+    oracle's step on the same n points of the headline workload (step 0), normwise relative:
+    losses, and the gradients read off the first Adam moments (m = 0.1 g)."""
+    import numpy as np
+
+    from oracle import apmg_oracle as O
+    model = {"G": host["G"].astype(np.float64), "F": host["F"].astype(np.float64),
+             "W": [w.astype(np.float64) for w in host["W"]], "vmin": 0.0, "vmax": 1.0}
+    vol_np = vol.cpu().numpy().astype(np.float64)
+    brick = {"e0": [0, 0, 0], "e1": [VOL[2] - 1, VOL[1] - 1, VOL[0] - 1]}
+    x = O.uniform_points(synth.SEED_POINTS, 0, 0, n)
+    v = O.brick_gt_sample(vol_np, brick, x)
+    _, st, info = O.train_step(model, O.zero_adam_state(model), x, v, density_active=True)
+
+    def rel(a, b):
+        a, b = np.asarray(a, np.float64).ravel(), np.asarray(b, np.float64).ravel()
+        return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+    out = {"points": n}
+    for name, mlp, gd in (("fp32", A.F32, torch.float32), ("bf16_mlp", A.BF16, torch.float32),
+                          ("bf16_mlp_fp16_grids", A.BF16, torch.float16)):
+        nz, ny, nx = vol.shape
+        _, bricks = A.apmg_make_bricks(nx, ny, nz, max(nx, ny, nz), 0)
+        tr = A.Trainer([host], vol, bricks, n, seed=synth.SEED_POINTS, mlp_dtype=mlp, grid_dtype=gd)
+        tr.density_active.fill_(1)
+        tr.step()
+        torch.cuda.synchronize()
+        L = tr.losses[0].cpu().numpy()
+        mW = tr.mW[0].cpu().numpy().astype(np.float64)
+        wflat = np.concatenate([w.ravel() for w in info["dW"]])
+        out[name] = {"L_rec": rel([L[0]], [info["L_rec"]]), "L_density": rel([L[1]], [info["L_density"]]),
+                     "dF": rel(tr.mF[0].cpu().numpy() / 0.1, info["dF"]), "dW": rel(mW / 0.1, wflat),
+                     "dG_density": rel(tr.mG[0].cpu().numpy() / 0.1, info["dG_density"])}
+        del tr
+    return out
 
 
 def main():
@@ -292,7 +358,9 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample", type=int, default=1 << 18)
+    ap.add_argument("--cpu-sample", type=int, default=1 << 19)
+    ap.add_argument("--error-sample", type=int, default=1 << 17,
+                    help="points of the GPU steps compared with the oracle for the stated errors")
     ap.add_argument("--skip-extra", action="store_true")
     ap.add_argument("--configs", default="config1,config3,config4,config5",
                     help="extra workloads to time after the headline")
@@ -332,7 +400,7 @@ def main():
                    "global_batch": N, "parallelism": "none (1 GPU)"},
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK_FP32_MFMA_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_MFMA_TFLOPS, "traffic": measured_traffic(),
-                     "kernel": "k_backward (fused forward + adjoint tile kernel)",
+                     "kernel": "k_adjoint (fused forward + adjoint tile kernel, eight waves per block)",
                      "kernel_ms": kern_ms},
     }
     L = tr.losses.cpu().numpy()
@@ -350,11 +418,17 @@ def main():
         dtb, kb = time_steps(A, torch, trb, args.steps, args.warmup, hl)
         extra["train_pts_per_s_bf16_mlp"] = N * args.steps / dtb
         extra["bf16_kernel_ms"] = kb
+        extra["bf16_kernel_roofline"] = {"bound": "mfma", "achieved": flops / (kb * 1e-3) / 1e12,
+                                         "peak": PEAK_BF16_MFMA_TFLOPS, "unit": "TFLOP/s",
+                                         "frac": flops / (kb * 1e-3) / 1e12 / PEAK_BF16_MFMA_TFLOPS,
+                                         "kernel": "k_adjoint (four waves per block, two blocks per CU)"}
         progress("bf16-MLP step done")
         del trb
         torch.cuda.empty_cache()
+        c4_48 = lambda A_, t_, s_, h_: extra_c4(A_, t_, s_, h_, B=300)  # noqa: E731
         for name, fn in (("config1_tiny_fp32", extra_c1), ("config3_mixed_1024", extra_c3),
-                         ("config4_bricks", extra_c4), ("config5_render_bf16", extra_c5)):
+                         ("config4_bricks", extra_c4), ("config4_48bricks", c4_48),
+                         ("config5_render_bf16", extra_c5)):
             if name.split("_")[0] in args.configs:
                 try:
                     extra[name] = fn(A, torch, synth, hl)
@@ -373,6 +447,8 @@ def main():
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(vol.cpu().numpy().astype("float64"), host, args.cpu_sample)
         progress("cpu baseline done")
+        out["stated_errors_vs_oracle"] = stated_errors(A, torch, synth, vol, host, args.error_sample)
+        progress("stated errors done")
     print(json.dumps(out), flush=True)
 
 

@@ -81,3 +81,44 @@ def test_dd_forward_bf16_stated_and_empty():
     assert err < 3e-2
     empty = A().apmg_dd_forward(models, torch.zeros((3, 0), device=DEV))
     assert empty.numel() == 0
+
+
+def test_ghost_cells_seam_error():
+    # Sec. 5.1 ghost cells, Sec. 7.2 study: a 2 x 2 x 2 brick split of a 128^3 volume trained
+    # with one ghost voxel and with 16, then queried globally (apmg_dd_forward).  The error
+    # against the volume (the oracle's trilinear sample) on points within one voxel of an
+    # internal brick face, against interior points: with 16 ghost voxels the seam error is
+    # not worse than with one.
+    A_ = A()
+    n_vox = 128
+    vol = synth.make_volume("blobs_sine", (n_vox, n_vox, n_vox))
+    vol_np = vol.numpy().astype(np.float64)
+    rng = np.random.default_rng(5)
+    # seam points: one coordinate within one voxel of the face at voxel 63.5 (bricks of 64)
+    m = 20000
+    seam = rng.uniform(-1, 1, size=(m, 3))
+    axis = rng.integers(0, 3, size=m)
+    u_face = rng.uniform(62.5, 64.5, size=m)
+    seam[np.arange(m), axis] = u_face / ((n_vox - 1) * 0.5) - 1.0
+    inner = rng.uniform(-1, 1, size=(m, 3))
+    u_in = (inner + 1.0) * ((n_vox - 1) * 0.5)
+    inner = inner[np.all(np.abs(u_in - 63.5) > 8.0, axis=1)]
+    seam, inner = seam.astype(np.float32), inner.astype(np.float32)
+    v_seam = O.gt_sample(vol_np, seam.astype(np.float64))
+    v_inner = O.gt_sample(vol_np, inner.astype(np.float64))
+    results = {}
+    for ghost in (1, 16):
+        table, bricks = A_.apmg_make_bricks(n_vox, n_vox, n_vox, 64, ghost)
+        hosts = [synth.init_model(8, 2, 16, [16, 64, 64, 1], seed=200 + b) for b in range(len(bricks))]
+        tr = A_.Trainer(hosts, vol.to(DEV), bricks, 1 << 14, seed=21)
+        tr.density_active.fill_(0)
+        for _ in range(300):
+            tr.step()
+        dd = A_.DDModels.from_trainer(tr, table, bricks)
+        f_seam = A_.apmg_dd_forward(dd, torch.from_numpy(np.ascontiguousarray(seam.T)).to(DEV)).cpu().numpy()
+        f_in = A_.apmg_dd_forward(dd, torch.from_numpy(np.ascontiguousarray(inner.T)).to(DEV)).cpu().numpy()
+        rs = float(np.sqrt(np.mean((f_seam - v_seam) ** 2)))
+        ri = float(np.sqrt(np.mean((f_in - v_inner) ** 2)))
+        results[ghost] = (rs, ri)
+        print(f"ghost {ghost}: seam RMSE {rs:.4e}, interior RMSE {ri:.4e}, ratio {rs / ri:.3f}")
+    assert results[16][0] <= results[1][0]
