@@ -43,16 +43,19 @@ def mlp_flops_fwd_bwd(K, Hd):
     return fwd + bwd
 
 
-COUNTERS_FILE = os.path.join(ROOT, "profiles", "k_backward_train_c2_fp32_counters.txt")
+COUNTERS_FILE = os.path.join(ROOT, "profiles", "k_adjoint_train_c2_fp32_counters.txt")
+
+# the sources the adjoint tile kernel is compiled from: its own file (with its launcher), the
+# forward tile it recomputes and the shared device helpers
+ADJOINT_SOURCES = ["apmg_adjoint.hip", "apmg_mlp.hip", "apmg_device.h", "apmg_kernels.h"]
 
 
 def source_hash():
-    """sha256 over the kernel sources and the ABI header (path and content, sorted)."""
+    """sha256 over the adjoint tile kernel's sources (path and content, in order)."""
     import hashlib
     h = hashlib.sha256()
-    files = [os.path.join("include", "apmg.h")]
     cdir = os.path.join("paper_2308_02494_amd", "csrc")
-    files += sorted(os.path.join(cdir, f) for f in os.listdir(os.path.join(ROOT, cdir)))
+    files = [os.path.join(cdir, f) for f in ADJOINT_SOURCES]
     for rel in files:
         h.update(rel.encode() + b"\0")
         with open(os.path.join(ROOT, rel), "rb") as f:
@@ -104,30 +107,44 @@ def make_trainer(A, torch, synth, mlp_dtype, n):
 
 
 def time_steps(A, torch, tr, steps, warmup, hl):
+    """Whole-step wall time of `steps` steps, and the mean launch time (ms) of the adjoint
+    tile kernel and of the grid-gradient gather, from HIP events the library records on the
+    stream each is launched on."""
     for _ in range(warmup):
         tr.step()
     torch.cuda.synchronize()
     evs = []
     for _ in range(steps):
-        a, b = ctypes.c_void_p(), ctypes.c_void_p()
-        hl.hipEventCreate(ctypes.byref(a))
-        hl.hipEventCreate(ctypes.byref(b))
-        evs.append((a, b))
+        pair = []
+        for _k in range(2):
+            a, b = ctypes.c_void_p(), ctypes.c_void_p()
+            hl.hipEventCreate(ctypes.byref(a))
+            hl.hipEventCreate(ctypes.byref(b))
+            pair.append((a, b))
+        evs.append(pair)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for a, b in evs:
-        A.apmg_profile_events(a, b)
+    for pair in evs:
+        A.apmg_profile_kernel_events(A.PROF_ADJOINT, *pair[0])
+        A.apmg_profile_kernel_events(A.PROF_GATHER, *pair[1])
         tr.step()
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
-    ks = []
-    for a, b in evs:
-        ms = ctypes.c_float()
-        hl.hipEventElapsedTime(ctypes.byref(ms), a, b)
-        ks.append(ms.value)
-        hl.hipEventDestroy(a)
-        hl.hipEventDestroy(b)
-    return dt, sum(ks) / len(ks)
+    ks = [[], []]
+    for pair in evs:
+        for k, (a, b) in enumerate(pair):
+            ms = ctypes.c_float()
+            hl.hipEventElapsedTime(ctypes.byref(ms), a, b)
+            ks[k].append(ms.value)
+            hl.hipEventDestroy(a)
+            hl.hipEventDestroy(b)
+    return dt, sum(ks[0]) / len(ks[0]), sum(ks[1]) / len(ks[1])
+
+
+def gather_bytes(n, Mg, Cg, Rg):
+    """Algorithmic HBM bytes of one grid-gradient gather: dL/dy of every (point, grid) pair
+    (4C bytes), each point once (a 16-byte record), and the gradient of every grid value."""
+    return n * Mg * Cg * 4 + n * 16 + Mg * Rg ** 3 * Cg * 4
 
 
 def time_forward(A, torch, host, n, reps=10):
@@ -242,16 +259,33 @@ def extra_c5(A, torch, synth, hl):
     n = pts.shape[1]
     ws = torch.empty(A._lib.apmg_workspace_bytes(A.OP_FORWARD, ctypes.byref(model.struct()), n),
                      dtype=torch.uint8, device="cuda")
-    out = torch.empty(n, device="cuda")
-    A.apmg_forward(model, pts, out=out, ws=ws)
+    out_f = torch.empty(n, device="cuda")
+    A.apmg_forward(model, pts, out=out_f, ws=ws)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     reps = 3
     for _ in range(reps):
-        A.apmg_forward(model, pts, out=out, ws=ws)
+        A.apmg_forward(model, pts, out=out_f, ws=ws)
     torch.cuda.synchronize()
     dt = (time.perf_counter() - t0) / reps
-    out = {"infer_pts_per_s": n / dt, "ms_per_frame": dt * 1e3, "points": n}
+    fl = 2 * (256 * 128 + 128 * 128 + 128) * n
+    out = {"infer_pts_per_s": n / dt, "ms_per_frame": dt * 1e3, "points": n,
+           "bf16_mfma_frac_forward": fl / dt / 1e12 / PEAK_BF16_MFMA_TFLOPS,
+           "logical_gather_TBps": n * 64 * 8 * 4 * 4 / dt / 1e12}
+    # the same frame with the grids stored in fp16 (128 MiB instead of 256 MiB)
+    model16 = A.Model.from_host(host, "cuda", grid_dtype=torch.float16, mlp_dtype=A.BF16)
+    ws16 = torch.empty(A._lib.apmg_workspace_bytes(A.OP_FORWARD, ctypes.byref(model16.struct()), n),
+                       dtype=torch.uint8, device="cuda")
+    A.apmg_forward(model16, pts, out=out_f, ws=ws16)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        A.apmg_forward(model16, pts, out=out_f, ws=ws16)
+    torch.cuda.synchronize()
+    dt16 = (time.perf_counter() - t0) / reps
+    out["fp16_grids"] = {"infer_pts_per_s": n / dt16, "ms_per_frame": dt16 * 1e3,
+                         "bf16_mfma_frac_forward": fl / dt16 / 1e12 / PEAK_BF16_MFMA_TFLOPS}
+    del model16, ws16
     # the 2^20-point adjoint of the same model (dF, dG, dW), bf16 MLP
     nb_ = 1 << 20
     bp = A.apmg_uniform_points(13, 0, 0, 0, nb_)
@@ -364,7 +398,10 @@ def main():
     ap.add_argument("--skip-extra", action="store_true")
     ap.add_argument("--configs", default="config1,config3,config4,config5",
                     help="extra workloads to time after the headline")
-    ap.add_argument("--source-hash", action="store_true", help="print the kernel source hash and exit")
+    ap.add_argument("--only", choices=["bf16", "config1", "config3", "config4", "config4_48", "config5"],
+                    help="time one extra workload alone (no headline line; for profiling runs)")
+    ap.add_argument("--source-hash", action="store_true",
+                    help="print the hash of the adjoint kernel's sources and exit")
     ap.add_argument("--copy-probe", action="store_true",
                     help="end with a plain 1 GiB device-to-device copy (the reference kernel that "
                          "calibrates the FETCH_SIZE / WRITE_SIZE counters)")
@@ -383,8 +420,20 @@ def main():
     import synth
 
     hl = hip()
+    if args.only:
+        if args.only == "bf16":
+            trb, _, _ = make_trainer(A, torch, synth, A.BF16, N)
+            dtb, kb, gbm = time_steps(A, torch, trb, args.steps, args.warmup, hl)
+            res = {"train_pts_per_s": N * args.steps / dtb, "ms_per_step": dtb * 1e3 / args.steps,
+                   "kernel_ms": kb, "gather_ms": gbm}
+        else:
+            fn = {"config1": extra_c1, "config3": extra_c3, "config4": extra_c4, "config5": extra_c5,
+                  "config4_48": lambda A_, t_, s_, h_: extra_c4(A_, t_, s_, h_, B=300)}[args.only]
+            res = fn(A, torch, synth, hl)
+        print(json.dumps({"only": args.only, "result": res}), flush=True)
+        return
     tr, vol, host = make_trainer(A, torch, synth, A.F32, N)
-    dt, kern_ms = time_steps(A, torch, tr, args.steps, args.warmup, hl)
+    dt, kern_ms, gather_ms = time_steps(A, torch, tr, args.steps, args.warmup, hl)
     ms_step = dt * 1e3 / args.steps
     progress(f"headline: {ms_step:.3f} ms per step")
     value = N * args.steps / dt
@@ -403,6 +452,11 @@ def main():
                      "kernel": "k_adjoint (fused forward + adjoint tile kernel, eight waves per block)",
                      "kernel_ms": kern_ms},
     }
+    gb = gather_bytes(N, M, C, R)
+    out["gather_roofline"] = {"bound": "hbm", "achieved": gb / (gather_ms * 1e-3) / 1e9, "peak": PEAK_HBM_GBS,
+                              "unit": "GB/s", "frac": gb / (gather_ms * 1e-3) / 1e9 / PEAK_HBM_GBS,
+                              "kernel": "k_cell_pull_wave (grid-gradient gather)", "kernel_ms": gather_ms,
+                              "algorithmic_bytes": gb}
     L = tr.losses.cpu().numpy()
     out["losses_last_step"] = {"L_rec": float(L[0, 0]), "L_density": float(L[0, 1])}
     if not args.skip_extra:
@@ -415,9 +469,11 @@ def main():
         del tr
         torch.cuda.empty_cache()
         trb, _, _ = make_trainer(A, torch, synth, A.BF16, N)
-        dtb, kb = time_steps(A, torch, trb, args.steps, args.warmup, hl)
+        dtb, kb, gbm = time_steps(A, torch, trb, args.steps, args.warmup, hl)
         extra["train_pts_per_s_bf16_mlp"] = N * args.steps / dtb
+        extra["bf16_ms_per_step"] = dtb * 1e3 / args.steps
         extra["bf16_kernel_ms"] = kb
+        extra["bf16_gather_ms"] = gbm
         extra["bf16_kernel_roofline"] = {"bound": "mfma", "achieved": flops / (kb * 1e-3) / 1e12,
                                          "peak": PEAK_BF16_MFMA_TFLOPS, "unit": "TFLOP/s",
                                          "frac": flops / (kb * 1e-3) / 1e12 / PEAK_BF16_MFMA_TFLOPS,

@@ -29,7 +29,7 @@ def test_counter_file_is_parsed_and_keyed_to_the_sources():
     sys.path.insert(0, ROOT)
     import bench
     t = bench.measured_traffic()
-    path = os.path.join(ROOT, "profiles", "k_backward_train_c2_fp32_counters.txt")
+    path = bench.COUNTERS_FILE
     text = open(path).read()
     key = re.search(r"^source_sha256 = ([0-9a-f]{64})$", text, re.M).group(1)
     if key == bench.source_hash():
