@@ -175,6 +175,52 @@ apmg_status apmg_backward(const apmg_model* model, const float* pts, int64_t ld,
                           const float* df, float* dF, double* dG, float* const* dW,
                           uint32_t flags, void* ws, size_t ws_bytes, hipStream_t stream);
 
+/* ---------------------------------------------------------------- encoder variants
+ * The two extensions of the encoder named in Sec. 9 ("Conclusion and future work"); the
+ * transforms (Eq. (1)), the mask of Eq. (2), the concatenation of Eq. (3) and the decoder
+ * are those of the dense model.
+ *  APMG_ENC_HASH -- a hash grid inside each adaptive grid (the multiresolution hash
+ *   encoding of Mueller et al., "Instant neural graphics primitives", 2022): grid i has
+ *   `levels` levels; level k has level_res[k] = N_k cells per axis across the local cube,
+ *   vertex coordinate u = fma(l, N_k/2, N_k/2), lower vertex clamp(floor(u), 0, N_k - 1)
+ *   (float32, as the dense grids with R - 1 = N_k), and a table of T = 2^table_log2
+ *   entries of C features.  Vertex v of level k reads entry v_x + (N_k+1)(v_y + (N_k+1) v_z)
+ *   when (N_k+1)^3 <= T, else (v_x XOR 2654435761 v_y XOR 805459861 v_z) mod 2^32 mod T.
+ *   The level's C features are the trilinear interpolation of its 8 corner entries; grid i
+ *   emits levels*C features, index (i*levels + k)*C + c, so width[0] = M*levels*C.
+ *   F: tables [M][levels][T][C] float32 (grid_layout ignored); R is not used.
+ *  APMG_ENC_TIME -- 4-D grids: F is [M][C][Rt][R][R][R] (APMG_GRIDS_MCRRR) or
+ *   [M][Rt][R][R][R][C] (APMG_GRIDS_MRRRC), float32; the points carry a fourth row, the
+ *   normalised time tau in [-1, 1] at pts[3*ld + n].  Time vertex k sits at
+ *   -1 + 2k/(Rt-1); u_t = fma(tau, (Rt-1)/2, (Rt-1)/2), lower vertex clamp(floor(u_t), 0,
+ *   Rt-2).  The features are the linear interpolation in time of the trilinear
+ *   interpolations (Eq. (2)) of the two time slices; a point with tau outside [-1, 1]
+ *   (or NaN) gets zero features from every grid.  width[0] = M*C.
+ * Built for C = 2, grid_dtype F32, MLP {width[0], 64, 64, 1} with width[0] <= 64, mlp_dtype
+ * F32 or BF16 (APMG_EUNSUPPORTED otherwise).  No spatial sort: the tile kernels run over
+ * the caller's points.  The backward adds the table / grid gradient with float atomics
+ * (every entry a vertex maps to, colliding vertices included), so dF is reproducible to
+ * rounding only; dW and dG (float64 per block, fixed order) are as in apmg_backward.
+ * Workspace: apmg_variant_workspace_bytes(APMG_OP_FORWARD or APMG_OP_BACKWARD, ...).
+ * Arguments, outputs, flags and errors otherwise as apmg_forward / apmg_backward; dF has
+ * F's layout. */
+#define APMG_ENC_HASH 1
+#define APMG_ENC_TIME 2
+typedef struct apmg_encoder {
+  int32_t kind;             /* APMG_ENC_HASH or APMG_ENC_TIME */
+  int32_t levels;           /* hash: levels per grid, 1..8 */
+  int32_t table_log2;       /* hash: T = 2^table_log2 entries per (grid, level), 1..24 */
+  int32_t level_res[8];     /* hash: cells per axis of level k, 1..65534 */
+  int32_t Rt;               /* time: vertices along the time axis, >= 2 */
+} apmg_encoder;
+
+size_t apmg_variant_workspace_bytes(int op, const apmg_model* model, const apmg_encoder* enc, int64_t n);
+apmg_status apmg_variant_forward(const apmg_model* model, const apmg_encoder* enc, const float* pts, int64_t ld,
+                                 int64_t n, float* f, void* ws, size_t ws_bytes, hipStream_t stream);
+apmg_status apmg_variant_backward(const apmg_model* model, const apmg_encoder* enc, const float* pts, int64_t ld,
+                                  int64_t n, const float* df, float* dF, double* dG, float* const* dW,
+                                  uint32_t flags, void* ws, size_t ws_bytes, hipStream_t stream);
+
 /* ---------------------------------------------------------------- density
  * Sec. 4.2.  rho(x) = sum_i det(G_i[0:3,0:3]) exp(-sum_d l_d^{2p})  (Eq. (7),
  * signed determinant, exp(-s) taken as 0 for s > 87 or NaN);
@@ -472,6 +518,13 @@ apmg_status apmg_gt_sample(const float* volume, int32_t nx, int32_t ny, int32_t 
  * then clears the hook.  The events are the caller's (hipEventCreate);
  * NULL, NULL clears the hook.  One hook per process; not thread-safe. */
 apmg_status apmg_profile_events(hipEvent_t start, hipEvent_t stop);
+
+/* The same hook for a chosen kernel: APMG_PROF_ADJOINT (as apmg_profile_events) or
+ * APMG_PROF_GATHER, the per-cell grid-gradient gather of the next call that computes dF
+ * (events around its launch, before the vertex sums).  One hook per kernel kind. */
+#define APMG_PROF_ADJOINT 0
+#define APMG_PROF_GATHER 1
+apmg_status apmg_profile_kernel_events(int32_t kernel, hipEvent_t start, hipEvent_t stop);
 
 #ifdef __cplusplus
 }

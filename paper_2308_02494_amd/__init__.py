@@ -28,6 +28,8 @@ ACCUMULATE, DETERMINISTIC, ADD_REC_DG, ERR_ABS = 0x1, 0x2, 0x4, 0x8
 DENSITY_ABS_DET, DENSITY_NORM_TARGET = 0x10, 0x20
 GRIDS_MCRRR, GRIDS_MRRRC = 0, 1
 OP_FORWARD, OP_BACKWARD, OP_DENSITY, OP_BATCHED_STEP, OP_DD_FORWARD = 0, 1, 2, 3, 4
+ENC_HASH, ENC_TIME = 1, 2
+PROF_ADJOINT, PROF_GATHER = 0, 1
 MAX_LAYERS = 8
 
 c_i32, c_i64, c_u32, c_u64, c_f32, c_f64 = (ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32,
@@ -40,6 +42,11 @@ class ApmgModel(ctypes.Structure):
                 ("width", c_i32 * (MAX_LAYERS + 1)), ("grid_dtype", c_i32), ("mlp_dtype", c_i32),
                 ("G", c_p), ("F", c_p), ("W", c_p * MAX_LAYERS), ("vmin", c_f32), ("vmax", c_f32),
                 ("grid_layout", c_i32), ("G_rows", c_i32)]
+
+
+class ApmgEncoder(ctypes.Structure):
+    _fields_ = [("kind", c_i32), ("levels", c_i32), ("table_log2", c_i32), ("level_res", c_i32 * 8),
+                ("Rt", c_i32)]
 
 
 class ApmgBrick(ctypes.Structure):
@@ -100,9 +107,15 @@ _sigs = {
     "apmg_uniform_points": [c_u64, c_u64, c_u32, c_i64, c_i64, c_p, c_i64, c_p],
     "apmg_gt_sample": [c_p, c_i32, c_i32, c_i32, c_p, c_i64, c_i64, c_p, c_p],
     "apmg_profile_events": [c_p, c_p],
+    "apmg_profile_kernel_events": [c_i32, c_p, c_p],
     "apmg_autotune_batched_step": [ctypes.POINTER(ApmgBatch), c_p, ctypes.c_size_t, c_p,
                                    ctypes.POINTER(ApmgTuning), ctypes.POINTER(c_f32)],
     "apmg_train_control": [ctypes.POINTER(ApmgControl), c_p, c_p],
+    "apmg_variant_workspace_bytes": [ctypes.c_int, ctypes.POINTER(ApmgModel), ctypes.POINTER(ApmgEncoder), c_i64],
+    "apmg_variant_forward": [ctypes.POINTER(ApmgModel), ctypes.POINTER(ApmgEncoder), c_p, c_i64, c_i64, c_p, c_p,
+                             ctypes.c_size_t, c_p],
+    "apmg_variant_backward": [ctypes.POINTER(ApmgModel), ctypes.POINTER(ApmgEncoder), c_p, c_i64, c_i64, c_p, c_p,
+                              c_p, c_p, c_u32, c_p, ctypes.c_size_t, c_p],
     "apmg_dd_forward": [ctypes.POINTER(ApmgDdModels), ctypes.POINTER(ApmgBrickTable), c_p, c_i64, c_i64, c_p, c_p,
                         ctypes.c_size_t, c_p],
 }
@@ -111,6 +124,7 @@ for _name, _args in _sigs.items():
     _fn.argtypes = _args
     _fn.restype = ctypes.c_int
 _lib.apmg_workspace_bytes.restype = ctypes.c_size_t
+_lib.apmg_variant_workspace_bytes.restype = ctypes.c_size_t
 _lib.apmg_forward_noalloc_scratch_bytes.restype = ctypes.c_size_t
 _lib.apmg_status_string.restype = ctypes.c_char_p
 
@@ -258,6 +272,89 @@ def apmg_backward(model: Model, pts_soa, df, want_dF=True, want_dG=True, want_dW
         _ptr(dG) if want_dG else None, ctypes.cast(dw_arr, c_p) if want_dW else None, flags, _ptr(ws),
         ws.numel(), _stream(dev)))
     return (dF if want_dF else None), (dG if want_dG else None), (dW if want_dW else None)
+
+
+class VariantModel:
+    """Device tensors of an APMGSRN with one of the encoder variants of Sec. 9.
+
+    kind ENC_HASH: G [M,3,4] or [M,4,4], F = hash tables [M, L, T, C] float32 (T = 2^k),
+    level_res = the L per-level cell counts.  kind ENC_TIME: F = 4-D grids [M, C, Rt, R, R, R]
+    (layout GRIDS_MCRRR) or [M, Rt, R, R, R, C] (GRIDS_MRRRC), float32; the points then carry
+    the time as a fourth row.  W, vmin, vmax, mlp_dtype as Model."""
+
+    def __init__(self, kind, G, F, W, vmin=0.0, vmax=1.0, mlp_dtype=F32, level_res=None, layout=GRIDS_MCRRR):
+        self.kind, self.G, self.F, self.W = kind, G, F, list(W)
+        self.vmin, self.vmax, self.mlp_dtype, self.layout = float(vmin), float(vmax), mlp_dtype, layout
+        self.level_res = list(level_res) if level_res is not None else []
+
+    def structs(self):
+        m = ApmgModel()
+        e = ApmgEncoder()
+        e.kind = self.kind
+        m.M = self.F.shape[0]
+        if self.kind == ENC_HASH:
+            _, L, T, C = self.F.shape
+            e.levels, e.table_log2 = L, int(T).bit_length() - 1
+            for k, r in enumerate(self.level_res):
+                e.level_res[k] = int(r)
+            m.C, m.R = C, 2
+        else:
+            if self.layout == GRIDS_MCRRR:
+                _, C, Rt, R = self.F.shape[:4]
+            else:
+                _, Rt, R = self.F.shape[:3]
+                C = self.F.shape[5]
+            e.Rt = Rt
+            m.C, m.R = C, R
+        m.n_layers = len(self.W)
+        m.width[0] = self.W[0].shape[1]
+        for k, w in enumerate(self.W):
+            m.width[k + 1] = w.shape[0]
+        m.grid_dtype, m.mlp_dtype = F32, self.mlp_dtype
+        m.G, m.F = self.G.data_ptr(), self.F.data_ptr()
+        for k, w in enumerate(self.W):
+            m.W[k] = w.data_ptr()
+        m.vmin, m.vmax = self.vmin, self.vmax
+        m.grid_layout = self.layout
+        m.G_rows = self.G.shape[1]
+        return m, e
+
+
+def _variant_ws(op, m, e, n, device):
+    nbytes = _lib.apmg_variant_workspace_bytes(op, ctypes.byref(m), ctypes.byref(e), n)
+    if nbytes == 0:
+        raise ApmgError("apmg_variant_workspace_bytes", EINVAL)
+    return torch.empty(nbytes, dtype=torch.uint8, device=device)
+
+
+def apmg_variant_forward(model: VariantModel, pts_soa, out=None, ws=None):
+    """f[n] for points pts_soa [3 or 4, n] (the time row for ENC_TIME)."""
+    n = pts_soa.shape[1]
+    dev = model.G.device
+    m, e = model.structs()
+    f = torch.empty(n, dtype=torch.float32, device=dev) if out is None else out
+    ws = _variant_ws(OP_FORWARD, m, e, n, dev) if ws is None else ws
+    _check("apmg_variant_forward", _lib.apmg_variant_forward(ctypes.byref(m), ctypes.byref(e), _ptr(pts_soa), n, n,
+                                                             _ptr(f), _ptr(ws), ws.numel(), _stream(dev)))
+    return f
+
+
+def apmg_variant_backward(model: VariantModel, pts_soa, df, want_dF=True, want_dG=True, want_dW=True, flags=0,
+                          ws=None):
+    """Gradients of sum_n df[n] f(x_n): (dF f32 in F's shape, dG f64 in G's shape, [dW1, dW2, dW3])."""
+    n = pts_soa.shape[1]
+    dev = model.G.device
+    m, e = model.structs()
+    dF = torch.empty(model.F.shape, dtype=torch.float32, device=dev) if want_dF else None
+    dG = torch.empty(tuple(model.G.shape), dtype=torch.float64, device=dev) if want_dG else None
+    dW = [torch.empty_like(w) for w in model.W] if want_dW else None
+    dw_arr = (ctypes.c_void_p * len(dW))(*[w.data_ptr() for w in dW]) if want_dW else None
+    ws = _variant_ws(OP_BACKWARD, m, e, n, dev) if ws is None else ws
+    _check("apmg_variant_backward", _lib.apmg_variant_backward(
+        ctypes.byref(m), ctypes.byref(e), _ptr(pts_soa), n, n, _ptr(df), _ptr(dF) if want_dF else None,
+        _ptr(dG) if want_dG else None, ctypes.cast(dw_arr, c_p) if want_dW else None, flags, _ptr(ws), ws.numel(),
+        _stream(dev)))
+    return dF, dG, dW
 
 
 def apmg_density_loss(model: Model, pts_soa, err, eps=1e-12, p=10, want_dG=True, want_rho=False, flags=0,
@@ -596,3 +693,9 @@ class DensityLossFunction(torch.autograd.Function):
 def apmg_profile_events(start, stop):
     """Arm the adjoint-kernel timing hook with two hipEvent_t handles (ints), or clear it."""
     _check("apmg_profile_events", _lib.apmg_profile_events(start, stop))
+
+
+def apmg_profile_kernel_events(kernel, start, stop):
+    """Arm the timing hook of one kernel kind (PROF_ADJOINT or PROF_GATHER) with two
+    hipEvent_t handles, or clear it."""
+    _check("apmg_profile_kernel_events", _lib.apmg_profile_kernel_events(kernel, start, stop))

@@ -50,6 +50,7 @@ apmg_status check_model(const apmg_model* m, bool need_params, Shape* out) {
   s.KH = s.Mh * s.C;
   s.KHP = (s.KH + 15) / 16 * 16;
   s.MC = m->M * m->C;
+  s.L = 1;
   if (out) *out = s;
   return APMG_OK;
 }
@@ -335,6 +336,14 @@ void take_cell(Carver& cv, const Shape& s, int64_t n, int nb, CellWs* o) {
   o->dGpart = cv.take<double>((size_t)nb * s.M * std::max(cell_blocks(s), wave_groups(s)) * 12);
 }
 
+// timing hooks: [0] the adjoint tile kernel, [1] the grid-gradient gather
+hipEvent_t g_prof_start[2] = {nullptr, nullptr}, g_prof_stop[2] = {nullptr, nullptr};
+void prof_begin(hipStream_t st, int k) { if (g_prof_start[k]) hipEventRecord(g_prof_start[k], st); }
+void prof_end(hipStream_t st, int k) {
+  if (g_prof_stop[k]) hipEventRecord(g_prof_stop[k], st);
+  g_prof_start[k] = g_prof_stop[k] = nullptr;
+}
+
 // Grid gradient (into dF when non-NULL) and, when want_dG, the per-block transform-gradient
 // partials (reduced into dG when non-NULL; otherwise left for a later k_reduce_cell_dG).
 hipError_t launch_cells(const Shape& s, bool gf16, const float* G, size_t G_stride, const void* F, size_t F_stride,
@@ -369,10 +378,12 @@ hipError_t launch_cells(const Shape& s, bool gf16, const float* G, size_t G_stri
   }
 #define APMG_CELL(CC_, F16_)                                                                        \
   if (s.C == CC_ && gf16 == F16_) {                                                                 \
+    prof_begin(st, 1);                                                                              \
     if (wave_kernel) {                                                                              \
       if (want_dG) APMG_WAVE(CC_, F16_, true) else APMG_WAVE(CC_, F16_, false)                      \
     } else if (want_dG) APMG_PULL(CC_, F16_, true)                                                   \
     else APMG_PULL(CC_, F16_, false)                                                                 \
+    prof_end(st, 1);                                                                                \
     if (dF) hipLaunchKernelGGL((k_cell_to_vertex<CC_>), dim3(grid1((int64_t)s.R * s.R * s.R, 1024), s.M, nb), \
                                dim3(256), 0, st, s, cw.CC, dF, dF_stride, dF_paper, accumulate, active); \
   }
@@ -578,12 +589,6 @@ SideStream* side_stream(hipStream_t st) {
 
 }  // namespace
 
-hipEvent_t g_prof_start = nullptr, g_prof_stop = nullptr;
-void prof_begin(hipStream_t st) { if (g_prof_start) hipEventRecord(g_prof_start, st); }
-void prof_end(hipStream_t st) {
-  if (g_prof_stop) hipEventRecord(g_prof_stop, st);
-  g_prof_start = g_prof_stop = nullptr;
-}
 
 // ======================================================================== ABI
 // domain-decomposition inference workspace (defined with its entry point below)
@@ -592,11 +597,15 @@ size_t dd_ws(const Shape& s, const apmg_model* shape, int nb, int64_t n, void* w
 
 extern "C" {
 
-apmg_status apmg_profile_events(hipEvent_t start, hipEvent_t stop) {
-  if ((start == nullptr) != (stop == nullptr)) return APMG_EINVAL;
-  g_prof_start = start;
-  g_prof_stop = stop;
+apmg_status apmg_profile_kernel_events(int32_t kernel, hipEvent_t start, hipEvent_t stop) {
+  if ((start == nullptr) != (stop == nullptr) || kernel < 0 || kernel > 1) return APMG_EINVAL;
+  g_prof_start[kernel] = start;
+  g_prof_stop[kernel] = stop;
   return APMG_OK;
+}
+
+apmg_status apmg_profile_events(hipEvent_t start, hipEvent_t stop) {
+  return apmg_profile_kernel_events(APMG_PROF_ADJOINT, start, stop);
 }
 
 const char* apmg_status_string(apmg_status s) {
@@ -777,11 +786,11 @@ apmg_status apmg_backward(const apmg_model* m, const float* pts, int64_t ld, int
     const int ncols = ps.c1_hi - ps.c1_lo, nrows = ps.w2_hi - ps.w2_lo;
     const PartLayout pl = part_layout(s, ncols, nrows);
     a.part_len = pl.len;
-    if (ps.first) prof_begin(st);
+    if (ps.first) prof_begin(st, 0);
     e = kb > 0 ? launch_adjoint(a, gf16, bf, 0, dim3(nblk, 1), st)
                : launch_tile(true, kb, a, gf16, bf, dim3(nblk, 1), backward_lds_bytes(s, ncols, nrows, bf, kb), st);
     if (e != hipSuccess) return APMG_EHIP;
-    if (&ps == &passes.back()) prof_end(st);
+    if (&ps == &passes.back()) prof_end(st, 0);
     if (ncols > 0)
       hipLaunchKernelGGL(k_reduce_parts, dim3(red_blocks((int64_t)s.H * ncols), 1), dim3(256), 0, st, w.part,
                          nblk, pl.len, pl.o_w1, s.H * ncols, ncols, s.MC, ps.c1_lo, dW[0], (double*)nullptr,
@@ -1092,12 +1101,12 @@ apmg_status run_step(const apmg_batch* b, const Shape& s, void* ws, const Tune& 
     const int ncols = ps.c1_hi - ps.c1_lo, nrows = ps.w2_hi - ps.w2_lo;
     const PartLayout pl = part_layout(s, ncols, nrows);
     a.part_len = pl.len;
-    if (pi == 0) prof_begin(st);
+    if (pi == 0) prof_begin(st, 0);
     e = (kb > 0 && tu.adjoint < 3)
             ? launch_adjoint(a, gf16, bf, tu.adjoint, dim3(nblk, nb), st)
             : launch_tile(true, kb, a, gf16, bf, dim3(nblk, nb), backward_lds_bytes(s, ncols, nrows, bf, kb), st);
     if (e != hipSuccess) return APMG_EHIP;
-    if (pi + 1 == passes.size()) prof_end(st);
+    if (pi + 1 == passes.size()) prof_end(st, 0);
     // the last pass's reductions wait for the fork below (they overlap the gather)
     if (pi + 1 < passes.size()) reduce_pass(ps, st);
   }
@@ -1314,3 +1323,244 @@ extern "C" apmg_status apmg_dd_forward(const apmg_dd_models* d, const apmg_brick
   return hip_status(hipGetLastError());
 }
 
+
+// ---------------------------------------------------------------- encoder variants (Sec. 9)
+namespace {
+
+// The variant's shape as the tile kernels see it: feature grids M' = M * levels (hash; grid g
+// reads transform g / levels) or M (time), C = 2, H = 64, at most 64 features.
+apmg_status check_variant(const apmg_model* m, const apmg_encoder* e, bool need_params, Shape* out,
+                          EncArgs* ea) {
+  if (!m || !e) return APMG_EINVAL;
+  if (m->M < 1 || m->C < 1 || m->n_layers != 3) return m->n_layers == 3 ? APMG_EINVAL : APMG_EUNSUPPORTED;
+  if (m->width[3] != 1 || m->width[1] < 1 || m->width[2] < 1) return APMG_EINVAL;
+  if (need_params) {
+    if (!m->G || !m->F) return APMG_EINVAL;
+    for (int k = 0; k < 3; ++k) if (!m->W[k]) return APMG_EINVAL;
+  }
+  if (!(m->G_rows == 0 || m->G_rows == 3 || m->G_rows == 4)) return APMG_EINVAL;
+  if (m->grid_layout != APMG_GRIDS_MCRRR && m->grid_layout != APMG_GRIDS_MRRRC) return APMG_EINVAL;
+  EncArgs a;
+  memset(&a, 0, sizeof(a));
+  Shape s;
+  memset(&s, 0, sizeof(s));
+  if (e->kind == APMG_ENC_HASH) {
+    if (e->levels < 1 || e->levels > kMaxLevels || e->table_log2 < 1 || e->table_log2 > 24) return APMG_EINVAL;
+    for (int k = 0; k < e->levels; ++k) {
+      if (e->level_res[k] < 1 || e->level_res[k] > 65534) return APMG_EINVAL;
+      a.res2[k / 2] |= (uint32_t)e->level_res[k] << (16 * (k & 1));
+    }
+    a.tmask = (1u << e->table_log2) - 1u;
+    if (m->width[0] != m->M * e->levels * m->C) return APMG_EINVAL;
+    if ((double)m->M * e->levels * ((double)a.tmask + 1.0) * m->C > 2e9) return APMG_EUNSUPPORTED;
+    s.M = m->M * e->levels;
+    s.L = e->levels;
+    s.R = 2;
+  } else if (e->kind == APMG_ENC_TIME) {
+    if (e->Rt < 2 || m->R < 2) return APMG_EINVAL;
+    if (m->width[0] != m->M * m->C) return APMG_EINVAL;
+    if ((double)m->M * e->Rt * (double)m->R * m->R * m->R * m->C > 2e9) return APMG_EUNSUPPORTED;
+    a.Rt = e->Rt;
+    s.M = m->M;
+    s.L = 1;
+    s.R = m->R;
+  } else {
+    return APMG_EINVAL;
+  }
+  if (m->C != 2 || m->grid_dtype != APMG_F32) return APMG_EUNSUPPORTED;
+  if (m->mlp_dtype != APMG_F32 && m->mlp_dtype != APMG_BF16) return APMG_EUNSUPPORTED;
+  if (m->width[1] != 64 || m->width[2] != 64 || m->width[0] > 64) return APMG_EUNSUPPORTED;
+  s.C = m->C;
+  s.H = 64;
+  s.Mh = (s.M + 1) / 2;
+  s.KH = s.Mh * s.C;
+  s.KHP = (s.KH + 15) / 16 * 16;
+  s.MC = s.M * s.C;
+  if (!adjoint_applies(s)) return APMG_EUNSUPPORTED;
+  if (out) *out = s;
+  if (ea) *ea = a;
+  return APMG_OK;
+}
+
+// grid values of the model: hash tables M' T C, time grids M Rt R^3 C
+size_t variant_f_elems(const Shape& s, const EncArgs& ea, int kind) {
+  return kind == APMG_ENC_HASH ? (size_t)s.M * ((size_t)ea.tmask + 1u) * s.C
+                               : (size_t)s.M * ea.Rt * s.R * s.R * s.R * s.C;
+}
+inline int variant_nbx(int64_t n) { return (int)std::max<int64_t>(1, (n + 255) / 256); }
+
+struct VarWs {
+  float* G;        // packed 3-row transforms (4-row input)
+  float* F;        // channel-last copy of paper-order time grids
+  void* swz; float* w3s;
+  double* part;    // adjoint partials (backward)
+  float* dY;       // [M'][n][C] (backward)
+  double* dGpart;  // [M'][nbx][12] (backward)
+  float* dFcl;     // channel-last time-grid gradient (backward, paper-order grids)
+};
+size_t var_ws(const Shape& s, const EncArgs& ea, const apmg_model* m, const apmg_encoder* e, int64_t n,
+              bool backward, void* ws, VarWs* o) {
+  Carver cv(ws);
+  VarWs w;
+  memset(&w, 0, sizeof(w));
+  const bool bf = m->mlp_dtype == APMG_BF16;
+  const bool time_paper = e->kind == APMG_ENC_TIME && paper_grids(m);
+  if (g_rows(m) == 4) w.G = cv.take<float>((size_t)12 * (s.M / s.L));
+  if (time_paper) w.F = cv.take<float>(variant_f_elems(s, ea, e->kind));
+  w.swz = cv.take<char>(swz_sizes(s).total() * (bf ? 2 : 4));
+  w.w3s = cv.take<float>(s.H);
+  if (backward) {
+    w.part = cv.take<double>((size_t)bwd_blocks(n, bf) * part_layout(s, s.MC, s.H).len);
+    w.dY = cv.take<float>((size_t)s.M * std::max<int64_t>(n, 1) * s.C);
+    w.dGpart = cv.take<double>((size_t)s.M * variant_nbx(n) * 12);
+    if (time_paper) w.dFcl = cv.take<float>(variant_f_elems(s, ea, e->kind));
+  }
+  if (o) *o = w;
+  return cv.off;
+}
+
+// transforms and grids as the kernels read them
+hipError_t variant_ops(const Shape& s, const EncArgs& ea, const apmg_model* m, const apmg_encoder* e,
+                       const VarWs& w, hipStream_t st, const float** Gc, const float** Fc) {
+  *Gc = m->G;
+  *Fc = (const float*)m->F;
+  if (w.G) {
+    hipLaunchKernelGGL(k_pack_G, dim3(grid1((int64_t)12 * (s.M / s.L))), dim3(256), 0, st, (int64_t)(s.M / s.L), m->G,
+                       w.G);
+    *Gc = w.G;
+  }
+  if (w.F) {
+    const int64_t V = (int64_t)ea.Rt * s.R * s.R * s.R;
+    hipLaunchKernelGGL((k_mirror_grids<2, float, float, true>), dim3(grid1(s.M * V, 8192)), dim3(256), 0, st,
+                       (int64_t)s.M, V, (const float*)m->F, w.F);
+    *Fc = w.F;
+  }
+  (void)e;
+  return hipGetLastError();
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t apmg_variant_workspace_bytes(int op, const apmg_model* m, const apmg_encoder* e, int64_t n) {
+  Shape s;
+  EncArgs ea;
+  if (n < 0 || check_variant(m, e, false, &s, &ea) != APMG_OK) return 0;
+  if (op == APMG_OP_FORWARD) return var_ws(s, ea, m, e, n, false, nullptr, nullptr);
+  if (op == APMG_OP_BACKWARD) return var_ws(s, ea, m, e, n, true, nullptr, nullptr);
+  return 0;
+}
+
+apmg_status apmg_variant_forward(const apmg_model* m, const apmg_encoder* e, const float* pts, int64_t ld,
+                                 int64_t n, float* f, void* ws, size_t ws_bytes, hipStream_t st) {
+  Shape s;
+  EncArgs ea;
+  apmg_status rc = check_variant(m, e, true, &s, &ea);
+  if (rc != APMG_OK) return rc;
+  if ((rc = check_points(pts, ld, n)) != APMG_OK) return rc;
+  if (n > 0 && !f) return APMG_EINVAL;
+  if (!ws || ws_bytes < var_ws(s, ea, m, e, n, false, nullptr, nullptr)) return APMG_EWORKSPACE;
+  if (n == 0) return APMG_OK;
+  const bool bf = m->mlp_dtype == APMG_BF16;
+  VarWs w;
+  var_ws(s, ea, m, e, n, false, ws, &w);
+  const float *Gc, *Fc;
+  if (variant_ops(s, ea, m, e, w, st, &Gc, &Fc) != hipSuccess) return APMG_EHIP;
+  if (launch_swizzle(s, bf, m->W[0], m->W[1], m->W[2], 0, w.swz, 0, w.w3s, 1, st) != hipSuccess) return APMG_EHIP;
+  TileArgs a;
+  memset(&a, 0, sizeof(a));
+  a.s = s;
+  a.enc = ea;
+  a.G = Gc; a.F = Fc; a.swz = w.swz; a.w3s = w.w3s;
+  a.vscale = m->vmax - m->vmin; a.voff = m->vmin;
+  a.pts = pts; a.ld = ld; a.f = f; a.n = n;
+  const int64_t tiles = (n + 31) / 32;
+  const dim3 grid((unsigned)std::min<int64_t>((tiles + kWavesPerBlock - 1) / kWavesPerBlock, 8192), 1);
+  if (launch_enc_forward(a, e->kind, bf, grid, forward_lds_bytes(s, bf), st) != hipSuccess) return APMG_EHIP;
+  return APMG_OK;
+}
+
+apmg_status apmg_variant_backward(const apmg_model* m, const apmg_encoder* e, const float* pts, int64_t ld,
+                                  int64_t n, const float* df, float* dF, double* dG, float* const* dW,
+                                  uint32_t flags, void* ws, size_t ws_bytes, hipStream_t st) {
+  Shape s;
+  EncArgs ea;
+  apmg_status rc = check_variant(m, e, true, &s, &ea);
+  if (rc != APMG_OK) return rc;
+  if ((rc = check_points(pts, ld, n)) != APMG_OK) return rc;
+  if (n > 0 && !df) return APMG_EINVAL;
+  if (dW) for (int k = 0; k < 3; ++k) if (!dW[k]) return APMG_EINVAL;
+  if (!ws || ws_bytes < var_ws(s, ea, m, e, n, true, nullptr, nullptr)) return APMG_EWORKSPACE;
+  const bool bf = m->mlp_dtype == APMG_BF16, acc = flags & APMG_ACCUMULATE;
+  const int grows = g_rows(m), mt = s.M / s.L;
+  const size_t nF = variant_f_elems(s, ea, e->kind);
+  VarWs w;
+  var_ws(s, ea, m, e, n, true, ws, &w);
+  if (!acc) {
+    if (dW) {
+      hipLaunchKernelGGL(k_fill_f32, dim3(grid1((int64_t)s.H * s.MC)), dim3(256), 0, st, dW[0], (size_t)s.H * s.MC, 0.f);
+      hipLaunchKernelGGL(k_fill_f32, dim3(grid1((int64_t)s.H * s.H)), dim3(256), 0, st, dW[1], (size_t)s.H * s.H, 0.f);
+      hipLaunchKernelGGL(k_fill_f32, dim3(1), dim3(256), 0, st, dW[2], (size_t)s.H, 0.f);
+    }
+    if (dF) hipLaunchKernelGGL(k_fill_f32, dim3(grid1(nF)), dim3(256), 0, st, dF, nF, 0.f);
+    if (dG) hipLaunchKernelGGL(k_fill_f64, dim3(1), dim3(256), 0, st, dG, (size_t)4 * grows * mt, 0.0);
+  }
+  if (n == 0) return hip_status(hipGetLastError());
+  const float *Gc, *Fc;
+  if (variant_ops(s, ea, m, e, w, st, &Gc, &Fc) != hipSuccess) return APMG_EHIP;
+  if (launch_swizzle(s, bf, m->W[0], m->W[1], m->W[2], 0, w.swz, 0, w.w3s, 1, st) != hipSuccess) return APMG_EHIP;
+  const bool want_enc = dF || dG;
+  const int nblk = bwd_blocks(n, bf);
+  const PartLayout pl = part_layout(s, s.MC, s.H);
+  TileArgs a;
+  memset(&a, 0, sizeof(a));
+  a.s = s;
+  a.enc = ea;
+  a.G = Gc; a.F = Fc; a.swz = w.swz; a.w3s = w.w3s;
+  a.vscale = m->vmax - m->vmin; a.voff = m->vmin;
+  a.pts = pts; a.ld = ld; a.n = n;
+  a.df = df;
+  a.dY = want_enc ? w.dY : nullptr;
+  a.c1_lo = 0; a.c1_hi = s.MC;
+  a.w2_lo = 0; a.w2_hi = s.H;
+  a.do_w3 = dW ? 1 : 0;
+  a.part = w.part;
+  a.part_len = pl.len;
+  if (launch_enc_adjoint(a, e->kind, bf, dim3(nblk, 1), st) != hipSuccess) return APMG_EHIP;
+  if (dW) {
+    hipLaunchKernelGGL(k_reduce_parts, dim3(red_blocks((int64_t)s.H * s.MC), 1), dim3(256), 0, st, w.part, nblk,
+                       pl.len, pl.o_w1, s.H * s.MC, s.MC, s.MC, 0, dW[0], (double*)nullptr, (size_t)0, 1,
+                       (const int32_t*)nullptr);
+    hipLaunchKernelGGL(k_reduce_parts, dim3(red_blocks((int64_t)s.H * s.H), 1), dim3(256), 0, st, w.part, nblk,
+                       pl.len, pl.o_w2, s.H * s.H, s.H * s.H, 0, 0, dW[1], (double*)nullptr, (size_t)0, 1,
+                       (const int32_t*)nullptr);
+    hipLaunchKernelGGL(k_reduce_parts, dim3(1, 1), dim3(256), 0, st, w.part, nblk, pl.len, pl.o_w3, s.H, s.H, 0, 0,
+                       dW[2], (double*)nullptr, (size_t)0, 1, (const int32_t*)nullptr);
+  }
+  if (!want_enc) return hip_status(hipGetLastError());
+  // grid / table gradient by the scatter (into the caller's dF, or a channel-last buffer that
+  // is then laid out in the paper's order), transform gradient per block in float64
+  float* dst = dF ? (w.dFcl ? w.dFcl : dF) : nullptr;
+  if (dst && w.dFcl) hipLaunchKernelGGL(k_fill_f32, dim3(grid1(nF)), dim3(256), 0, st, w.dFcl, nF, 0.f);
+  EncScatterArgs sa;
+  memset(&sa, 0, sizeof(sa));
+  sa.s = s; sa.enc = ea; sa.G = Gc; sa.F = Fc;
+  sa.pts = pts; sa.ld = ld; sa.n = n;
+  sa.dY = w.dY;
+  sa.dF = dst;
+  sa.dGpart = dG ? w.dGpart : nullptr;
+  sa.nbx = variant_nbx(n);
+  if (launch_enc_scatter(sa, e->kind, st) != hipSuccess) return APMG_EHIP;
+  if (w.dFcl && dF) {
+    const int64_t V = (int64_t)ea.Rt * s.R * s.R * s.R;
+    hipLaunchKernelGGL(k_cl_to_paper<2>, dim3(grid1(s.M * V, 8192)), dim3(256), 0, st, (int64_t)s.M, V, w.dFcl, dF,
+                       acc ? 1 : 0);
+  }
+  if (dG)
+    hipLaunchKernelGGL(k_reduce_cell_dG, dim3(mt, 1), dim3(256), 0, st, w.dGpart, mt, s.L * sa.nbx, dG,
+                       (size_t)0, grows, acc ? 1 : 0, (const int32_t*)nullptr);
+  return hip_status(hipGetLastError());
+}
+
+}  // extern "C"

@@ -34,10 +34,11 @@ template <bool BF> struct AdjT {
 // operands hb[st] (h1 = relu(z1) in accumulator row order).  The grids of a half are
 // unrolled at compile time (at most 32 features per half); gathers run PD - 1 grids ahead
 // of the grid being interpolated.
-template <int C, bool GF16, bool BF, int PD>
+template <int C, bool GF16, bool BF, int PD, int ENC = kEncDense>
 __device__ inline void adj_fwd(const Shape& s, const float* sG, const void* F, const void* swz, const float* w3s,
                                float x, float y, float z, bool valid, int lane, f32x16 (&z1)[2], f32x16 (&z2)[2],
-                               float& m, float (&yv)[32], bf16x8 (&yb)[4], bf16x8 (&hb)[4]) {
+                               float& m, float (&yv)[32], bf16x8 (&yb)[4], bf16x8 (&hb)[4], const EncArgs& ea,
+                               float tq) {
   constexpr int GMAX = 32 / C;
   constexpr int H = 64, NB = 2;
   const int hf = lane >> 5;
@@ -53,19 +54,19 @@ __device__ inline void adj_fwd(const Shape& s, const float* sG, const void* F, c
 #pragma unroll
     for (int st = 0; st < 4; ++st) yb[st] = bf16x8{0, 0, 0, 0, 0, 0, 0, 0};
   }
-  GridTap<C> tp[PD];
+  GridTap<C, ENC> tp[PD];
   auto gidx = [&](int gi) { return gi < s.Mh ? hf * s.Mh + gi : s.M; };
 #pragma unroll
-  for (int q = 0; q < PD - 1; ++q) grid_tap<C, GF16>(s, sG, F, gidx(q), x, y, z, valid, hR, tp[q]);
+  for (int q = 0; q < PD - 1; ++q) enc_tap<C, GF16, ENC>(s, sG, F, ea, gidx(q), x, y, z, tq, valid, hR, tp[q]);
   if constexpr (!BF) {
     const float* W1 = (const float*)swz;
 #pragma unroll
     for (int gi = 0; gi < GMAX; ++gi) {
       if (gi < s.Mh) {
-        if (gi + PD - 1 < GMAX) grid_tap<C, GF16>(s, sG, F, gidx(gi + PD - 1), x, y, z, valid, hR, tp[(gi + PD - 1) % PD]);
+        if (gi + PD - 1 < GMAX) enc_tap<C, GF16, ENC>(s, sG, F, ea, gidx(gi + PD - 1), x, y, z, tq, valid, hR, tp[(gi + PD - 1) % PD]);
         sched_barrier();
         float e[C];
-        grid_tap_value<C>(tp[gi % PD], e);
+        enc_value<C, ENC>(tp[gi % PD], e);
 #pragma unroll
         for (int c = 0; c < C; ++c) {
           const int k = gi * C + c;
@@ -86,10 +87,10 @@ __device__ inline void adj_fwd(const Shape& s, const float* sG, const void* F, c
 #pragma unroll
         for (int u = 0; u < GPS; ++u) {
           const int gi = st * GPS + u;
-          if (gi + PD - 1 < GMAX) grid_tap<C, GF16>(s, sG, F, gidx(gi + PD - 1), x, y, z, valid, hR, tp[(gi + PD - 1) % PD]);
+          if (gi + PD - 1 < GMAX) enc_tap<C, GF16, ENC>(s, sG, F, ea, gidx(gi + PD - 1), x, y, z, tq, valid, hR, tp[(gi + PD - 1) % PD]);
           sched_barrier();
           float e[C];
-          grid_tap_value<C>(tp[gi % PD], e);
+          enc_value<C, ENC>(tp[gi % PD], e);
 #pragma unroll
           for (int c = 0; c < C; ++c) Bv[u * C + c] = e[c];
         }
@@ -174,7 +175,7 @@ __device__ inline void adj_put(typename AdjT<BF>::T* T, int row, int col, float 
 // at the headline workload: a deeper gather prefetch, PD = 3, changes nothing; float32
 // weights read from global memory instead of LDS, to fit two four-wave blocks per CU,
 // take twice as long.)
-template <int C, bool GF16, bool BF, int NW>
+template <int C, bool GF16, bool BF, int NW, int ENC = kEncDense>
 __global__ void __launch_bounds__(NW * kWave, 8 / NW) k_adjoint(TileArgs a) {
   extern __shared__ float smem[];
   typedef typename AdjT<BF>::T TT_;
@@ -209,7 +210,7 @@ __global__ void __launch_bounds__(NW * kWave, 8 / NW) k_adjoint(TileArgs a) {
 
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, j = lane & 31, hf = lane >> 5;
   const float* G = a.G + model * a.G_stride;
-  for (int i = threadIdx.x; i < 12 * s.M; i += blockDim.x) sG[i] = G[i];
+  for (int i = threadIdx.x; i < 12 * (s.M / s.L); i += blockDim.x) sG[i] = G[i];
   for (int i = threadIdx.x; i < kAdjWaves * H; i += blockDim.x) sW3w[i] = 0.f;
   const void* F = GF16 ? (const void*)((const __half*)a.F + model * a.F_stride)
                        : (const void*)((const float*)a.F + model * a.F_stride);
@@ -247,13 +248,14 @@ __global__ void __launch_bounds__(NW * kWave, 8 / NW) k_adjoint(TileArgs a) {
     const int64_t tile = rbase + wave;
     const int64_t p = tile * 32 + j;
     const bool valid = tile < t_end && p < a.n;
-    float x = 0.f, y = 0.f, z = 0.f;
+    float x = 0.f, y = 0.f, z = 0.f, tq = 0.f;
     if (valid) { x = Pp[p]; y = Pp[a.ld + p]; z = Pp[2 * a.ld + p]; }
+    if constexpr (ENC == kEncTime) tq = valid ? Pp[3 * a.ld + p] : 0.f;
     f32x16 z1[NB], z2[NB];
     float m;
     float yv[32];
     bf16x8 yb[4], hb[4];
-    adj_fwd<C, GF16, BF, PD>(s, sG, F, swz, w3s, x, y, z, valid, lane, z1, z2, m, yv, yb, hb);
+    adj_fwd<C, GF16, BF, PD, ENC>(s, sG, F, swz, w3s, x, y, z, valid, lane, z1, z2, m, yv, yb, hb, a.enc, tq);
 
     float df = 0.f;
     if (valid) {

@@ -12,7 +12,27 @@ struct Shape {
   int KH;           // features per half = Mh*C
   int KHP;          // KH rounded up to a multiple of 16
   int MC;           // M*C (= width[0])
+  int L;            // feature grids per transform: 1, or the hash levels of the hash-grid encoder
+                    // (grid g then reads transform g / L); transforms = M / L
 };
+
+// Encoder variants of Sec. 9 (the dense trilinear grids of Eq. (2) are encoder 0).
+// 1: a hash grid inside each adaptive grid: feature grid g = (grid g / L, level g % L), level k
+//    with res(k) cells per axis, a table of T = tmask + 1 entries of C features per (grid,
+//    level), tables [M][L][T][C]; 2: 4-D grids with Rt time vertices, gathered from the
+//    channel-last copy [M][Rt][R^3][C] (time slice t of grid g is grid g * Rt + t there),
+//    the time coordinate in a fourth row of the points.
+constexpr int kEncDense = 0, kEncHash = 1, kEncTime = 2;
+constexpr int kMaxLevels = 8;
+struct EncArgs {
+  uint32_t res2[kMaxLevels / 2];   // hash: cells per axis of level k in bits 16 (k % 2) of word k / 2
+  uint32_t tmask;                  // hash: T - 1
+  int Rt;                          // time: vertices along the time axis
+};
+__host__ __device__ inline int enc_level_res(const EncArgs& e, int k) {
+  const uint32_t w = k < 2 ? e.res2[0] : k < 4 ? e.res2[1] : k < 6 ? e.res2[2] : e.res2[3];
+  return (int)((w >> (16 * (k & 1))) & 0xffffu);
+}
 
 // Element counts of the swizzled weight operands of one model: the first
 // layer (A operand order), the second layer and its transpose, the first
@@ -62,6 +82,7 @@ struct TileArgs {
   // products are stored instead of accumulated (float32, or bf16 with the bf16 MLP), one block
   // per 32-point tile of act_rows rows x 32 points, rows y [MC] | h1 [H] | delta1 [H] | delta2 [H]
   void* act; int act_rows; size_t act_stride;   // act_stride: elements per model
+  EncArgs enc;                            // encoder variants (zero for the dense grids)
 };
 
 // Per-block partial sums of the adjoint, float64: [dW1 slice H x ncols]

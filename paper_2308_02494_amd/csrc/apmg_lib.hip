@@ -13,4 +13,5 @@
 #include "apmg_sort.hip"
 #include "apmg_dd.hip"
 #include "apmg_scatter.hip"
+#include "apmg_variants.hip"
 #include "apmg_abi.hip"

@@ -14,11 +14,12 @@
 // the A operand row/k order matches.  Nothing but the transforms goes to LDS
 // in the forward pass.
 //
-// The adjoint recomputes the forward pass per tile, back-propagates through
-// the MLP with the transposed swizzles, produces dL/dy in the same per-half
-// grid order, scatters dL/dF with float atomics, reduces the transform
-// gradient through the trilinear weights, and forms the weight gradients as
-// matrix products over the tile's 32 points after an LDS transpose.
+// The adjoint (k_backward here; the tiled k_adjoint in apmg_adjoint.hip for the
+// register-resident shapes) recomputes the forward pass per tile,
+// back-propagates through the MLP with the transposed swizzles, stores dL/dy
+// per (grid, point) for the per-cell gather of the grid gradient, and forms
+// the weight gradients as matrix products over the tile's points after an LDS
+// transpose (or stores the activations for k_dw_gemm).
 
 namespace apmg {
 
@@ -107,9 +108,16 @@ __device__ inline void tt_put(typename TT<BF>::T* t, int row, int j, float v) {
 // while this one is consumed: grid_tap issues the 8 corner loads (always from a valid
 // address: cell 0 of grid 0 when the point is outside, invalid or past the last grid),
 // grid_tap_value interpolates and applies the Eq. (2) mask.
-template <int C> struct GridTap {
+template <int C, int ENC = kEncDense> struct GridTap {
   float w[3];
   float val[8][C];
+  bool in;
+};
+// 4-D grids: the corners of the two time slices and the time offset
+template <int C> struct GridTap<C, kEncTime> {
+  float w[3];
+  float wt;
+  float va[8][C], vb[8][C];
   bool in;
 };
 
@@ -134,14 +142,97 @@ __device__ inline void grid_tap_value(const GridTap<C>& t, float e[C]) {
   for (int c = 0; c < C; ++c) e[c] = t.in ? e[c] : 0.f;
 }
 
+// Entry of vertex (vx, vy, vz) of a hash level with n1 = N + 1 vertices per axis: one entry
+// per vertex while the level's n1^3 vertices fit the table (x fastest), else the spatial hash
+// of Mueller et al. 2022 (coordinates times 1, 2654435761 and 805459861, XOR, mod 2^32),
+// masked to the table size.
+__device__ inline uint32_t hash_entry(uint32_t vx, uint32_t vy, uint32_t vz, uint32_t n1, bool dense, uint32_t tmask) {
+  return dense ? vx + n1 * (vy + n1 * vz) : ((vx ^ (vy * 2654435761u) ^ (vz * 805459861u)) & tmask);
+}
+
+// The lookup of feature grid g for the encoder variants.  Hash (Sec. 9 (1)): the local point of
+// transform g / L (Eq. (1)), the mask of Eq. (2), the cell of level k = g % L at N_k cells per
+// axis (u = fma(l, N_k/2, N_k/2), as a dense grid with R - 1 = N_k), and the C features of its 8
+// corner entries in table g.  Time (Sec. 9 (2)): the spatial cell of Eq. (2), the time cell
+// u_t = fma(t, (Rt-1)/2, (Rt-1)/2) (lower vertex clamped to [0, Rt-2]; a time outside [-1, 1]
+// masks the grid), and the corners of the two time slices.  Every load reads a valid address.
+template <int C, bool GF16, int ENC>
+__device__ inline void enc_tap(const Shape& s, const float* sG, const void* F, const EncArgs& ea, int g, float x,
+                               float y, float z, float tq, bool valid, float hR, GridTap<C, ENC>& t) {
+  if constexpr (ENC == kEncDense) {
+    grid_tap<C, GF16>(s, sG, F, g, x, y, z, valid, hR, t);
+  } else if constexpr (ENC == kEncHash) {
+    const bool gok = valid && g < s.M;
+    const int gg = gok ? g : 0;
+    const int gt = gg / s.L, k = gg - gt * s.L;
+    const int N = enc_level_res(ea, k);
+    float l[3];
+    local_coords(sG + 12 * gt, x, y, z, l);
+    int i0[3];
+    t.in = cell_of(l, 0.5f * (float)N, N + 1, i0, t.w) && gok;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) i0[d] = t.in ? i0[d] : 0;
+    const uint32_t n1 = (uint32_t)N + 1u;
+    const bool dense = (uint64_t)n1 * n1 * n1 <= (uint64_t)ea.tmask + 1u;
+    const float* base = (const float*)F + (size_t)gg * ((size_t)ea.tmask + 1u) * C;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const uint32_t ent = hash_entry((uint32_t)i0[0] + (q & 1), (uint32_t)i0[1] + ((q >> 1) & 1),
+                                      (uint32_t)i0[2] + (q >> 2), n1, dense, ea.tmask);
+      const float* p = base + (size_t)ent * C;
+      if constexpr (C == 1) {
+        t.val[q][0] = p[0];
+      } else if constexpr (C == 2) {
+        const f32x2a4 v = *(const f32x2a4*)p;
+        t.val[q][0] = v.x; t.val[q][1] = v.y;
+      } else {
+        const f32x4 v = *(const f32x4*)p;
+        t.val[q][0] = v.x; t.val[q][1] = v.y; t.val[q][2] = v.z; t.val[q][3] = v.w;
+      }
+    }
+  } else {
+    const bool gok = valid && g < s.M;
+    const int gg = gok ? g : 0;
+    float l[3];
+    local_coords(sG + 12 * gg, x, y, z, l);
+    int i0[3];
+    bool in = cell_of(l, hR, s.R, i0, t.w);
+    const float ht = 0.5f * (float)(ea.Rt - 1);
+    const float ut = __builtin_fmaf(tq, ht, ht);
+    const float ft = fminf(fmaxf(floorf(ut), 0.0f), (float)(ea.Rt - 2));   // NaN -> 0 via fmaxf
+    t.in = in && (tq >= -1.0f) && (tq <= 1.0f) && gok;
+    t.wt = ut - ft;
+    const int t0 = t.in ? (int)ft : 0;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) i0[d] = t.in ? i0[d] : 0;
+    gather_cell<C, false>(F, gg * ea.Rt + t0, s.R, i0, t.va);
+    gather_cell<C, false>(F, gg * ea.Rt + t0 + 1, s.R, i0, t.vb);
+  }
+}
+
+template <int C, int ENC>
+__device__ inline void enc_value(const GridTap<C, ENC>& t, float e[C]) {
+  if constexpr (ENC != kEncTime) {
+    trilerp<C>(t.val, t.w, e);
+  } else {
+    float e0[C], e1[C];
+    trilerp<C>(t.va, t.w, e0);
+    trilerp<C>(t.vb, t.w, e1);
+#pragma unroll
+    for (int c = 0; c < C; ++c) e[c] = __builtin_fmaf(t.wt, e1[c] - e0[c], e0[c]);
+  }
+#pragma unroll
+  for (int c = 0; c < C; ++c) e[c] = t.in ? e[c] : 0.f;
+}
+
 // Forward pass of one 32-point tile.  With STY, the features are also written to the
 // LDS tile Ty in dy-block order: feature t of half hf goes to row 32 (t/16) + 16 hf + t%16.
-template <int C, int H, bool GF16, bool BF, bool STY = false>
+template <int C, int H, bool GF16, bool BF, bool STY = false, int ENC = kEncDense>
 __device__ inline void tile_fwd(const Shape& s, const float* sG, const void* F, const void* swz,
                                 const float* w3s, float x, float y, float z, bool valid, int lane,
                                 f32x16 (&z1)[H / 32], f32x16 (&z2)[H / 32], float& m,
                                 typename TT<BF>::T* Ty = nullptr, void* yact = nullptr, int64_t yld = 0,
-                                int64_t ypa = 0) {
+                                int64_t ypa = 0, EncArgs ea = {}, float tq = 0.f) {
   constexpr int NB = H / 32;
   const int hf = lane >> 5;
   const float hR = 0.5f * (float)(s.R - 1);
@@ -153,14 +244,14 @@ __device__ inline void tile_fwd(const Shape& s, const float* sG, const void* F, 
   // two alternating taps (no register copies); every tap load is unconditional (a zero tap
   // past the last grid), so the loads stay in straight-line code and each grid waits only
   // for its own.
-  GridTap<C> ta, tb;
+  GridTap<C, ENC> ta, tb;
   auto gidx = [&](int gi) { return gi < s.Mh ? hf * s.Mh + gi : s.M; };
-  grid_tap<C, GF16>(s, sG, F, gidx(0), x, y, z, valid, hR, ta);
+  enc_tap<C, GF16, ENC>(s, sG, F, ea, gidx(0), x, y, z, tq, valid, hR, ta);
   if constexpr (!BF) {
     const float* W1 = (const float*)swz;
-    auto consume = [&](const GridTap<C>& t, int gi) {
+    auto consume = [&](const GridTap<C, ENC>& t, int gi) {
       float e[C];
-      grid_tap_value<C>(t, e);
+      enc_value<C, ENC>(t, e);
       if (yact && hf * s.Mh + gi < s.M) {
 #pragma unroll
         for (int c = 0; c < C; ++c) act_put<BF>(yact, (size_t)((hf * s.Mh + gi) * C + c) * yld + ypa, e[c]);
@@ -174,10 +265,10 @@ __device__ inline void tile_fwd(const Shape& s, const float* sG, const void* F, 
       }
     };
     for (int gi = 0; gi < s.Mh; gi += 2) {
-      grid_tap<C, GF16>(s, sG, F, gidx(gi + 1), x, y, z, valid, hR, tb);
+      enc_tap<C, GF16, ENC>(s, sG, F, ea, gidx(gi + 1), x, y, z, tq, valid, hR, tb);
       sched_barrier();   // keep the loads ahead of the consumer (no sinking under register pressure)
       consume(ta, gi);
-      grid_tap<C, GF16>(s, sG, F, gidx(gi + 2), x, y, z, valid, hR, ta);
+      enc_tap<C, GF16, ENC>(s, sG, F, ea, gidx(gi + 2), x, y, z, tq, valid, hR, ta);
       sched_barrier();
       if (gi + 1 < s.Mh) consume(tb, gi + 1);
     }
@@ -190,12 +281,12 @@ __device__ inline void tile_fwd(const Shape& s, const float* sG, const void* F, 
 #pragma unroll
       for (int u = 0; u < GPS; ++u) {
         const int gi = st * GPS + u;
-        GridTap<C>& cur = (u & 1) ? tb : ta;
-        GridTap<C>& nxt = (u & 1) ? ta : tb;
-        grid_tap<C, GF16>(s, sG, F, gidx(gi + 1), x, y, z, valid, hR, nxt);
+        GridTap<C, ENC>& cur = (u & 1) ? tb : ta;
+        GridTap<C, ENC>& nxt = (u & 1) ? ta : tb;
+        enc_tap<C, GF16, ENC>(s, sG, F, ea, gidx(gi + 1), x, y, z, tq, valid, hR, nxt);
         sched_barrier();
         float e[C];
-        grid_tap_value<C>(cur, e);
+        enc_value<C, ENC>(cur, e);
         if (yact && gi < s.Mh && hf * s.Mh + gi < s.M) {
 #pragma unroll
           for (int c = 0; c < C; ++c) act_put<BF>(yact, (size_t)((hf * s.Mh + gi) * C + c) * yld + ypa, e[c]);
@@ -263,7 +354,7 @@ __host__ __device__ inline size_t fwd_weight_bytes(const Shape& s, bool bf) {
 }
 
 // WL: the swizzled weights are staged in LDS (after the transforms).
-template <int C, int H, bool GF16, bool BF, bool WL>
+template <int C, int H, bool GF16, bool BF, bool WL, int ENC = kEncDense>
 __global__ void __launch_bounds__(kBlock) k_forward(TileArgs a) {
   extern __shared__ float smem[];
   // logical block: models in order, each model's blocks over contiguous runs of its
@@ -274,7 +365,7 @@ __global__ void __launch_bounds__(kBlock) k_forward(TileArgs a) {
   const Shape s = a.s;
   float* sG = smem;
   const float* G = a.G + model * a.G_stride;
-  for (int i = threadIdx.x; i < 12 * s.M; i += blockDim.x) sG[i] = G[i];
+  for (int i = threadIdx.x; i < 12 * (s.M / s.L); i += blockDim.x) sG[i] = G[i];
   const void* F = GF16 ? (const void*)((const __half*)a.F + model * a.F_stride)
                        : (const void*)((const float*)a.F + model * a.F_stride);
   const size_t esz = BF ? 2 : 4;
@@ -302,11 +393,13 @@ __global__ void __launch_bounds__(kBlock) k_forward(TileArgs a) {
   for (int64_t tile = lb * per + wave; tile < t_end; tile += kWavesPerBlock) {
     const int64_t p = tile * 32 + j;
     const bool valid = p < cnt;
-    float x = 0.f, y = 0.f, z = 0.f;
+    float x = 0.f, y = 0.f, z = 0.f, tq = 0.f;
     if (valid) { x = P[p]; y = P[a.ld + p]; z = P[2 * a.ld + p]; }
+    if constexpr (ENC == kEncTime) tq = valid ? P[3 * a.ld + p] : 0.f;
     f32x16 z1[H / 32], z2[H / 32];
     float m;
-    tile_fwd<C, H, GF16, BF>(s, sG, F, swz, w3s, x, y, z, valid, lane, z1, z2, m);
+    tile_fwd<C, H, GF16, BF, false, ENC>(s, sG, F, swz, w3s, x, y, z, valid, lane, z1, z2, m, nullptr, nullptr, 0, 0,
+                                          a.enc, tq);
     if (valid && lane < 32) fo[p] = __builtin_fmaf(m, vs, vo);
   }
 }

@@ -1,0 +1,199 @@
+// Adjoint of the two encoder variants of Sec. 9 (a hash grid inside each adaptive grid; 4-D
+// grids with a time axis) with respect to their tables / grids and the transforms.
+//
+// The forward and the MLP adjoint are the tile kernels (k_forward, k_adjoint) instantiated
+// with the variant's lookup (enc_tap); k_adjoint stores dL/dy per (feature grid, point).  The
+// scatter below then adds w_q dL/dy_c into the corner entries with float atomics: a hash table
+// entry collects the contributions of every vertex that maps to it, so the per-cell gather of
+// the dense grids does not apply, and the 4-D grids share the scatter.  The sums of float
+// atomics are not in a fixed order (results reproducible to rounding).  The transform gradient
+// through the interpolation weights is reduced per block in float64, in a fixed order.
+
+namespace apmg {
+
+struct EncScatterArgs {
+  Shape s;
+  EncArgs enc;
+  const float* G;          // [M / L][12]
+  const float* F;          // hash: tables [M][T][C]; time: channel-last [M][Rt][R^3][C]
+  const float* pts; int64_t ld; int64_t n;
+  const float* dY;         // [M][n][C], dL/dy per feature grid (M feature grids)
+  float* dF;               // same layout as F (channel-last for time), accumulated; NULL: no grid gradient
+  double* dGpart;          // [M][nbx][12], or NULL for no transform gradient
+  int nbx;                 // point blocks per feature grid
+};
+
+// dl_d = sum_c dy_c d(trilinear_c)/dw_d for corner values val and offsets w.
+template <int C>
+__device__ inline void trilerp_dw(const float val[8][C], const float w[3], const float dy[C], float dl[3]) {
+#pragma unroll
+  for (int d = 0; d < 3; ++d) dl[d] = 0.f;
+#pragma unroll
+  for (int q = 0; q < 8; ++q) {
+    const float wx = (q & 1) ? w[0] : 1.f - w[0], wy = (q & 2) ? w[1] : 1.f - w[1], wz = (q & 4) ? w[2] : 1.f - w[2];
+    const float sx = (q & 1) ? 1.f : -1.f, sy = (q & 2) ? 1.f : -1.f, sz = (q & 4) ? 1.f : -1.f;
+    float gq = 0.f;
+#pragma unroll
+    for (int c = 0; c < C; ++c) gq = __builtin_fmaf(val[q][c], dy[c], gq);
+    dl[0] = __builtin_fmaf(gq * sx, wy * wz, dl[0]);
+    dl[1] = __builtin_fmaf(gq * sy, wx * wz, dl[1]);
+    dl[2] = __builtin_fmaf(gq * sz, wx * wy, dl[2]);
+  }
+}
+
+__device__ inline float tri_weight(int q, const float w[3]) {
+  return ((q & 1) ? w[0] : 1.f - w[0]) * ((q & 2) ? w[1] : 1.f - w[1]) * ((q & 4) ? w[2] : 1.f - w[2]);
+}
+
+// One thread per (point, feature grid): blockIdx.y = feature grid g, 256 points per block.
+template <int C, int ENC>
+__global__ void __launch_bounds__(256) k_enc_scatter(EncScatterArgs a) {
+  __shared__ float sG[12 * 256];
+  __shared__ double sred[4][12];
+  const Shape s = a.s;
+  const int g = blockIdx.y, bx = blockIdx.x;
+  const int mt = s.M / s.L;
+  for (int i = threadIdx.x; i < 12 * mt; i += blockDim.x) sG[i] = a.G[i];
+  __syncthreads();
+  const int64_t p = (int64_t)bx * blockDim.x + threadIdx.x;
+  const bool valid = p < a.n;
+  float x = 0.f, y = 0.f, z = 0.f, tq = 0.f;
+  if (valid) { x = a.pts[p]; y = a.pts[a.ld + p]; z = a.pts[2 * a.ld + p]; }
+  if constexpr (ENC == kEncTime) tq = valid ? a.pts[3 * a.ld + p] : 0.f;
+  float dy[C];
+#pragma unroll
+  for (int c = 0; c < C; ++c) dy[c] = valid ? a.dY[((size_t)g * a.n + p) * C + c] : 0.f;
+  GridTap<C, ENC> t;
+  const float hR = 0.5f * (float)(s.R - 1);
+  enc_tap<C, false, ENC>(s, sG, a.F, a.enc, g, x, y, z, tq, valid, hR, t);
+  float dl[3] = {0.f, 0.f, 0.f};
+  if (t.in) {
+    if constexpr (ENC == kEncHash) {
+      const int gt = g / s.L, k = g - gt * s.L;
+      const int N = enc_level_res(a.enc, k);
+      const uint32_t n1 = (uint32_t)N + 1u;
+      const bool dense = (uint64_t)n1 * n1 * n1 <= (uint64_t)a.enc.tmask + 1u;
+      // the cell again (the lookup keeps only its offsets; the same float32 decision)
+      float l[3];
+      local_coords(sG + 12 * gt, x, y, z, l);
+      int i0[3];
+      float w[3];
+      cell_of(l, 0.5f * (float)N, N + 1, i0, w);
+      (void)w;
+      if (a.dF) {
+        float* base = a.dF + (size_t)g * ((size_t)a.enc.tmask + 1u) * C;
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+          const uint32_t ent = hash_entry((uint32_t)i0[0] + (q & 1), (uint32_t)i0[1] + ((q >> 1) & 1),
+                                          (uint32_t)i0[2] + (q >> 2), n1, dense, a.enc.tmask);
+          const float wq = tri_weight(q, t.w);
+#pragma unroll
+          for (int c = 0; c < C; ++c) unsafeAtomicAdd(base + (size_t)ent * C + c, wq * dy[c]);
+        }
+      }
+      trilerp_dw<C>(t.val, t.w, dy, dl);
+      const float sc = 0.5f * (float)N;
+#pragma unroll
+      for (int d = 0; d < 3; ++d) dl[d] *= sc;
+    } else {
+      float l[3];
+      local_coords(sG + 12 * g, x, y, z, l);
+      int i0[3];
+      float w[3];
+      cell_of(l, hR, s.R, i0, w);
+      (void)w;
+      const float ht = 0.5f * (float)(a.enc.Rt - 1);
+      const float ut = __builtin_fmaf(tq, ht, ht);
+      const int t0 = (int)fminf(fmaxf(floorf(ut), 0.0f), (float)(a.enc.Rt - 2));
+      const uint32_t R = (uint32_t)s.R, RC = R * C, RRC = R * R * C;
+#pragma unroll
+      for (int sl = 0; sl < (a.dF ? 2 : 0); ++sl) {
+        const float ws = sl ? t.wt : 1.f - t.wt;
+        float* base = a.dF + (((size_t)g * a.enc.Rt + t0 + sl) * R * R * R) * C;
+        const uint32_t cb = ((uint32_t)i0[2] * R + i0[1]) * RC + (uint32_t)i0[0] * C;
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+          const float wq = ws * tri_weight(q, t.w);
+          const uint32_t o = cb + (q & 1) * C + ((q >> 1) & 1) * RC + (q >> 2) * RRC;
+#pragma unroll
+          for (int c = 0; c < C; ++c) unsafeAtomicAdd(base + o + c, wq * dy[c]);
+        }
+      }
+      float d0[3], d1[3];
+      trilerp_dw<C>(t.va, t.w, dy, d0);
+      trilerp_dw<C>(t.vb, t.w, dy, d1);
+#pragma unroll
+      for (int d = 0; d < 3; ++d) dl[d] = ((1.f - t.wt) * d0[d] + t.wt * d1[d]) * hR;
+    }
+  }
+  if (a.dGpart) {
+    const float xs[4] = {t.in ? x : 0.f, t.in ? y : 0.f, t.in ? z : 0.f, t.in ? 1.f : 0.f};
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const double v = wave_sum((double)dl[r] * (double)xs[k]);
+        if (lane == 0) sred[wave][4 * r + k] = v;
+      }
+    __syncthreads();
+    if (threadIdx.x < 12) {
+      const double v = sred[0][threadIdx.x] + sred[1][threadIdx.x] + sred[2][threadIdx.x] + sred[3][threadIdx.x];
+      a.dGpart[((size_t)g * a.nbx + bx) * 12 + threadIdx.x] = v;
+    }
+  }
+}
+
+// Channel-last [nm][V][C] -> the paper's order [nm][C][V], added into dst when accumulate.
+template <int C>
+__global__ void k_cl_to_paper(int64_t nm, int64_t V, const float* __restrict__ src, float* __restrict__ dst,
+                              int accumulate) {
+  const int64_t total = nm * V;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t g = i / V, v = i - g * V;
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+      float* d = dst + (g * C + c) * V + v;
+      *d = accumulate ? *d + src[i * C + c] : src[i * C + c];
+    }
+  }
+}
+
+hipError_t launch_enc_scatter(const EncScatterArgs& a, int enc, hipStream_t st) {
+  const dim3 grid((unsigned)a.nbx, (unsigned)a.s.M);
+  if (a.s.C != 2) return hipErrorInvalidValue;
+  if (enc == kEncHash) hipLaunchKernelGGL((k_enc_scatter<2, kEncHash>), grid, dim3(256), 0, st, a);
+  else if (enc == kEncTime) hipLaunchKernelGGL((k_enc_scatter<2, kEncTime>), grid, dim3(256), 0, st, a);
+  else return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+// The tile kernels of the variants (C = 2, H = 64): forward with the weights in LDS, and the
+// tiled adjoint with the waves per block of the dense shapes.
+hipError_t launch_enc_forward(const TileArgs& a, int enc, bool bf, dim3 grid, size_t shmem, hipStream_t st) {
+  if (a.s.C != 2 || a.s.H != 64 || fwd_weight_bytes(a.s, bf) > kFwdWeightLdsMax) return hipErrorInvalidValue;
+#define APMG_EF(E)                                                                                \
+  if (bf) hipLaunchKernelGGL((k_forward<2, 64, false, true, true, E>), grid, dim3(kBlock), shmem, st, a); \
+  else hipLaunchKernelGGL((k_forward<2, 64, false, false, true, E>), grid, dim3(kBlock), shmem, st, a);
+  if (enc == kEncHash) { APMG_EF(kEncHash) }
+  else if (enc == kEncTime) { APMG_EF(kEncTime) }
+  else return hipErrorInvalidValue;
+#undef APMG_EF
+  return hipGetLastError();
+}
+
+hipError_t launch_enc_adjoint(const TileArgs& a, int enc, bool bf, dim3 grid, hipStream_t st) {
+  if (a.s.C != 2 || !adjoint_applies(a.s)) return hipErrorInvalidValue;
+  const int nw = adjoint_waves(0, bf);
+  const size_t shmem = adjoint_lds_bytes(a.s, bf, nw);
+#define APMG_EA(E)                                                                                          \
+  if (bf) hipLaunchKernelGGL((k_adjoint<2, false, true, 4, E>), grid, dim3(4 * kWave), shmem, st, a);      \
+  else hipLaunchKernelGGL((k_adjoint<2, false, false, 8, E>), grid, dim3(8 * kWave), shmem, st, a);
+  if (enc == kEncHash) { APMG_EA(kEncHash) }
+  else if (enc == kEncTime) { APMG_EA(kEncTime) }
+  else return hipErrorInvalidValue;
+#undef APMG_EA
+  return hipGetLastError();
+}
+
+}  // namespace apmg

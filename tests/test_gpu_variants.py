@@ -1,0 +1,279 @@
+"""GPU parity of the encoder variants of Sec. 9 (a hash grid inside each adaptive grid; 4-D
+time grids) against their FP64 oracle, through the C ABI (apmg_variant_forward /
+apmg_variant_backward).
+
+Bars as for the dense model: per output tensor, normwise relative error <= 1e-5 and
+max |x - x*| <= 1e-5 ||x*||_inf in float32; points whose hidden pre-activations come within
+1e-4 (relative) of a ReLU kink are dropped from adjoint inputs.  The table / grid gradient is
+a sum of float atomics (order not fixed), held to the same bars.  BF16 MLP errors are stated.
+"""
+import ctypes
+
+import numpy as np
+import pytest
+import torch
+
+import synth
+from oracle import apmg_variants as V
+
+pytestmark = [pytest.mark.gpu,
+              pytest.mark.skipif(not torch.cuda.is_available(), reason="needs a GPU")]
+
+DEV = "cuda"
+TOL = 1e-5
+
+
+def A():
+    import paper_2308_02494_amd as mod
+    return mod
+
+
+def errs(got, want):
+    got = np.asarray(got, np.float64)
+    want = np.asarray(want, np.float64)
+    nrm = np.linalg.norm(want)
+    norm_rel = np.linalg.norm(got - want) / nrm if nrm > 0 else np.linalg.norm(got - want)
+    inf = np.max(np.abs(want)) if want.size else 0.0
+    max_rel = np.max(np.abs(got - want)) / inf if inf > 0 else (np.max(np.abs(got - want)) if got.size else 0.0)
+    return norm_rel, max_rel
+
+
+def assert_close(name, got, want, tol=TOL):
+    a, b = errs(got, want)
+    print(f"{name}: normwise {a:.2e}, max {b:.2e}", flush=True)
+    assert a <= tol and b <= tol, (name, a, b)
+
+
+def points(n, seed=3, time=False):
+    x = synth.uniform_points_host(n, seed=seed).astype(np.float32)
+    if n >= 16:
+        x[0] = [1.0, 1.0, 1.0]
+        x[1] = [-1.0, -1.0, -1.0]
+        x[2] = [np.nan, 0.1, 0.2]
+        x[3] = [1.3, 0.0, 0.0]
+        x[4] = [0.0, -1.7, 0.4]
+        x[5] = [0.0, 0.0, 0.0]
+    if not time:
+        return x
+    rng = np.random.default_rng(seed + 100)
+    t = rng.uniform(-1.0, 1.0, size=(n, 1)).astype(np.float32)
+    if n >= 16:
+        t[6] = 1.0
+        t[7] = -1.0
+        t[8] = 1.25        # outside the time range: every grid masked
+        t[9] = np.nan
+        t[10] = 0.5        # on a time vertex (Rt = 5)
+    return np.concatenate([x, t], axis=1)
+
+
+def soa(x):
+    return torch.from_numpy(np.ascontiguousarray(x.T)).to(DEV)
+
+
+def transforms(M, seed):
+    return synth.init_model(M, 2, 4, [2 * M, 64, 64, 1], seed=seed, extra_translation=0.1)["G"]
+
+
+def mlp(K, seed):
+    rng = np.random.default_rng(seed)
+    lim = lambda i, o: np.sqrt(6.0 / (i + o))  # noqa: E731  (Glorot uniform, Sec. 4.3.3)
+    return [rng.uniform(-lim(K, 64), lim(K, 64), size=(64, K)).astype(np.float32),
+            rng.uniform(-lim(64, 64), lim(64, 64), size=(64, 64)).astype(np.float32),
+            rng.uniform(-lim(64, 1), lim(64, 1), size=(1, 64)).astype(np.float32)]
+
+
+def hash_host(M=8, L=4, T=1 << 12, res=(3, 7, 15, 31), seed=1):
+    rng = np.random.default_rng(seed)
+    return {"G": transforms(M, seed), "Theta": rng.uniform(-0.5, 0.5, size=(M, L, T, 2)).astype(np.float32),
+            "res": list(res), "W": mlp(M * L * 2, seed + 1), "vmin": -0.5, "vmax": 2.0}
+
+
+def time_host(M=16, R=9, Rt=5, seed=2):
+    rng = np.random.default_rng(seed)
+    return {"G": transforms(M, seed), "F4": rng.uniform(-0.5, 0.5, size=(M, 2, Rt, R, R, R)).astype(np.float32),
+            "W": mlp(M * 2, seed + 1), "vmin": -0.5, "vmax": 2.0}
+
+
+def f64(h):
+    return {k: ([np.asarray(w, np.float64) for w in v] if k == "W" else
+                (np.asarray(v, np.float64) if isinstance(v, np.ndarray) else v)) for k, v in h.items()}
+
+
+def hash_model(h, mlp_dtype=None):
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(DEV)  # noqa: E731
+    return A().VariantModel(A().ENC_HASH, dev(h["G"]), dev(h["Theta"]), [dev(w) for w in h["W"]], h["vmin"],
+                            h["vmax"], A().F32 if mlp_dtype is None else mlp_dtype, level_res=h["res"])
+
+
+def time_model(h, mlp_dtype=None, channel_last=False):
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(DEV)  # noqa: E731
+    F = h["F4"].transpose(0, 2, 3, 4, 5, 1) if channel_last else h["F4"]
+    return A().VariantModel(A().ENC_TIME, dev(h["G"]), dev(F), [dev(w) for w in h["W"]], h["vmin"], h["vmax"],
+                            A().F32 if mlp_dtype is None else mlp_dtype,
+                            layout=A().GRIDS_MRRRC if channel_last else A().GRIDS_MCRRR)
+
+
+def kink_free(cache, tau=1e-4):
+    keep = None
+    for z in cache["z"][:-1]:
+        scale = np.sqrt(np.mean(z * z, axis=1, keepdims=True)) + 1e-30
+        k = np.all(np.abs(z) / scale > tau, axis=1)
+        keep = k if keep is None else keep & k
+    return keep
+
+
+# ------------------------------------------------------------------ hash grid
+
+def test_hash_forward_fp32():
+    h = hash_host()
+    x = points(3001)
+    f = A().apmg_variant_forward(hash_model(h), soa(x)).cpu().numpy()
+    fo, _ = V.hash_forward(f64(h), x.astype(np.float64))
+    assert_close("f", f, fo)
+    assert f[3] == np.float32(h["vmin"]) and f[2] == np.float32(h["vmin"])   # outside and NaN points
+
+
+def test_hash_backward_fp32():
+    h = hash_host(M=4, L=4, T=1 << 10, res=(2, 6, 12, 24), seed=5)     # levels 2, 3 hashed (collisions)
+    x = points(4001, seed=7)
+    _, cache = V.hash_forward(f64(h), x.astype(np.float64))
+    x = x[kink_free(cache)]
+    df = np.random.default_rng(8).normal(size=x.shape[0]).astype(np.float32)
+    dF, dG, dW = A().apmg_variant_backward(hash_model(h), soa(x), torch.from_numpy(df).to(DEV))
+    go = V.hash_backward(f64(h), x.astype(np.float64), df.astype(np.float64))
+    assert np.count_nonzero(go["dTheta"][:, 3]) > 0
+    assert_close("dTheta", dF.cpu().numpy(), go["dTheta"])
+    assert_close("dG", dG.cpu().numpy(), go["dG"])
+    for k in range(3):
+        assert_close(f"dW{k + 1}", dW[k].cpu().numpy(), go["dW"][k])
+
+
+def test_hash_dense_level_equals_the_dense_model_bitwise():
+    # one level with N = R - 1 and T >= R^3 reads every vertex once: the same decisions, corner
+    # values and arithmetic as apmg_forward of the dense grid (entry x + R(y + Rz))
+    M, R = 16, 8
+    host = synth.init_model(M, 2, R, [2 * M, 64, 64, 1], seed=9, extra_translation=0.1)
+    Theta = np.zeros((M, 1, 512, 2), np.float32)
+    Theta[:, 0, :R ** 3, :] = host["F"].transpose(0, 2, 3, 4, 1).reshape(M, R ** 3, 2)
+    h = {"G": host["G"], "Theta": Theta, "res": [R - 1], "W": host["W"], "vmin": -1.0, "vmax": 3.0}
+    x = points(5000, seed=11)
+    fv = A().apmg_variant_forward(hash_model(h), soa(x)).cpu().numpy()
+    dense = A().Model.from_host(dict(host, vmin=-1.0, vmax=3.0), DEV)
+    fd = A().apmg_forward(dense, soa(x)).cpu().numpy()
+    np.testing.assert_array_equal(fv, fd)
+
+
+def test_hash_transform_gradient_only_and_accumulate():
+    h = hash_host(M=4, L=2, T=1 << 9, res=(3, 20), seed=12)
+    x = points(1500, seed=13)
+    _, cache = V.hash_forward(f64(h), x.astype(np.float64))
+    x = x[kink_free(cache)]
+    df = np.random.default_rng(14).normal(size=x.shape[0]).astype(np.float32)
+    model = hash_model(h)
+    dfd = torch.from_numpy(df).to(DEV)
+    _, dG, _ = A().apmg_variant_backward(model, soa(x), dfd, want_dF=False, want_dW=False)
+    go = V.hash_backward(f64(h), x.astype(np.float64), df.astype(np.float64))
+    assert_close("dG (alone)", dG.cpu().numpy(), go["dG"])
+    dF1, dG1, dW1 = A().apmg_variant_backward(model, soa(x), dfd)
+    m, e = model.structs()
+    ws = A()._variant_ws(A().OP_BACKWARD, m, e, x.shape[0], DEV)
+    arr = (ctypes.c_void_p * 3)(*[w.data_ptr() for w in dW1])
+    A()._check("apmg_variant_backward", A()._lib.apmg_variant_backward(
+        ctypes.byref(m), ctypes.byref(e), A()._ptr(soa(x)), x.shape[0], x.shape[0], A()._ptr(dfd), A()._ptr(dF1),
+        A()._ptr(dG1), ctypes.cast(arr, ctypes.c_void_p), A().ACCUMULATE, A()._ptr(ws), ws.numel(),
+        A()._stream(DEV)))
+    assert_close("2 dTheta", dF1.cpu().numpy(), 2 * go["dTheta"])
+    assert_close("2 dG", dG1.cpu().numpy(), 2 * go["dG"])
+    assert_close("2 dW1", dW1[0].cpu().numpy(), 2 * go["dW"][0])
+
+
+# ------------------------------------------------------------------ 4-D grids
+
+def test_time_forward_fp32_both_layouts():
+    h = time_host()
+    x = points(3001, time=True)
+    f = A().apmg_variant_forward(time_model(h), soa(x)).cpu().numpy()
+    fo, _ = V.time_forward(f64(h), x[:, :3].astype(np.float64), x[:, 3].astype(np.float64))
+    assert_close("f", f, fo)
+    assert f[8] == np.float32(h["vmin"]) and f[9] == np.float32(h["vmin"])   # time outside / NaN
+    fc = A().apmg_variant_forward(time_model(h, channel_last=True), soa(x)).cpu().numpy()
+    np.testing.assert_array_equal(f, fc)
+
+
+def test_time_backward_fp32_both_layouts():
+    h = time_host(M=8, R=6, Rt=4, seed=15)
+    x = points(4001, seed=16, time=True)
+    _, cache = V.time_forward(f64(h), x[:, :3].astype(np.float64), x[:, 3].astype(np.float64))
+    x = x[kink_free(cache)]
+    df = np.random.default_rng(17).normal(size=x.shape[0]).astype(np.float32)
+    go = V.time_backward(f64(h), x[:, :3].astype(np.float64), x[:, 3].astype(np.float64), df.astype(np.float64))
+    for cl in (False, True):
+        dF, dG, dW = A().apmg_variant_backward(time_model(h, channel_last=cl), soa(x), torch.from_numpy(df).to(DEV))
+        dFn = dF.cpu().numpy()
+        if cl:
+            dFn = dFn.transpose(0, 5, 1, 2, 3, 4)
+        assert_close(f"dF4 (channel-last {cl})", dFn, go["dF4"])
+        assert_close("dG", dG.cpu().numpy(), go["dG"])
+        for k in range(3):
+            assert_close(f"dW{k + 1}", dW[k].cpu().numpy(), go["dW"][k])
+
+
+def test_time_equal_slices_equal_the_dense_model_bitwise():
+    M, R, Rt = 16, 8, 3
+    host = synth.init_model(M, 2, R, [2 * M, 64, 64, 1], seed=18, extra_translation=0.1)
+    F4 = np.repeat(host["F"][:, :, None], Rt, axis=2)
+    h = {"G": host["G"], "F4": F4, "W": host["W"], "vmin": 0.0, "vmax": 1.0}
+    x = points(4000, seed=19, time=True)
+    x[8:10, 3] = 0.3                                     # keep every time inside here
+    fv = A().apmg_variant_forward(time_model(h), soa(x)).cpu().numpy()
+    fd = A().apmg_forward(A().Model.from_host(host, DEV), soa(np.ascontiguousarray(x[:, :3]))).cpu().numpy()
+    np.testing.assert_array_equal(fv, fd)
+
+
+# ------------------------------------------------------------------ stated, edges
+
+@pytest.mark.parametrize("kind", ["hash", "time"])
+def test_variants_bf16_mlp_stated(kind):
+    if kind == "hash":
+        h = hash_host(seed=21)
+        x = points(3001, seed=22)
+        model = hash_model(h, A().BF16)
+        fo, cache = V.hash_forward(f64(h), x.astype(np.float64))
+    else:
+        h = time_host(seed=23)
+        x = points(3001, seed=24, time=True)
+        model = time_model(h, A().BF16)
+        fo, cache = V.time_forward(f64(h), x[:, :3].astype(np.float64), x[:, 3].astype(np.float64))
+    f = A().apmg_variant_forward(model, soa(x)).cpu().numpy()
+    a, b = errs(f, fo)
+    print(f"{kind} bf16 MLP: f normwise {a:.2e}, max {b:.2e}")
+    assert a < 3e-2
+    keep = kink_free(cache)
+    xk = x[keep]
+    df = np.random.default_rng(25).normal(size=xk.shape[0]).astype(np.float32)
+    dF, dG, dW = A().apmg_variant_backward(model, soa(xk), torch.from_numpy(df).to(DEV))
+    if kind == "hash":
+        go = V.hash_backward(f64(h), xk.astype(np.float64), df.astype(np.float64))
+        ref = go["dTheta"]
+    else:
+        go = V.time_backward(f64(h), xk[:, :3].astype(np.float64), xk[:, 3].astype(np.float64),
+                             df.astype(np.float64))
+        ref = go["dF4"]
+    for name, got, want in (("dF", dF.cpu().numpy(), ref), ("dG", dG.cpu().numpy(), go["dG"]),
+                            ("dW1", dW[0].cpu().numpy(), go["dW"][0])):
+        a, _ = errs(got, want)
+        print(f"{kind} bf16 MLP: {name} normwise {a:.2e}")
+        assert a < 1e-1   # stated (BF16 rounding of dL/dy through W1^T), sanity bound
+
+
+def test_variant_empty_and_unsupported():
+    h = hash_host(M=2, L=2, T=64, res=(2, 4))
+    model = hash_model(h)
+    f = A().apmg_variant_forward(model, torch.zeros((3, 0), device=DEV))
+    assert f.numel() == 0
+    dF, dG, dW = A().apmg_variant_backward(model, torch.zeros((3, 0), device=DEV), torch.zeros(0, device=DEV))
+    assert float(dF.abs().max()) == 0.0 and float(dG.abs().max()) == 0.0 and float(dW[0].abs().max()) == 0.0
+    # more than 64 MLP inputs: no register-resident adjoint for the variants
+    big = hash_host(M=9, L=4, T=64, res=(1, 2, 3, 4))
+    with pytest.raises(A().ApmgError):
+        A().apmg_variant_forward(hash_model(big), torch.zeros((3, 4), device=DEV))
