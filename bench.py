@@ -300,6 +300,58 @@ def extra_c5(A, torch, synth, hl):
     return out
 
 
+def extra_f4(A, torch, synth, hl, n=1 << 20, reps=5):
+    """Sec. 9 encoder variants with the FP32 MLP 64-64-64-1 on 2^20 uniform points: (1) a hash
+    grid inside each of 8 adaptive grids (4 levels at 16, 32, 64, 128 cells per axis, 2^16
+    entries of 2 features per level, U(-1e-4, 1e-4) entries: 64 features); (2) 4-D grids,
+    32 grids at 32^3 x 8 time vertices x 2 features, uniform times.  Forward and
+    forward + adjoint (table / grid, transform and MLP gradients) points/s."""
+    import numpy as np
+    rng = np.random.default_rng(41)
+
+    def glorot(i, o):
+        lim = np.sqrt(6.0 / (i + o))
+        return torch.from_numpy(rng.uniform(-lim, lim, size=(o, i)).astype(np.float32)).cuda()
+
+    def run(model, pts):
+        df = torch.full((n,), 1.0 / n, device="cuda")
+        m, e = model.structs()
+        wsf = A._variant_ws(A.OP_FORWARD, m, e, n, "cuda")
+        wsb = A._variant_ws(A.OP_BACKWARD, m, e, n, "cuda")
+        f = torch.empty(n, device="cuda")
+        A.apmg_variant_forward(model, pts, out=f, ws=wsf)
+        A.apmg_variant_backward(model, pts, df, ws=wsb)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            A.apmg_variant_forward(model, pts, out=f, ws=wsf)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for _ in range(reps):
+            A.apmg_variant_backward(model, pts, df, ws=wsb)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        return {"infer_pts_per_s": n * reps / (t1 - t0), "ms_forward": (t1 - t0) / reps * 1e3,
+                "fwd_bwd_pts_per_s": n * reps / (t2 - t1), "ms_forward_adjoint": (t2 - t1) / reps * 1e3}
+
+    out = {}
+    M, L, T = 8, 4, 1 << 16
+    G = torch.from_numpy(synth.init_model(M, 2, 4, [2 * M, 64, 64, 1], seed=43)["G"]).cuda()
+    Th = torch.from_numpy(rng.uniform(-1e-4, 1e-4, size=(M, L, T, 2)).astype(np.float32)).cuda()
+    hm = A.VariantModel(A.ENC_HASH, G, Th, [glorot(M * L * 2, 64), glorot(64, 64), glorot(64, 1)],
+                        level_res=[16, 32, 64, 128])
+    pts = A.apmg_uniform_points(45, 0, 0, 0, n)
+    out["hash_8x4_levels"] = run(hm, pts)
+    del hm, Th
+    M, R, Rt = 32, 32, 8
+    G = torch.from_numpy(synth.init_model(M, 2, R, [2 * M, 64, 64, 1], seed=47)["G"]).cuda()
+    F4 = torch.from_numpy(rng.uniform(-1e-4, 1e-4, size=(M, 2, Rt, R, R, R)).astype(np.float32)).cuda()
+    tm = A.VariantModel(A.ENC_TIME, G, F4, [glorot(M * 2, 64), glorot(64, 64), glorot(64, 1)])
+    pts4 = torch.cat([pts, torch.from_numpy(rng.uniform(-1, 1, size=(1, n)).astype(np.float32)).cuda()], 0)
+    out["time_32x32cubed_x8"] = run(tm, pts4.contiguous())
+    return out
+
+
 def _oracle_chunk(args):
     """One FP64 oracle training step on a chunk of the sample (a worker of the CPU baseline)."""
     import numpy as np
@@ -396,9 +448,9 @@ def main():
     ap.add_argument("--error-sample", type=int, default=1 << 17,
                     help="points of the GPU steps compared with the oracle for the stated errors")
     ap.add_argument("--skip-extra", action="store_true")
-    ap.add_argument("--configs", default="config1,config3,config4,config5",
+    ap.add_argument("--configs", default="config1,config3,config4,config5,f4",
                     help="extra workloads to time after the headline")
-    ap.add_argument("--only", choices=["bf16", "config1", "config3", "config4", "config4_48", "config5"],
+    ap.add_argument("--only", choices=["bf16", "config1", "config3", "config4", "config4_48", "config5", "f4"],
                     help="time one extra workload alone (no headline line; for profiling runs)")
     ap.add_argument("--source-hash", action="store_true",
                     help="print the hash of the adjoint kernel's sources and exit")
@@ -427,7 +479,7 @@ def main():
             res = {"train_pts_per_s": N * args.steps / dtb, "ms_per_step": dtb * 1e3 / args.steps,
                    "kernel_ms": kb, "gather_ms": gbm}
         else:
-            fn = {"config1": extra_c1, "config3": extra_c3, "config4": extra_c4, "config5": extra_c5,
+            fn = {"config1": extra_c1, "config3": extra_c3, "config4": extra_c4, "config5": extra_c5, "f4": extra_f4,
                   "config4_48": lambda A_, t_, s_, h_: extra_c4(A_, t_, s_, h_, B=300)}[args.only]
             res = fn(A, torch, synth, hl)
         print(json.dumps({"only": args.only, "result": res}), flush=True)
@@ -484,7 +536,7 @@ def main():
         c4_48 = lambda A_, t_, s_, h_: extra_c4(A_, t_, s_, h_, B=300)  # noqa: E731
         for name, fn in (("config1_tiny_fp32", extra_c1), ("config3_mixed_1024", extra_c3),
                          ("config4_bricks", extra_c4), ("config4_48bricks", c4_48),
-                         ("config5_render_bf16", extra_c5)):
+                         ("config5_render_bf16", extra_c5), ("f4_variants", extra_f4)):
             if name.split("_")[0] in args.configs:
                 try:
                     extra[name] = fn(A, torch, synth, hl)

@@ -197,10 +197,12 @@ apmg_status apmg_backward(const apmg_model* model, const float* pts, int64_t ld,
  *   interpolations (Eq. (2)) of the two time slices; a point with tau outside [-1, 1]
  *   (or NaN) gets zero features from every grid.  width[0] = M*C.
  * Built for C = 2, grid_dtype F32, MLP {width[0], 64, 64, 1} with width[0] <= 64, mlp_dtype
- * F32 or BF16 (APMG_EUNSUPPORTED otherwise).  No spatial sort: the tile kernels run over
- * the caller's points.  The backward adds the table / grid gradient with float atomics
- * (every entry a vertex maps to, colliding vertices included), so dF is reproducible to
- * rounding only; dW and dG (float64 per block, fixed order) are as in apmg_backward.
+ * F32 or BF16 (APMG_EUNSUPPORTED otherwise).  The forward runs over the caller's points
+ * (no spatial sort).  The backward first sorts the points into spatial bins (as
+ * apmg_backward does), then adds the table / grid gradient with float atomics (every entry
+ * a vertex maps to, colliding vertices included; a run of sorted points in one cell is
+ * summed in registers and added once), so dF is reproducible to rounding only; dW and dG
+ * (float64 per block, fixed order) are as in apmg_backward.
  * Workspace: apmg_variant_workspace_bytes(APMG_OP_FORWARD or APMG_OP_BACKWARD, ...).
  * Arguments, outputs, flags and errors otherwise as apmg_forward / apmg_backward; dF has
  * F's layout. */
@@ -406,7 +408,11 @@ apmg_status apmg_batched_step(const apmg_batch* batch, void* ws, size_t ws_bytes
  * tile kernel, grid-gradient gather, density passes; no Adam update, no
  * counter change -- parameters, moments and the step counter are left as they
  * are, the losses array is written) for candidate launch shapes around the
- * defaults, and returns the fastest in *best (HOST) with its time in *best_ms.
+ * defaults -- first tile-kernel blocks per model (1/2x to 4x the default) times the
+ * adjoint's waves per block (eight, or four with two blocks per CU) with the default
+ * gather, then the gathers (wave-cooperative with 2/4/8 lanes per run, one thread per
+ * cell with 2/4/8 candidates per batch) at the best of those -- and returns the
+ * fastest in *best (HOST) with its time in *best_ms.
  * Needs the workspace of APMG_OP_BATCHED_STEP for this batch.  Synchronises
  * `stream` (hipEvent timing), so it must not be called during graph capture.
  * The caller keeps the result and passes it as batch->tuning. */

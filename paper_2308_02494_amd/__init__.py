@@ -539,7 +539,8 @@ class Trainer:
                                               _stream(self.device), ctypes.byref(best), ctypes.byref(ms)))
         self.set_tuning(best)
         return {"tile_blocks": best.tile_blocks, "cell_unroll": best.cell_unroll,
-                "cell_kernel": best.cell_kernel, "cell_group": best.cell_group}, ms.value
+                "cell_kernel": best.cell_kernel, "cell_group": best.cell_group,
+                "adjoint_kernel": best.adjoint_kernel}, ms.value
 
     def enable_control(self, total_iters, delay=500, ma_window=1000, ma_rel=1e-4, stop_frac=0.8, patience=500,
                        plateau_rel=1e-4, plateau_factor=0.1, max_reductions=3):

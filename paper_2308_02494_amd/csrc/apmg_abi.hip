@@ -431,7 +431,7 @@ size_t bwd_ws(const Shape& s, const apmg_model* m, int64_t n, void* ws, BwdWs* o
 int dens_blocks(int64_t n) { return (int)std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, kDensBlocks)); }
 int dens_chunks(int64_t n) { return (int)std::max<int64_t>(1, (n + kDensChunk - 1) / kDensChunk); }
 
-struct DenWs { float *rho, *coef; double *pa, *sums, *pb1, *lq, *pb2, *U; };
+struct DenWs { float *rho, *coef; double *pa, *sums, *pb1, *lq, *pb2, *U, *a; };
 size_t den_ws(const Shape& s, int64_t n, int nb, void* ws, DenWs* o) {
   Carver cv(ws);
   DenWs d;
@@ -443,6 +443,7 @@ size_t den_ws(const Shape& s, int64_t n, int nb, void* ws, DenWs* o) {
   d.lq = cv.take<double>((size_t)nb * 3);
   d.pb2 = cv.take<double>((size_t)nb * dens_chunks(n) * 13 * s.M);
   d.U = cv.take<double>((size_t)nb * 13 * s.M);
+  d.a = cv.take<double>((size_t)nb * std::max<int64_t>(n, 1));
   if (o) *o = d;
   return cv.off;
 }
@@ -478,13 +479,14 @@ hipError_t launch_density(const Shape& s, const float* G, size_t G_stride, const
     hipLaunchKernelGGL(k_density_a<0>, dim3(ba, nb), dim3(256), shA, st, s, G, G_stride, pts, ld, pts_stride, n,
                        err, err_stride, p, abs_det, rho, rho_stride, w.pa, active);
   hipLaunchKernelGGL(k_density_sums, dim3(nb), dim3(256), 0, st, w.pa, ba, w.sums, nb);
+  const size_t astride = (size_t)std::max<int64_t>(n, 1);
   hipLaunchKernelGGL(k_density_b1, dim3(ba, nb), dim3(256), 0, st, rho, rho_stride, err, err_stride, n,
-                     w.sums, eps, w.pb1, active);
+                     w.sums, eps, w.pb1, w.a, astride, active);
   hipLaunchKernelGGL(k_density_lq, dim3(nb), dim3(256), 0, st, w.pb1, ba, n, w.lq, nb, norm);
   if (dG) {
     const size_t cstride = (size_t)std::max<int64_t>(n, 1);
-    hipLaunchKernelGGL(k_density_coef, dim3(grid1(n, 2048), nb), dim3(256), 0, st, rho, rho_stride, err, err_stride, n,
-                       w.sums, w.lq, eps, w.coef, cstride, active);
+    hipLaunchKernelGGL(k_density_coef, dim3(grid1(n, 2048), nb), dim3(256), 0, st, w.a, astride, n, w.sums, w.lq,
+                       w.coef, cstride, active);
     if (p == 10)
       hipLaunchKernelGGL(k_density_b2<10>, dim3(nch, (s.M + 3) / 4, nb), dim3(256), 0, st, s, G, G_stride, pts,
                          ld, pts_stride, n, w.coef, cstride, p, w.pb2, active);
@@ -999,28 +1001,42 @@ apmg_status run_step(const apmg_batch* b, const Shape& s, void* ws, const Tune& 
   const size_t swz_stride = swz_sizes(s).total();
   hipLaunchKernelGGL(k_live_masks, dim3((nb + 63) / 64), dim3(64), 0, st, b->frozen, b->density_active, w.live,
                      w.dlive, nb);
-  // the grids the encoder gathers: the masters themselves (channel-last float32) or their
-  // mirror (paper order, or F16 gathers)
   const bool paper = paper_grids(&b->shape);
-  const float* Gc;
-  const void* Fg;
-  if (launch_ops(s, nb, b->G, 3, b->F, false, paper, w.ops, gf16, st, &Gc, &Fg) != hipSuccess) return APMG_EHIP;
-  (void)Gc;   // the step's transforms are [nb][M][3][4] already
-
-  // 1. batch points, sorted by spatial bin, and the ground truth at the sorted points
-  if (n > 0) {
-    hipError_t e0 = launch_step_sort(b->seed, b->step, b->stream0, n, nb, w.srt, b->volume, b->vol[0], b->vol[1],
-                                     b->bricks, w.v, st);
-    if (e0 != hipSuccess) return APMG_EHIP;
+  const void* Fg = nullptr;
+  hipError_t e = hipSuccess;
+  {
+    // The gather copy of the grids, the weights' operands, the output scaling and the zeroed
+    // gradients do not depend on the batch points: they run on the device's side stream while
+    // the points are generated, sorted and sampled.
+    std::lock_guard<std::mutex> lk(g_side_mu);     // one fork..join at a time per process
+    SideStream* side = n > 0 ? side_stream(st) : nullptr;
+    hipStream_t pst = st;
+    if (side && hipEventRecord(side->fork, st) == hipSuccess && hipStreamWaitEvent(side->s, side->fork, 0) == hipSuccess)
+      pst = side->s;
+    // the grids the encoder gathers: the masters themselves (channel-last float32) or their
+    // mirror (paper order, or F16 gathers); the step's transforms are [nb][M][3][4] already
+    const float* Gc;
+    if (launch_ops(s, nb, b->G, 3, b->F, false, paper, w.ops, gf16, pst, &Gc, &Fg) != hipSuccess) return APMG_EHIP;
+    (void)Gc;
+    // 2. operands of this step's weights, output scaling, zeroed gradients
+    e = launch_swizzle(s, bf, b->W, b->W + (size_t)s.H * s.MC, b->W + (size_t)s.H * s.MC + (size_t)s.H * s.H, nW,
+                       w.swz, swz_stride, w.w3s, nb, pst);
+    if (e != hipSuccess) return APMG_EHIP;
+    hipLaunchKernelGGL(k_brick_scale, dim3((nb + 63) / 64), dim3(64), 0, pst, b->bricks, w.scale, nb);
+    hipLaunchKernelGGL(k_fill_f32, dim3(grid1((int64_t)(nb * nW))), dim3(256), 0, pst, w.dW, nb * nW, 0.f);
+    hipLaunchKernelGGL(k_fill_f64, dim3(1), dim3(256), 0, pst, w.lrec, (size_t)nb, 0.0);
+    if (n == 0) hipLaunchKernelGGL(k_fill_f32, dim3(grid1((int64_t)(nb * nF))), dim3(256), 0, pst, w.dF, nb * nF, 0.f);
+    // 1. batch points, sorted by spatial bin, and the ground truth at the sorted points
+    if (n > 0) {
+      hipError_t e0 = launch_step_sort(b->seed, b->step, b->stream0, n, nb, w.srt, b->volume, b->vol[0], b->vol[1],
+                                       b->bricks, w.v, st);
+      if (e0 != hipSuccess) return APMG_EHIP;
+    }
+    if (pst != st) {
+      if (hipEventRecord(side->join, pst) != hipSuccess || hipStreamWaitEvent(st, side->join, 0) != hipSuccess)
+        return APMG_EHIP;
+    }
   }
-  // 2. operands of this step's weights, output scaling, zeroed gradients
-  hipError_t e = launch_swizzle(s, bf, b->W, b->W + (size_t)s.H * s.MC, b->W + (size_t)s.H * s.MC + (size_t)s.H * s.H,
-                                nW, w.swz, swz_stride, w.w3s, nb, st);
-  if (e != hipSuccess) return APMG_EHIP;
-  hipLaunchKernelGGL(k_brick_scale, dim3((nb + 63) / 64), dim3(64), 0, st, b->bricks, w.scale, nb);
-  hipLaunchKernelGGL(k_fill_f32, dim3(grid1((int64_t)(nb * nW))), dim3(256), 0, st, w.dW, nb * nW, 0.f);
-  hipLaunchKernelGGL(k_fill_f64, dim3(1), dim3(256), 0, st, w.lrec, (size_t)nb, 0.0);
-  if (n == 0) hipLaunchKernelGGL(k_fill_f32, dim3(grid1((int64_t)(nb * nF))), dim3(256), 0, st, w.dF, nb * nF, 0.f);
 
   // 3. forward + adjoint of L_rec (part 1 of the step)
   const int nblk = tu.tile_blocks;
@@ -1124,13 +1140,15 @@ apmg_status run_step(const apmg_batch* b, const Shape& s, void* ws, const Tune& 
     hipStream_t dst = st;
     if (side && hipEventRecord(side->fork, st) == hipSuccess && hipStreamWaitEvent(side->s, side->fork, 0) == hipSuccess)
       dst = side->s;
+    // the density chain first: it is the longer of the two streams' work, and the
+    // weight-gradient reductions are needed only by Adam
+    const hipError_t ed = launch_density(s, b->G, nG, w.srt.spts, n, (size_t)3 * n, n, w.err, n, b->eps_density,
+                                         b->p, b->flags, b->losses + 1, 2, w.dG, nG, 3, 0, nullptr, w.den, nb,
+                                         w.dlive, dst);
     reduce_pass(passes.back(), dst);
     if (use_act) act_products(dst);
     hipLaunchKernelGGL(k_copy_f64, dim3((nb + 63) / 64), dim3(64), 0, dst, w.lrec, 1, b->losses, 2, nb,
                        1.0 / (double)n);
-    const hipError_t ed = launch_density(s, b->G, nG, w.srt.spts, n, (size_t)3 * n, n, w.err, n, b->eps_density,
-                                         b->p, b->flags, b->losses + 1, 2, w.dG, nG, 3, 0, nullptr, w.den, nb,
-                                         w.dlive, dst);
     const hipError_t ec = launch_cells(s, gf16, b->G, nG, Fg, nF, w.srt, n, w.cell, w.dF, nF, paper ? 1 : 0, 0,
                                        rec_dG, nullptr, 0, 3, 0, nb, w.live, st, tu.cell_unroll, nullptr,
                                        tu.cell_kernel, tu.cell_group);
@@ -1192,25 +1210,39 @@ extern "C" apmg_status apmg_autotune_batched_step(const apmg_batch* b, void* ws,
   float best_t = -1.f;
   Tune best_tu = {d, 4, 0, kDefaultCellGroup, 0};
   apmg_status out = APMG_OK;
-  // gathers: the wave-cooperative one with 2, 4 or 8 lanes per candidate run, then one
-  // thread per cell with 2, 4 or 8 candidates per batch
-  struct Gather { int kernel, unroll, group; };
-  const Gather gathers[] = {{0, 4, 2}, {0, 4, 4}, {0, 4, 8}, {1, 2, kDefaultCellGroup},
-                            {1, 4, kDefaultCellGroup}, {1, 8, kDefaultCellGroup}};
+  // one warm-up step, then the mean of three (no parameter update)
+  const auto time_tune = [&](const Tune& tu) -> apmg_status {
+    apmg_status r = run_step(b, s, ws, tu, false, st);
+    if (r != APMG_OK) return r;
+    if (hipEventRecord(e0, st) != hipSuccess) return APMG_EHIP;
+    for (int k = 0; k < 3 && r == APMG_OK; ++k) r = run_step(b, s, ws, tu, false, st);
+    if (r != APMG_OK) return r;
+    if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) return APMG_EHIP;
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, e0, e1) != hipSuccess) return APMG_EHIP;
+    ms /= 3.f;
+    if (best_t < 0.f || ms < best_t) { best_t = ms; best_tu = tu; }
+    return APMG_OK;
+  };
+  // 1. tile-kernel blocks per model x waves per adjoint block (eight, or four with two blocks
+  // per CU) for the register-resident shapes, with the default gather
+  std::vector<int> adjs = {0};
+  if (adjoint_applies(s)) adjs = {1, 2};
   for (int tb : blocks) {
-    for (const Gather& ga : gathers) {
-      const Tune tu = {tb, ga.unroll, ga.kernel, ga.group, 0};
-      if ((rc = run_step(b, s, ws, tu, false, st)) != APMG_OK) { out = rc; break; }   // warm-up
-      if (hipEventRecord(e0, st) != hipSuccess) { out = APMG_EHIP; break; }
-      for (int r = 0; r < 3 && rc == APMG_OK; ++r) rc = run_step(b, s, ws, tu, false, st);
-      if (rc != APMG_OK) { out = rc; break; }
-      if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) { out = APMG_EHIP; break; }
-      float ms = 0.f;
-      if (hipEventElapsedTime(&ms, e0, e1) != hipSuccess) { out = APMG_EHIP; break; }
-      ms /= 3.f;
-      if (best_t < 0.f || ms < best_t) { best_t = ms; best_tu = tu; }
+    for (int adj : adjs) {
+      if ((out = time_tune({tb, 4, 0, kDefaultCellGroup, adj})) != APMG_OK) break;
     }
     if (out != APMG_OK) break;
+  }
+  // 2. with those: the wave-cooperative gather with 2, 4 or 8 lanes per candidate run, and
+  // one thread per cell with 2, 4 or 8 candidates per batch
+  struct Gather { int kernel, unroll, group; };
+  const Gather gathers[] = {{0, 4, 2}, {0, 4, 8}, {1, 2, kDefaultCellGroup}, {1, 4, kDefaultCellGroup},
+                            {1, 8, kDefaultCellGroup}};
+  const Tune stage1 = best_tu;
+  for (const Gather& ga : gathers) {
+    if (out != APMG_OK) break;
+    out = time_tune({stage1.tile_blocks, ga.unroll, ga.kernel, ga.group, stage1.adjoint});
   }
   hipEventDestroy(e0);
   hipEventDestroy(e1);
@@ -1388,6 +1420,8 @@ size_t variant_f_elems(const Shape& s, const EncArgs& ea, int kind) {
                                : (size_t)s.M * ea.Rt * s.R * s.R * s.R * s.C;
 }
 inline int variant_nbx(int64_t n) { return (int)std::max<int64_t>(1, (n + 255) / 256); }
+// 4-D grids with at most one radix digit of time cells are sorted by time cell as well
+inline bool time_sorted(const EncArgs& ea) { return ea.Rt >= 3 && ea.Rt - 1 <= kRadixDigits; }
 
 struct VarWs {
   float* G;        // packed 3-row transforms (4-row input)
@@ -1397,6 +1431,11 @@ struct VarWs {
   float* dY;       // [M'][n][C] (backward)
   double* dGpart;  // [M'][nbx][12] (backward)
   float* dFcl;     // channel-last time-grid gradient (backward, paper-order grids)
+  SortWs srt;      // the points (and dL/df) in spatial-bin order (backward)
+  float* tau;      // their times (backward, time grids)
+  // time grids: a further stable pass by time cell -> (time cell, spatial bin) order
+  uint32_t *tk0, *tv0, *tk1, *tv1;
+  float *tpts, *tdf;
 };
 size_t var_ws(const Shape& s, const EncArgs& ea, const apmg_model* m, const apmg_encoder* e, int64_t n,
               bool backward, void* ws, VarWs* o) {
@@ -1414,6 +1453,16 @@ size_t var_ws(const Shape& s, const EncArgs& ea, const apmg_model* m, const apmg
     w.dY = cv.take<float>((size_t)s.M * std::max<int64_t>(n, 1) * s.C);
     w.dGpart = cv.take<double>((size_t)s.M * variant_nbx(n) * 12);
     if (time_paper) w.dFcl = cv.take<float>(variant_f_elems(s, ea, e->kind));
+    take_sort(cv, n, 1, true, &w.srt);
+    if (e->kind == APMG_ENC_TIME) {
+      const size_t nn = (size_t)std::max<int64_t>(n, 1);
+      w.tau = cv.take<float>(nn);
+      if (time_sorted(ea)) {
+        w.tk0 = cv.take<uint32_t>(nn); w.tv0 = cv.take<uint32_t>(nn);
+        w.tk1 = cv.take<uint32_t>(nn); w.tv1 = cv.take<uint32_t>(nn);
+        w.tpts = cv.take<float>(3 * nn); w.tdf = cv.take<float>(nn);
+      }
+    }
   }
   if (o) *o = w;
   return cv.off;
@@ -1475,6 +1524,7 @@ apmg_status apmg_variant_forward(const apmg_model* m, const apmg_encoder* e, con
   a.G = Gc; a.F = Fc; a.swz = w.swz; a.w3s = w.w3s;
   a.vscale = m->vmax - m->vmin; a.voff = m->vmin;
   a.pts = pts; a.ld = ld; a.f = f; a.n = n;
+  a.tau = pts + 3 * ld;
   const int64_t tiles = (n + 31) / 32;
   const dim3 grid((unsigned)std::min<int64_t>((tiles + kWavesPerBlock - 1) / kWavesPerBlock, 8192), 1);
   if (launch_enc_forward(a, e->kind, bf, grid, forward_lds_bytes(s, bf), st) != hipSuccess) return APMG_EHIP;
@@ -1510,6 +1560,27 @@ apmg_status apmg_variant_backward(const apmg_model* m, const apmg_encoder* e, co
   const float *Gc, *Fc;
   if (variant_ops(s, ea, m, e, w, st, &Gc, &Fc) != hipSuccess) return APMG_EHIP;
   if (launch_swizzle(s, bf, m->W[0], m->W[1], m->W[2], 0, w.swz, 0, w.w3s, 1, st) != hipSuccess) return APMG_EHIP;
+  // the points, dL/df (and times) in spatial-bin order: neighbouring lanes of the adjoint and
+  // of the scatter then share cells, and the scatter adds each run of equal cells once
+  if (launch_sort(pts, ld, 0, nullptr, n, 1, w.srt, df, st) != hipSuccess) return APMG_EHIP;
+  const float* bpts = w.srt.spts;
+  const float* bdf = w.srt.sf;
+  if (w.tpts) {
+    // then a stable pass by time cell: neighbouring points share the time slices too
+    const int nt = sort_tiles(n);
+    hipLaunchKernelGGL(k_time_keys, dim3(grid1(n)), dim3(256), 0, st, pts + 3 * ld, w.srt.v0, n, ea.Rt, w.tk0, w.tv0);
+    hipLaunchKernelGGL(k_radix_hist, dim3(nt, 1), dim3(256), 0, st, w.tk0, n, 0, w.srt.hist, nt);
+    hipLaunchKernelGGL(k_radix_rowscan, dim3(kRadixDigits, 1), dim3(256), 0, st, w.srt.hist, nt, w.srt.rowtot);
+    hipLaunchKernelGGL(k_radix_digitscan, dim3(1), dim3(256), 0, st, w.srt.rowtot, w.srt.dbase);
+    hipLaunchKernelGGL(k_radix_scatter, dim3(nt, 1), dim3(256), 0, st, w.tk0, w.tv0, w.tk1, w.tv1, n, 0, w.srt.hist,
+                       w.srt.dbase, nt);
+    hipLaunchKernelGGL(k_time_permute, dim3(grid1(n)), dim3(256), 0, st, w.srt.spts, w.srt.sf, pts + 3 * ld,
+                       w.srt.v0, w.tv1, n, w.tpts, w.tdf, w.tau);
+    bpts = w.tpts;
+    bdf = w.tdf;
+  } else if (w.tau) {
+    hipLaunchKernelGGL(k_gather_f32, dim3(grid1(n)), dim3(256), 0, st, pts + 3 * ld, w.srt.v0, n, w.tau);
+  }
   const bool want_enc = dF || dG;
   const int nblk = bwd_blocks(n, bf);
   const PartLayout pl = part_layout(s, s.MC, s.H);
@@ -1519,8 +1590,9 @@ apmg_status apmg_variant_backward(const apmg_model* m, const apmg_encoder* e, co
   a.enc = ea;
   a.G = Gc; a.F = Fc; a.swz = w.swz; a.w3s = w.w3s;
   a.vscale = m->vmax - m->vmin; a.voff = m->vmin;
-  a.pts = pts; a.ld = ld; a.n = n;
-  a.df = df;
+  a.pts = bpts; a.ld = n; a.n = n;
+  a.tau = w.tau;
+  a.df = bdf;
   a.dY = want_enc ? w.dY : nullptr;
   a.c1_lo = 0; a.c1_hi = s.MC;
   a.w2_lo = 0; a.w2_hi = s.H;
@@ -1546,7 +1618,8 @@ apmg_status apmg_variant_backward(const apmg_model* m, const apmg_encoder* e, co
   EncScatterArgs sa;
   memset(&sa, 0, sizeof(sa));
   sa.s = s; sa.enc = ea; sa.G = Gc; sa.F = Fc;
-  sa.pts = pts; sa.ld = ld; sa.n = n;
+  sa.pts = bpts; sa.ld = n; sa.n = n;
+  sa.tau = w.tau;
   sa.dY = w.dY;
   sa.dF = dst;
   sa.dGpart = dG ? w.dGpart : nullptr;

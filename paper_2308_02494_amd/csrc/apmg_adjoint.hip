@@ -250,7 +250,7 @@ __global__ void __launch_bounds__(NW * kWave, 8 / NW) k_adjoint(TileArgs a) {
     const bool valid = tile < t_end && p < a.n;
     float x = 0.f, y = 0.f, z = 0.f, tq = 0.f;
     if (valid) { x = Pp[p]; y = Pp[a.ld + p]; z = Pp[2 * a.ld + p]; }
-    if constexpr (ENC == kEncTime) tq = valid ? Pp[3 * a.ld + p] : 0.f;
+    if constexpr (ENC == kEncTime) tq = valid ? a.tau[p] : 0.f;
     f32x16 z1[NB], z2[NB];
     float m;
     float yv[32];

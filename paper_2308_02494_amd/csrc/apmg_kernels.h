@@ -83,6 +83,7 @@ struct TileArgs {
   // per 32-point tile of act_rows rows x 32 points, rows y [MC] | h1 [H] | delta1 [H] | delta2 [H]
   void* act; int act_rows; size_t act_stride;   // act_stride: elements per model
   EncArgs enc;                            // encoder variants (zero for the dense grids)
+  const float* tau;                       // 4-D grids: [n] time of each point (model 0 only)
 };
 
 // Per-block partial sums of the adjoint, float64: [dW1 slice H x ncols]

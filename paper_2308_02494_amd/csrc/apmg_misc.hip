@@ -316,9 +316,11 @@ __device__ inline void target_terms(double rho, double S, double hbar, double h,
 }
 
 // Pass B1: per block, {sum of loss summands, Q = sum a rho_s, sum rho*} (a and the loss
-// summands with the unnormalised target).  part: [model][block][3]
+// summands with the unnormalised target); a of every point is kept for the coefficient pass.
+// part: [model][block][3]; a_out: [model][a_stride]
 __global__ void __launch_bounds__(256) k_density_b1(const float* rho, size_t rho_stride, const float* err,
-    size_t err_stride, int64_t n, const double* sums, double eps, double* part, const int32_t* active) {
+    size_t err_stride, int64_t n, const double* sums, double eps, double* part, double* a_out, size_t a_stride,
+    const int32_t* active) {
   __shared__ double spart[12];   // [wave][3]
   const int model = blockIdx.y;
   const bool act = (!active || active[model]) && sums[2 * model] != 0.0;
@@ -328,6 +330,7 @@ __global__ void __launch_bounds__(256) k_density_b1(const float* rho, size_t rho
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
       double term, a, rs, tg;
       target_terms(rho[model * rho_stride + i], S, hbar, err[model * err_stride + i], eps, (double)n, term, a, rs, tg);
+      a_out[model * a_stride + i] = a;
       sl += term;
       sq += a * rs;
       sz += tg;
@@ -363,20 +366,15 @@ __global__ void __launch_bounds__(256) k_density_lq(const double* part, int nblk
 }
 
 // Per-point coefficient c(x) = dL/drho(x) = (a(x)/Z - Q)/S (float64 arithmetic, stored float32).
-__global__ void k_density_coef(const float* rho, size_t rho_stride, const float* err, size_t err_stride, int64_t n,
-                               const double* sums, const double* lq, double eps, float* coef, size_t coef_stride,
-                               const int32_t* active) {
+__global__ void k_density_coef(const double* a_in, size_t a_stride, int64_t n, const double* sums, const double* lq,
+                               float* coef, size_t coef_stride, const int32_t* active) {
   const int model = blockIdx.y;
   const bool act = (!active || active[model]) && sums[2 * model] != 0.0;
-  const double S = sums[2 * model], hbar = sums[2 * model + 1] / (double)n;
+  const double S = sums[2 * model];
   const double Q = lq[3 * model + 1], Z = lq[3 * model + 2];
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
     float c = 0.f;
-    if (act) {
-      double term, a, rs, tg;
-      target_terms(rho[model * rho_stride + i], S, hbar, err[model * err_stride + i], eps, (double)n, term, a, rs, tg);
-      c = (float)((a / Z - Q) / S);
-    }
+    if (act) c = (float)((a_in[model * a_stride + i] / Z - Q) / S);
     coef[model * coef_stride + i] = c;
   }
 }

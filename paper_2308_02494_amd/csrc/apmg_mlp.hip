@@ -395,7 +395,7 @@ __global__ void __launch_bounds__(kBlock) k_forward(TileArgs a) {
     const bool valid = p < cnt;
     float x = 0.f, y = 0.f, z = 0.f, tq = 0.f;
     if (valid) { x = P[p]; y = P[a.ld + p]; z = P[2 * a.ld + p]; }
-    if constexpr (ENC == kEncTime) tq = valid ? P[3 * a.ld + p] : 0.f;
+    if constexpr (ENC == kEncTime) tq = valid ? a.tau[p] : 0.f;
     f32x16 z1[H / 32], z2[H / 32];
     float m;
     tile_fwd<C, H, GF16, BF, false, ENC>(s, sG, F, swz, w3s, x, y, z, valid, lane, z1, z2, m, nullptr, nullptr, 0, 0,

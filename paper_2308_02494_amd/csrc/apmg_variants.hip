@@ -2,12 +2,15 @@
 // grids with a time axis) with respect to their tables / grids and the transforms.
 //
 // The forward and the MLP adjoint are the tile kernels (k_forward, k_adjoint) instantiated
-// with the variant's lookup (enc_tap); k_adjoint stores dL/dy per (feature grid, point).  The
-// scatter below then adds w_q dL/dy_c into the corner entries with float atomics: a hash table
-// entry collects the contributions of every vertex that maps to it, so the per-cell gather of
-// the dense grids does not apply, and the 4-D grids share the scatter.  The sums of float
-// atomics are not in a fixed order (results reproducible to rounding).  The transform gradient
-// through the interpolation weights is reduced per block in float64, in a fixed order.
+// with the variant's lookup (enc_tap); k_adjoint stores dL/dy per (feature grid, point) of the
+// spatially sorted points.  The scatter below then adds w_q dL/dy_c into the corner entries
+// with float atomics: a hash table entry collects the contributions of every vertex that maps
+// to it, so the per-cell gather of the dense grids does not apply, and the 4-D grids share the
+// scatter.  Neighbouring sorted points mostly share a cell, so each wave first sums the runs
+// of lanes with the same cell and only the run's first lane issues the atomics.  The sums of
+// float atomics are not in a fixed order (results reproducible to rounding).  The transform
+// gradient through the interpolation weights is reduced per block in float64, in a fixed
+// order.
 
 namespace apmg {
 
@@ -17,6 +20,7 @@ struct EncScatterArgs {
   const float* G;          // [M / L][12]
   const float* F;          // hash: tables [M][T][C]; time: channel-last [M][Rt][R^3][C]
   const float* pts; int64_t ld; int64_t n;
+  const float* tau;        // time: [n] time of each point
   const float* dY;         // [M][n][C], dL/dy per feature grid (M feature grids)
   float* dF;               // same layout as F (channel-last for time), accumulated; NULL: no grid gradient
   double* dGpart;          // [M][nbx][12], or NULL for no transform gradient
@@ -45,6 +49,42 @@ __device__ inline float tri_weight(int q, const float w[3]) {
   return ((q & 1) ? w[0] : 1.f - w[0]) * ((q & 2) ? w[1] : 1.f - w[1]) * ((q & 4) ? w[2] : 1.f - w[2]);
 }
 
+// Runs of consecutive lanes with the same key (the points are spatially sorted, so
+// neighbouring lanes mostly share a cell): seg = the run's first lane; nxt[k] = lane
+// + 2^k is in the same run.  A segmented suffix sum over the run then leaves each run's
+// total in its first lane, which alone issues the atomics.
+struct WaveRuns {
+  bool head;
+  bool nxt[6];
+};
+__device__ inline WaveRuns wave_runs(uint64_t key, int lane) {
+  WaveRuns r;
+  const uint32_t klo = (uint32_t)key, khi = (uint32_t)(key >> 32);
+  const uint32_t plo = __shfl_up(klo, 1, 64), phi = __shfl_up(khi, 1, 64);
+  r.head = lane == 0 || plo != klo || phi != khi;
+  int seg = r.head ? lane : 0;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const int t = __shfl_up(seg, o, 64);
+    if (lane >= o) seg = max(seg, t);
+  }
+#pragma unroll
+  for (int k = 0; k < 6; ++k) {
+    const int o = 1 << k;
+    const int t = __shfl_down(seg, o, 64);
+    r.nxt[k] = lane + o < 64 && t == seg;
+  }
+  return r;
+}
+__device__ inline float run_sum(float v, const WaveRuns& r) {
+#pragma unroll
+  for (int k = 0; k < 6; ++k) {
+    const float t = __shfl_down(v, 1 << k, 64);
+    v += r.nxt[k] ? t : 0.f;
+  }
+  return v;
+}
+
 // One thread per (point, feature grid): blockIdx.y = feature grid g, 256 points per block.
 template <int C, int ENC>
 __global__ void __launch_bounds__(256) k_enc_scatter(EncScatterArgs a) {
@@ -59,7 +99,7 @@ __global__ void __launch_bounds__(256) k_enc_scatter(EncScatterArgs a) {
   const bool valid = p < a.n;
   float x = 0.f, y = 0.f, z = 0.f, tq = 0.f;
   if (valid) { x = a.pts[p]; y = a.pts[a.ld + p]; z = a.pts[2 * a.ld + p]; }
-  if constexpr (ENC == kEncTime) tq = valid ? a.pts[3 * a.ld + p] : 0.f;
+  if constexpr (ENC == kEncTime) tq = valid ? a.tau[p] : 0.f;
   float dy[C];
 #pragma unroll
   for (int c = 0; c < C; ++c) dy[c] = valid ? a.dY[((size_t)g * a.n + p) * C + c] : 0.f;
@@ -67,35 +107,39 @@ __global__ void __launch_bounds__(256) k_enc_scatter(EncScatterArgs a) {
   const float hR = 0.5f * (float)(s.R - 1);
   enc_tap<C, false, ENC>(s, sG, a.F, a.enc, g, x, y, z, tq, valid, hR, t);
   float dl[3] = {0.f, 0.f, 0.f};
-  if (t.in) {
-    if constexpr (ENC == kEncHash) {
+  const int lane = threadIdx.x & 63;
+  if constexpr (ENC == kEncHash) {
+    if (a.dF) {
+      // the cell of this lane's point (the same float32 decision as the lookup)
       const int gt = g / s.L, k = g - gt * s.L;
       const int N = enc_level_res(a.enc, k);
-      const uint32_t n1 = (uint32_t)N + 1u;
-      const bool dense = (uint64_t)n1 * n1 * n1 <= (uint64_t)a.enc.tmask + 1u;
-      // the cell again (the lookup keeps only its offsets; the same float32 decision)
       float l[3];
       local_coords(sG + 12 * gt, x, y, z, l);
       int i0[3];
       float w[3];
       cell_of(l, 0.5f * (float)N, N + 1, i0, w);
       (void)w;
-      if (a.dF) {
-        float* base = a.dF + (size_t)g * ((size_t)a.enc.tmask + 1u) * C;
+      const uint64_t key = t.in ? ((uint64_t)i0[2] << 40 | (uint64_t)i0[1] << 20 | (uint64_t)i0[0]) : ~0ull - lane;
+      const WaveRuns rn = wave_runs(key, lane);
+      const uint32_t n1 = (uint32_t)N + 1u;
+      const bool dense = (uint64_t)n1 * n1 * n1 <= (uint64_t)a.enc.tmask + 1u;
+      float* base = a.dF + (size_t)g * ((size_t)a.enc.tmask + 1u) * C;
 #pragma unroll
-        for (int q = 0; q < 8; ++q) {
+      for (int q = 0; q < 8; ++q) {
+        const float wq = t.in ? tri_weight(q, t.w) : 0.f;
+        float v[C];
+#pragma unroll
+        for (int c = 0; c < C; ++c) v[c] = run_sum(wq * dy[c], rn);
+        if (t.in && rn.head) {
           const uint32_t ent = hash_entry((uint32_t)i0[0] + (q & 1), (uint32_t)i0[1] + ((q >> 1) & 1),
                                           (uint32_t)i0[2] + (q >> 2), n1, dense, a.enc.tmask);
-          const float wq = tri_weight(q, t.w);
 #pragma unroll
-          for (int c = 0; c < C; ++c) unsafeAtomicAdd(base + (size_t)ent * C + c, wq * dy[c]);
+          for (int c = 0; c < C; ++c) unsafeAtomicAdd(base + (size_t)ent * C + c, v[c]);
         }
       }
-      trilerp_dw<C>(t.val, t.w, dy, dl);
-      const float sc = 0.5f * (float)N;
-#pragma unroll
-      for (int d = 0; d < 3; ++d) dl[d] *= sc;
-    } else {
+    }
+  } else {
+    if (a.dF) {
       float l[3];
       local_coords(sG + 12 * g, x, y, z, l);
       int i0[3];
@@ -106,19 +150,34 @@ __global__ void __launch_bounds__(256) k_enc_scatter(EncScatterArgs a) {
       const float ut = __builtin_fmaf(tq, ht, ht);
       const int t0 = (int)fminf(fmaxf(floorf(ut), 0.0f), (float)(a.enc.Rt - 2));
       const uint32_t R = (uint32_t)s.R, RC = R * C, RRC = R * R * C;
+      const uint64_t key = t.in ? ((((uint64_t)t0 * R + i0[2]) * R + i0[1]) * R + i0[0]) : ~0ull - lane;
+      const WaveRuns rn = wave_runs(key, lane);
+      const uint32_t cb = t.in ? ((uint32_t)i0[2] * R + i0[1]) * RC + (uint32_t)i0[0] * C : 0u;
 #pragma unroll
-      for (int sl = 0; sl < (a.dF ? 2 : 0); ++sl) {
+      for (int sl = 0; sl < 2; ++sl) {
         const float ws = sl ? t.wt : 1.f - t.wt;
-        float* base = a.dF + (((size_t)g * a.enc.Rt + t0 + sl) * R * R * R) * C;
-        const uint32_t cb = ((uint32_t)i0[2] * R + i0[1]) * RC + (uint32_t)i0[0] * C;
+        float* base = a.dF + (((size_t)g * a.enc.Rt + (t.in ? t0 : 0) + sl) * R * R * R) * C;
 #pragma unroll
         for (int q = 0; q < 8; ++q) {
-          const float wq = ws * tri_weight(q, t.w);
+          const float wq = t.in ? ws * tri_weight(q, t.w) : 0.f;
           const uint32_t o = cb + (q & 1) * C + ((q >> 1) & 1) * RC + (q >> 2) * RRC;
 #pragma unroll
-          for (int c = 0; c < C; ++c) unsafeAtomicAdd(base + o + c, wq * dy[c]);
+          for (int c = 0; c < C; ++c) {
+            const float v = run_sum(wq * dy[c], rn);
+            if (t.in && rn.head) unsafeAtomicAdd(base + o + c, v);
+          }
         }
       }
+    }
+  }
+  if (t.in) {
+    if constexpr (ENC == kEncHash) {
+      const int N = enc_level_res(a.enc, g - (g / s.L) * s.L);
+      trilerp_dw<C>(t.val, t.w, dy, dl);
+      const float sc = 0.5f * (float)N;
+#pragma unroll
+      for (int d = 0; d < 3; ++d) dl[d] *= sc;
+    } else {
       float d0[3], d1[3];
       trilerp_dw<C>(t.va, t.w, dy, d0);
       trilerp_dw<C>(t.vb, t.w, dy, d1);
@@ -128,7 +187,7 @@ __global__ void __launch_bounds__(256) k_enc_scatter(EncScatterArgs a) {
   }
   if (a.dGpart) {
     const float xs[4] = {t.in ? x : 0.f, t.in ? y : 0.f, t.in ? z : 0.f, t.in ? 1.f : 0.f};
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int wave = threadIdx.x >> 6;
 #pragma unroll
     for (int r = 0; r < 3; ++r)
 #pragma unroll
@@ -141,6 +200,42 @@ __global__ void __launch_bounds__(256) k_enc_scatter(EncScatterArgs a) {
       const double v = sred[0][threadIdx.x] + sred[1][threadIdx.x] + sred[2][threadIdx.x] + sred[3][threadIdx.x];
       a.dGpart[((size_t)g * a.nbx + bx) * 12 + threadIdx.x] = v;
     }
+  }
+}
+
+// dst[j] = src[perm[j]] (a per-point array in spatially sorted order).
+__global__ void k_gather_f32(const float* __restrict__ src, const uint32_t* __restrict__ perm, int64_t n,
+                             float* __restrict__ dst) {
+  for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < n; j += (int64_t)gridDim.x * blockDim.x)
+    dst[j] = src[perm[j]];
+}
+
+// 4-D grids: the time cell of each spatially sorted point (the float32 decision of the lookup;
+// outside or NaN times -> 0) as a radix key, with the point's sorted position as its value.
+__global__ void k_time_keys(const float* __restrict__ tau, const uint32_t* __restrict__ perm, int64_t n, int Rt,
+                            uint32_t* __restrict__ keys, uint32_t* __restrict__ vals) {
+  const float ht = 0.5f * (float)(Rt - 1);
+  for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < n; j += (int64_t)gridDim.x * blockDim.x) {
+    const float t = tau[perm[j]];
+    const float ft = fminf(fmaxf(floorf(__builtin_fmaf(t, ht, ht)), 0.0f), (float)(Rt - 2));
+    keys[j] = (t >= -1.0f && t <= 1.0f) ? (uint32_t)ft : 0u;
+    vals[j] = (uint32_t)j;
+  }
+}
+
+// The points, dL/df and times in (time cell, spatial bin) order: position j takes spatially
+// sorted position q = perm2[j] (original point perm[q]).
+__global__ void k_time_permute(const float* __restrict__ spts, const float* __restrict__ sf,
+                               const float* __restrict__ tau, const uint32_t* __restrict__ perm,
+                               const uint32_t* __restrict__ perm2, int64_t n, float* __restrict__ pts2,
+                               float* __restrict__ f2, float* __restrict__ tau2) {
+  for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < n; j += (int64_t)gridDim.x * blockDim.x) {
+    const uint32_t q = perm2[j];
+    pts2[j] = spts[q];
+    pts2[n + j] = spts[n + q];
+    pts2[2 * n + j] = spts[2 * n + q];
+    f2[j] = sf[q];
+    tau2[j] = tau[perm[q]];
   }
 }
 
