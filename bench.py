@@ -402,8 +402,9 @@ def cpu_baseline(vol_np, host, n_sample):
 
 def stated_errors(A, torch, synth, vol, host, n):
     """Error of one GPU training step (FP32, BF16 MLP, BF16 MLP + FP16 grids) against the FP64
-    oracle's step on the same n points of the headline workload (step 0), normwise relative:
-    losses, and the gradients read off the first Adam moments (m = 0.1 g)."""
+    oracle's step on the same n points of the headline workload (step 0), and of one brick
+    model's BF16 step of the brick workload, normwise relative: losses, and the gradients read
+    off the first Adam moments (m = 0.1 g)."""
     import numpy as np
 
     from oracle import apmg_oracle as O
@@ -435,6 +436,34 @@ def stated_errors(A, torch, synth, vol, host, n):
                      "dF": rel(tr.mF[0].cpu().numpy() / 0.1, info["dF"]), "dW": rel(mW / 0.1, wflat),
                      "dG_density": rel(tr.mG[0].cpu().numpy() / 0.1, info["dG_density"])}
         del tr
+    # one brick model of the 80-brick workload (brick 21 of the 1000x1200x900 volume in 256^3
+    # bricks, 16 grids at 32^3 x 2, MLP 32-64-64-1 in BF16), the same number of points
+    del vol
+    torch.cuda.empty_cache()
+    vol4 = synth.make_volume("blobs_turb", (900, 1200, 1000), device="cuda")
+    _, bricks = A.apmg_make_bricks(1000, 1200, 900, 256, 1)
+    k = 21
+    bk = bricks[k]
+    e0, e1 = list(bk.e0), list(bk.e1)
+    sub = vol4[e0[2]:e1[2] + 1, e0[1]:e1[1] + 1, e0[0]:e1[0] + 1].cpu().numpy().astype(np.float64)
+    host4 = synth.init_model(16, 2, 32, [32, 64, 64, 1], seed=synth.SEED_MODEL + k)
+    tr = A.Trainer([host4], vol4, [bk], n, seed=synth.SEED_POINTS, mlp_dtype=A.BF16)
+    tr.density_active.fill_(1)
+    tr.step()
+    torch.cuda.synchronize()
+    m4 = {"G": host4["G"].astype(np.float64), "F": host4["F"].astype(np.float64),
+          "W": [w.astype(np.float64) for w in host4["W"]], "vmin": float(bk.vmin), "vmax": float(bk.vmax)}
+    x4 = O.uniform_points(synth.SEED_POINTS, 0, 0, n)
+    v4 = O.brick_gt_sample(sub, {"e0": [0, 0, 0], "e1": [e1[0] - e0[0], e1[1] - e0[1], e1[2] - e0[2]]}, x4)
+    _, _, info4 = O.train_step(m4, O.zero_adam_state(m4), x4, v4, density_active=True)
+    L = tr.losses[0].cpu().numpy()
+    w4 = np.concatenate([w.ravel() for w in info4["dW"]])
+    out["config4_brick_bf16_mlp"] = {
+        "L_rec": rel([L[0]], [info4["L_rec"]]), "L_density": rel([L[1]], [info4["L_density"]]),
+        "dF": rel(tr.mF[0].cpu().numpy() / 0.1, info4["dF"]),
+        "dW": rel(tr.mW[0].cpu().numpy().astype(np.float64) / 0.1, w4),
+        "dG_density": rel(tr.mG[0].cpu().numpy() / 0.1, info4["dG_density"])}
+    del tr, vol4
     return out
 
 

@@ -290,16 +290,26 @@ void radix_passes(int64_t n, int nb, int nt, const SortWs& w, hipStream_t st) {
   }
 }
 
+// with_starts: also the bin starts and the 16-byte point records (the per-cell gather's
+// candidate lists; a forward pass, which sorts only to order its work, needs neither)
 hipError_t launch_sort(const float* pts, int64_t ld, size_t pts_stride, const float4* pts4, int64_t n, int nb,
-                       const SortWs& w, const float* src_f, hipStream_t st) {
+                       const SortWs& w, const float* src_f, hipStream_t st, bool with_starts = true) {
   const int nt = sort_tiles(n);
   SortIn in;
   in.pts = pts; in.ld = ld; in.pts_stride = pts_stride; in.pts4 = pts4;
   hipLaunchKernelGGL(k_bin_keys, dim3(grid1(n), nb), dim3(256), 0, st, in, n, w.k0, w.v0);
   radix_passes(n, nb, nt, w, st);
-  hipLaunchKernelGGL(k_permute_points, dim3(grid1(n), nb), dim3(256), 0, st, in, n, w.v0, w.spts, w.spts4,
-                     src_f, w.sf);
-  hipLaunchKernelGGL(k_bin_starts, dim3(grid1(n + 1), nb), dim3(256), 0, st, w.k0, n, w.start);
+  hipLaunchKernelGGL(k_permute_points, dim3(grid1(n), nb), dim3(256), 0, st, in, n, w.v0, w.spts,
+                     with_starts ? w.spts4 : nullptr, src_f, w.sf);
+  // bin starts: one thread per position (gaps between neighbouring keys are short when the
+  // points are few per bin), or one per bin (binary search) for large point sets, whose empty
+  // regions would leave a few position threads writing long gaps
+  constexpr int64_t kBins = (int64_t)kBinsPerAxis * kBinsPerAxis * kBinsPerAxis;
+  if (!with_starts) return hipGetLastError();
+  if (n > 8 * kBins)
+    hipLaunchKernelGGL(k_bin_starts_search, dim3(grid1(kBins + 1), nb), dim3(256), 0, st, w.k0, n, w.start);
+  else
+    hipLaunchKernelGGL(k_bin_starts, dim3(grid1(n + 1), nb), dim3(256), 0, st, w.k0, n, w.start);
   return hipGetLastError();
 }
 
@@ -675,7 +685,8 @@ apmg_status forward_impl(const apmg_model* m, const float* pts, int64_t ld, int6
   if (e != hipSuccess) return APMG_EHIP;
   e = launch_swizzle(s, bf, m->W[0], m->W[1], m->W[2], 0, w.swz, 0, w.w3s, 1, st);
   if (e != hipSuccess) return APMG_EHIP;
-  if (w.sorted && (e = launch_sort(pts, ld, 0, nullptr, n, 1, w.srt, nullptr, st)) != hipSuccess) return APMG_EHIP;
+  if (w.sorted && (e = launch_sort(pts, ld, 0, nullptr, n, 1, w.srt, nullptr, st, false)) != hipSuccess)
+    return APMG_EHIP;
   TileArgs a;
   memset(&a, 0, sizeof(a));
   a.s = s;

@@ -183,6 +183,27 @@ __global__ void k_bin_starts(const uint32_t* keys, int64_t n, uint32_t* start) {
   }
 }
 
+// The same bin starts with one thread per bin: start[b] = the first position whose key is
+// >= b (n if none), by binary search over the sorted keys.  Balanced where the points leave
+// large runs of bins empty (the per-position kernel then has a few threads writing long
+// gaps); used for large point sets.
+__global__ void k_bin_starts_search(const uint32_t* keys, int64_t n, uint32_t* start) {
+  const int model = blockIdx.y;
+  const uint32_t nbins = (uint32_t)kBinsPerAxis * kBinsPerAxis * kBinsPerAxis;
+  const uint32_t* K = keys + model * n;
+  uint32_t* S = start + (size_t)model * (nbins + 1);
+  for (int64_t b = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; b <= (int64_t)nbins;
+       b += (int64_t)gridDim.x * blockDim.x) {
+    int64_t lo = 0, hi = n;                 // first index in [lo, hi) with K >= b
+    while (lo < hi) {
+      const int64_t mid = lo + ((hi - lo) >> 1);
+      if (K[mid] < (uint32_t)b) lo = mid + 1;
+      else hi = mid;
+    }
+    S[b] = (uint32_t)lo;
+  }
+}
+
 // The training batch's sort keys straight from the counter stream: point i of every model
 // is generated and binned (the points themselves are not stored; they are regenerated in
 // sorted order below).  Model b draws from stream stream0 + b.
@@ -229,7 +250,7 @@ __global__ void k_permute_points(SortIn in, int64_t n, const uint32_t* perm, flo
     float x, y, z;
     in.get(model, n, i, x, y, z);
     O[j] = x; O[n + j] = y; O[2 * n + j] = z;
-    out4[model * n + j] = make_float4(x, y, z, 0.f);
+    if (out4) out4[model * n + j] = make_float4(x, y, z, 0.f);
     if (src_f) dst_f[model * n + j] = src_f[model * n + i];
   }
 }

@@ -781,3 +781,26 @@ def test_abi_paper_order_grids_and_4x4_transforms():
     (out * dft).sum().backward()
     assert torch.equal(Fp.grad, dF) and torch.all(Gp.grad[:, 3, :] == 0)
     assert_close("autograd dG (4x4)", Gp.grad[:, :3, :].cpu().numpy(), go["dG"])
+
+
+def test_backward_large_batch_bin_starts_by_search():
+    # more than 8 points per spatial bin (2^21 + 4096 points): the bin starts come from one
+    # binary search per bin instead of one thread per position; the gradients equal the sum
+    # of the two halves' (each under the per-position path), to float32 rounding of the sums
+    host = host_model(8, 2, 16, 64, extra_t=0.1)
+    n = (1 << 21) + 4096
+    x = synth.uniform_points_host(n, seed=41).astype(np.float32)
+    x[:4096] = 0.02 * x[:4096] + 0.5                   # a dense clump, so that many bins stay empty
+    # positive weights: the sums do not cancel, so their float32 rounding stays far below the bar
+    df = np.random.default_rng(42).uniform(0.5, 1.5, size=n).astype(np.float32)
+    model = A().Model.from_host(host, DEV)
+    xd, dfd = soa(x), torch.from_numpy(df).to(DEV)
+    dF, dG, dW = A().apmg_backward(model, xd, dfd)
+    h = n // 2
+    xa, xb = soa(x[:h]), soa(x[h:])
+    dFa, dGa, dWa = A().apmg_backward(model, xa, dfd[:h].contiguous())
+    dFb, dGb, dWb = A().apmg_backward(model, xb, dfd[h:].contiguous())
+    assert_close("dF (one call vs halves)", dF.cpu().numpy(), (dFa + dFb).cpu().numpy())
+    assert_close("dG (one call vs halves)", dG.cpu().numpy(), (dGa + dGb).cpu().numpy())
+    for k in range(3):
+        assert_close(f"dW{k + 1} (one call vs halves)", dW[k].cpu().numpy(), (dWa[k] + dWb[k]).cpu().numpy())

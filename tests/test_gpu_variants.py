@@ -178,10 +178,12 @@ def test_hash_transform_gradient_only_and_accumulate():
     m, e = model.structs()
     ws = A()._variant_ws(A().OP_BACKWARD, m, e, x.shape[0], DEV)
     arr = (ctypes.c_void_p * 3)(*[w.data_ptr() for w in dW1])
+    xd = soa(x)      # device buffers stay referenced until the call has run
     A()._check("apmg_variant_backward", A()._lib.apmg_variant_backward(
-        ctypes.byref(m), ctypes.byref(e), A()._ptr(soa(x)), x.shape[0], x.shape[0], A()._ptr(dfd), A()._ptr(dF1),
+        ctypes.byref(m), ctypes.byref(e), A()._ptr(xd), x.shape[0], x.shape[0], A()._ptr(dfd), A()._ptr(dF1),
         A()._ptr(dG1), ctypes.cast(arr, ctypes.c_void_p), A().ACCUMULATE, A()._ptr(ws), ws.numel(),
         A()._stream(DEV)))
+    torch.cuda.synchronize()
     assert_close("2 dTheta", dF1.cpu().numpy(), 2 * go["dTheta"])
     assert_close("2 dG", dG1.cpu().numpy(), 2 * go["dG"])
     assert_close("2 dW1", dW1[0].cpu().numpy(), 2 * go["dW"][0])
@@ -277,3 +279,38 @@ def test_variant_empty_and_unsupported():
     big = hash_host(M=9, L=4, T=64, res=(1, 2, 3, 4))
     with pytest.raises(A().ApmgError):
         A().apmg_variant_forward(hash_model(big), torch.zeros((3, 4), device=DEV))
+
+
+def test_variants_4x4_transforms_and_accumulate_time():
+    # [M][4][4] transforms (row 3 not read) and APMG_ACCUMULATE on the 4-D grids: the second
+    # call adds the same gradients again
+    h = time_host(M=6, R=5, Rt=3, seed=31)
+    x = points(1200, seed=32, time=True)
+    _, cache = V.time_forward(f64(h), x[:, :3].astype(np.float64), x[:, 3].astype(np.float64))
+    x = x[kink_free(cache)]
+    df = np.random.default_rng(33).normal(size=x.shape[0]).astype(np.float32)
+    G4 = np.zeros((h["G"].shape[0], 4, 4), np.float32)
+    G4[:, :3, :] = h["G"]
+    G4[:, 3, :] = [5.0, -7.0, 9.0, 11.0]          # garbage in the unused row
+    model = time_model(h)
+    model.G = torch.from_numpy(G4).to(DEV)
+    f = A().apmg_variant_forward(model, soa(x)).cpu().numpy()
+    fo, _ = V.time_forward(f64(h), x[:, :3].astype(np.float64), x[:, 3].astype(np.float64))
+    assert_close("f (4x4)", f, fo)
+    dF, dG, dW = A().apmg_variant_backward(model, soa(x), torch.from_numpy(df).to(DEV))
+    go = V.time_backward(f64(h), x[:, :3].astype(np.float64), x[:, 3].astype(np.float64), df.astype(np.float64))
+    assert_close("dF4 (4x4)", dF.cpu().numpy(), go["dF4"])
+    assert_close("dG rows 0-2 (4x4)", dG.cpu().numpy()[:, :3, :], go["dG"])
+    assert float(dG[:, 3, :].abs().max()) == 0.0
+    m, e = model.structs()
+    ws = A()._variant_ws(A().OP_BACKWARD, m, e, x.shape[0], DEV)
+    arr = (ctypes.c_void_p * 3)(*[w.data_ptr() for w in dW])
+    xd, dfd = soa(x), torch.from_numpy(df).to(DEV)   # referenced until the call has run
+    A()._check("apmg_variant_backward", A()._lib.apmg_variant_backward(
+        ctypes.byref(m), ctypes.byref(e), A()._ptr(xd), x.shape[0], x.shape[0], A()._ptr(dfd), A()._ptr(dF),
+        A()._ptr(dG), ctypes.cast(arr, ctypes.c_void_p), A().ACCUMULATE, A()._ptr(ws), ws.numel(),
+        A()._stream(DEV)))
+    torch.cuda.synchronize()
+    assert_close("2 dF4", dF.cpu().numpy(), 2 * go["dF4"])
+    assert_close("2 dG", dG.cpu().numpy()[:, :3, :], 2 * go["dG"])
+    assert_close("2 dW2", dW[1].cpu().numpy(), 2 * go["dW"][1])
