@@ -354,8 +354,12 @@ __host__ __device__ inline size_t fwd_weight_bytes(const Shape& s, bool bf) {
 }
 
 // WL: the swizzled weights are staged in LDS (after the transforms).
-template <int C, int H, bool GF16, bool BF, bool WL, int ENC = kEncDense>
-__global__ void __launch_bounds__(kBlock) k_forward(TileArgs a) {
+// NWF waves per block: 4, or 8 where the staged weights are so large that one block fills a
+// CU's LDS (then eight waves share them, two per SIMD, instead of one; measured on the 64-grid
+// 256-128-128-1 BF16 model: 8.06 -> 6.14 ms per 16.6 M-point frame; twelve waves, three per
+// SIMD, 6.26 ms).
+template <int C, int H, bool GF16, bool BF, bool WL, int ENC = kEncDense, int NWF = kWavesPerBlock>
+__global__ void __launch_bounds__(NWF * kWave) k_forward(TileArgs a) {
   extern __shared__ float smem[];
   // logical block: models in order, each model's blocks over contiguous runs of its
   // (spatially sorted) tiles, dealt to the XCDs in slabs
@@ -390,7 +394,7 @@ __global__ void __launch_bounds__(kBlock) k_forward(TileArgs a) {
   const int64_t ntiles = (cnt + 31) / 32;
   const int64_t per = (ntiles + gridDim.x - 1) / gridDim.x;
   const int64_t t_end = min(ntiles, (lb + 1) * per);
-  for (int64_t tile = lb * per + wave; tile < t_end; tile += kWavesPerBlock) {
+  for (int64_t tile = lb * per + wave; tile < t_end; tile += NWF) {
     const int64_t p = tile * 32 + j;
     const bool valid = p < cnt;
     float x = 0.f, y = 0.f, z = 0.f, tq = 0.f;
@@ -836,15 +840,19 @@ __global__ void __launch_bounds__(256) k_dw_gemm(const void* act, int act_rows, 
 
 // ------------------------------------------------------------------ instantiation
 constexpr size_t kFwdWeightLdsMax = 120 * 1024;
+// above this much LDS per block only one forward block fits a compute unit: eight-wave blocks
+constexpr size_t kFwdWideLds = 80 * 1024;
 
 template <int C, int H, bool GF16, bool BF>
 hipError_t launch_tile_kernels(bool backward, int kb, const TileArgs& a, dim3 grid, size_t shmem,
                                hipStream_t st) {
   if (!backward) {
-    if (fwd_weight_bytes(a.s, BF) <= kFwdWeightLdsMax)
-      hipLaunchKernelGGL((k_forward<C, H, GF16, BF, true>), grid, dim3(kBlock), shmem, st, a);
-    else
+    if (fwd_weight_bytes(a.s, BF) > kFwdWeightLdsMax)
       hipLaunchKernelGGL((k_forward<C, H, GF16, BF, false>), grid, dim3(kBlock), shmem, st, a);
+    else if (shmem > kFwdWideLds)
+      hipLaunchKernelGGL((k_forward<C, H, GF16, BF, true, kEncDense, 8>), grid, dim3(8 * kWave), shmem, st, a);
+    else
+      hipLaunchKernelGGL((k_forward<C, H, GF16, BF, true>), grid, dim3(kBlock), shmem, st, a);
   } else if (a.act) {
     hipLaunchKernelGGL((k_backward<C, H, GF16, BF, 0, true>), grid, dim3(kBlock), shmem, st, a);
   } else if constexpr (H == 64) {
