@@ -223,6 +223,12 @@ __global__ void __launch_bounds__(NW * kWave, 8 / NW) k_adjoint(TileArgs a) {
   const float* Pp = a.pts + model * a.pts_stride;
   float* dY = a.dY ? a.dY + (size_t)model * s.M * a.n * C : nullptr;
   const size_t o2t = (size_t)2 * H * s.KHP + (size_t)H * H, o1t = o2t + (size_t)H * H;
+  // a model's dL/dy below 2 GiB is stored through a buffer resource (32-bit offsets)
+  const size_t dy_bytes = (size_t)s.M * a.n * C * 4;
+  const bool dy_buf = dY && dy_bytes < ((size_t)1 << 31);
+  const __amdgpu_buffer_rsrc_t dy_rsrc =
+      __builtin_amdgcn_make_buffer_rsrc(dY, (short)0, dy_buf ? (int)dy_bytes : 0, kBufferRsrcWord3);
+  const int dy_grid = dy_buf ? (int)(a.n * C * 4) : 0;   // bytes per grid
 
   // this wave's weight-gradient blocks: dW2 block (ib2, kb2) over published points
   // [k2len part2, +k2len); dW1 block (ib1, kb1) over [k1len part1, +k1len)
@@ -248,6 +254,7 @@ __global__ void __launch_bounds__(NW * kWave, 8 / NW) k_adjoint(TileArgs a) {
     const int64_t tile = rbase + wave;
     const int64_t p = tile * 32 + j;
     const bool valid = tile < t_end && p < a.n;
+    const int dy_lane = dy_buf ? (int)(((int64_t)hf * s.Mh * a.n + p) * C * 4) : 0;
     float x = 0.f, y = 0.f, z = 0.f, tq = 0.f;
     if (valid) { x = Pp[p]; y = Pp[a.ld + p]; z = Pp[2 * a.ld + p]; }
     if constexpr (ENC == kEncTime) tq = valid ? a.tau[p] : 0.f;
@@ -385,9 +392,22 @@ __global__ void __launch_bounds__(NW * kWave, 8 / NW) k_adjoint(TileArgs a) {
             const int gi = 16 * blk / C + u;
             const int g = hf * s.Mh + gi;
             if (valid && gi < s.Mh && g < s.M) {
-              float* dst = dY + ((size_t)g * a.n + p) * C;
+              if (dy_buf) {
+                // byte offset = lane part (this half's first grid, this point) + a uniform
+                // per-grid part: no 64-bit address per grid is held across the tile (the
+                // builtin takes the value's bits as an unsigned integer)
 #pragma unroll
-              for (int c = 0; c < C; ++c) dst[c] = dy[u * C + c];
+                for (int c = 0; c < C; ++c)
+                  __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(dy[u * C + c]), dy_rsrc, dy_lane + 4 * c, gi * dy_grid, 0);
+              } else {
+                // (the grid index is opaque here, so its 64-bit offset is formed at the store
+                // instead of being hoisted out of the tile loop and held, or spilled)
+                int gl = g;
+                asm volatile("" : "+v"(gl));
+                float* dst = dY + ((size_t)gl * a.n + p) * C;
+#pragma unroll
+                for (int c = 0; c < C; ++c) dst[c] = dy[u * C + c];
+              }
             }
           }
         }

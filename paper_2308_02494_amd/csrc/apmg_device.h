@@ -16,6 +16,8 @@ typedef uint32_t u32x4a8 __attribute__((ext_vector_type(4), aligned(8)));
 
 constexpr int kWave = 64;
 constexpr int kBlock = 256;   // threads per workgroup in the tile kernels
+// third dword of a raw buffer resource (untyped 32-bit accesses) on gfx950
+constexpr int kBufferRsrcWord3 = 0x00020000;
 constexpr int kWavesPerBlock = kBlock / kWave;
 constexpr float kSMax = 87.0f;  // exp(-s) is taken as 0 above this (float32 range)
 
