@@ -92,11 +92,28 @@ template <bool BF> struct TT {
   typedef typename std::conditional<BF, uint16_t, float>::type T;
 };
 
+// One 32-point tile's block of stored activations (rows x 32 points, float32 or bf16) behind
+// a buffer resource based at the block's row row0: a store's row offset is then a constant or
+// uniform operand of the instruction, not a 64-bit address per row held in registers across
+// the tile.  Row row0 + vrow + srow of point j: vrow may differ per lane, srow is uniform.
 template <bool BF>
-__device__ inline void act_put(void* act, size_t idx, float v) {
-  if constexpr (BF) ((uint16_t*)act)[idx] = bf16_bits(v);
-  else ((float*)act)[idx] = v;
-}
+struct ActTile {
+  static constexpr int kEsz = BF ? 2 : 4, kRowBytes = 32 * kEsz;
+  __amdgpu_buffer_rsrc_t rsrc;
+  int lane_off;   // j * element size
+  __device__ inline ActTile(void* block, int row0, int rows, int j)
+      : rsrc(__builtin_amdgcn_make_buffer_rsrc((char*)block + (size_t)row0 * kRowBytes, (short)0,
+                                               (rows - row0) * kRowBytes, kBufferRsrcWord3)),
+        lane_off(j * kEsz) {}
+  __device__ inline void put(int vrow, int srow, float v) const {
+    // (the builtins take the value's bits as an unsigned integer)
+    if constexpr (BF)
+      __builtin_amdgcn_raw_buffer_store_b16(bf16_bits(v), rsrc, lane_off + vrow * kRowBytes, srow * kRowBytes, 0);
+    else
+      __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), rsrc, lane_off + vrow * kRowBytes,
+                                            srow * kRowBytes, 0);
+  }
+};
 
 template <bool BF>
 __device__ inline void tt_put(typename TT<BF>::T* t, int row, int j, float v) {
@@ -231,8 +248,8 @@ template <int C, int H, bool GF16, bool BF, bool STY = false, int ENC = kEncDens
 __device__ inline void tile_fwd(const Shape& s, const float* sG, const void* F, const void* swz,
                                 const float* w3s, float x, float y, float z, bool valid, int lane,
                                 f32x16 (&z1)[H / 32], f32x16 (&z2)[H / 32], float& m,
-                                typename TT<BF>::T* Ty = nullptr, void* yact = nullptr, int64_t yld = 0,
-                                int64_t ypa = 0, EncArgs ea = {}, float tq = 0.f) {
+                                typename TT<BF>::T* Ty = nullptr, const ActTile<BF>* yact = nullptr,
+                                EncArgs ea = {}, float tq = 0.f) {
   constexpr int NB = H / 32;
   const int hf = lane >> 5;
   const float hR = 0.5f * (float)(s.R - 1);
@@ -254,7 +271,7 @@ __device__ inline void tile_fwd(const Shape& s, const float* sG, const void* F, 
       enc_value<C, ENC>(t, e);
       if (yact && hf * s.Mh + gi < s.M) {
 #pragma unroll
-        for (int c = 0; c < C; ++c) act_put<BF>(yact, (size_t)((hf * s.Mh + gi) * C + c) * yld + ypa, e[c]);
+        for (int c = 0; c < C; ++c) yact->put(hf * s.Mh * C, gi * C + c, e[c]);
       }
 #pragma unroll
       for (int c = 0; c < C; ++c) {
@@ -289,7 +306,7 @@ __device__ inline void tile_fwd(const Shape& s, const float* sG, const void* F, 
         enc_value<C, ENC>(cur, e);
         if (yact && gi < s.Mh && hf * s.Mh + gi < s.M) {
 #pragma unroll
-          for (int c = 0; c < C; ++c) act_put<BF>(yact, (size_t)((hf * s.Mh + gi) * C + c) * yld + ypa, e[c]);
+          for (int c = 0; c < C; ++c) yact->put(hf * s.Mh * C, gi * C + c, e[c]);
         }
 #pragma unroll
         for (int c = 0; c < C; ++c) {
@@ -402,7 +419,7 @@ __global__ void __launch_bounds__(NWF * kWave) k_forward(TileArgs a) {
     if constexpr (ENC == kEncTime) tq = valid ? a.tau[p] : 0.f;
     f32x16 z1[H / 32], z2[H / 32];
     float m;
-    tile_fwd<C, H, GF16, BF, false, ENC>(s, sG, F, swz, w3s, x, y, z, valid, lane, z1, z2, m, nullptr, nullptr, 0, 0,
+    tile_fwd<C, H, GF16, BF, false, ENC>(s, sG, F, swz, w3s, x, y, z, valid, lane, z1, z2, m, nullptr, nullptr,
                                           a.enc, tq);
     if (valid && lane < 32) fo[p] = __builtin_fmaf(m, vs, vo);
   }
@@ -541,17 +558,18 @@ __global__ void __launch_bounds__(kBlock) k_backward(TileArgs a) {
     if (valid) { x = P[p]; y = P[a.ld + p]; z = P[2 * a.ld + p]; }
     f32x16 z1[NB], z2[NB];
     float m;
-    // stored activations: every lane of the tile writes (points past n write zeros); row r of
-    // this lane's point is at pa + 32 r (row offsets are constants, not per-row registers)
-    const size_t pa = (size_t)model * a.act_stride + (size_t)tile * a.act_rows * 32 + j;
+    // stored activations: every lane of the tile writes (points past n write zeros), the
+    // features y through ya (rows from 0), h1, delta1 and delta2 through ha (rows from MC)
+    void* ablk = (char*)a.act + ((size_t)model * a.act_stride + (size_t)tile * a.act_rows * 32) * (BF ? 2 : 4);
+    const ActTile<BF> ya(ablk, 0, s.MC, j), ha(ablk, s.MC, a.act_rows, j);
     tile_fwd<C, H, GF16, BF, REG>(s, sG, F, swz, w3s, x, y, z, valid, lane, z1, z2, m, Ty,
-                                  ACT ? a.act : nullptr, 32, (int64_t)pa);
+                                  ACT ? &ya : nullptr);
     if constexpr (ACT) {
 #pragma unroll
       for (int b = 0; b < NB; ++b)
 #pragma unroll
         for (int r = 0; r < 16; ++r)
-          act_put<BF>(a.act, pa + (size_t)(s.MC + 32 * b + acc_row(r, hf)) * 32, fmaxf(z1[b][r], 0.f));
+          ha.put(4 * hf, 32 * b + 8 * (r >> 2) + (r & 3), fmaxf(z1[b][r], 0.f));
     }
 
     // dL/df for this point
@@ -614,7 +632,7 @@ __global__ void __launch_bounds__(kBlock) k_backward(TileArgs a) {
       for (int b = 0; b < NB; ++b)
 #pragma unroll
         for (int r = 0; r < 16; ++r)
-          act_put<BF>(a.act, pa + (size_t)(s.MC + 2 * H + 32 * b + acc_row(r, hf)) * 32, d2[b][r]);
+          ha.put(4 * hf, 2 * H + 32 * b + 8 * (r >> 2) + (r & 3), d2[b][r]);
     }
 
     // dW2 rows [w2_lo, w2_hi) = sum_j delta2_j h1_j^T, one 32-row block of h1 at a time
@@ -671,7 +689,7 @@ __global__ void __launch_bounds__(kBlock) k_backward(TileArgs a) {
       for (int b = 0; b < NB; ++b)
 #pragma unroll
         for (int r = 0; r < 16; ++r)
-          act_put<BF>(a.act, pa + (size_t)(s.MC + H + 32 * b + acc_row(r, hf)) * 32, d1[b][r]);
+          ha.put(4 * hf, H + 32 * b + 8 * (r >> 2) + (r & 3), d1[b][r]);
     }
 
     const bool any_w1 = REG && ncols > 0;
