@@ -175,7 +175,10 @@ __device__ inline void adj_put(typename AdjT<BF>::T* T, int row, int col, float 
 // at the headline workload: a deeper gather prefetch, PD = 3, changes nothing; float32
 // weights read from global memory instead of LDS, to fit two four-wave blocks per CU,
 // take twice as long.)
-template <int C, bool GF16, bool BF, int NW, int ENC = kEncDense>
+// FULL: the dense encoder with 64 / C grids, so each half holds exactly 32 features; the
+// shape is then a compile-time constant and the per-grid bounds tests of the unrolled
+// loops fold away (otherwise their uniform outcomes are held in scalar registers).
+template <int C, bool GF16, bool BF, int NW, int ENC = kEncDense, bool FULL = false>
 __global__ void __launch_bounds__(NW * kWave, 8 / NW) k_adjoint(TileArgs a) {
   extern __shared__ float smem[];
   typedef typename AdjT<BF>::T TT_;
@@ -187,7 +190,11 @@ __global__ void __launch_bounds__(NW * kWave, 8 / NW) k_adjoint(TileArgs a) {
   // logical block as in k_backward (partials indexed by it, in tile order)
   const int64_t lbl = xcd_logical(blockIdx.x + (int64_t)gridDim.x * blockIdx.y, (int64_t)gridDim.x * gridDim.y);
   const int model = (int)(lbl / gridDim.x), lb = (int)(lbl % gridDim.x);
-  const Shape s = a.s;
+  Shape s = a.s;
+  if constexpr (FULL) {
+    static_assert(ENC == kEncDense, "full halves: the dense encoder");
+    s.C = C; s.H = H; s.M = 64 / C; s.Mh = 32 / C; s.KH = 32; s.KHP = 32; s.MC = 64; s.L = 1;
+  }
   const PartLayout pl = part_layout(s, s.MC, H);
   double* part = a.part + ((size_t)model * gridDim.x + lb) * pl.len;
   const bool act = !a.active || a.active[model];
@@ -533,8 +540,12 @@ hipError_t launch_adjoint(const TileArgs& a, bool grid_f16, bool mlp_bf16, int v
   if (!adjoint_applies(a.s)) return hipErrorInvalidValue;
   const int nw = adjoint_waves(variant, mlp_bf16);
   const size_t shmem = adjoint_lds_bytes(a.s, mlp_bf16, nw);
+  const bool full = a.s.M == 64 / a.s.C && a.s.L == 1;
 #define APMG_ADJ_V(CC, G16, B16)                                                                                   \
-  if (nw == 4) hipLaunchKernelGGL((k_adjoint<CC, G16, B16, 4>), grid, dim3(4 * kWave), shmem, st, a);              \
+  if (full) {                                                                                                     \
+    if (nw == 4) hipLaunchKernelGGL((k_adjoint<CC, G16, B16, 4, kEncDense, true>), grid, dim3(4 * kWave), shmem, st, a); \
+    else hipLaunchKernelGGL((k_adjoint<CC, G16, B16, 8, kEncDense, true>), grid, dim3(8 * kWave), shmem, st, a);  \
+  } else if (nw == 4) hipLaunchKernelGGL((k_adjoint<CC, G16, B16, 4>), grid, dim3(4 * kWave), shmem, st, a);      \
   else hipLaunchKernelGGL((k_adjoint<CC, G16, B16, 8>), grid, dim3(8 * kWave), shmem, st, a);
 #define APMG_ADJ(CC)                                                                                              \
   if (a.s.C == CC) {                                                                                              \
