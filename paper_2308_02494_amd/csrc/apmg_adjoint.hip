@@ -175,10 +175,11 @@ __device__ inline void adj_put(typename AdjT<BF>::T* T, int row, int col, float 
 // at the headline workload: a deeper gather prefetch, PD = 3, changes nothing; float32
 // weights read from global memory instead of LDS, to fit two four-wave blocks per CU,
 // take twice as long.)
-// FULL: the dense encoder with 64 / C grids, so each half holds exactly 32 features; the
-// shape is then a compile-time constant and the per-grid bounds tests of the unrolled
-// loops fold away (otherwise their uniform outcomes are held in scalar registers).
-template <int C, bool GF16, bool BF, int NW, int ENC = kEncDense, bool FULL = false>
+// KF > 0: the dense encoder with an even number of grids and exactly KF features per half
+// (KF = 16 or 32); the shape is then a compile-time constant and the per-grid bounds tests
+// of the unrolled loops fold away (otherwise their uniform outcomes are held in scalar
+// registers).  KF = 0: the shape as given.
+template <int C, bool GF16, bool BF, int NW, int ENC = kEncDense, int KF = 0>
 __global__ void __launch_bounds__(NW * kWave, 8 / NW) k_adjoint(TileArgs a) {
   extern __shared__ float smem[];
   typedef typename AdjT<BF>::T TT_;
@@ -191,9 +192,9 @@ __global__ void __launch_bounds__(NW * kWave, 8 / NW) k_adjoint(TileArgs a) {
   const int64_t lbl = xcd_logical(blockIdx.x + (int64_t)gridDim.x * blockIdx.y, (int64_t)gridDim.x * gridDim.y);
   const int model = (int)(lbl / gridDim.x), lb = (int)(lbl % gridDim.x);
   Shape s = a.s;
-  if constexpr (FULL) {
-    static_assert(ENC == kEncDense, "full halves: the dense encoder");
-    s.C = C; s.H = H; s.M = 64 / C; s.Mh = 32 / C; s.KH = 32; s.KHP = 32; s.MC = 64; s.L = 1;
+  if constexpr (KF > 0) {
+    static_assert(ENC == kEncDense && (KF == 16 || KF == 32), "fixed halves: the dense encoder");
+    s.C = C; s.H = H; s.M = 2 * KF / C; s.Mh = KF / C; s.KH = KF; s.KHP = KF; s.MC = 2 * KF; s.L = 1;
   }
   const PartLayout pl = part_layout(s, s.MC, H);
   double* part = a.part + ((size_t)model * gridDim.x + lb) * pl.len;
@@ -540,13 +541,14 @@ hipError_t launch_adjoint(const TileArgs& a, bool grid_f16, bool mlp_bf16, int v
   if (!adjoint_applies(a.s)) return hipErrorInvalidValue;
   const int nw = adjoint_waves(variant, mlp_bf16);
   const size_t shmem = adjoint_lds_bytes(a.s, mlp_bf16, nw);
-  const bool full = a.s.M == 64 / a.s.C && a.s.L == 1;
+  const int kf = (a.s.L == 1 && a.s.M % 2 == 0) ? (a.s.MC == 64 ? 32 : a.s.MC == 32 ? 16 : 0) : 0;
+#define APMG_ADJ_K(CC, G16, B16, KF_)                                                                              \
+  if (nw == 4) hipLaunchKernelGGL((k_adjoint<CC, G16, B16, 4, kEncDense, KF_>), grid, dim3(4 * kWave), shmem, st, a); \
+  else hipLaunchKernelGGL((k_adjoint<CC, G16, B16, 8, kEncDense, KF_>), grid, dim3(8 * kWave), shmem, st, a);
 #define APMG_ADJ_V(CC, G16, B16)                                                                                   \
-  if (full) {                                                                                                     \
-    if (nw == 4) hipLaunchKernelGGL((k_adjoint<CC, G16, B16, 4, kEncDense, true>), grid, dim3(4 * kWave), shmem, st, a); \
-    else hipLaunchKernelGGL((k_adjoint<CC, G16, B16, 8, kEncDense, true>), grid, dim3(8 * kWave), shmem, st, a);  \
-  } else if (nw == 4) hipLaunchKernelGGL((k_adjoint<CC, G16, B16, 4>), grid, dim3(4 * kWave), shmem, st, a);      \
-  else hipLaunchKernelGGL((k_adjoint<CC, G16, B16, 8>), grid, dim3(8 * kWave), shmem, st, a);
+  if (kf == 32) { APMG_ADJ_K(CC, G16, B16, 32) }                                                                  \
+  else if (kf == 16) { APMG_ADJ_K(CC, G16, B16, 16) }                                                             \
+  else { APMG_ADJ_K(CC, G16, B16, 0) }
 #define APMG_ADJ(CC)                                                                                              \
   if (a.s.C == CC) {                                                                                              \
     if (!grid_f16 && !mlp_bf16) { APMG_ADJ_V(CC, false, false) }                                                  \
@@ -560,6 +562,7 @@ hipError_t launch_adjoint(const TileArgs& a, bool grid_f16, bool mlp_bf16, int v
   APMG_ADJ(4)
 #undef APMG_ADJ
 #undef APMG_ADJ_V
+#undef APMG_ADJ_K
   return hipErrorInvalidValue;
 }
 
