@@ -280,10 +280,10 @@ void radix_passes(int64_t n, int nb, int nt, const SortWs& w, hipStream_t st) {
   uint32_t *ki = w.k0, *vi = w.v0, *ko = w.k1, *vo = w.v1;
   static_assert((kBinBits + kRadixBits - 1) / kRadixBits % 2 == 0, "an even number of passes");
   for (int shift = 0; shift < kBinBits; shift += kRadixBits) {
-    hipLaunchKernelGGL(k_radix_hist, dim3(nt, nb), dim3(256), 0, st, ki, n, shift, w.hist, nt);
+    hipLaunchKernelGGL(k_radix_hist, dim3(nt, nb), dim3(kSortThreads), 0, st, ki, n, shift, w.hist, nt);
     hipLaunchKernelGGL(k_radix_rowscan, dim3(kRadixDigits, nb), dim3(256), 0, st, w.hist, nt, w.rowtot);
     hipLaunchKernelGGL(k_radix_digitscan, dim3(nb), dim3(256), 0, st, w.rowtot, w.dbase);
-    hipLaunchKernelGGL(k_radix_scatter, dim3(nt, nb), dim3(256), 0, st, ki, vi, ko, vo, n, shift, w.hist, w.dbase,
+    hipLaunchKernelGGL(k_radix_scatter, dim3(nt, nb), dim3(kSortThreads), 0, st, ki, vi, ko, vo, n, shift, w.hist, w.dbase,
                        nt);
     std::swap(ki, ko);
     std::swap(vi, vo);
@@ -1333,10 +1333,10 @@ extern "C" apmg_status apmg_dd_forward(const apmg_dd_models* d, const apmg_brick
   const int nt = sort_tiles(n);
   uint32_t *ki = w.k0, *vi = w.v0, *ko = w.k1, *vo = w.v1;
   for (int shift = 0; shift < key_bits(nb); shift += kRadixBits) {
-    hipLaunchKernelGGL(k_radix_hist, dim3(nt, 1), dim3(256), 0, st, ki, n, shift, w.hist, nt);
+    hipLaunchKernelGGL(k_radix_hist, dim3(nt, 1), dim3(kSortThreads), 0, st, ki, n, shift, w.hist, nt);
     hipLaunchKernelGGL(k_radix_rowscan, dim3(kRadixDigits, 1), dim3(256), 0, st, w.hist, nt, w.rowtot);
     hipLaunchKernelGGL(k_radix_digitscan, dim3(1), dim3(256), 0, st, w.rowtot, w.dbase);
-    hipLaunchKernelGGL(k_radix_scatter, dim3(nt, 1), dim3(256), 0, st, ki, vi, ko, vo, n, shift, w.hist, w.dbase, nt);
+    hipLaunchKernelGGL(k_radix_scatter, dim3(nt, 1), dim3(kSortThreads), 0, st, ki, vi, ko, vo, n, shift, w.hist, w.dbase, nt);
     std::swap(ki, ko);
     std::swap(vi, vo);
   }
@@ -1580,10 +1580,10 @@ apmg_status apmg_variant_backward(const apmg_model* m, const apmg_encoder* e, co
     // then a stable pass by time cell: neighbouring points share the time slices too
     const int nt = sort_tiles(n);
     hipLaunchKernelGGL(k_time_keys, dim3(grid1(n)), dim3(256), 0, st, pts + 3 * ld, w.srt.v0, n, ea.Rt, w.tk0, w.tv0);
-    hipLaunchKernelGGL(k_radix_hist, dim3(nt, 1), dim3(256), 0, st, w.tk0, n, 0, w.srt.hist, nt);
+    hipLaunchKernelGGL(k_radix_hist, dim3(nt, 1), dim3(kSortThreads), 0, st, w.tk0, n, 0, w.srt.hist, nt);
     hipLaunchKernelGGL(k_radix_rowscan, dim3(kRadixDigits, 1), dim3(256), 0, st, w.srt.hist, nt, w.srt.rowtot);
     hipLaunchKernelGGL(k_radix_digitscan, dim3(1), dim3(256), 0, st, w.srt.rowtot, w.srt.dbase);
-    hipLaunchKernelGGL(k_radix_scatter, dim3(nt, 1), dim3(256), 0, st, w.tk0, w.tv0, w.tk1, w.tv1, n, 0, w.srt.hist,
+    hipLaunchKernelGGL(k_radix_scatter, dim3(nt, 1), dim3(kSortThreads), 0, st, w.tk0, w.tv0, w.tk1, w.tv1, n, 0, w.srt.hist,
                        w.srt.dbase, nt);
     hipLaunchKernelGGL(k_time_permute, dim3(grid1(n)), dim3(256), 0, st, w.srt.spts, w.srt.sf, pts + 3 * ld,
                        w.srt.v0, w.tv1, n, w.tpts, w.tdf, w.tau);

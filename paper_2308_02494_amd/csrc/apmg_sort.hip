@@ -12,7 +12,10 @@ constexpr int kBinsPerAxis = 64;          // NB
 constexpr int kBinBits = 18;              // 3 * log2(NB)
 constexpr int kRadixBits = 9;
 constexpr int kRadixDigits = 1 << kRadixBits;
-constexpr int kSortTile = 1024;           // keys per block of the histogram / scatter kernels
+constexpr int kSortTile = 4096;           // keys per block of the histogram / scatter kernels
+constexpr int kSortThreads = 512;         // threads per block of the histogram / scatter kernels
+constexpr int kSortWaves = kSortThreads / 64;
+constexpr int kSortRounds = kSortTile / kSortThreads;
 
 // Bin index of a point; coordinates outside [-1, 1) clamp to the edge bins, NaN to 0.
 __device__ inline uint32_t bin_of(float x, float y, float z) {
@@ -54,7 +57,7 @@ __global__ void k_bin_keys(SortIn in, int64_t n, uint32_t* keys, uint32_t* vals)
 }
 
 // Digit histogram per tile: hist[model][digit][tile].
-__global__ void __launch_bounds__(256) k_radix_hist(const uint32_t* keys, int64_t n, int shift, uint32_t* hist,
+__global__ void __launch_bounds__(kSortThreads) k_radix_hist(const uint32_t* keys, int64_t n, int shift, uint32_t* hist,
                                                     int ntiles) {
   __shared__ uint32_t h[kRadixDigits];
   const int model = blockIdx.y, tile = blockIdx.x;
@@ -62,10 +65,15 @@ __global__ void __launch_bounds__(256) k_radix_hist(const uint32_t* keys, int64_
   __syncthreads();
   const uint32_t* K = keys + model * n;
   const int64_t base = (int64_t)tile * kSortTile;
-  for (int k = threadIdx.x; k < kSortTile; k += blockDim.x) {
-    const int64_t i = base + k;
-    if (i < n) atomicAdd(&h[(K[i] >> shift) & (kRadixDigits - 1)], 1u);
+  uint32_t kk[kSortRounds];
+#pragma unroll
+  for (int r = 0; r < kSortRounds; ++r) {
+    const int64_t i = base + r * kSortThreads + threadIdx.x;
+    kk[r] = i < n ? K[i] : 0u;
   }
+#pragma unroll
+  for (int r = 0; r < kSortRounds; ++r)
+    if (base + r * kSortThreads + threadIdx.x < n) atomicAdd(&h[(kk[r] >> shift) & (kRadixDigits - 1)], 1u);
   __syncthreads();
   for (int d = threadIdx.x; d < kRadixDigits; d += blockDim.x)
     hist[((size_t)model * kRadixDigits + d) * ntiles + tile] = h[d];
@@ -120,32 +128,47 @@ __global__ void __launch_bounds__(256) k_radix_digitscan(const uint32_t* rowtot,
   }
 }
 
-// Stable scatter of one radix pass.  Each block walks its tile in rounds of 256
-// keys in index order; within a round, lanes are ranked by wave (wave order) and
-// by lane (lane order) among keys with the same digit.
-__global__ void __launch_bounds__(256) k_radix_scatter(const uint32_t* kin, const uint32_t* vin, uint32_t* kout,
+// Stable scatter of one radix pass.  A block ranks its tile's keys among equal digits in
+// index order (rounds of kSortThreads keys; within a round by wave, then lane), places them in LDS in
+// digit order, and writes each digit's run of keys to consecutive output positions: stores
+// of neighbouring threads land side by side instead of one word per digit bucket.
+__global__ void __launch_bounds__(kSortThreads) k_radix_scatter(const uint32_t* kin, const uint32_t* vin, uint32_t* kout,
                                                        uint32_t* vout, int64_t n, int shift, const uint32_t* offs,
                                                        const uint32_t* dbase, int ntiles) {
-  __shared__ uint32_t running[kRadixDigits];
-  __shared__ uint32_t wcnt[4][kRadixDigits];
+  __shared__ uint32_t sk[kSortTile], sv[kSortTile];
+  __shared__ uint32_t lcount[kRadixDigits];   // keys of each digit ranked so far, then the digit's first slot
+  __shared__ uint32_t gbase[kRadixDigits];    // output position of the tile's first key of each digit
+  __shared__ uint32_t wcnt[kSortWaves][kRadixDigits];  // keys of each digit in each wave of the current round
+  __shared__ uint32_t wsum[kSortWaves];
   const int model = blockIdx.y, tile = blockIdx.x;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const uint32_t* Kin = kin + model * n;
   const uint32_t* Vin = vin + model * n;
   uint32_t* Kout = kout + model * n;
   uint32_t* Vout = vout + model * n;
-  for (int d = threadIdx.x; d < kRadixDigits; d += blockDim.x)
-    running[d] = offs[((size_t)model * kRadixDigits + d) * ntiles + tile] + dbase[(size_t)model * kRadixDigits + d];
+  for (int d = threadIdx.x; d < kRadixDigits; d += blockDim.x) {
+    gbase[d] = offs[((size_t)model * kRadixDigits + d) * ntiles + tile] + dbase[(size_t)model * kRadixDigits + d];
+    lcount[d] = 0;
+  }
+  for (int d = threadIdx.x; d < kSortWaves * kRadixDigits; d += blockDim.x) (&wcnt[0][0])[d] = 0;
   const int64_t base = (int64_t)tile * kSortTile;
+  const int tn = (int)min((int64_t)kSortTile, n - base);   // keys in this tile
   const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-  for (int r = 0; r < kSortTile / 256; ++r) {
-    for (int d = threadIdx.x; d < 4 * kRadixDigits; d += blockDim.x) (&wcnt[0][0])[d] = 0;
-    __syncthreads();
-    const int64_t i = base + r * 256 + threadIdx.x;
-    const bool valid = i < n;
-    uint32_t key = 0, val = 0, dig = 0;
-    if (valid) { key = Kin[i]; val = Vin[i]; dig = (key >> shift) & (kRadixDigits - 1); }
-    // lanes with the same digit (and valid)
+  uint32_t key[kSortRounds], val[kSortRounds], rk[kSortRounds];
+  // every load of the tile is issued before the first barrier (one wait, not one per round)
+#pragma unroll
+  for (int r = 0; r < kSortRounds; ++r) {
+    const int e = r * kSortThreads + threadIdx.x;
+    key[r] = e < tn ? Kin[base + e] : 0u;
+    val[r] = e < tn ? Vin[base + e] : 0u;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < kSortRounds; ++r) {
+    const int e = r * kSortThreads + threadIdx.x;
+    const bool valid = e < tn;
+    const uint32_t dig = valid ? (key[r] >> shift) & (kRadixDigits - 1) : 0u;
+    // lanes of this wave with the same digit (and valid)
     uint64_t same = __ballot(valid);
 #pragma unroll
     for (int b = 0; b < kRadixBits; ++b) {
@@ -156,15 +179,54 @@ __global__ void __launch_bounds__(256) k_radix_scatter(const uint32_t* kin, cons
     if (valid && rank == 0) wcnt[wave][dig] = (uint32_t)__popcll(same);
     __syncthreads();
     if (valid) {
-      uint32_t pos = running[dig] + rank;
-      for (int w = 0; w < wave; ++w) pos += wcnt[w][dig];
-      Kout[pos] = key;
-      Vout[pos] = val;
+      uint32_t q = lcount[dig] + rank;
+      for (int w = 0; w < wave; ++w) q += wcnt[w][dig];
+      rk[r] = q;
     }
     __syncthreads();
-    for (int d = threadIdx.x; d < kRadixDigits; d += blockDim.x)
-      running[d] += wcnt[0][d] + wcnt[1][d] + wcnt[2][d] + wcnt[3][d];
+    // every rank is taken: the first lane of each (wave, digit) group adds its group to the
+    // digit's count and clears the group's entry for the next round (only this wave writes it)
+    if (valid && rank == 0) {
+      atomicAdd(&lcount[dig], wcnt[wave][dig]);
+      wcnt[wave][dig] = 0;
+    }
+  }
+  __syncthreads();
+  // exclusive scan of the digit counts: the first LDS slot of each digit (one digit a thread)
+  static_assert(kSortThreads == kRadixDigits, "one digit per thread in the scan");
+  {
+    const uint32_t c0 = lcount[threadIdx.x];
+    uint32_t x = c0;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const uint32_t y = __shfl_up(x, o, 64);
+      if (lane >= o) x += y;
+    }
+    if (lane == 63) wsum[wave] = x;
     __syncthreads();
+    uint32_t pre = 0;
+    for (int w = 0; w < wave; ++w) pre += wsum[w];
+    lcount[threadIdx.x] = pre + x - c0;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < kSortRounds; ++r) {
+    const int e = r * kSortThreads + threadIdx.x;
+    if (e < tn) {
+      const uint32_t dig = (key[r] >> shift) & (kRadixDigits - 1);
+      const uint32_t slot = lcount[dig] + rk[r];
+      sk[slot] = key[r];
+      sv[slot] = val[r];
+    }
+  }
+  __syncthreads();
+  // slot e holds the (e - first slot of its digit)-th key of that digit in index order
+  for (int e = threadIdx.x; e < tn; e += kSortThreads) {
+    const uint32_t k = sk[e];
+    const uint32_t dig = (k >> shift) & (kRadixDigits - 1);
+    const uint32_t pos = gbase[dig] + ((uint32_t)e - lcount[dig]);
+    Kout[pos] = k;
+    Vout[pos] = sv[e];
   }
 }
 
