@@ -128,8 +128,9 @@ typedef struct apmg_model {
 /* ---------------------------------------------------------------- forward
  * f[n] = d(e(x_n)) for n points (Sec. 4.1, Eqs. (1)-(3) and the decoder).
  * f: [n] float32 output.  From 2^15 points on, the points are first sorted
- * into spatial bins (the workspace then grows with n) and the outputs are
- * scattered back to the caller's order; each value is the same either way. */
+ * into spatial bins (the workspace then grows with n) and the tiles walk that
+ * order, reading each point and writing its output in the caller's order; each
+ * value is the same either way. */
 apmg_status apmg_forward(const apmg_model* model, const float* pts, int64_t ld, int64_t n,
                          float* f, void* ws, size_t ws_bytes, hipStream_t stream);
 

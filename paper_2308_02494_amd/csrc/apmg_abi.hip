@@ -232,13 +232,13 @@ hipError_t launch_ops(const Shape& s, int nb, const float* G, int grows, const v
 // sorted points and an optional permuted per-point array.
 struct SortWs { uint32_t *k0, *v0, *k1, *v1, *hist, *rowtot, *dbase, *start; float *spts, *sf; float4* spts4; };
 inline int sort_tiles(int64_t n) { return (int)std::max<int64_t>(1, (n + kSortTile - 1) / kSortTile); }
-void take_sort(Carver& cv, int64_t n, int nb, bool with_f, SortWs* o);
+void take_sort(Carver& cv, int64_t n, int nb, bool with_f, SortWs* o, bool keys_only = false);
 
 // Forward operands; from kFwdSortMin points on, the points are first sorted into spatial
-// bins (neighbouring points of a wave then share grid cells in cache) and the outputs
-// scattered back to the caller's order.
+// bins (neighbouring points of a wave then share grid cells in cache) and the tiles read
+// their points and write their outputs through the sort's permutation.
 constexpr int64_t kFwdSortMin = (int64_t)1 << 15;
-struct FwdWs { void* swz; float* w3s; bool sorted; SortWs srt; float* fs; OpsWs ops; };
+struct FwdWs { void* swz; float* w3s; bool sorted; SortWs srt; OpsWs ops; };
 // sortable = false: the direct tile path for every n (the sort only orders the work; each
 // output is bitwise the same either way)
 size_t fwd_ws(const Shape& s, const apmg_model* m, int64_t n, void* ws, FwdWs* o, bool sortable = true) {
@@ -250,16 +250,13 @@ size_t fwd_ws(const Shape& s, const apmg_model* m, int64_t n, void* ws, FwdWs* o
   w.swz = cv.take<char>(swz_sizes(s).total() * esz);
   w.w3s = cv.take<float>(s.H);
   w.sorted = sortable && n >= kFwdSortMin;
-  w.fs = nullptr;
-  if (w.sorted) {
-    take_sort(cv, n, 1, false, &w.srt);
-    w.fs = cv.take<float>((size_t)n);
-  }
+  if (w.sorted) take_sort(cv, n, 1, false, &w.srt, true);
   if (o) *o = w;
   return cv.off;
 }
 
-void take_sort(Carver& cv, int64_t n, int nb, bool with_f, SortWs* o) {
+// keys_only: the radix passes' buffers alone (a forward pass reads through the permutation)
+void take_sort(Carver& cv, int64_t n, int nb, bool with_f, SortWs* o, bool keys_only) {
   const int64_t nn = std::max<int64_t>(n, 1);
   o->k0 = cv.take<uint32_t>((size_t)nb * nn);
   o->v0 = cv.take<uint32_t>((size_t)nb * nn);
@@ -268,6 +265,10 @@ void take_sort(Carver& cv, int64_t n, int nb, bool with_f, SortWs* o) {
   o->hist = cv.take<uint32_t>((size_t)nb * kRadixDigits * sort_tiles(n));
   o->rowtot = cv.take<uint32_t>((size_t)nb * kRadixDigits);
   o->dbase = cv.take<uint32_t>((size_t)nb * kRadixDigits);
+  if (keys_only) {
+    o->start = nullptr; o->spts = nullptr; o->sf = nullptr; o->spts4 = nullptr;
+    return;
+  }
   o->start = cv.take<uint32_t>((size_t)nb * (kBinsPerAxis * kBinsPerAxis * kBinsPerAxis + 1));
   o->spts = cv.take<float>((size_t)nb * 3 * nn);
   o->sf = with_f ? cv.take<float>((size_t)nb * nn) : nullptr;
@@ -290,8 +291,9 @@ void radix_passes(int64_t n, int nb, int nt, const SortWs& w, hipStream_t st) {
   }
 }
 
-// with_starts: also the bin starts and the 16-byte point records (the per-cell gather's
-// candidate lists; a forward pass, which sorts only to order its work, needs neither)
+// with_starts: also the points in sorted order, the 16-byte point records and the bin starts
+// (the per-cell gather's candidate lists); a forward pass, which sorts only to order its
+// work, reads its points through the permutation (v0) and needs none of them
 hipError_t launch_sort(const float* pts, int64_t ld, size_t pts_stride, const float4* pts4, int64_t n, int nb,
                        const SortWs& w, const float* src_f, hipStream_t st, bool with_starts = true) {
   const int nt = sort_tiles(n);
@@ -299,13 +301,13 @@ hipError_t launch_sort(const float* pts, int64_t ld, size_t pts_stride, const fl
   in.pts = pts; in.ld = ld; in.pts_stride = pts_stride; in.pts4 = pts4;
   hipLaunchKernelGGL(k_bin_keys, dim3(grid1(n), nb), dim3(256), 0, st, in, n, w.k0, w.v0);
   radix_passes(n, nb, nt, w, st);
-  hipLaunchKernelGGL(k_permute_points, dim3(grid1(n), nb), dim3(256), 0, st, in, n, w.v0, w.spts,
-                     with_starts ? w.spts4 : nullptr, src_f, w.sf);
+  if (!with_starts) return hipGetLastError();
+  hipLaunchKernelGGL(k_permute_points, dim3(grid1(n), nb), dim3(256), 0, st, in, n, w.v0, w.spts, w.spts4, src_f,
+                     w.sf);
   // bin starts: one thread per position (gaps between neighbouring keys are short when the
   // points are few per bin), or one per bin (binary search) for large point sets, whose empty
   // regions would leave a few position threads writing long gaps
   constexpr int64_t kBins = (int64_t)kBinsPerAxis * kBinsPerAxis * kBinsPerAxis;
-  if (!with_starts) return hipGetLastError();
   if (n > 8 * kBins)
     hipLaunchKernelGGL(k_bin_starts_search, dim3(grid1(kBins + 1), nb), dim3(256), 0, st, w.k0, n, w.start);
   else
@@ -692,14 +694,13 @@ apmg_status forward_impl(const apmg_model* m, const float* pts, int64_t ld, int6
   a.s = s;
   a.G = Gc; a.F = Fc; a.swz = w.swz; a.w3s = w.w3s;
   a.vscale = m->vmax - m->vmin; a.voff = m->vmin;
-  if (w.sorted) { a.pts = w.srt.spts; a.ld = n; a.f = w.fs; }
-  else { a.pts = pts; a.ld = ld; a.f = f; }
+  a.pts = pts; a.ld = ld; a.f = f;
+  if (w.sorted) a.perm = w.srt.v0;   // tiles walk the spatial order, inputs and outputs in place
   a.n = n;
   const int64_t tiles = (n + 31) / 32;
   dim3 grid((unsigned)std::min<int64_t>((tiles + kWavesPerBlock - 1) / kWavesPerBlock, 8192), 1);
   e = launch_tile(false, 0, a, gf16, bf, grid, forward_lds_bytes(s, bf), st);
   if (e != hipSuccess) return APMG_EHIP;
-  if (w.sorted) hipLaunchKernelGGL(k_dd_scatter, dim3(grid1(n)), dim3(256), 0, st, w.fs, w.srt.v0, n, f);
   return hip_status(hipGetLastError());
 }
 

@@ -64,6 +64,8 @@ struct TileArgs {
   const float* boff;                      // per model vmin or NULL
   const float* pts; int64_t ld; size_t pts_stride; int64_t n;
   const uint32_t* seg;                    // forward only: [models + 1] segment starts in one shared array, or NULL
+  const uint32_t* perm;                   // forward only, model 0, no segments: the tile's point p is input and
+                                          // output position perm[p] (a spatial order of the points), or NULL
   // forward
   float* f;
   // adjoint

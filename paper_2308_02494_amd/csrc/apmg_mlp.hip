@@ -414,14 +414,16 @@ __global__ void __launch_bounds__(NWF * kWave) k_forward(TileArgs a) {
   for (int64_t tile = lb * per + wave; tile < t_end; tile += NWF) {
     const int64_t p = tile * 32 + j;
     const bool valid = p < cnt;
+    // the point at the tile's position p, or, in a spatial order, at position perm[p]
+    const int64_t q = (a.perm && valid) ? (int64_t)a.perm[p] : p;
     float x = 0.f, y = 0.f, z = 0.f, tq = 0.f;
-    if (valid) { x = P[p]; y = P[a.ld + p]; z = P[2 * a.ld + p]; }
-    if constexpr (ENC == kEncTime) tq = valid ? a.tau[p] : 0.f;
+    if (valid) { x = P[q]; y = P[a.ld + q]; z = P[2 * a.ld + q]; }
+    if constexpr (ENC == kEncTime) tq = valid ? a.tau[q] : 0.f;
     f32x16 z1[H / 32], z2[H / 32];
     float m;
     tile_fwd<C, H, GF16, BF, false, ENC>(s, sG, F, swz, w3s, x, y, z, valid, lane, z1, z2, m, nullptr, nullptr,
                                           a.enc, tq);
-    if (valid && lane < 32) fo[p] = __builtin_fmaf(m, vs, vo);
+    if (valid && lane < 32) fo[q] = __builtin_fmaf(m, vs, vo);
   }
 }
 
