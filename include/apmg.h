@@ -198,11 +198,15 @@ apmg_status apmg_backward(const apmg_model* model, const float* pts, int64_t ld,
  *   interpolations (Eq. (2)) of the two time slices; a point with tau outside [-1, 1]
  *   (or NaN) gets zero features from every grid.  width[0] = M*C.
  * Built for C = 2, grid_dtype F32, MLP {width[0], 64, 64, 1} with width[0] <= 64, mlp_dtype
- * F32 or BF16 (APMG_EUNSUPPORTED otherwise).  The forward runs over the caller's points
- * (no spatial sort).  The backward first sorts the points into spatial bins (as
- * apmg_backward does), then adds the table / grid gradient with float atomics (every entry
- * a vertex maps to, colliding vertices included; a run of sorted points in one cell is
- * summed in registers and added once), so dF is reproducible to rounding only; dW and dG
+ * F32 or BF16 (APMG_EUNSUPPORTED otherwise).  From 2^15 points on the forward sorts the
+ * points into spatial bins first and its tiles walk that order, as apmg_forward does (each
+ * value is the same either way).  The backward first sorts the points into spatial bins (as
+ * apmg_backward does).  Hash grids: the table gradient is added with float atomics (every
+ * entry a vertex maps to, colliding vertices included; a run of sorted points in one cell
+ * is summed in registers and added once), so dF is reproducible to rounding only.  4-D grids
+ * with Rt >= 3: a further stable sort by time cell, then the grid gradient is gathered per
+ * (time cell, grid cell) as apmg_backward gathers dF, in a fixed order (bitwise
+ * reproducible); with Rt = 2 it is added with atomics as for the hash grids.  dW and dG
  * (float64 per block, fixed order) are as in apmg_backward.
  * Workspace: apmg_variant_workspace_bytes(APMG_OP_FORWARD or APMG_OP_BACKWARD, ...).
  * Arguments, outputs, flags and errors otherwise as apmg_forward / apmg_backward; dF has

@@ -1448,6 +1448,10 @@ struct VarWs {
   // time grids: a further stable pass by time cell -> (time cell, spatial bin) order
   uint32_t *tk0, *tv0, *tk1, *tv1;
   float *tpts, *tdf;
+  // and the atomic-free per-cell gather of the 4-D grid gradient: (x, y, z, t) records, the
+  // starts of every (time cell, bin) and the per-time-cell corner sums
+  float4* trec; uint32_t* tstart; float* tcc;
+  bool fsorted;    // forward from kFwdSortMin points on: the tiles walk a spatial order (srt keys only)
 };
 size_t var_ws(const Shape& s, const EncArgs& ea, const apmg_model* m, const apmg_encoder* e, int64_t n,
               bool backward, void* ws, VarWs* o) {
@@ -1460,6 +1464,10 @@ size_t var_ws(const Shape& s, const EncArgs& ea, const apmg_model* m, const apmg
   if (time_paper) w.F = cv.take<float>(variant_f_elems(s, ea, e->kind));
   w.swz = cv.take<char>(swz_sizes(s).total() * (bf ? 2 : 4));
   w.w3s = cv.take<float>(s.H);
+  if (!backward && n >= kFwdSortMin) {
+    take_sort(cv, n, 1, false, &w.srt, true);
+    w.fsorted = true;
+  }
   if (backward) {
     w.part = cv.take<double>((size_t)bwd_blocks(n, bf) * part_layout(s, s.MC, s.H).len);
     w.dY = cv.take<float>((size_t)s.M * std::max<int64_t>(n, 1) * s.C);
@@ -1473,6 +1481,9 @@ size_t var_ws(const Shape& s, const EncArgs& ea, const apmg_model* m, const apmg
         w.tk0 = cv.take<uint32_t>(nn); w.tv0 = cv.take<uint32_t>(nn);
         w.tk1 = cv.take<uint32_t>(nn); w.tv1 = cv.take<uint32_t>(nn);
         w.tpts = cv.take<float>(3 * nn); w.tdf = cv.take<float>(nn);
+        w.trec = cv.take<float4>(nn);
+        w.tstart = cv.take<uint32_t>((size_t)(ea.Rt - 1) * kBinsPerAxis * kBinsPerAxis * kBinsPerAxis + 1);
+        w.tcc = cv.take<float>((size_t)(ea.Rt - 1) * s.M * 16 * n_cells(s) * s.C);
       }
     }
   }
@@ -1537,6 +1548,11 @@ apmg_status apmg_variant_forward(const apmg_model* m, const apmg_encoder* e, con
   a.vscale = m->vmax - m->vmin; a.voff = m->vmin;
   a.pts = pts; a.ld = ld; a.f = f; a.n = n;
   a.tau = pts + 3 * ld;
+  // as apmg_forward: the tiles walk the points' spatial order (each value is unchanged)
+  if (w.fsorted) {
+    if (launch_sort(pts, ld, 0, nullptr, n, 1, w.srt, nullptr, st, false) != hipSuccess) return APMG_EHIP;
+    a.perm = w.srt.v0;
+  }
   const int64_t tiles = (n + 31) / 32;
   const dim3 grid((unsigned)std::min<int64_t>((tiles + kWavesPerBlock - 1) / kWavesPerBlock, 8192), 1);
   if (launch_enc_forward(a, e->kind, bf, grid, forward_lds_bytes(s, bf), st) != hipSuccess) return APMG_EHIP;
@@ -1587,7 +1603,9 @@ apmg_status apmg_variant_backward(const apmg_model* m, const apmg_encoder* e, co
     hipLaunchKernelGGL(k_radix_scatter, dim3(nt, 1), dim3(kSortThreads), 0, st, w.tk0, w.tv0, w.tk1, w.tv1, n, 0, w.srt.hist,
                        w.srt.dbase, nt);
     hipLaunchKernelGGL(k_time_permute, dim3(grid1(n)), dim3(256), 0, st, w.srt.spts, w.srt.sf, pts + 3 * ld,
-                       w.srt.v0, w.tv1, n, w.tpts, w.tdf, w.tau);
+                       w.srt.v0, w.tv1, n, w.tpts, w.tdf, w.tau, w.trec);
+    hipLaunchKernelGGL(k_time_bin_starts, dim3(grid1(n + 1)), dim3(256), 0, st, w.tk1, w.srt.k0, w.tv1, n, ea.Rt,
+                       w.tstart);
     bpts = w.tpts;
     bdf = w.tdf;
   } else if (w.tau) {
@@ -1627,13 +1645,36 @@ apmg_status apmg_variant_backward(const apmg_model* m, const apmg_encoder* e, co
   // is then laid out in the paper's order), transform gradient per block in float64
   float* dst = dF ? (w.dFcl ? w.dFcl : dF) : nullptr;
   if (dst && w.dFcl) hipLaunchKernelGGL(k_fill_f32, dim3(grid1(nF)), dim3(256), 0, st, w.dFcl, nF, 0.f);
+  // 4-D grids in (time cell, bin) order: the grid gradient by the per-cell gather (one pass per
+  // time cell, no atomics, a fixed order), then the vertex sums over both time neighbours
+  const bool pull = dst && w.tcc;
+  if (pull) {
+    CellArgs c;
+    memset(&c, 0, sizeof(c));
+    c.s = s; c.G = Gc; c.F = Fc;
+    c.pts4 = w.trec; c.n = n; c.start = w.tstart; c.dY = w.dY; c.CC = w.tcc; c.Rt = ea.Rt;
+    const int64_t wgroups = (int64_t)wave_groups(s) * s.M * (ea.Rt - 1);
+    if (wgroups > 0x7fffffff) return APMG_EUNSUPPORTED;
+    hipLaunchKernelGGL((k_cell_pull_wave<2, false, kDefaultCellGroup, false, 2>), dim3((unsigned)wgroups), dim3(256),
+                       0, st, c);
+    hipLaunchKernelGGL(k_cell_to_vertex_time<2>, dim3(grid1((int64_t)s.R * s.R * s.R, 1024), s.M, ea.Rt), dim3(256),
+                       0, st, s, ea.Rt, w.tcc, dst);
+  }
+  if (!dG && pull) {
+    if (w.dFcl && dF) {
+      const int64_t V = (int64_t)ea.Rt * s.R * s.R * s.R;
+      hipLaunchKernelGGL(k_cl_to_paper<2>, dim3(grid1(s.M * V, 8192)), dim3(256), 0, st, (int64_t)s.M, V, w.dFcl, dF,
+                         acc ? 1 : 0);
+    }
+    return hip_status(hipGetLastError());
+  }
   EncScatterArgs sa;
   memset(&sa, 0, sizeof(sa));
   sa.s = s; sa.enc = ea; sa.G = Gc; sa.F = Fc;
   sa.pts = bpts; sa.ld = n; sa.n = n;
   sa.tau = w.tau;
   sa.dY = w.dY;
-  sa.dF = dst;
+  sa.dF = pull ? nullptr : dst;   // with the gather done, the scatter forms the transform gradient only
   sa.dGpart = dG ? w.dGpart : nullptr;
   sa.nbx = variant_nbx(n);
   if (launch_enc_scatter(sa, e->kind, st) != hipSuccess) return APMG_EHIP;

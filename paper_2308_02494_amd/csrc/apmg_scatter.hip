@@ -20,6 +20,7 @@ struct CellArgs {
   double* dGpart;                       // [model][M][nblk][12] (DG)
   const int32_t* active;
   int nblk;                             // blocks of 256 cells per grid; launch nmodels * M * nblk blocks
+  int Rt;                               // 4-D grids (two time slices per cell): time vertices
 };
 
 // Corner weight q = a + 2b + 4c of the trilinear weights of offsets w.  Both gathers add
@@ -276,11 +277,17 @@ constexpr int kRowBatch = 128;               // bin rows per batch (two per lane
 // DG: also the transform gradient of L_rec through the trilinear weights: every lane adds
 // the terms of the records it produces (in step order) to its own 12 sums, reduced per
 // workgroup in a fixed order into dGpart[model][g][group][12].
-template <int C, bool GF16, int G, bool DG>
+// TS = 2: the 4-D grids of Sec. 9, one pass per time cell ("model" index = time cell tc over
+// one shared point array sorted by (time cell, bin); start = [tc][NB^3] positions in it, the
+// records (x, y, z, t), dL/dy [M][n][C]); a point of cell tc adds (1 - wt) w_q dL/dy to the
+// cell's slice-0 corners and wt w_q dL/dy to its slice-1 corners (time weight wt, Eq. (2)
+// extended by linear interpolation in time), written as CC[tc][g][slice][8][cells][C].
+template <int C, bool GF16, int G, bool DG, int TS = 1>
 __global__ void __launch_bounds__(256) k_cell_pull_wave(CellArgs a) {
   static_assert(G == 1 || G == 2 || G == 4 || G == 8, "lanes per run");
+  static_assert(TS == 1 || (TS == 2 && !DG), "the 4-D pass has no transform gradient");
   constexpr int NR = 64 / G;                 // runs per batch
-  constexpr int RW = 2 * C;                  // float4 words per record: the 8 C products w_q dL/dy_c
+  constexpr int RW = 2 * C * TS;             // float4 words per record: the 8 TS C products w_q dL/dy_c
   __shared__ float4 sRec[4][64][RW];
   __shared__ float sG[4][12];
   __shared__ uint32_t sRow0[4][kRowBatch];   // first sorted position of each row of the batch
@@ -298,7 +305,7 @@ __global__ void __launch_bounds__(256) k_cell_pull_wave(CellArgs a) {
   const int64_t grp = (L % per_model) / s.M;
   const int g = (int)(L % s.M);
   const int64_t cb = grp * 4 + wave;                            // this wave's cell block
-  const bool act = (!a.active || a.active[model]) && cb < nblk_grid;
+  const bool act = (TS == 2 || !a.active || a.active[model]) && cb < nblk_grid;
   if (lane < 12) sG[wave][lane] = a.G[model * a.G_stride + 12 * g + lane];
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
@@ -306,9 +313,9 @@ __global__ void __launch_bounds__(256) k_cell_pull_wave(CellArgs a) {
   const int bx = (int)(cb % nbx), by = (int)((cb / nbx) % nbx), bz = (int)(cb / ((int64_t)nbx * nbx));
   const int cx = bx * kBlk + (lane & 3), cy = by * kBlk + ((lane >> 2) & 3), cz = bz * kBlk + (lane >> 4);
   const bool own = act && cx < R1 && cy < R1 && cz < R1;
-  float acc[8][C];
+  float acc[8 * TS][C];
 #pragma unroll
-  for (int q = 0; q < 8; ++q)
+  for (int q = 0; q < 8 * TS; ++q)
 #pragma unroll
     for (int c = 0; c < C; ++c) acc[q][c] = 0.f;
   float gacc[DG ? 12 : 1];
@@ -347,9 +354,11 @@ __global__ void __launch_bounds__(256) k_cell_pull_wave(CellArgs a) {
         hi[d] = (int)fminf(fmaxf(f1, 0.f), (float)(kBinsPerAxis - 1));
       }
     }
-    const float4* P4 = a.pts4 + (size_t)model * a.n;
-    const float* dY = a.dY + ((size_t)model * s.M + g) * a.n * C;
-    const uint32_t* start = a.start + (size_t)model * (kBinsPerAxis * kBinsPerAxis * kBinsPerAxis + 1);
+    constexpr size_t kNB3 = (size_t)kBinsPerAxis * kBinsPerAxis * kBinsPerAxis;
+    const float4* P4 = TS == 1 ? a.pts4 + (size_t)model * a.n : a.pts4;
+    const float* dY = a.dY + ((size_t)(TS == 1 ? model : 0) * s.M + g) * a.n * C;
+    const uint32_t* start = a.start + (size_t)model * (TS == 1 ? kNB3 + 1 : kNB3);
+    const float ht = 0.5f * (float)(a.Rt - 1);
     const float hR = 0.5f * (float)R1;
     const int ny_r = hi[1] - lo[1] + 1, nz_r = hi[2] - lo[2] + 1;
     const int nrows = ny_r * nz_r;
@@ -389,22 +398,33 @@ __global__ void __launch_bounds__(256) k_cell_pull_wave(CellArgs a) {
       int t = -1;
       float w[3] = {0.f, 0.f, 0.f};
       int i0[3] = {0, 0, 0};
+      float wt = 0.f;
       if (cd.valid) {
         float l[3];
         local_coords(Gg, cd.q.x, cd.q.y, cd.q.z, l);
-        const bool in = cell_of(l, hR, s.R, i0, w);
+        bool in = cell_of(l, hR, s.R, i0, w);
+        if constexpr (TS == 2) {
+          // the time cell and weight as the 4-D lookup takes them; times outside [-1, 1] add nothing
+          const float tq = cd.q.w;
+          const float ut = __builtin_fmaf(tq, ht, ht);
+          const float ft = fminf(fmaxf(floorf(ut), 0.0f), (float)(a.Rt - 2));
+          in = in && tq >= -1.0f && tq <= 1.0f && (int)ft == model;
+          wt = ut - ft;
+        }
         const int ox = i0[0] - b0[0], oy = i0[1] - b0[1], oz = i0[2] - b0[2];
         if (in && ox >= 0 && ox < kBlk && oy >= 0 && oy < kBlk && oz >= 0 && oz < kBlk)
           t = (oz * kBlk + oy) * kBlk + ox;
       }
       if (t >= 0) {
-        float pr[8 * C];
+        float pr[8 * TS * C];
 #pragma unroll
-        for (int qq = 0; qq < 8; ++qq) {
-          const float wq = corner_weight(qq, w);
+        for (int sl = 0; sl < TS; ++sl)
 #pragma unroll
-          for (int c = 0; c < C; ++c) pr[qq * C + c] = corner_product(wq, cd.dy[c]);
-        }
+          for (int qq = 0; qq < 8; ++qq) {
+            const float wq = TS == 1 ? corner_weight(qq, w) : (sl ? wt : 1.f - wt) * corner_weight(qq, w);
+#pragma unroll
+            for (int c = 0; c < C; ++c) pr[(8 * sl + qq) * C + c] = corner_product(wq, cd.dy[c]);
+          }
 #pragma unroll
         for (int k = 0; k < RW; ++k)
           sRec[wave][lane][k] = make_float4(pr[4 * k], pr[4 * k + 1], pr[4 * k + 2], pr[4 * k + 3]);
@@ -508,9 +528,9 @@ __global__ void __launch_bounds__(256) k_cell_pull_wave(CellArgs a) {
   if (own) {
     const int64_t cell = ((int64_t)cz * R1 + cy) * R1 + cx;
     const int64_t ncell = (int64_t)R1 * R1 * R1;
-    float* out = a.CC + ((size_t)model * s.M + g) * 8 * ncell * C + cell * C;
+    float* out = a.CC + ((size_t)model * s.M + g) * 8 * TS * ncell * C + cell * C;
 #pragma unroll
-    for (int q = 0; q < 8; ++q)
+    for (int q = 0; q < 8 * TS; ++q)
 #pragma unroll
       for (int c = 0; c < C; ++c) out[q * ncell * C + c] = acc[q][c];
   }
@@ -555,6 +575,39 @@ __global__ void k_cell_to_vertex(Shape s, const float* CC, float* dF, size_t dF_
     const size_t cs = paper ? (size_t)nv : 1;
 #pragma unroll
     for (int c = 0; c < C; ++c) dst[c * cs] = accumulate ? dst[c * cs] + sum[c] : sum[c];
+  }
+}
+
+// 4-D grids: dF[g][t][v][c] += the slice-0 corner sums of time cell t and the slice-1 corner
+// sums of time cell t - 1 over the cells adjacent to vertex v (CC of the TS = 2 gather,
+// dF channel-last [M][Rt][R^3][C]); a fixed order.
+template <int C>
+__global__ void k_cell_to_vertex_time(Shape s, int Rt, const float* CC, float* dF) {
+  const int g = blockIdx.y, tv = blockIdx.z;
+  const int R = s.R, R1 = R - 1;
+  const int64_t nv = (int64_t)R * R * R, ncell = (int64_t)R1 * R1 * R1;
+  for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < nv; v += (int64_t)gridDim.x * blockDim.x) {
+    const int vx = (int)(v % R), vy = (int)((v / R) % R), vz = (int)(v / ((int64_t)R * R));
+    float sum[C];
+#pragma unroll
+    for (int c = 0; c < C; ++c) sum[c] = 0.f;
+#pragma unroll
+    for (int sl = 0; sl < 2; ++sl) {
+      const int tc = tv - sl;
+      if (tc < 0 || tc > Rt - 2) continue;
+      const float* cc = CC + (((size_t)tc * s.M + g) * 16 + 8 * sl) * ncell * C;
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        const int cx = vx - (q & 1), cy = vy - ((q >> 1) & 1), cz = vz - (q >> 2);
+        if (cx < 0 || cy < 0 || cz < 0 || cx >= R1 || cy >= R1 || cz >= R1) continue;
+        const float* src = cc + ((q * ncell + ((int64_t)cz * R1 + cy) * R1 + cx)) * C;
+#pragma unroll
+        for (int c = 0; c < C; ++c) sum[c] += src[c];
+      }
+    }
+    float* dst = dF + (((size_t)g * Rt + tv) * nv + v) * C;
+#pragma unroll
+    for (int c = 0; c < C; ++c) dst[c] += sum[c];
   }
 }
 

@@ -224,18 +224,34 @@ __global__ void k_time_keys(const float* __restrict__ tau, const uint32_t* __res
 }
 
 // The points, dL/df and times in (time cell, spatial bin) order: position j takes spatially
-// sorted position q = perm2[j] (original point perm[q]).
+// sorted position q = perm2[j] (original point perm[q]); also as (x, y, z, t) records.
 __global__ void k_time_permute(const float* __restrict__ spts, const float* __restrict__ sf,
                                const float* __restrict__ tau, const uint32_t* __restrict__ perm,
                                const uint32_t* __restrict__ perm2, int64_t n, float* __restrict__ pts2,
-                               float* __restrict__ f2, float* __restrict__ tau2) {
+                               float* __restrict__ f2, float* __restrict__ tau2, float4* __restrict__ rec) {
   for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < n; j += (int64_t)gridDim.x * blockDim.x) {
     const uint32_t q = perm2[j];
-    pts2[j] = spts[q];
-    pts2[n + j] = spts[n + q];
-    pts2[2 * n + j] = spts[2 * n + q];
+    const float x = spts[q], y = spts[n + q], z = spts[2 * n + q], t = tau[perm[q]];
+    pts2[j] = x;
+    pts2[n + j] = y;
+    pts2[2 * n + j] = z;
     f2[j] = sf[q];
-    tau2[j] = tau[perm[q]];
+    tau2[j] = t;
+    rec[j] = make_float4(x, y, z, t);
+  }
+}
+
+// start[k] for k in [0, (Rt - 1) NB^3]: the first position of the (time cell, bin) order whose
+// combined key tc NB^3 + bin is >= k (as k_bin_starts over the combined keys: time keys
+// tkey[j] of the sorted order, bin keys bkey[pos[j]] of the spatial order it was taken from).
+__global__ void k_time_bin_starts(const uint32_t* __restrict__ tkey, const uint32_t* __restrict__ bkey,
+                                  const uint32_t* __restrict__ pos, int64_t n, int Rt, uint32_t* __restrict__ start) {
+  const uint32_t nb3 = (uint32_t)kBinsPerAxis * kBinsPerAxis * kBinsPerAxis;
+  const uint32_t nkeys = (uint32_t)(Rt - 1) * nb3;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i <= n; i += (int64_t)gridDim.x * blockDim.x) {
+    const uint32_t lo = i == 0 ? 0u : tkey[i - 1] * nb3 + bkey[pos[i - 1]] + 1u;
+    const uint32_t hi = i == n ? nkeys : tkey[i] * nb3 + bkey[pos[i]];
+    for (uint32_t b = lo; b <= hi; ++b) start[b] = (uint32_t)i;
   }
 }
 

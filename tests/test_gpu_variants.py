@@ -4,8 +4,9 @@ apmg_variant_backward).
 
 Bars as for the dense model: per output tensor, normwise relative error <= 1e-5 and
 max |x - x*| <= 1e-5 ||x*||_inf in float32; points whose hidden pre-activations come within
-1e-4 (relative) of a ReLU kink are dropped from adjoint inputs.  The table / grid gradient is
-a sum of float atomics (order not fixed), held to the same bars.  BF16 MLP errors are stated.
+1e-4 (relative) of a ReLU kink are dropped from adjoint inputs.  The hash-table gradient is a
+sum of float atomics (order not fixed), held to the same bars; the 4-D grid gradient is
+gathered per cell in a fixed order (bitwise reproducible).  BF16 MLP errors are stated.
 """
 import ctypes
 
@@ -218,6 +219,52 @@ def test_time_backward_fp32_both_layouts():
         assert_close("dG", dG.cpu().numpy(), go["dG"])
         for k in range(3):
             assert_close(f"dW{k + 1}", dW[k].cpu().numpy(), go["dW"][k])
+
+
+def test_time_backward_gathered_per_cell_reproducible():
+    # the 4-D grid gradient is gathered per (time cell, grid cell) in a fixed order: two calls
+    # give the same bits, the gradient alone (no transform gradient, no dW) the same bits again,
+    # and it matches the oracle at a size that spans many bins and every time cell
+    h = time_host(M=8, R=7, Rt=6, seed=41)
+    x = points(30000, seed=42, time=True)
+    _, cache = V.time_forward(f64(h), x[:, :3].astype(np.float64), x[:, 3].astype(np.float64))
+    x = x[kink_free(cache)]
+    df = np.random.default_rng(43).normal(size=x.shape[0]).astype(np.float32)
+    xd, dfd = soa(x), torch.from_numpy(df).to(DEV)
+    model = time_model(h)
+    dF1, dG1, dW1 = A().apmg_variant_backward(model, xd, dfd)
+    dF2, dG2, dW2 = A().apmg_variant_backward(model, xd, dfd)
+    dF3, _, _ = A().apmg_variant_backward(model, xd, dfd, want_dG=False, want_dW=False)
+    torch.cuda.synchronize()
+    assert torch.equal(dF1, dF2) and torch.equal(dG1, dG2)
+    assert all(torch.equal(a, b) for a, b in zip(dW1, dW2))
+    assert torch.equal(dF1, dF3)
+    go = V.time_backward(f64(h), x[:, :3].astype(np.float64), x[:, 3].astype(np.float64), df.astype(np.float64))
+    assert_close("dF4 (30000 points)", dF1.cpu().numpy(), go["dF4"])
+    assert_close("dG (30000 points)", dG1.cpu().numpy(), go["dG"])
+
+
+@pytest.mark.parametrize("kind", ["hash", "time"])
+def test_variant_forward_sorted_path_equals_direct_bitwise(kind):
+    # from 2^15 points on the forward walks the points' spatial order: each output has the same
+    # bits as from calls below the threshold (direct order), and matches the oracle on a sample
+    if kind == "hash":
+        h = hash_host(seed=51)
+        model = hash_model(h)
+    else:
+        h = time_host(M=8, R=9, Rt=6, seed=52)
+        model = time_model(h)
+    x = points(40000, seed=53, time=kind == "time")
+    big = A().apmg_variant_forward(model, soa(x)).cpu().numpy()
+    parts = [A().apmg_variant_forward(model, soa(x[i:i + 10000])).cpu().numpy() for i in range(0, 40000, 10000)]
+    np.testing.assert_array_equal(big, np.concatenate(parts))
+    idx = np.r_[0:64, np.random.default_rng(54).choice(40000, 300, replace=False)]
+    xs = x[idx].astype(np.float64)
+    if kind == "hash":
+        want, _ = V.hash_forward(f64(h), xs)
+    else:
+        want, _ = V.time_forward(f64(h), xs[:, :3], xs[:, 3])
+    assert_close(f"{kind} forward sorted path, sample", big[idx], want)
 
 
 def test_time_equal_slices_equal_the_dense_model_bitwise():
