@@ -474,26 +474,49 @@ size_t den_model_ws(const Shape& s, const apmg_model* m, int64_t n, void* ws, Op
 // Density loss launch sequence for nb models sharing one shape.  pts/err/rho are per
 // model with the given strides; outputs loss (stride lstride) and dG (stride dG_stride).
 // flags: APMG_DENSITY_ABS_DET, APMG_DENSITY_NORM_TARGET; dG has dG_rows rows per transform.
+// Pass A of the training step over the batch as drawn (counter stream), before the sort has
+// finished: rho in draw order into w.rho and the rho half of the pass-A partials.
+void launch_density_a_gen(const Shape& s, const float* G, size_t G_stride, uint64_t seed, const uint64_t* step_ctr,
+                          uint32_t stream0, int64_t n, int p, uint32_t flags, const DenWs& w, int nb,
+                          const int32_t* active, hipStream_t st) {
+  const int abs_det = (flags & APMG_DENSITY_ABS_DET) ? 1 : 0;
+  const size_t rho_stride = (size_t)std::max<int64_t>(n, 1);
+  const int ba = dens_blocks(n);
+  const size_t shA = 64 + (size_t)13 * s.M * 4;
+  if (p == 10)
+    hipLaunchKernelGGL((k_density_a<10, true>), dim3(ba, nb), dim3(256), shA, st, s, G, G_stride, (const float*)nullptr,
+                       (int64_t)0, (size_t)0, n, (const float*)nullptr, (size_t)0, p, abs_det, w.rho, rho_stride, w.pa,
+                       active, seed, step_ctr, stream0);
+  else
+    hipLaunchKernelGGL((k_density_a<0, true>), dim3(ba, nb), dim3(256), shA, st, s, G, G_stride, (const float*)nullptr,
+                       (int64_t)0, (size_t)0, n, (const float*)nullptr, (size_t)0, p, abs_det, w.rho, rho_stride, w.pa,
+                       active, seed, step_ctr, stream0);
+}
+
+// rho_perm (the training step): pass A already ran over the drawn batch (launch_density_a_gen,
+// rho in draw order); only its error sums are formed here and B1 reads rho through rho_perm.
 hipError_t launch_density(const Shape& s, const float* G, size_t G_stride, const float* pts, int64_t ld,
                           size_t pts_stride, int64_t n, const float* err, size_t err_stride, double eps,
                           int p, uint32_t flags, double* loss, int lstride, double* dG, size_t dG_stride, int dG_rows,
                           int accumulate, float* rho_user, const DenWs& w, int nb, const int32_t* active,
-                          hipStream_t st) {
+                          hipStream_t st, const uint32_t* rho_perm = nullptr) {
   const int abs_det = (flags & APMG_DENSITY_ABS_DET) ? 1 : 0, norm = (flags & APMG_DENSITY_NORM_TARGET) ? 1 : 0;
   float* rho = rho_user ? rho_user : w.rho;
   const size_t rho_stride = rho_user ? (size_t)n : (size_t)std::max<int64_t>(n, 1);
   const int ba = dens_blocks(n), nch = dens_chunks(n);
   const size_t shA = 64 + (size_t)13 * s.M * 4;
-  if (p == 10)
+  if (rho_perm)
+    hipLaunchKernelGGL(k_density_errsum, dim3(ba, nb), dim3(256), 0, st, err, err_stride, n, w.pa, active);
+  else if (p == 10)
     hipLaunchKernelGGL(k_density_a<10>, dim3(ba, nb), dim3(256), shA, st, s, G, G_stride, pts, ld, pts_stride, n,
-                       err, err_stride, p, abs_det, rho, rho_stride, w.pa, active);
+                       err, err_stride, p, abs_det, rho, rho_stride, w.pa, active, 0, nullptr, 0);
   else
     hipLaunchKernelGGL(k_density_a<0>, dim3(ba, nb), dim3(256), shA, st, s, G, G_stride, pts, ld, pts_stride, n,
-                       err, err_stride, p, abs_det, rho, rho_stride, w.pa, active);
+                       err, err_stride, p, abs_det, rho, rho_stride, w.pa, active, 0, nullptr, 0);
   hipLaunchKernelGGL(k_density_sums, dim3(nb), dim3(256), 0, st, w.pa, ba, w.sums, nb);
   const size_t astride = (size_t)std::max<int64_t>(n, 1);
   hipLaunchKernelGGL(k_density_b1, dim3(ba, nb), dim3(256), 0, st, rho, rho_stride, err, err_stride, n,
-                     w.sums, eps, w.pb1, w.a, astride, active);
+                     w.sums, eps, w.pb1, w.a, astride, active, rho_perm);
   hipLaunchKernelGGL(k_density_lq, dim3(nb), dim3(256), 0, st, w.pb1, ba, n, w.lq, nb, norm);
   if (dG) {
     const size_t cstride = (size_t)std::max<int64_t>(n, 1);
@@ -1038,6 +1061,9 @@ apmg_status run_step(const apmg_batch* b, const Shape& s, void* ws, const Tune& 
     hipLaunchKernelGGL(k_fill_f32, dim3(grid1((int64_t)(nb * nW))), dim3(256), 0, pst, w.dW, nb * nW, 0.f);
     hipLaunchKernelGGL(k_fill_f64, dim3(1), dim3(256), 0, pst, w.lrec, (size_t)nb, 0.0);
     if (n == 0) hipLaunchKernelGGL(k_fill_f32, dim3(grid1((int64_t)(nb * nF))), dim3(256), 0, pst, w.dF, nb * nF, 0.f);
+    // pass A of the density loss needs the drawn points and the transforms only: beside the sort
+    if (n > 0)
+      launch_density_a_gen(s, b->G, nG, b->seed, b->step, b->stream0, n, b->p, b->flags, w.den, nb, w.dlive, pst);
     // 1. batch points, sorted by spatial bin, and the ground truth at the sorted points
     if (n > 0) {
       hipError_t e0 = launch_step_sort(b->seed, b->step, b->stream0, n, nb, w.srt, b->volume, b->vol[0], b->vol[1],
@@ -1156,7 +1182,7 @@ apmg_status run_step(const apmg_batch* b, const Shape& s, void* ws, const Tune& 
     // weight-gradient reductions are needed only by Adam
     const hipError_t ed = launch_density(s, b->G, nG, w.srt.spts, n, (size_t)3 * n, n, w.err, n, b->eps_density,
                                          b->p, b->flags, b->losses + 1, 2, w.dG, nG, 3, 0, nullptr, w.den, nb,
-                                         w.dlive, dst);
+                                         w.dlive, dst, w.srt.v0);
     reduce_pass(passes.back(), dst);
     if (use_act) act_products(dst);
     hipLaunchKernelGGL(k_copy_f64, dim3((nb + 63) / 64), dim3(64), 0, dst, w.lrec, 1, b->losses, 2, nb,

@@ -222,10 +222,16 @@ __device__ inline void flat_pow2(float l, int p, float& e2p, float& e2pm1) {
 
 // Pass A: rho per point (Eq. (7)) and block sums of rho and err.
 // part: [model][block][2] = {sum rho, sum err}
-template <int PF>
+// GEN: the training batch as it is drawn -- point i of model b regenerated from its counter
+// (stream stream0 + b, the bits the sort and the ground truth use), rho kept at draw index i
+// (pass B1 reads it through the sort's permutation), only part[..][0]; the error sums
+// (part[..][1]) come from k_density_errsum once the adjoint has run.  This needs neither the
+// sorted points nor the errors, so it runs beside the batch sort.
+template <int PF, bool GEN = false>
 __global__ void __launch_bounds__(256) k_density_a(Shape s, const float* Gall, size_t G_stride,
     const float* pts, int64_t ld, size_t pts_stride, int64_t n, const float* err, size_t err_stride,
-    int p, int abs_det, float* rho, size_t rho_stride, double* part, const int32_t* active) {
+    int p, int abs_det, float* rho, size_t rho_stride, double* part, const int32_t* active,
+    uint64_t seed = 0, const uint64_t* step_ctr = nullptr, uint32_t stream0 = 0) {
   extern __shared__ float smem[];
   const int model = blockIdx.y;
   double* spart = (double*)smem;   // [wave][2]
@@ -243,9 +249,12 @@ __global__ void __launch_bounds__(256) k_density_a(Shape s, const float* Gall, s
   __syncthreads();
   double srho = 0.0, serr = 0.0;
   const float* P = pts + model * pts_stride;
+  const uint64_t step = GEN ? *step_ctr : 0;
   if (act) {
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-      const float x = P[i], y = P[ld + i], z = P[2 * ld + i];
+      float x, y, z;
+      if constexpr (GEN) uniform_point(seed, step, stream0 + (uint32_t)model, (uint64_t)i, x, y, z);
+      else { x = P[i]; y = P[ld + i]; z = P[2 * ld + i]; }
       float r = 0.f;
       for (int g = 0; g < s.M; ++g) {
         float l[3];
@@ -255,16 +264,33 @@ __global__ void __launch_bounds__(256) k_density_a(Shape s, const float* Gall, s
       }
       if (rho) rho[model * rho_stride + i] = r;
       srho += r;
-      serr += err[model * err_stride + i];
+      if constexpr (!GEN) serr += err[model * err_stride + i];
     }
   }
   srho = wave_sum(srho);
   serr = wave_sum(serr);
   if ((threadIdx.x & 63) == 0) { spart[2 * (threadIdx.x >> 6)] = srho; spart[2 * (threadIdx.x >> 6) + 1] = serr; }
   __syncthreads();
-  if (threadIdx.x < 2)
+  if (threadIdx.x < (GEN ? 1 : 2))
     part[((size_t)model * gridDim.x + blockIdx.x) * 2 + threadIdx.x] =
         ((spart[threadIdx.x] + spart[2 + threadIdx.x]) + spart[4 + threadIdx.x]) + spart[6 + threadIdx.x];
+}
+
+// The error half of pass A's partials (part[model][block][1] = block sum of err, the blocks and
+// the order of k_density_a), for the training step's pass A over the drawn batch.
+__global__ void __launch_bounds__(256) k_density_errsum(const float* err, size_t err_stride, int64_t n, double* part,
+                                                        const int32_t* active) {
+  __shared__ double spart[4];
+  const int model = blockIdx.y;
+  double serr = 0.0;
+  if (!active || active[model])
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+      serr += err[model * err_stride + i];
+  serr = wave_sum(serr);
+  if ((threadIdx.x & 63) == 0) spart[threadIdx.x >> 6] = serr;
+  __syncthreads();
+  if (threadIdx.x == 0)
+    part[((size_t)model * gridDim.x + blockIdx.x) * 2 + 1] = ((spart[0] + spart[1]) + spart[2]) + spart[3];
 }
 
 // Fixed-order block sum of the K-tuples part[model][k][K], k < nblk: out[q] = sum_k [q].
@@ -318,9 +344,11 @@ __device__ inline void target_terms(double rho, double S, double hbar, double h,
 // Pass B1: per block, {sum of loss summands, Q = sum a rho_s, sum rho*} (a and the loss
 // summands with the unnormalised target); a of every point is kept for the coefficient pass.
 // part: [model][block][3]; a_out: [model][a_stride]
+// rho_perm (or NULL): point i's rho is at rho_perm[model][i] (rho in the batch's draw order,
+// the points and errors in sorted order).
 __global__ void __launch_bounds__(256) k_density_b1(const float* rho, size_t rho_stride, const float* err,
     size_t err_stride, int64_t n, const double* sums, double eps, double* part, double* a_out, size_t a_stride,
-    const int32_t* active) {
+    const int32_t* active, const uint32_t* rho_perm = nullptr) {
   __shared__ double spart[12];   // [wave][3]
   const int model = blockIdx.y;
   const bool act = (!active || active[model]) && sums[2 * model] != 0.0;
@@ -329,7 +357,8 @@ __global__ void __launch_bounds__(256) k_density_b1(const float* rho, size_t rho
     const double S = sums[2 * model], hbar = sums[2 * model + 1] / (double)n;
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
       double term, a, rs, tg;
-      target_terms(rho[model * rho_stride + i], S, hbar, err[model * err_stride + i], eps, (double)n, term, a, rs, tg);
+      const int64_t ri = rho_perm ? (int64_t)rho_perm[model * n + i] : i;
+      target_terms(rho[model * rho_stride + ri], S, hbar, err[model * err_stride + i], eps, (double)n, term, a, rs, tg);
       a_out[model * a_stride + i] = a;
       sl += term;
       sq += a * rs;
