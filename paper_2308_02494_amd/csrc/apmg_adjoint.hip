@@ -175,10 +175,10 @@ __device__ inline void adj_put(typename AdjT<BF>::T* T, int row, int col, float 
 // at the headline workload: a deeper gather prefetch, PD = 3, changes nothing; float32
 // weights read from global memory instead of LDS, to fit two four-wave blocks per CU,
 // take twice as long.)
-// KF > 0: the dense encoder with an even number of grids and exactly KF features per half
-// (KF = 16 or 32); the shape is then a compile-time constant and the per-grid bounds tests
-// of the unrolled loops fold away (otherwise their uniform outcomes are held in scalar
-// registers).  KF = 0: the shape as given.
+// KF > 0: an even number of feature grids and exactly KF features per half (KF = 16 or 32);
+// the shape is then a compile-time constant (for the hash encoder all but its levels per
+// grid) and the per-grid bounds tests of the unrolled loops fold away (otherwise their
+// uniform outcomes are held in scalar registers).  KF = 0: the shape as given.
 template <int C, bool GF16, bool BF, int NW, int ENC = kEncDense, int KF = 0>
 __global__ void __launch_bounds__(NW * kWave, 8 / NW) k_adjoint(TileArgs a) {
   extern __shared__ float smem[];
@@ -193,8 +193,9 @@ __global__ void __launch_bounds__(NW * kWave, 8 / NW) k_adjoint(TileArgs a) {
   const int model = (int)(lbl / gridDim.x), lb = (int)(lbl % gridDim.x);
   Shape s = a.s;
   if constexpr (KF > 0) {
-    static_assert(ENC == kEncDense && (KF == 16 || KF == 32), "fixed halves: the dense encoder");
-    s.C = C; s.H = H; s.M = 2 * KF / C; s.Mh = KF / C; s.KH = KF; s.KHP = KF; s.MC = 2 * KF; s.L = 1;
+    static_assert(KF == 16 || KF == 32, "fixed halves");
+    s.C = C; s.H = H; s.M = 2 * KF / C; s.Mh = KF / C; s.KH = KF; s.KHP = KF; s.MC = 2 * KF;
+    if constexpr (ENC != kEncHash) s.L = 1;
   }
   const PartLayout pl = part_layout(s, s.MC, H);
   double* part = a.part + ((size_t)model * gridDim.x + lb) * pl.len;

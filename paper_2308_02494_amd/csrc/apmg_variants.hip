@@ -297,11 +297,13 @@ hipError_t launch_enc_adjoint(const TileArgs& a, int enc, bool bf, dim3 grid, hi
   if (a.s.C != 2 || !adjoint_applies(a.s)) return hipErrorInvalidValue;
   const int nw = adjoint_waves(0, bf);
   const size_t shmem = adjoint_lds_bytes(a.s, bf, nw);
-#define APMG_EA(E)                                                                                          \
-  if (bf) hipLaunchKernelGGL((k_adjoint<2, false, true, 4, E>), grid, dim3(4 * kWave), shmem, st, a);      \
-  else hipLaunchKernelGGL((k_adjoint<2, false, false, 8, E>), grid, dim3(8 * kWave), shmem, st, a);
-  if (enc == kEncHash) { APMG_EA(kEncHash) }
-  else if (enc == kEncTime) { APMG_EA(kEncTime) }
+  // 32 feature grids of 2 (64 features): the adjoint compiled for that shape
+  const bool kf32 = a.s.M == 32;
+#define APMG_EA(E, KF_)                                                                                     \
+  if (bf) hipLaunchKernelGGL((k_adjoint<2, false, true, 4, E, KF_>), grid, dim3(4 * kWave), shmem, st, a);  \
+  else hipLaunchKernelGGL((k_adjoint<2, false, false, 8, E, KF_>), grid, dim3(8 * kWave), shmem, st, a);
+  if (enc == kEncHash) { if (kf32) { APMG_EA(kEncHash, 32) } else { APMG_EA(kEncHash, 0) } }
+  else if (enc == kEncTime) { if (kf32) { APMG_EA(kEncTime, 32) } else { APMG_EA(kEncTime, 0) } }
   else return hipErrorInvalidValue;
 #undef APMG_EA
   return hipGetLastError();
