@@ -236,6 +236,22 @@ def test_both_gathers_give_the_same_step():
                 assert torch.equal(x, y), unroll
 
 
+@pytest.mark.parametrize("group", [1, 2, 8])
+def test_wave_gather_lane_groups_give_the_same_step(group):
+    # the wave gather with 1, 2 or 8 lanes per run against the one-thread-per-cell gather: the
+    # same terms in another fixed order
+    ref = _bricks_trainer(nb=2, n=6000, tuning={"cell_kernel": 2})
+    ref.step()
+    other = _bricks_trainer(nb=2, n=6000, tuning={"cell_kernel": 1, "cell_group": group})
+    other.step()
+    torch.cuda.synchronize()
+    for x, y in zip((ref.W, ref.G), (other.W, other.G)):
+        assert torch.equal(x, y), group
+    rel = ((ref.mF - other.mF).norm() / ref.mF.norm()).item()
+    print(f"lanes per run {group}: first moment rel {rel:.2e}")
+    assert rel < 1e-6, (group, rel)
+
+
 def test_steps_from_two_host_threads_match_sequential_steps():
     # two trainers stepping at the same time from two host threads, each on its own stream:
     # the library's per-device side stream is forked and joined under a lock, so each
