@@ -344,7 +344,9 @@ inline int wave_groups(const Shape& s) {
 inline int dg_parts(const Shape& s, int cell_kernel) { return cell_kernel != 1 ? wave_groups(s) : cell_blocks(s); }
 void take_cell(Carver& cv, const Shape& s, int64_t n, int nb, CellWs* o) {
   o->dY = cv.take<float>((size_t)nb * s.M * std::max<int64_t>(n, 1) * s.C);
-  o->CC = cv.take<float>((size_t)nb * s.M * n_cells(s) * 8 * s.C);
+  // corner sums per cell (the per-cell gather) or vertex lattices per cell block (the wave gather)
+  const int64_t nbx = (s.R - 1 + kBlk - 1) / kBlk;
+  o->CC = cv.take<float>((size_t)nb * s.M * std::max<int64_t>(n_cells(s) * 8, nbx * nbx * nbx * kLat) * s.C);
   o->dGpart = cv.take<double>((size_t)nb * s.M * std::max(cell_blocks(s), wave_groups(s)) * 12);
 }
 
@@ -396,8 +398,11 @@ hipError_t launch_cells(const Shape& s, bool gf16, const float* G, size_t G_stri
     } else if (want_dG) APMG_PULL(CC_, F16_, true)                                                   \
     else APMG_PULL(CC_, F16_, false)                                                                 \
     prof_end(st, 1);                                                                                \
-    if (dF) hipLaunchKernelGGL((k_cell_to_vertex<CC_>), dim3(grid1((int64_t)s.R * s.R * s.R, 1024), s.M, nb), \
-                               dim3(256), 0, st, s, cw.CC, dF, dF_stride, dF_paper, accumulate, active); \
+    if (dF && wave_kernel)                                                                          \
+      hipLaunchKernelGGL((k_block_to_vertex<CC_>), dim3(grid1((int64_t)s.R * s.R * s.R, 1024), s.M, nb),   \
+                         dim3(256), 0, st, s, cw.CC, dF, dF_stride, dF_paper, accumulate, active);    \
+    else if (dF) hipLaunchKernelGGL((k_cell_to_vertex<CC_>), dim3(grid1((int64_t)s.R * s.R * s.R, 1024), s.M, nb), \
+                                    dim3(256), 0, st, s, cw.CC, dF, dF_stride, dF_paper, accumulate, active); \
   }
   APMG_CELL(1, false) APMG_CELL(2, false) APMG_CELL(4, false)
   APMG_CELL(1, true) APMG_CELL(2, true) APMG_CELL(4, true)

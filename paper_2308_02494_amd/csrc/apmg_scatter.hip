@@ -273,6 +273,7 @@ __global__ void __launch_bounds__(256) k_cell_pull(CellArgs a) {
 // fixed order (step, then lane) set by the candidate sequence and G: bitwise reproducible,
 // but not the plain candidate order of k_cell_pull.
 constexpr int kBlk = 4;                      // cells per block edge
+constexpr int kLat = (kBlk + 1) * (kBlk + 1) * (kBlk + 1);   // vertices of a block
 constexpr int kRowBatch = 128;               // bin rows per batch (two per lane)
 // DG: also the transform gradient of L_rec through the trilinear weights: every lane adds
 // the terms of the records it produces (in step order) to its own 12 sums, reduced per
@@ -293,6 +294,8 @@ __global__ void __launch_bounds__(256) k_cell_pull_wave(CellArgs a) {
   __shared__ uint32_t sRow0[4][kRowBatch];   // first sorted position of each row of the batch
   __shared__ uint32_t sPre[4][kRowBatch + 1];  // exclusive prefix of the rows' lengths; [kRowBatch] = total
   __shared__ double sDG[DG ? 4 : 1][12];
+  // TS = 1: the block's (kBlk + 1)^3 vertex lattice, C values per vertex
+  __shared__ float sLat[TS == 1 ? 4 : 1][TS == 1 ? kLat * C : 1];
   const Shape s = a.s;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int R1 = s.R - 1;
@@ -525,7 +528,33 @@ __global__ void __launch_bounds__(256) k_cell_pull_wave(CellArgs a) {
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     }
   }
-  if (own) {
+  if constexpr (TS == 1) {
+    // the block's cells fold their corner sums into its vertex lattice: in phase q every
+    // owner adds its corner q to vertex cell + offset(q), which no other cell of the block
+    // addresses in that phase (a fixed order, no atomics); the lattice is written whole, and
+    // k_block_to_vertex adds the lattices of the (up to 8) blocks that share a vertex
+    float* lat = sLat[wave];
+    for (int i = lane; i < kLat * C; i += 64) lat[i] = 0.f;
+    const int lx = lane & 3, ly = (lane >> 2) & 3, lz = lane >> 4;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      if (own) {
+        const int v = ((lz + (q >> 2)) * (kBlk + 1) + ly + ((q >> 1) & 1)) * (kBlk + 1) + lx + (q & 1);
+#pragma unroll
+        for (int c = 0; c < C; ++c) lat[v * C + c] = add_rounded(lat[v * C + c], acc[q][c]);
+      }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    if (act) {
+      float* out = a.CC + (((size_t)model * s.M + g) * nblk_grid + cb) * kLat * C;
+      for (int i = lane; i < kLat * C; i += 64) out[i] = lat[i];
+    }
+  } else if (own) {
     const int64_t cell = ((int64_t)cz * R1 + cy) * R1 + cx;
     const int64_t ncell = (int64_t)R1 * R1 * R1;
     float* out = a.CC + ((size_t)model * s.M + g) * 8 * TS * ncell * C + cell * C;
@@ -571,6 +600,48 @@ __global__ void k_cell_to_vertex(Shape s, const float* CC, float* dF, size_t dF_
 #pragma unroll
       for (int c = 0; c < C; ++c) sum[c] += src[c];
     }
+    float* dst = dF + model * dF_stride + (paper ? (size_t)g * C * nv + v : ((size_t)g * nv + v) * C);
+    const size_t cs = paper ? (size_t)nv : 1;
+#pragma unroll
+    for (int c = 0; c < C; ++c) dst[c * cs] = accumulate ? dst[c * cs] + sum[c] : sum[c];
+  }
+}
+
+// dF[model][g][v][c] (+)= sum over the cell blocks that contain vertex v of their lattice
+// values (the dense wave gather's output, [model][M][blocks][kLat][C]; along each axis a
+// vertex at a block boundary belongs to two blocks), in a fixed order.  dF layout as for
+// k_cell_to_vertex.
+template <int C>
+__global__ void k_block_to_vertex(Shape s, const float* BL, float* dF, size_t dF_stride, int paper, int accumulate,
+                                  const int32_t* active) {
+  const int model = blockIdx.z, g = blockIdx.y;
+  if (active && !active[model]) return;
+  const int R = s.R, R1 = R - 1;
+  const int nbx = (R1 + kBlk - 1) / kBlk;
+  const int64_t nv = (int64_t)R * R * R;
+  const float* bl = BL + ((size_t)model * s.M + g) * ((size_t)nbx * nbx * nbx) * kLat * C;
+  for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < nv; v += (int64_t)gridDim.x * blockDim.x) {
+    const int vc[3] = {(int)(v % R), (int)((v / R) % R), (int)(v / ((int64_t)R * R))};
+    int b0[3], nb[3];
+    for (int d = 0; d < 3; ++d) {
+      // blocks b with 0 <= vc - kBlk b <= kBlk: the lower one (vc on its upper face) first
+      const int hi = min(vc[d] / kBlk, nbx - 1);
+      b0[d] = (vc[d] % kBlk == 0 && vc[d] > 0 && hi == vc[d] / kBlk) ? hi - 1 : hi;
+      nb[d] = hi - b0[d] + 1;
+    }
+    float sum[C];
+#pragma unroll
+    for (int c = 0; c < C; ++c) sum[c] = 0.f;
+    for (int iz = 0; iz < nb[2]; ++iz)
+      for (int iy = 0; iy < nb[1]; ++iy)
+        for (int ix = 0; ix < nb[0]; ++ix) {
+          const int bx = b0[0] + ix, by = b0[1] + iy, bz = b0[2] + iz;
+          const int lx = vc[0] - kBlk * bx, ly = vc[1] - kBlk * by, lz = vc[2] - kBlk * bz;
+          const float* src = bl + (((size_t)(bz * nbx + by) * nbx + bx) * kLat +
+                                   (lz * (kBlk + 1) + ly) * (kBlk + 1) + lx) * C;
+#pragma unroll
+          for (int c = 0; c < C; ++c) sum[c] += src[c];
+        }
     float* dst = dF + model * dF_stride + (paper ? (size_t)g * C * nv + v : ((size_t)g * nv + v) * C);
     const size_t cs = paper ? (size_t)nv : 1;
 #pragma unroll
