@@ -55,8 +55,14 @@ __device__ inline void local_box(const float* Gg, const int c0[3], int w, int R1
 // float64, with the row widened by 1e-5 (the float32 rounding of the binning) and the x-range
 // by 1e-4.  The edge rows of the bin grid reach to infinity, because the binning clamps points
 // outside the domain into them.  Returns false for an empty row.
-__device__ inline bool row_x_span(const float* Gg, const double blo[3], const double bhi[3], int lo0, int hi0,
-                                  int yb, int zb, int& x0, int& x1) {
+// ra[d] = 1 / Gg[4 d] (0 where that coefficient is 0), from span_recips once per transform:
+// the x-range's bounds are multiplied by it rather than divided (they are padded anyway).
+__device__ inline void span_recips(const float* Gg, double ra[3]) {
+#pragma unroll
+  for (int d = 0; d < 3; ++d) ra[d] = Gg[4 * d] != 0.f ? 1.0 / (double)Gg[4 * d] : 0.0;
+}
+__device__ inline bool row_x_span(const float* Gg, const double ra[3], const double blo[3], const double bhi[3],
+                                  int lo0, int hi0, int yb, int zb, int& x0, int& x1) {
   constexpr double kInf = __builtin_inf(), kW = 2.0 / kBinsPerAxis;
   const double ylo = yb == 0 ? -kInf : -1.0 + yb * kW - 1e-5;
   const double yhi = yb == kBinsPerAxis - 1 ? kInf : -1.0 + (yb + 1) * kW + 1e-5;
@@ -70,8 +76,8 @@ __device__ inline bool row_x_span(const float* Gg, const double blo[3], const do
     const double m_lo = (a1 > 0 ? a1 * ylo : a1 < 0 ? a1 * yhi : 0.0) + (a2 > 0 ? a2 * zlo : a2 < 0 ? a2 * zhi : 0.0);
     const double m_hi = (a1 > 0 ? a1 * yhi : a1 < 0 ? a1 * ylo : 0.0) + (a2 > 0 ? a2 * zhi : a2 < 0 ? a2 * zlo : 0.0);
     const double P = blo[d] - m_hi, Q = bhi[d] - m_lo;      // P <= a0 x <= Q
-    if (a0 > 0) { xl = fmax(xl, P / a0); xh = fmin(xh, Q / a0); }
-    else if (a0 < 0) { xl = fmax(xl, Q / a0); xh = fmin(xh, P / a0); }
+    if (a0 > 0) { xl = fmax(xl, P * ra[d]); xh = fmin(xh, Q * ra[d]); }
+    else if (a0 < 0) { xl = fmax(xl, Q * ra[d]); xh = fmin(xh, P * ra[d]); }
     else if (P > 0.0 || Q < 0.0) return false;
   }
   if (!(xl <= xh)) return false;
@@ -197,13 +203,14 @@ __global__ void __launch_bounds__(256) k_cell_pull(CellArgs a) {
                                 : (const void*)((const float*)a.F + model * a.F_stride),
                            g, s.R, me, val);
     }
-    double blo[3], bhi[3];
+    double blo[3], bhi[3], ra[3];
     const int me0[3] = {cx, cy, cz};
     local_box(sG, me0, 1, R1, blo, bhi);
+    span_recips(sG, ra);
     for (int bz = lo[2]; bz <= hi[2]; ++bz)
       for (int by = lo[1]; by <= hi[1]; ++by) {
         int x0 = lo[0], x1 = hi[0];
-        if (!sBad && !row_x_span(sG, blo, bhi, lo[0], hi[0], by, bz, x0, x1)) continue;
+        if (!sBad && !row_x_span(sG, ra, blo, bhi, lo[0], hi[0], by, bz, x0, x1)) continue;
         const int row = (bz * kBinsPerAxis + by) * kBinsPerAxis;
         const uint32_t p0 = start[row + x0], p1 = start[row + x1 + 1];
         for (uint32_t p = p0; p < p1; p += kCellUnroll) {
@@ -336,7 +343,8 @@ __global__ void __launch_bounds__(256) k_cell_pull_wave(CellArgs a) {
                            c02, A[0][1] * A[2][0] - A[0][0] * A[2][1], A[0][0] * A[1][1] - A[0][1] * A[1][0]};
     bool bad = !(fabs(det) > 1e-30);
     float Ai[9];
-    for (int k = 0; k < 9; ++k) { Ai[k] = (float)(inv[k] / det); bad = bad || !isfinite(Ai[k]); }
+    const double rdet = 1.0 / det;
+    for (int k = 0; k < 9; ++k) { Ai[k] = (float)(inv[k] * rdet); bad = bad || !isfinite(Ai[k]); }
     int lo[3], hi[3];
     const int b0[3] = {bx * kBlk, by * kBlk, bz * kBlk};
     if (bad) {
@@ -365,8 +373,9 @@ __global__ void __launch_bounds__(256) k_cell_pull_wave(CellArgs a) {
     const float hR = 0.5f * (float)R1;
     const int ny_r = hi[1] - lo[1] + 1, nz_r = hi[2] - lo[2] + 1;
     const int nrows = ny_r * nz_r;
-    double blo[3], bhi[3];
+    double blo[3], bhi[3], ra[3];
     local_box(Gg, b0, kBlk, R1, blo, bhi);
+    span_recips(Gg, ra);
     // A candidate: its point and dL/dy, loaded for every lane (a lane past the end of its run
     // loads point 0), so the loads of the next step are in flight while this one is used.
     struct Cand { float4 q; float dy[C]; bool valid; };
@@ -475,7 +484,7 @@ __global__ void __launch_bounds__(256) k_cell_pull_wave(CellArgs a) {
         int x0 = lo[0], x1 = hi[0];
         if (rr < nrows) {
           const int yb = lo[1] + rr % ny_r, zb = lo[2] + rr / ny_r;
-          if (bad || row_x_span(Gg, blo, bhi, lo[0], hi[0], yb, zb, x0, x1)) {
+          if (bad || row_x_span(Gg, ra, blo, bhi, lo[0], hi[0], yb, zb, x0, x1)) {
             const int row = (zb * kBinsPerAxis + yb) * kBinsPerAxis;
             s0[k] = start[row + x0];
             len[k] = start[row + x1 + 1] - s0[k];
