@@ -313,6 +313,27 @@ def test_backward_accumulate_and_partial_outputs():
     assert_close("dW2 alone", only_w[2][1].cpu().numpy(), dW[1].cpu().numpy(), 1e-6)
 
 
+def test_backward_empty_batch():
+    # an empty batch: the gradients of an empty sum are zero (outputs pre-filled with 7 so the
+    # clearing is seen), and under ACCUMULATE the outputs keep their values bit for bit
+    host = host_model(4, 2, 6, 64)
+    model = A().Model.from_host(host, DEV)
+    empty = torch.empty((3, 0), dtype=torch.float32, device=DEV)
+    no_df = torch.empty(0, dtype=torch.float32, device=DEV)
+    dF0 = torch.full(model.F.shape, 7.0, dtype=torch.float32, device=DEV)
+    dG0 = torch.full(tuple(model.G.shape), 7.0, dtype=torch.float64, device=DEV)
+    dW0 = [torch.full_like(w, 7.0) for w in model.W]
+    dF, dG, dW = A().apmg_backward(model, empty, no_df, dF=dF0, dG=dG0, dW=dW0)
+    torch.cuda.synchronize()
+    assert not dF.any() and not dG.any() and not any(w.any() for w in dW)
+    x = make_points(300, special=False)
+    dF1, dG1, dW1 = A().apmg_backward(model, soa(x), torch.ones(x.shape[0], device=DEV))
+    dF2, dG2, dW2 = A().apmg_backward(model, empty, no_df, flags=A().ACCUMULATE, dF=dF1.clone(),
+                                      dG=dG1.clone(), dW=[w.clone() for w in dW1])
+    assert torch.equal(dF2, dF1) and torch.equal(dG2, dG1)
+    assert all(torch.equal(a, b) for a, b in zip(dW2, dW1))
+
+
 def test_backward_wide_first_layer_activation_path():
     # 256 input features and 128 hidden: outside the register-resident adjoint, so the weight
     # gradients come from the stored activations and the matrix-core products
