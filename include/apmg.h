@@ -390,7 +390,8 @@ typedef struct apmg_batch {
   const float* volume;        /* [nz][ny][nx] float32 */
   const apmg_brick* bricks;   /* [nb] device brick descriptors (extents, vmin, vmax) */
   int32_t vol[3];             /* nx, ny, nz */
-  int64_t n;                  /* points per model per step */
+  int64_t n;                  /* points per model per step; n = 0 is an empty batch: both losses
+                                 0, every gradient zero, so Adam still steps from its moments */
   uint64_t seed;
   uint64_t* step;             /* device step counter */
   float lr, lr_G, beta1, beta2, adam_eps;

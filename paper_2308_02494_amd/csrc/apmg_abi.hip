@@ -1065,7 +1065,12 @@ apmg_status run_step(const apmg_batch* b, const Shape& s, void* ws, const Tune& 
     hipLaunchKernelGGL(k_brick_scale, dim3((nb + 63) / 64), dim3(64), 0, pst, b->bricks, w.scale, nb);
     hipLaunchKernelGGL(k_fill_f32, dim3(grid1((int64_t)(nb * nW))), dim3(256), 0, pst, w.dW, nb * nW, 0.f);
     hipLaunchKernelGGL(k_fill_f64, dim3(1), dim3(256), 0, pst, w.lrec, (size_t)nb, 0.0);
-    if (n == 0) hipLaunchKernelGGL(k_fill_f32, dim3(grid1((int64_t)(nb * nF))), dim3(256), 0, pst, w.dF, nb * nF, 0.f);
+    // an empty batch: every gradient of the (empty) losses is zero, the transforms' included
+    // (the density chain that writes dG runs only for a non-empty batch)
+    if (n == 0) {
+      hipLaunchKernelGGL(k_fill_f32, dim3(grid1((int64_t)(nb * nF))), dim3(256), 0, pst, w.dF, nb * nF, 0.f);
+      hipLaunchKernelGGL(k_fill_f64, dim3(grid1((int64_t)(nb * nG))), dim3(256), 0, pst, w.dG, nb * nG, 0.0);
+    }
     // pass A of the density loss needs the drawn points and the transforms only: beside the sort
     if (n > 0)
       launch_density_a_gen(s, b->G, nG, b->seed, b->step, b->stream0, n, b->p, b->flags, w.den, nb, w.dlive, pst);

@@ -516,3 +516,48 @@ def test_step_adjoint_kernel_variants_match_oracle(variant):
         assert_close("L_rec " + tag, [got["losses"][0]], [info["L_rec"]])
         check_env("mF " + tag, got["mF"], ost["mF"], trk.amF)
         check_env("mW " + tag, got["mW"], flat_w(ost["mW"]), trk.amW)
+
+
+def test_empty_batch_step_is_adam_on_zero_gradients():
+    # a step over an empty batch (n = 0): both losses are 0 and every gradient is zero, so F
+    # and W take the Adam update of a zero gradient from their current moments at t + 1, the
+    # transforms do the same (at tG + 1) only where the density phase is on, and elsewhere
+    # G, mG, vG and tG are left bit for bit
+    vol = synth.make_volume("blobs_sine", (40, 44, 36))
+    nb = 2
+    bricks, _ = brick_setup(vol, nb, 24, 1)
+    hosts = [synth.init_model(8, 2, 8, [16, 64, 64, 1], seed=70 + b, grid_range=0.2) for b in range(nb)]
+    tr = A().Trainer(hosts, vol.to(DEV), bricks, 0, seed=7)
+    rng = np.random.default_rng(17)
+    for k in ("mF", "mW", "mG"):
+        m = getattr(tr, k)
+        vk = getattr(tr, "v" + k[1:])
+        mv = rng.normal(0.0, 1e-3, tuple(m.shape))
+        m.copy_(torch.from_numpy(mv.astype(np.float32)))
+        vk.copy_(torch.from_numpy((mv * mv * rng.uniform(0.5, 2.0, mv.shape) + 1e-12).astype(np.float32)))
+    t0, tG0 = 4, 2
+    tr.t.fill_(t0)
+    tr.tG.fill_(tG0)
+    tr.density_active.copy_(torch.tensor([1, 0], dtype=torch.int32))
+    before = [snapshot(tr, b) for b in range(nb)]
+    tr.step()
+    torch.cuda.synchronize()
+    for b in range(nb):
+        got, old = snapshot(tr, b), before[b]
+        assert np.array_equal(got["losses"], [0.0, 0.0]), got["losses"]
+        assert got["t"] == t0 + 1
+        for k in ("F", "W"):
+            want, wm, wv = O.adam_update(old[k], 0.0, old["m" + k], old["v" + k], t0 + 1, O.LR_DEFAULT)
+            assert_close(f"{k} [model {b}]", got[k], want)
+            assert_close(f"m{k} [model {b}]", got["m" + k], wm)
+            assert_close(f"v{k} [model {b}]", got["v" + k], wv)
+        if b == 0:
+            assert got["tG"] == tG0 + 1
+            want, wm, wv = O.adam_update(old["G"], 0.0, old["mG"], old["vG"], tG0 + 1, O.LR_TRANSFORM)
+            assert_close(f"G [model {b}]", got["G"], want)
+            assert_close(f"mG [model {b}]", got["mG"], wm)
+            assert_close(f"vG [model {b}]", got["vG"], wv)
+        else:
+            assert got["tG"] == tG0
+            for k in ("G", "mG", "vG"):
+                assert np.array_equal(got[k], old[k]), k
