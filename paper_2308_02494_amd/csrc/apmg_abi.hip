@@ -759,6 +759,7 @@ apmg_status apmg_forward_noalloc(const apmg_model* m, const float* pts, int64_t 
   Shape s;
   apmg_status rc = check_model(m, true, &s);
   if (rc != APMG_OK) return rc;
+  if ((rc = check_points(pts, ld, n)) != APMG_OK) return rc;    // before sizing: n >= 0
   if (fwd_ws(s, m, n, nullptr, nullptr, false) > kScratchBytes) return APMG_EWORKSPACE;
   void* ws = device_scratch();
   if (!ws) return APMG_EHIP;

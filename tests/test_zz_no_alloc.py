@@ -65,3 +65,7 @@ def test_noalloc_forward_refuses_scratch_beyond_the_array():
         m.W[k] = 16
     rc = A_._lib.apmg_forward_noalloc(ctypes.byref(m), fake, 8, 8, fake, None)
     assert rc == A_.EWORKSPACE
+    # invalid point counts are refused as invalid arguments before the scratch is sized or
+    # touched (host-side checks; no launch)
+    assert A_._lib.apmg_forward_noalloc(ctypes.byref(m), fake, 8, -1, fake, None) == A_.EINVAL
+    assert A_._lib.apmg_forward_noalloc(ctypes.byref(m), fake, 4, 8, fake, None) == A_.EINVAL
