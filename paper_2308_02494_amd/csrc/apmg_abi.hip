@@ -1000,7 +1000,6 @@ apmg_status apmg_convert_grids(int32_t M, int32_t C, int32_t R, const void* src,
                                int32_t to_cl, hipStream_t st) {
   if (M < 1 || C < 1 || R < 2 || !src || !dst) return APMG_EINVAL;
   if (!((sd == APMG_F32 || sd == APMG_F16) && (dd == APMG_F32 || dd == APMG_F16))) return APMG_EUNSUPPORTED;
-  if (sd == APMG_F16 && dd == APMG_F32 && false) return APMG_EUNSUPPORTED;
   const size_t total = (size_t)M * C * R * R * R;
   const unsigned g = grid1((int64_t)total);
   if (sd == APMG_F32 && dd == APMG_F32)
