@@ -68,6 +68,11 @@ def test_forward_argument_validation_needs_no_gpu():
     assert f(ctypes.byref(m), fake, 4, 8, fake, fake, 1 << 30, None) == A.EINVAL   # ld < n
     assert f(ctypes.byref(m), fake, 8, -1, fake, fake, 1 << 30, None) == A.EINVAL  # n < 0
     assert f(ctypes.byref(m), fake, 8, 8, fake, fake, 16, None) == A.EWORKSPACE
+    # the allocation-free variant checks the same arguments before sizing its scratch
+    g = A._lib.apmg_forward_noalloc
+    assert g(None, None, 0, 0, None, None) == A.EINVAL
+    assert g(ctypes.byref(m), fake, 4, 8, fake, None) == A.EINVAL                   # ld < n
+    assert g(ctypes.byref(m), fake, 8, -1, fake, None) == A.EINVAL                  # n < 0
     for field, val in [("C", 3), ("R", 1)]:
         bad = _model()
         setattr(bad, field, val)
