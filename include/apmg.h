@@ -394,7 +394,8 @@ typedef struct apmg_batch {
                                  0, every gradient zero, so Adam still steps from its moments */
   uint64_t seed;
   uint64_t* step;             /* device step counter */
-  float lr, lr_G, beta1, beta2, adam_eps;
+  float lr, lr_G, beta1, beta2, adam_eps;  /* lr, lr_G, adam_eps >= 0; beta1, beta2 in [0, 1), else
+                                             APMG_EINVAL */
   double eps_density;
   int32_t p;                  /* flat-top strength (10) */
   uint32_t flags;

@@ -1027,6 +1027,10 @@ apmg_status check_batch(const apmg_batch* b, Shape* s) {
   if (b->shape.G_rows == 4) return APMG_EUNSUPPORTED;
   for (int d = 0; d < 3; ++d) if (b->vol[d] < 2) return APMG_EINVAL;
   if (b->p < 1 || !(b->eps_density >= 0.0)) return APMG_EINVAL;
+  // Adam: 1 - beta^t is the bias correction's divisor, so each beta lies in [0, 1)
+  if (!(b->beta1 >= 0.f && b->beta1 < 1.f && b->beta2 >= 0.f && b->beta2 < 1.f && b->adam_eps >= 0.f &&
+        b->lr >= 0.f && b->lr_G >= 0.f))
+    return APMG_EINVAL;
   return APMG_OK;
 }
 

@@ -210,3 +210,31 @@ def test_new_entry_points_validate_without_gpu():
     assert A._lib.apmg_train_control(ctypes.byref(c), None, None) == A.EINVAL
     c.nb = 1
     assert A._lib.apmg_train_control(ctypes.byref(c), 1, None) == A.EINVAL   # NULL state arrays
+
+
+def test_batched_step_rejects_adam_settings_outside_their_range():
+    # beta in [0, 1) (1 - beta^t divides the moments), adam_eps and the rates >= 0: checked on
+    # the host before the workspace; with valid settings the missing workspace is reported
+    b = A.ApmgBatch()
+    b.nb, b.n = 1, 8
+    s = b.shape
+    s.M, s.C, s.R, s.n_layers = 8, 2, 8, 3
+    for k, w in enumerate([16, 64, 64, 1]):
+        s.width[k] = w
+    s.grid_dtype, s.mlp_dtype = A.F32, A.F32
+    for f in ("G", "F", "W", "mG", "vG", "mF", "vF", "mW", "vW", "t", "tG", "density_active", "volume",
+              "bricks", "step", "losses"):
+        setattr(b, f, 0x1000)
+    b.vol[0], b.vol[1], b.vol[2] = 8, 8, 8
+    b.p, b.eps_density = 10, 1e-12
+
+    def rc(**kw):
+        b.lr, b.lr_G, b.beta1, b.beta2, b.adam_eps = 0.01, 0.001, 0.9, 0.99, 1e-8
+        for k, v in kw.items():
+            setattr(b, k, v)
+        return A._lib.apmg_batched_step(ctypes.byref(b), None, 0, None)
+
+    assert rc() == A.EWORKSPACE
+    for bad in ({"beta1": 1.0}, {"beta2": 1.5}, {"beta1": -0.1}, {"beta2": float("nan")},
+                {"adam_eps": -1e-8}, {"lr": -0.01}, {"lr_G": float("nan")}):
+        assert rc(**bad) == A.EINVAL, bad
